@@ -1,0 +1,307 @@
+"""One time step of the Hermite-matrix MRT-LB method, in FP64 NumPy.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The state is the shifted population f_bar of eq. (2-3) (theta = gamma = 1,
+full correction), stored as an array (b, [Nz,] Ny, Nx) with x fastest.  One
+step is, in the paper's order:
+
+  1. macroscopic variables, eq. (2-4-2) / (2-4-1) with lambda = lambda1 =
+     lambda2 = 1 (eq. M-NSEs-6a);
+  2. Hermite moments m = H f_bar of the rows of order <= 3 (Sec. IV);
+  3. equilibrium Hermite moments m_eq from the raw moments M0..M3 the model
+     prescribes: M0 = rho_bar, M1 = rho u, M2 = rho uu + p I,
+     M3 = p Delta.u + M30 with M30 = rho uuu on multispeed lattices
+     (eqs. M-NSEs-6a, M-NSEs-6 / M-NSEs-6-1, and the multispeed special cases
+     of Sec. III), or for the NCDE M0 = phi, M1 = B = phi u,
+     M2 = cs^2 D + M20 with D = Phi(phi) I and M20 = phi uu (eq. M-NCDE-6);
+  4. source moments: M1F = F, M2F = 0 (eq. M-NSEs-5); the auxiliary second
+     moment of G is (I - S2/2)(uF + Fu) (eq. M2G-1 with isothermal p, S = 0
+     and M30 = rho uuu); for the NCDE the auxiliary first moment of G is
+     (I - S1/2)(d_t M1 + div M20) (eq. M-NCDE-6, case (1));
+  5. relaxation with diagonal S in Hermite space and the update
+     m* = m - S (m - m_eq) + m_G + (I - S/2) m_F (eq. 2-3 with
+     Lambda = H^-1 S H, eq. H-MRT-LB);
+  6. back to populations with the reduced form of eq. (H-MRT-LB-1): every row
+     above third order relaxes at the single rate s_h, so
+     f* = (1 - s_h) f + W sum_{r<=3} H_r^T (m*_r - (1 - s_h) m_r) / n_r;
+  7. propagation f_bar_j(x + c_j dt) = f*_j(x) (eq. 2-2), periodic.
+
+Readings of points the paper leaves open (all listed in the design notes):
+Hermite moments of F and G above their constrained orders are zero;
+the equilibrium has no Hermite component above third order (eq. feq-1 with
+m = 3), and none above second order for the NCDE; the NCDE time derivative
+is first-order backward and the gradient is a central difference of the
+previous step's phi; K = dt cs^2 (1/s1 - 1/2) (the printed (S1 - I/2) is a
+typo, compare eq. ME-NCDE-3).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .lattice import Lattice
+
+NSE_INC, NSE_COMP, NCDE = "NSE_INC", "NSE_COMP", "NCDE"
+
+
+@dataclass
+class Model:
+    eq: str = NSE_INC
+    rho0: float = 1.0
+    s0: float = 1.2
+    s1: float = 1.2
+    s_shear: float = 1.25
+    s_bulk: float = 1.2
+    s3: float = 1.2
+    s_h: float = 1.2
+    m30: bool = True
+    D0: float = 0.0          # NCDE: D(phi) = D0 (1 + D2 phi^2)
+    D2: float = 0.0
+    adv_u: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
+
+    def rate(self, group: str) -> float:
+        return {"rho": self.s0, "j": self.s1, "bulk": self.s_bulk, "shear": self.s_shear,
+                "third": self.s3, "high": self.s_h}[group]
+
+
+def rates(lat: Lattice, model: Model) -> np.ndarray:
+    return np.array([model.rate(r.group) for r in lat.rows])
+
+
+# --------------------------------------------------------------------------
+# raw moment tensors -> Hermite moments
+# --------------------------------------------------------------------------
+
+def _raw_component(M, exp):
+    idx = tuple(a for a, k in enumerate(exp) for _ in range(k))
+    if len(idx) == 0:
+        return M[0]
+    T = M[len(idx)]
+    if T is None:
+        raise ValueError("raw moment of order %d not provided" % len(idx))
+    return T[idx]
+
+
+def hermite_from_raw(lat: Lattice, M, max_order: int) -> np.ndarray:
+    """Hermite moments sum_j H_rj g_j of a distribution g whose raw moments
+    sum_j g_j c_j..c_j are M = [M0, M1, M2, M3] (tensors with a trailing node
+    axis); rows above ``max_order`` get zero."""
+    n = np.shape(M[0])[-1]
+    out = np.zeros((len(lat.rows), n))
+    for r, row in enumerate(lat.rows):
+        if row.order > max_order:
+            continue
+        for exp, coef in row.poly.items():
+            out[r] += coef * _raw_component(M, exp)
+    return out
+
+
+def _delta_u(d, v):
+    """(Delta . v)_abc = delta_ab v_c + delta_ac v_b + delta_bc v_a."""
+    n = v.shape[-1]
+    T = np.zeros((d, d, d, n))
+    for a in range(d):
+        for b in range(d):
+            for c in range(d):
+                T[a, b, c] = (a == b) * v[c] + (a == c) * v[b] + (b == c) * v[a]
+    return T
+
+
+def _uu(u):
+    return np.einsum("an,bn->abn", u, u)
+
+
+def _uuu(u):
+    return np.einsum("an,bn,cn->abcn", u, u, u)
+
+
+# --------------------------------------------------------------------------
+# macroscopic variables (eq. 2-4-2 / 2-4-1)
+# --------------------------------------------------------------------------
+
+def macroscopic(lat: Lattice, model: Model, f: np.ndarray, force=None):
+    """(rho_bar or phi, u, rho_m) from pre-collision f_bar of shape (b, n)."""
+    R0 = f.sum(axis=0)
+    if model.eq == NCDE:
+        u = np.repeat(np.asarray(model.adv_u[: lat.d], dtype=np.float64)[:, None], f.shape[1], axis=1)
+        return R0, u, None
+    j = lat.E.T @ f
+    if force is not None:
+        j = j + 0.5 * force
+    rho_m = np.full_like(R0, model.rho0) if model.eq == NSE_INC else R0
+    return R0, j / rho_m, rho_m
+
+
+def equilibrium_raw(lat: Lattice, model: Model, R0, u, rho_m):
+    """Raw moments M0..M3 of f_eq prescribed by the model (None = unconstrained)."""
+    d, cs2 = lat.d, lat.cs2
+    I = np.eye(d)[:, :, None]
+    if model.eq == NCDE:
+        phi = R0
+        K = cs2 * (1.0 / model.s1 - 0.5)
+        Phi = (model.D0 / K) * (phi + model.D2 * phi ** 3 / 3.0)
+        return [phi, phi * u, cs2 * Phi * I + phi * _uu(u), None]
+    p = cs2 * R0                                    # p = cs^2 rho_bar (INC) or cs^2 rho (COMP)
+    M3 = p * _delta_u(d, u) if model.eq == NSE_COMP else rho_m * cs2 * _delta_u(d, u)
+    if model.m30:
+        M3 = M3 + rho_m * _uuu(u)
+    return [R0, rho_m * u, rho_m * _uu(u) + p * I, M3]
+
+
+def equilibrium_hermite(lat, model, R0, u, rho_m):
+    M = equilibrium_raw(lat, model, R0, u, rho_m)
+    return hermite_from_raw(lat, M, max_order=2 if model.eq == NCDE else 3)
+
+
+def force_hermite(lat, n, force):
+    """Hermite moments of the force distribution F_j: M0F = 0, M1F = F, M2F = 0."""
+    d = lat.d
+    if force is None:
+        return np.zeros((len(lat.rows), n))
+    M = [np.zeros(n), force, np.zeros((d, d, n)), None]
+    return hermite_from_raw(lat, M, max_order=2)
+
+
+def aux_hermite(lat, model, s, u, force, extra=None):
+    """Hermite moments of the auxiliary distribution G.
+
+    NSE: M2G = (I - S2/2)(uF + Fu) (Hermite-diagonal S2), zero otherwise.
+    NCDE: M1G = (I - S1/2) B with B = d_t(phi u) + div(phi uu) supplied in
+    ``extra``.
+    """
+    n = u.shape[1]
+    d = lat.d
+    if model.eq == NCDE:
+        if extra is None:
+            return np.zeros((len(lat.rows), n))
+        M = [np.zeros(n), extra, None, None]
+        return (1 - 0.5 * s)[:, None] * hermite_from_raw(lat, M, max_order=1)
+    if force is None:
+        return np.zeros((len(lat.rows), n))
+    T = np.einsum("an,bn->abn", u, force) + np.einsum("an,bn->abn", force, u)
+    M = [np.zeros(n), np.zeros((d, n)), T, None]
+    mg = hermite_from_raw(lat, M, max_order=2)
+    mg[[r.order != 2 for r in lat.rows]] = 0.0
+    return (1 - 0.5 * s)[:, None] * mg
+
+
+def populations_from_hermite(lat: Lattice, m: np.ndarray) -> np.ndarray:
+    """g = W sum_r H_r^T m_r / n_r (eq. geq), for moments of the low rows."""
+    H = lat.H()
+    n = lat.norms()
+    return (lat.w[:, None] * H.T) @ (m / n[:, None])
+
+
+# --------------------------------------------------------------------------
+# NCDE helper: B^n = u [ (phi^n - phi^{n-1}) / dt + u . grad_h phi^{n-1} ]
+# --------------------------------------------------------------------------
+
+def ncde_B(lat: Lattice, model: Model, phi_grid: np.ndarray, phi_prev_grid: np.ndarray):
+    d = lat.d
+    u = np.asarray(model.adv_u[:d], dtype=np.float64)
+    nd = phi_grid.ndim
+    adv = np.zeros_like(phi_prev_grid)
+    for a in range(d):
+        axis = nd - 1 - a                       # x is the last axis
+        grad = (np.roll(phi_prev_grid, -1, axis=axis) - np.roll(phi_prev_grid, 1, axis=axis)) / (2 * lat.c[a])
+        adv += u[a] * grad
+    scal = (phi_grid - phi_prev_grid) + adv
+    return u[:, None] * scal.reshape(1, -1)
+
+
+# --------------------------------------------------------------------------
+# one step
+# --------------------------------------------------------------------------
+
+@dataclass
+class State:
+    f: np.ndarray                 # (b, *grid) pre-collision f_bar
+    phi_prev: np.ndarray = None   # NCDE only: phi of the previous step
+
+
+def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None):
+    """Post-collision populations f* (b, n) from pre-collision f_bar (b, n).
+
+    ``ncde_b`` is the NCDE field B^n (d, n) of the auxiliary first moment."""
+    n = f.shape[1]
+    s = rates(lat, model)
+    R0, u, rho_m = macroscopic(lat, model, f, force)
+    m = lat.H() @ f
+    meq = equilibrium_hermite(lat, model, R0, u, rho_m)
+    mF = force_hermite(lat, n, force) if model.eq != NCDE else np.zeros_like(m)
+    mG = aux_hermite(lat, model, s, u, force, extra=ncde_b)
+    mstar = m - s[:, None] * (m - meq) + mG + (1 - 0.5 * s)[:, None] * mF
+    return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
+
+
+def stream(lat: Lattice, fstar_grid: np.ndarray) -> np.ndarray:
+    out = np.empty_like(fstar_grid)
+    nd = fstar_grid.ndim - 1
+    for j in range(lat.b):
+        shifts = tuple(int(lat.e[j, a]) for a in range(lat.d))
+        axes = tuple(nd - 1 - a for a in range(lat.d))   # x -> last axis
+        out[j] = np.roll(fstar_grid[j], shifts, axis=axes)
+    return out
+
+
+def step(lat: Lattice, model: Model, st: State, force=None) -> State:
+    grid = st.f.shape[1:]
+    f = st.f.reshape(lat.b, -1)
+    extra = None
+    phi = None
+    if model.eq == NCDE:
+        phi = f.sum(axis=0).reshape(grid)
+        extra = ncde_B(lat, model, phi, st.phi_prev)
+    F = None if force is None else force.reshape(lat.d, -1)
+    fstar = collide(lat, model, f, F, extra)
+    return State(stream(lat, fstar.reshape(st.f.shape)), phi)
+
+
+def run(lat, model, st: State, steps: int, force=None) -> State:
+    for _ in range(steps):
+        st = step(lat, model, st, force)
+    return st
+
+
+# --------------------------------------------------------------------------
+# initialisation and read-out
+# --------------------------------------------------------------------------
+
+def init_state(lat: Lattice, model: Model, rho_or_phi: np.ndarray, u=None, force=None) -> State:
+    """f_bar(x, 0) = f_eq(rho, u) - dt/2 F (NSE) or f_eq(phi) (NCDE)."""
+    grid = rho_or_phi.shape
+    R0 = rho_or_phi.reshape(-1).astype(np.float64)
+    n = R0.size
+    if model.eq == NCDE:
+        uu = np.repeat(np.asarray(model.adv_u[: lat.d], dtype=np.float64)[:, None], n, axis=1)
+        meq = equilibrium_hermite(lat, model, R0, uu, None)
+        f = populations_from_hermite(lat, meq)
+        return State(f.reshape((lat.b,) + grid), rho_or_phi.astype(np.float64).copy())
+    uv = u.reshape(lat.d, -1).astype(np.float64)
+    rho_m = np.full(n, model.rho0) if model.eq == NSE_INC else R0
+    meq = equilibrium_hermite(lat, model, R0, uv, rho_m)
+    f = populations_from_hermite(lat, meq)
+    if force is not None:
+        f = f - 0.5 * populations_from_hermite(lat, force_hermite(lat, n, force.reshape(lat.d, -1)))
+    return State(f.reshape((lat.b,) + grid), None)
+
+
+def moments(lat: Lattice, model: Model, st: State, force=None):
+    """(rho_bar or phi, u) on the grid at the current time."""
+    grid = st.f.shape[1:]
+    f = st.f.reshape(lat.b, -1)
+    F = None if force is None else force.reshape(lat.d, -1)
+    R0, u, _ = macroscopic(lat, model, f, F)
+    return R0.reshape(grid), u.reshape((lat.d,) + grid)
+
+
+def conserved(lat: Lattice, model: Model, st: State, force=None):
+    f = st.f.reshape(lat.b, -1)
+    mass = f.sum()
+    mom = lat.E.T @ f.sum(axis=1)
+    if force is not None:
+        mom = mom + 0.5 * force.reshape(lat.d, -1).sum(axis=1)
+    return float(mass), mom

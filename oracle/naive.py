@@ -1,0 +1,99 @@
+"""Brute-force formulation of the same method, for tiny grids.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Differs from ``model`` on purpose, so that each pins the other:
+  * the collision is done in velocity space with an explicit b x b matrix
+    Lambda = H^-1 S H (eq. H-MRT-LB), where H is the Hermite basis completed
+    to b rows and H^-1 is a numerical matrix inverse (not W H^T N^-1);
+  * equilibrium, source and auxiliary distributions are vectors in velocity
+    space obtained as H^-1 applied to their Hermite moments (eqs. geq, feq);
+  * the update is eq. (2-3) written literally:
+        f*_j = f_j - Lambda_jk (f_k - f_eq_k) + G_j + (delta_jk - Lambda_jk/2) F_k;
+  * macroscopic sums and propagation are explicit loops over nodes and
+    populations (eq. 2-2).
+"""
+
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+from . import model as M
+from .lattice import Lattice, complete_rows, full_H
+
+
+class NaiveStepper:
+    def __init__(self, lat: Lattice, mdl: M.Model):
+        self.lat, self.mdl = lat, mdl
+        rows = complete_rows(lat, lat.rows)
+        self.Hf = full_H(lat, rows)
+        s_low = M.rates(lat, mdl)
+        s = np.concatenate([s_low, np.full(lat.b - len(lat.rows), mdl.s_h)])
+        self.Hinv = np.linalg.inv(self.Hf)
+        self.Lam = self.Hinv @ np.diag(s) @ self.Hf
+        self.nlow = len(lat.rows)
+        self.s_low = s_low
+
+    def _velocity_space(self, m_low):
+        full = np.zeros(self.lat.b)
+        full[: self.nlow] = m_low
+        return self.Hinv @ full
+
+    def step(self, st: M.State, force=None) -> M.State:
+        lat, mdl = self.lat, self.mdl
+        b, d = lat.b, lat.d
+        grid = st.f.shape[1:]
+        E = lat.E
+        fstar = np.empty_like(st.f)
+        phi_grid = None
+        Bfield = None
+        if mdl.eq == M.NCDE:
+            phi_grid = np.zeros(grid)
+            for x in itertools.product(*[range(n) for n in grid]):
+                phi_grid[x] = sum(st.f[(j,) + x] for j in range(b))
+            Bfield = M.ncde_B(lat, mdl, phi_grid, st.phi_prev).reshape((d,) + grid)
+        for x in itertools.product(*[range(n) for n in grid]):
+            f = np.array([st.f[(j,) + x] for j in range(b)])
+            F = None if force is None else np.array([force[(a,) + x] for a in range(d)])
+            rho = 0.0
+            mom = np.zeros(d)
+            for j in range(b):
+                rho += f[j]
+                mom += E[j] * f[j]
+            if mdl.eq == M.NCDE:
+                u = np.asarray(mdl.adv_u[:d], dtype=np.float64)
+                rho_m = None
+            else:
+                if F is not None:
+                    mom = mom + 0.5 * F
+                rho_m = mdl.rho0 if mdl.eq == M.NSE_INC else rho
+                u = mom / rho_m
+            R0 = np.array([rho])
+            uv = u[:, None]
+            rm = None if rho_m is None else np.array([rho_m])
+            feq = self._velocity_space(M.equilibrium_hermite(lat, mdl, R0, uv, rm)[:, 0])
+            if mdl.eq == M.NCDE:
+                Bx = np.array([Bfield[(a,) + x] for a in range(d)])[:, None]
+                G = self._velocity_space(M.aux_hermite(lat, mdl, self.s_low, uv, None, extra=Bx)[:, 0])
+                Fv = np.zeros(b)
+            else:
+                Fa = None if F is None else F[:, None]
+                G = self._velocity_space(M.aux_hermite(lat, mdl, self.s_low, uv, Fa)[:, 0])
+                Fv = np.zeros(b) if F is None else self._velocity_space(M.force_hermite(lat, 1, Fa)[:, 0])
+            out = f - self.Lam @ (f - feq) + G + (np.eye(b) - 0.5 * self.Lam) @ Fv
+            for j in range(b):
+                fstar[(j,) + x] = out[j]
+        # propagation, one population and one node at a time
+        new = np.empty_like(fstar)
+        for j in range(b):
+            for x in itertools.product(*[range(n) for n in grid]):
+                # grid index order is (.., y, x): the physical axis a lives at
+                # array axis len(grid) - 1 - a
+                tgt = list(x)
+                for a in range(d):
+                    ax = len(grid) - 1 - a
+                    tgt[ax] = (x[ax] + int(lat.e[j, a])) % grid[ax]
+                new[(j,) + tuple(tgt)] = fstar[(j,) + x]
+        return M.State(new, phi_grid)

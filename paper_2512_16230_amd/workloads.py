@@ -1,0 +1,224 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module holds workload parameters and initial/forcing fields only; it
+contains none of the lattice Boltzmann arithmetic (no weights, no Hermite
+rows, no equilibria).  Every field is FP64 on the host, laid out with x
+fastest: scalars (Ny, Nx) or (Nz, Ny, Nx), vectors (d, Ny, Nx) or
+(d, Nz, Ny, Nx).  Positions are physical: x = i * dx_a with dx_a = c_a dt,
+dt = 1.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from math import pi
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# lattice cards (kind, c_alpha, cs^2, free weights).  The free weights are a
+# parameter choice: a point well inside the region where every weight is
+# positive (analytic centre of the positivity polytope, rounded).
+# ---------------------------------------------------------------------------
+
+
+@dataclass(frozen=True)
+class Card:
+    kind: str
+    c: tuple
+    cs2: float
+    free: tuple = ()
+
+    @property
+    def d(self):
+        return len(self.c)
+
+
+Q25_RECT = Card("rD2Q25", (1.5, 1.0), 1.5, (5.35e-3, 6.25e-4, 2.46e-2, 8.2e-4))
+Q13_SQUARE = Card("rD2Q13", (1.0, 1.0), 0.5)
+Q53_RECT = Card("rD3Q53", (1.0, 1.25, 1.5), 1.0, (6.56e-3, 2.05e-3, 3.0e-4, 2.3e-4))
+Q33_CUBIC = Card("rD3Q33", (1.0, 1.0, 1.0), 0.45)
+
+
+@dataclass
+class Rates:
+    s0: float = 1.2
+    s1: float = 1.2
+    s_shear: float = 1.25
+    s_bulk: float = 1.2
+    s3: float = 1.2
+    s_h: float = 1.2
+
+
+def rates_tau(tau_shear: float, other: float = 1.2) -> Rates:
+    """Shear rate 1/tau, every other diagonal entry of S equal to ``other``."""
+    return Rates(other, other, 1.0 / tau_shear, other, other, other)
+
+
+# ---------------------------------------------------------------------------
+# fields
+# ---------------------------------------------------------------------------
+
+def grid_coords(card: Card, shape):
+    """Physical coordinates, one array per axis, broadcast to ``shape``."""
+    d = card.d
+    axes = []
+    for a in range(d):
+        n = shape[d - 1 - a]               # x is the last array axis
+        coord = np.arange(n, dtype=np.float64) * card.c[a]
+        sh = [1] * d
+        sh[d - 1 - a] = n
+        axes.append(np.broadcast_to(coord.reshape(sh), shape))
+    return axes
+
+
+def taylor_green_2d(card: Card, shape, U0, rho0=1.0, t=0.0, nu=0.0):
+    """Incompressible 2D Taylor-Green vortex on a periodic rectangle.
+
+    kx = 2 pi / Lx, ky = 2 pi / Ly (Lx = Nx dx, Ly = Ny dy);
+    u = -U0 sqrt(ky/kx) cos(kx x) sin(ky y) F, v = U0 sqrt(kx/ky) sin(kx x) cos(ky y) F,
+    p = -(rho0 U0^2 / 4) [ (ky/kx) cos(2 kx x) + (kx/ky) cos(2 ky y) ] F^2,
+    F = exp(-nu (kx^2 + ky^2) t).  Returns (p, u) with u of shape (2, Ny, Nx).
+    """
+    Ny, Nx = shape
+    kx = 2 * pi / (Nx * card.c[0])
+    ky = 2 * pi / (Ny * card.c[1])
+    x, y = grid_coords(card, shape)
+    F = np.exp(-nu * (kx * kx + ky * ky) * t)
+    u = -U0 * np.sqrt(ky / kx) * np.cos(kx * x) * np.sin(ky * y) * F
+    v = U0 * np.sqrt(kx / ky) * np.sin(kx * x) * np.cos(ky * y) * F
+    p = -(rho0 * U0 * U0 / 4) * ((ky / kx) * np.cos(2 * kx * x) + (kx / ky) * np.cos(2 * ky * y)) * F * F
+    return p, np.stack([u, v])
+
+
+def taylor_green_3d(card: Card, shape, U0, drho=1e-2):
+    """3D Taylor-Green start: u = U0 sin(kx x) cos(ky y) cos(kz z),
+    v = -U0 (kx/ky) cos(kx x) sin(ky y) cos(kz z), w = 0 (divergence free),
+    rho = 1 + drho cos(kx x) cos(ky y) cos(kz z).  Returns (rho, u (3, ...))."""
+    Nz, Ny, Nx = shape
+    kx = 2 * pi / (Nx * card.c[0])
+    ky = 2 * pi / (Ny * card.c[1])
+    kz = 2 * pi / (Nz * card.c[2])
+    x, y, z = grid_coords(card, shape)
+    u = U0 * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)
+    v = -U0 * (kx / ky) * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)
+    w = np.zeros_like(u)
+    rho = 1.0 + drho * np.cos(kx * x) * np.cos(ky * y) * np.cos(kz * z)
+    return rho, np.stack([u, v, w])
+
+
+def gaussian_hill(card: Card, shape, amplitude=1.0, sigma0=None, center=None):
+    """phi0 = A exp(-|x - x0|^2 / (2 sigma0^2)) with periodic images summed
+    (images at +-1 period in each axis), sigma0 in physical units."""
+    d = card.d
+    L = [shape[d - 1 - a] * card.c[a] for a in range(d)]
+    if sigma0 is None:
+        sigma0 = min(L) / 16.0
+    if center is None:
+        center = [0.5 * La for La in L]
+    X = grid_coords(card, shape)
+    out = np.zeros(shape)
+    for shift in np.ndindex(*([3] * d)):
+        r2 = np.zeros(shape)
+        for a in range(d):
+            r2 = r2 + (X[a] - center[a] + (shift[a] - 1) * L[a]) ** 2
+        out += np.exp(-r2 / (2 * sigma0 ** 2))
+    return amplitude * out
+
+
+def sinusoidal_force(card: Card, shape, F0, seed, modes=3):
+    """F(x) = F0 sum_m n_m sin(k_m . x + phase_m), n_m seeded unit vectors,
+    k_m seeded integer wave vectors of the periodic box."""
+    rng = np.random.default_rng(seed)
+    d = card.d
+    L = [shape[d - 1 - a] * card.c[a] for a in range(d)]
+    X = grid_coords(card, shape)
+    F = np.zeros((d,) + tuple(shape))
+    for _ in range(modes):
+        n = rng.normal(size=d)
+        n /= np.linalg.norm(n)
+        k = rng.integers(1, 3, size=d) * rng.choice([-1, 1], size=d)
+        ph = rng.uniform(0, 2 * pi)
+        arg = sum(2 * pi * k[a] / L[a] * X[a] for a in range(d)) + ph
+        F += F0 * n.reshape((d,) + (1,) * d) * np.sin(arg)[None]
+    return F
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    card: Card
+    eq: str                       # NSE_INC, NSE_COMP, NCDE
+    shape: tuple                  # (Ny, Nx) or (Nz, Ny, Nx)
+    steps: int
+    rates: Rates
+    rho0: float = 1.0
+    rho_or_phi: np.ndarray = None
+    u: np.ndarray = None
+    force: np.ndarray = None
+    adv_u: tuple = (0.0, 0.0, 0.0)
+    D0: float = 0.0
+    D2: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+
+def tgv_small(seed=0, shape=(64, 64), steps=500):
+    """rD2Q25 incompressible Taylor-Green vortex, 64 x 64, dx/dy = 1.5,
+    U0 ~ U[0.01, 0.05] (seeded), rho0 = 1, tau_shear = 0.8, other rates 1.2."""
+    rng = np.random.default_rng(seed)
+    U0 = 0.01 + 0.04 * rng.uniform()
+    card = Q25_RECT
+    p, u = taylor_green_2d(card, shape, U0)
+    rho_bar = 1.0 + p / card.cs2
+    return Workload("tgv-rD2Q25-%dx%d" % (shape[1], shape[0]), card, "NSE_INC", shape, steps,
+                    rates_tau(0.8), 1.0, rho_bar, u, meta={"U0": U0})
+
+
+def tgv_large(seed=0, shape=(4096, 4096), steps=1000, sigma=1e-3):
+    """rD2Q25 incompressible Taylor-Green vortex at Ma = 0.1 (U0 = 0.1 cs)
+    plus iid N(0, sigma^2) per velocity component, tau_shear = 0.6."""
+    rng = np.random.default_rng(seed)
+    card = Q25_RECT
+    U0 = 0.1 * np.sqrt(card.cs2)
+    p, u = taylor_green_2d(card, shape, U0)
+    u = u + rng.normal(0.0, sigma, size=u.shape)
+    rho_bar = 1.0 + p / card.cs2
+    return Workload("tgv-rD2Q25-%dx%d" % (shape[1], shape[0]), card, "NSE_INC", shape, steps,
+                    rates_tau(0.6), 1.0, rho_bar, u, meta={"U0": U0, "sigma": sigma})
+
+
+def tgv3d(shape=(256, 256, 256), steps=1000, U0=0.05, drho=1e-2, card=Q53_RECT):
+    """Compressible isothermal 3D Taylor-Green start on rD3Q53 (1 : 1.25 : 1.5)."""
+    rho, u = taylor_green_3d(card, shape, U0, drho)
+    return Workload("tgv3d-%s-%dx%dx%d" % (card.kind, shape[2], shape[1], shape[0]), card, "NSE_COMP",
+                    shape, steps, rates_tau(0.8), 1.0, rho, u, meta={"U0": U0})
+
+
+def ncde_hill(shape=(128, 128), steps=1000, adv_u=(0.03, -0.02), D0=0.1, D2=1.0, card=Q13_SQUARE):
+    """rD2Q13 NCDE: Gaussian hill (amplitude 1, sigma0 = N/16), constant
+    advection, D(phi) = D0 (1 + D2 phi^2), s1 chosen so K = D0."""
+    K = D0
+    s1 = 1.0 / (K / card.cs2 + 0.5)
+    r = Rates(1.2, s1, 1.2, 1.2, 1.2, 1.2)
+    phi = gaussian_hill(card, shape)
+    return Workload("ncde-%s-%dx%d" % (card.kind, shape[1], shape[0]), card, "NCDE", shape, steps, r,
+                    0.0, phi, None, adv_u=tuple(adv_u) + (0.0,) * (3 - len(adv_u)), D0=D0, D2=D2)
+
+
+def ncde_batch_sizes(n=256, lo=128, hi=1024, seed=0):
+    """Log-uniform square side lengths for a batch of NCDE solves."""
+    rng = np.random.default_rng(seed)
+    return [int(round(np.exp(rng.uniform(np.log(lo), np.log(hi))))) for _ in range(n)]
+
+
+def ncde_batch(n=256, lo=128, hi=1024, seed=0, steps=1000):
+    rng = np.random.default_rng(seed + 1)
+    out = []
+    for N in ncde_batch_sizes(n, lo, hi, seed):
+        adv = tuple(rng.uniform(-0.05, 0.05, size=2))
+        out.append(ncde_hill((N, N), steps, adv_u=adv))
+    return out

@@ -1,0 +1,242 @@
+"""Pins of the oracle's equilibrium and collision.
+
+Expected values come from the paper's moment prescriptions (written out
+here as tensors and compared by brute-force velocity sums), from textbook
+closed forms the method reduces to (third-order Hermite equilibrium on an
+isotropic square lattice; BGK collision with Guo forcing when every rate is
+equal), from exact invariants, and from the brute-force formulation in
+``oracle.naive`` (explicit b x b collision matrix, loop streaming).
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lattice as L
+from oracle import model as M
+from oracle import naive as N
+from paper_2512_16230_amd import workloads as W
+
+CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC]
+
+
+def card_lattice(card):
+    return L.make_lattice(card.kind, card.c, card.cs2, card.free)
+
+
+def square_case3():
+    """App. C D2Q17 case 3 (exact rational weights, cs^2 = 3/4), from the
+    golden fixture, as an rD2Q25 subgroup."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    data = json.load(open(os.path.join(root, "golden", "d2q17_weights.json")))["cases"]["3"]
+    ev = lambda s: float(eval(s, {"__builtins__": {}}, {"sqrt": math.sqrt}))  # noqa: E731
+    cs2 = ev(data["cs2"])
+    free = (0.0, ev(data["g9"]), ev(data["g9"]), ev(data["g13"]))
+    w = L.weights_rd2q25((1, 1), cs2, free)
+    return L.subgroup(L.custom_lattice("D2Q17-3", (1, 1), cs2, L.velocity_set("rD2Q25"), w), tol=1e-12)
+
+
+def _random_state(lat, n, rng, amp=0.05):
+    R0 = 1 + amp * rng.normal(size=n)
+    u = amp * rng.normal(size=(lat.d, n))
+    return R0, u
+
+
+def _tensor_moments(lat, g):
+    E = lat.E
+    return (g.sum(0), E.T @ g, np.einsum("ja,jb,jn->abn", E, E, g),
+            np.einsum("ja,jb,jc,jn->abcn", E, E, E, g))
+
+
+def _delta_u(d, v):
+    I = np.eye(d)
+    return (np.einsum("ab,cn->abcn", I, v) + np.einsum("ac,bn->abcn", I, v) + np.einsum("bc,an->abcn", I, v))
+
+
+# --------------------------------------------------------------------------
+# equilibrium
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("card", CARDS, ids=lambda c: c.kind)
+@pytest.mark.parametrize("eq", [M.NSE_INC, M.NSE_COMP])
+def test_equilibrium_moments_nse(card, eq):
+    """sum f_eq {1, c, cc, ccc} = M0..M3 of eqs. (M-NSEs-6a), (M-NSEs-6) /
+    (M-NSEs-6-1) with k = 0 and M30 = rho uuu (multispeed lattices)."""
+    lat = card_lattice(card)
+    rng = np.random.default_rng(7)
+    n, d, cs2, rho0 = 6, lat.d, lat.cs2, 1.3
+    R0, u = _random_state(lat, n, rng)
+    mdl = M.Model(eq=eq, rho0=rho0)
+    rho = np.full(n, rho0) if eq == M.NSE_INC else R0
+    feq = M.populations_from_hermite(lat, M.equilibrium_hermite(lat, mdl, R0, u, rho))
+    m0, m1, m2, m3 = _tensor_moments(lat, feq)
+    p = cs2 * R0
+    I = np.eye(d)[:, :, None]
+    assert np.allclose(m0, R0, atol=1e-13)
+    assert np.allclose(m1, rho * u, atol=1e-13)
+    assert np.allclose(m2, np.einsum("n,an,bn->abn", rho, u, u) + p * I, atol=1e-13)
+    visc = (p if eq == M.NSE_COMP else rho * cs2) * _delta_u(d, u)
+    assert np.allclose(m3, visc + np.einsum("n,an,bn,cn->abcn", rho, u, u, u), atol=1e-13)
+
+
+@pytest.mark.parametrize("card", [W.Q13_SQUARE, W.Q25_RECT], ids=lambda c: c.kind)
+def test_equilibrium_moments_ncde(card):
+    """NCDE: M0 = phi, M1 = phi u, M2 = cs^2 Phi(phi) I + phi uu with
+    K Phi'(phi) = D(phi) = D0 (1 + D2 phi^2) (eqs. M-NCDE-6, GNCDE)."""
+    lat = card_lattice(card)
+    rng = np.random.default_rng(8)
+    n, d, cs2 = 5, lat.d, lat.cs2
+    phi = rng.uniform(0, 1.5, size=n)
+    adv = (0.03, -0.04, 0.0)
+    mdl = M.Model(eq=M.NCDE, s1=1 / 0.7, D0=0.07, D2=0.8, adv_u=adv)
+    u = np.repeat(np.array(adv[:d])[:, None], n, axis=1)
+    feq = M.populations_from_hermite(lat, M.equilibrium_hermite(lat, mdl, phi, u, None))
+    m0, m1, m2, _ = _tensor_moments(lat, feq)
+    K = cs2 * (1 / mdl.s1 - 0.5)
+    Phi = (mdl.D0 / K) * (phi + mdl.D2 * phi ** 3 / 3)
+    assert np.allclose(m0, phi, atol=1e-14)
+    assert np.allclose(m1, phi * u, atol=1e-14)
+    assert np.allclose(m2, cs2 * Phi * np.eye(d)[:, :, None] + np.einsum("n,an,bn->abn", phi, u, u), atol=1e-13)
+    # dPhi/dphi * K reproduces D(phi)
+    h = 1e-6
+    dPhi = (mdl.D0 / K) * ((phi + h + mdl.D2 * (phi + h) ** 3 / 3) - (phi - h + mdl.D2 * (phi - h) ** 3 / 3)) / (2 * h)
+    assert np.allclose(K * dPhi, mdl.D0 * (1 + mdl.D2 * phi ** 2), rtol=1e-8)
+
+
+def test_equilibrium_is_textbook_third_order_hermite_on_isotropic_square():
+    """On D2Q17 case 3 (square, sixth-order isotropic, App. C) the
+    projection of eq. (feq-1) is the classical third-order Hermite
+    equilibrium w rho [1 + (c.u)/cs^2 + ((c.u)^2 - cs^2 u^2)/(2 cs^4)
+    + ((c.u)^3 - 3 cs^2 (c.u) u^2)/(6 cs^6)]."""
+    lat = square_case3()
+    rng = np.random.default_rng(9)
+    R0, u = _random_state(lat, 8, rng, 0.1)
+    mdl = M.Model(eq=M.NSE_COMP)
+    feq = M.populations_from_hermite(lat, M.equilibrium_hermite(lat, mdl, R0, u, R0))
+    cs2 = lat.cs2
+    cu = lat.E @ u
+    u2 = (u * u).sum(0)
+    ref = lat.w[:, None] * R0 * (1 + cu / cs2 + (cu ** 2 - cs2 * u2) / (2 * cs2 ** 2)
+                                 + (cu ** 3 - 3 * cs2 * cu * u2) / (6 * cs2 ** 3))
+    assert np.allclose(feq, ref, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# collision
+# --------------------------------------------------------------------------
+
+def _noneq(lat, n, rng):
+    R0, u = _random_state(lat, n, rng)
+    mdl = M.Model(eq=M.NSE_COMP)
+    feq = M.populations_from_hermite(lat, M.equilibrium_hermite(lat, mdl, R0, u, R0))
+    return feq + 2e-3 * lat.w[:, None] * rng.normal(size=feq.shape)
+
+
+@pytest.mark.parametrize("card", CARDS, ids=lambda c: c.kind)
+@pytest.mark.parametrize("eq", [M.NSE_INC, M.NSE_COMP])
+def test_collision_conserves_mass_and_adds_force(card, eq):
+    """Per node: sum f* = sum f_bar and sum c f* = sum c f_bar + dt F
+    (eq. M-NSEs-1 with S = 0 and the source moments of eq. M-NSEs-2)."""
+    lat = card_lattice(card)
+    rng = np.random.default_rng(10)
+    n = 7
+    f = _noneq(lat, n, rng)
+    F = 1e-3 * rng.normal(size=(lat.d, n))
+    mdl = M.Model(eq=eq, rho0=1.0, s0=1.1, s1=1.3, s_shear=1.7, s_bulk=0.9, s3=1.4, s_h=1.05)
+    fs = M.collide(lat, mdl, f, F)
+    assert np.allclose(fs.sum(0), f.sum(0), atol=1e-14)
+    assert np.allclose(lat.E.T @ fs, lat.E.T @ f + F, atol=1e-14)
+
+
+def test_collision_is_bgk_with_guo_forcing_when_rates_equal():
+    """All rates 1/tau: the collision is the textbook BGK operator with the
+    Guo forcing term (1 - 1/(2 tau)) w [(c - u).F/cs^2 + (c.u)(c.F)/cs^4],
+    u = (sum c f + F/2)/rho, on the isotropic square D2Q17 case 3."""
+    lat = square_case3()
+    rng = np.random.default_rng(11)
+    n, tau = 9, 0.73
+    f = _noneq(lat, n, rng)
+    F = 2e-3 * rng.normal(size=(2, n))
+    om = 1 / tau
+    mdl = M.Model(eq=M.NSE_COMP, s0=om, s1=om, s_shear=om, s_bulk=om, s3=om, s_h=om)
+    fs = M.collide(lat, mdl, f, F)
+    cs2 = lat.cs2
+    rho = f.sum(0)
+    u = (lat.E.T @ f + 0.5 * F) / rho
+    cu = lat.E @ u
+    u2 = (u * u).sum(0)
+    feq = lat.w[:, None] * rho * (1 + cu / cs2 + (cu ** 2 - cs2 * u2) / (2 * cs2 ** 2)
+                                  + (cu ** 3 - 3 * cs2 * cu * u2) / (6 * cs2 ** 3))
+    cF = lat.E @ F
+    guo = lat.w[:, None] * ((cF - (u * F).sum(0)) / cs2 + cu * cF / cs2 ** 2)
+    ref = f - om * (f - feq) + (1 - 0.5 * om) * guo
+    assert np.allclose(fs, ref, atol=1e-14)
+
+
+@pytest.mark.parametrize("card,eq,shape", [
+    (W.Q25_RECT, M.NSE_INC, (4, 3)),
+    (W.Q25_RECT, M.NSE_COMP, (3, 5)),
+    (W.Q13_SQUARE, M.NCDE, (4, 5)),
+    (W.Q33_CUBIC, M.NSE_COMP, (3, 4, 3)),
+    (W.Q53_RECT, M.NSE_INC, (2, 3, 2)),
+], ids=lambda v: getattr(v, "kind", str(v)))
+def test_vectorised_step_equals_brute_force(card, eq, shape):
+    """Three steps of the vectorised reduced form vs the explicit b x b
+    Lambda = H^-1 S H collision in velocity space with loop streaming."""
+    lat = card_lattice(card)
+    rng = np.random.default_rng(12)
+    d = lat.d
+    mdl = M.Model(eq=eq, rho0=1.0, s0=1.1, s1=1.3 if eq == M.NCDE else 1.15, s_shear=1.6, s_bulk=1.05,
+                  s3=1.4, s_h=0.9, D0=0.1, D2=1.0, adv_u=(0.03, -0.02, 0.01))
+    rho = 1 + 0.05 * rng.normal(size=shape)
+    u = 0.05 * rng.normal(size=(d,) + shape)
+    F = None if eq == M.NCDE else 1e-3 * rng.normal(size=(d,) + shape)
+    st = M.init_state(lat, mdl, rho, u, F)
+    st.f = st.f + 1e-3 * rng.normal(size=st.f.shape) * lat.w.reshape((-1,) + (1,) * len(shape))
+    if eq == M.NCDE:
+        st.phi_prev = st.phi_prev + 0.01 * rng.normal(size=shape)
+    nv = N.NaiveStepper(lat, mdl)
+    a = st
+    b = M.State(st.f.copy(), None if st.phi_prev is None else st.phi_prev.copy())
+    for _ in range(3):
+        a = M.step(lat, mdl, a, F)
+        b = nv.step(b, F)
+    assert np.abs(a.f - b.f).max() < 1e-13
+
+
+def test_uniform_flow_is_a_fixed_point():
+    lat = card_lattice(W.Q25_RECT)
+    mdl = M.Model(eq=M.NSE_COMP, s_shear=1.6)
+    shape = (5, 6)
+    rho = np.full(shape, 1.02)
+    u = np.stack([np.full(shape, 0.04), np.full(shape, -0.03)])
+    st = M.init_state(lat, mdl, rho, u)
+    f0 = st.f.copy()
+    st = M.run(lat, mdl, st, 4)
+    assert np.abs(st.f - f0).max() < 1e-15
+
+
+def test_mirror_symmetry_x():
+    """Mirroring x -> -x commutes with a step (checks signs and indices of
+    the odd rows and of the propagation)."""
+    lat = card_lattice(W.Q25_RECT)
+    mdl = M.Model(eq=M.NSE_COMP, s_shear=1.6, s_bulk=1.1, s3=1.3, s_h=0.95)
+    rng = np.random.default_rng(13)
+    shape = (6, 7)
+    rho = 1 + 0.03 * rng.normal(size=shape)
+    u = 0.03 * rng.normal(size=(2,) + shape)
+    st = M.init_state(lat, mdl, rho, u)
+    st.f = st.f + 1e-3 * rng.normal(size=st.f.shape) * lat.w[:, None, None]
+    e = lat.e.tolist()
+    perm = [e.index([-a, b]) for a, b in e]
+    ix = (-np.arange(shape[1])) % shape[1]
+
+    def mirror(f):
+        return f[perm][:, :, ix]
+
+    a = M.step(lat, mdl, M.State(mirror(st.f)))
+    b = M.step(lat, mdl, st)
+    assert np.abs(a.f - mirror(b.f)).max() < 1e-15

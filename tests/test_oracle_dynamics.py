@@ -1,0 +1,144 @@
+"""Pins of the oracle's dynamics against analytic solutions and invariants.
+
+  * 2D Taylor-Green decay on the rectangular rD2Q25 (dx/dy = 1.5): decay
+    rate nu (kx^2 + ky^2) with nu = cs^2 (1/s_shear - 1/2) dt (eq. 4-29,
+    k = 0), second-order convergence of the velocity error;
+  * 3D Taylor-Green start on rD3Q53 (1 : 1.25 : 1.5) and rD3Q33: early
+    kinetic-energy decay -2 nu |k|^2 E, second-order convergence;
+  * rD2Q13 NCDE: advected Gaussian hill closed form for linear D,
+    variance growth 2 D0 per axis, and for D(phi) = D0 (1 + phi^2) the
+    identity d/dt int |x|^2 phi = 2 d int G(phi), G' = D (eq. GNCDE).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import lattice as L
+from oracle import model as M
+from paper_2512_16230_amd import workloads as W
+
+
+def setup(wl):
+    card = wl.card
+    lat = L.make_lattice(card.kind, card.c, card.cs2, card.free)
+    r = wl.rates
+    mdl = M.Model(eq=wl.eq, rho0=wl.rho0, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3,
+                  s_h=r.s_h, D0=wl.D0, D2=wl.D2, adv_u=wl.adv_u)
+    return lat, mdl
+
+
+def _tgv2d_error(shape, steps, seed=0):
+    wl = W.tgv_small(seed, shape=shape, steps=steps)
+    lat, mdl = setup(wl)
+    st = M.init_state(lat, mdl, wl.rho_or_phi, wl.u)
+    nu = lat.cs2 * (1 / mdl.s_shear - 0.5)
+    E, ts = [], []
+    for n in range(steps + 1):
+        if n % 25 == 0:
+            _, u = M.moments(lat, mdl, st)
+            E.append((u ** 2).sum())
+            ts.append(n)
+        if n < steps:
+            st = M.step(lat, mdl, st)
+    _, u = M.moments(lat, mdl, st)
+    _, ua = W.taylor_green_2d(wl.card, shape, wl.meta["U0"], t=steps, nu=nu)
+    err = np.sqrt(((u - ua) ** 2).sum() / (ua ** 2).sum())
+    kx = 2 * np.pi / (shape[1] * wl.card.c[0])
+    ky = 2 * np.pi / (shape[0] * wl.card.c[1])
+    rate = -np.polyfit(ts[2:], np.log(E[2:]), 1)[0] / 2
+    return err, rate / (nu * (kx * kx + ky * ky))
+
+
+def test_taylor_green_2d_decay_and_convergence():
+    err64, ratio64 = _tgv2d_error((64, 64), 500)
+    err32, ratio32 = _tgv2d_error((32, 32), 125)
+    assert abs(ratio64 - 1) < 0.01
+    assert err64 < 2.5e-2
+    assert 3.0 < err32 / err64 < 5.0
+
+
+def _tgv3d_rate(card, shape, steps=30):
+    wl = W.tgv3d(shape=shape, U0=1e-3, drho=0.0, card=card)
+    lat, mdl = setup(wl)
+    st = M.init_state(lat, mdl, wl.rho_or_phi, wl.u)
+    nu = lat.cs2 * (1 / mdl.s_shear - 0.5)
+    Nz, Ny, Nx = shape
+    k2 = sum((2 * np.pi / (n * c)) ** 2 for n, c in zip((Nx, Ny, Nz), card.c))
+    E = []
+    for _ in range(steps + 1):
+        rho, u = M.moments(lat, mdl, st)
+        E.append(0.5 * (rho * (u ** 2).sum(0)).sum())
+        st = M.step(lat, mdl, st)
+    rate = -np.polyfit(np.arange(5, steps + 1), np.log(E[5:]), 1)[0]
+    return rate / (2 * nu * k2)
+
+
+@pytest.mark.parametrize("card", [W.Q53_RECT, W.Q33_CUBIC], ids=lambda c: c.kind)
+def test_taylor_green_3d_energy_decay(card):
+    coarse = _tgv3d_rate(card, (12, 16, 16))
+    fine = _tgv3d_rate(card, (24, 32, 32))
+    assert abs(fine - 1) < 0.02
+    assert 3.0 < abs(coarse - 1) / abs(fine - 1) < 5.5
+
+
+def _hill_error(N, steps, adv=(0.03, -0.02), D0=0.1):
+    wl = W.ncde_hill((N, N), adv_u=adv, D0=D0, D2=0.0)
+    lat, mdl = setup(wl)
+    st = M.init_state(lat, mdl, wl.rho_or_phi)
+    mass0 = st.f.sum()
+    st = M.run(lat, mdl, st, steps)
+    phi, _ = M.moments(lat, mdl, st)
+    s0 = N / 16.0
+    s2 = s0 ** 2 + 2 * D0 * steps
+    x = np.arange(N)[None, :]
+    y = np.arange(N)[:, None]
+    ref = np.zeros((N, N))
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            ref += s0 ** 2 / s2 * np.exp(-((x - N / 2 - adv[0] * steps + i * N) ** 2
+                                           + (y - N / 2 - adv[1] * steps + j * N) ** 2) / (2 * s2))
+    return np.abs(phi - ref).max() / ref.max(), (st.f.sum() - mass0) / mass0
+
+
+def test_gaussian_hill_linear_diffusion():
+    e64, dm = _hill_error(64, 100)
+    e32, _ = _hill_error(32, 25)
+    assert abs(dm) < 1e-13
+    assert e64 < 1.5e-2
+    assert 3.0 < e32 / e64 < 5.0
+
+
+def test_variance_grows_at_2D0():
+    wl = W.ncde_hill((64, 64), adv_u=(0.0, 0.0), D0=0.1, D2=0.0)
+    lat, mdl = setup(wl)
+    st = M.init_state(lat, mdl, wl.rho_or_phi)
+    x = np.arange(64)[None, :] - 32.0
+    y = np.arange(64)[:, None] - 32.0
+
+    def var(phi):
+        m = phi.sum()
+        return (phi * x ** 2).sum() / m, (phi * y ** 2).sum() / m
+
+    st = M.run(lat, mdl, st, 20)
+    v0 = var(M.moments(lat, mdl, st)[0])
+    st = M.run(lat, mdl, st, 40)
+    v1 = var(M.moments(lat, mdl, st)[0])
+    for a in range(2):
+        assert abs((v1[a] - v0[a]) / 40 / (2 * 0.1) - 1) < 1e-6
+
+
+def test_nonlinear_diffusion_second_moment_identity():
+    D0 = 0.1
+    wl = W.ncde_hill((64, 64), adv_u=(0.0, 0.0), D0=D0, D2=1.0)
+    lat, mdl = setup(wl)
+    st = M.init_state(lat, mdl, wl.rho_or_phi)
+    st = M.run(lat, mdl, st, 10)
+    r2 = (np.arange(64)[None, :] - 32.0) ** 2 + (np.arange(64)[:, None] - 32.0) ** 2
+    phis = []
+    for _ in range(21):
+        phis.append(M.moments(lat, mdl, st)[0])
+        st = M.step(lat, mdl, st)
+    G = lambda p: D0 * (p + p ** 3 / 3)  # noqa: E731
+    lhs = ((phis[20] * r2).sum() - (phis[0] * r2).sum()) / 20
+    rhs = sum(2 * 2 * G(p).sum() * (0.5 if k in (0, 20) else 1.0) for k, p in enumerate(phis)) / 20
+    assert abs(lhs / rhs - 1) < 3e-3
