@@ -1,0 +1,180 @@
+"""Benchmark of the fused collide-and-stream step (one JSON line on stdout).
+
+Workload: rD2Q25 (dx/dy = 1.5, cs^2 = 1.5) incompressible Navier-Stokes,
+4096 x 4096 periodic, Taylor-Green vortex at Ma = 0.1 plus a seeded
+N(0, 1e-3^2) velocity perturbation, tau_shear = 0.6, every other rate 1.2,
+plain FP32 SoA populations.  A step is one launch of the fused pull
+collide-and-stream kernel over all 16.8M nodes (every step of the method).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage fp32]
+
+Reported: MLUPS (million lattice-node updates per second), the roofline of
+the step kernel (HBM bound: 2 b s bytes per node, b = 25 populations of s
+bytes), and the FP64 oracle timed on the host on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_dev": "f32", "fp16_dev": "f32 (fp16 storage)",
+         "bf16_dev": "f32 (bf16 storage)"}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("mrtlb.hip", "kernels.h", "lattices.h"):
+        with open(os.path.join(ROOT, "paper_2512_16230_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, launch_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_step_rD2Q25_%s_4096x4096_traffic.json" % storage)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(sample_shape=(512, 512), steps=30):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    from oracle import lattice as OL
+    from oracle import model as OM
+    from paper_2512_16230_amd import workloads as W
+
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((p.get("num_threads") or 1) for p in threadpool_info()) if threadpool_info() else 1
+    except Exception:
+        threads = os.cpu_count()
+    wl = W.tgv_large(0, shape=sample_shape, steps=steps)
+    card, r = wl.card, wl.rates
+    lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
+    mdl = OM.Model(eq=wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_h=r.s_h)
+    st = OM.init_state(lat, mdl, wl.rho_or_phi, wl.u)
+    st = OM.step(lat, mdl, st)               # warm-up
+    t0 = time.perf_counter()
+    OM.run(lat, mdl, st, steps)
+    dt = time.perf_counter() - t0
+    n = sample_shape[0] * sample_shape[1]
+    return {"value": round(n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "%dx%d rD2Q25 TGV, %d FP64 steps, %.1f s (elementwise NumPy single-threaded, "
+                      "BLAS matmuls on %s threads)" % (sample_shape[1], sample_shape[0], steps, dt, threads)}
+
+
+def copy_probe(torch, dev, steps, warmup):
+    n = 25 * 4096 * 4096                       # one FP32 population buffer of the workload
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(warmup):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"probe": "device copy", "bytes_per_launch": 2 * 4 * n, "ms_per_launch": round(ms, 5),
+                      "GB_per_s": round(2 * 4 * n / ms / 1e6, 1)}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="fp32", choices=sorted(STORE_BYTES))
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain device copy of 2 x 1.68 GB instead (HBM reference and counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU (slab-decomposed) path is not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2512_16230_amd import _mrtlb as H
+    from paper_2512_16230_amd import workloads as W
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    if args.copy_probe:
+        copy_probe(torch, dev, args.steps, args.warmup)
+        return
+    stream = torch.cuda.current_stream(dev)
+    shape = (args.size, args.size)
+    wl = W.tgv_large(0, shape=shape, steps=args.steps)
+    card, r = wl.card, wl.rates
+    ctx = H.Context(0, stream=stream.cuda_stream)
+    lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
+    md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h)
+    s = H.Solve(ctx, lat, md, shape, args.storage)
+    s.init_fields(wl.rho_or_phi, wl.u)
+    del wl
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = s.step_timed(args.steps)      # HIP events on the launch stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mass, _ = s.conserved()
+    nodes = shape[0] * shape[1]
+    b = 25
+    launch_bytes = 2 * b * STORE_BYTES[args.storage] * nodes
+    per_launch_s = kernel_ms / 1e3 / args.steps
+    achieved = launch_bytes / per_launch_s / 1e9
+    value = nodes * args.steps / wall / 1e6
+    out = {
+        "metric": "rD2Q25 MRT-LB MLUPS (fused collide-and-stream), % of HBM roofline",
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.storage],
+        "data": "synthetic",
+        "config": {"workload": "tgv-rD2Q25-%dx%d" % (shape[1], shape[0]), "lattice": "rD2Q25",
+                   "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes,
+                   "tau_shear": 0.6, "mass_check": mass},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.storage, launch_bytes),
+                     "kernel_ms_per_launch": round(per_launch_s * 1e3, 5),
+                     "algorithmic_bytes_per_launch": launch_bytes},
+    }
+    s.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

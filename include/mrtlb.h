@@ -1,0 +1,211 @@
+/*
+ * mrtlb.h -- C ABI of the MI355X (gfx950) Hermite-matrix MRT lattice
+ * Boltzmann library.
+ *
+ * The library runs the per-time-step fused collide-and-stream of the unified
+ * MRT-LB method of Shi, Yuan & Chai (arXiv 2512.16230) on multispeed
+ * rectangular lattices: the update of eq. (2-3) (theta = gamma = 1, full
+ * correction) with the Hermite-space collision of eq. (H-MRT-LB), the
+ * generalized third-order equilibrium of eq. (feq-1), the auxiliary moments
+ * M30 / M2G for the Navier-Stokes equations (Sec. III) and M20 / M1G for the
+ * nonlinear convection-diffusion equation (App. A), and propagation along
+ * the rD2Q25, rD2Q13, rD3Q53 and rD3Q33 velocity sets (Sec. V, App. D).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an mrtlb_status (0 = success, < 0 = error) and never
+ *    throws; mrtlb_last_error() returns a thread-local message describing the
+ *    last failure on the calling thread.
+ *  - Host arrays are borrowed for the duration of the call only, are FP64,
+ *    and are laid out structure-of-arrays with x fastest: a scalar field has
+ *    N = nx*ny*nz entries at index (z*ny + y)*nx + x; a vector field of
+ *    dimension d is d consecutive scalar fields (component-major); a
+ *    population array is b consecutive scalar fields, population j in the
+ *    lattice's velocity order (mrtlb_lattice_query).
+ *  - Device memory belongs to the library and is released by the matching
+ *    destroy call.  All device work of a solve is enqueued on the stream given
+ *    to mrtlb_ctx_create (borrowed; e.g. a PyTorch stream); calls that return
+ *    host data synchronize that stream first.
+ *  - Periodic boundaries in every direction; dt = 1 and dx_a = c_a (lattice
+ *    units).
+ *  - Handles are not thread-safe: one thread at a time per context.
+ */
+#ifndef MRTLB_H
+#define MRTLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MRTLB_OK = 0,
+  MRTLB_EINVAL = -1,   /* bad argument: null pointer, size, enum, rates    */
+  MRTLB_ENOMEM = -2,   /* footprint over the context's HBM budget, or a
+                          device allocation failed; nothing is allocated  */
+  MRTLB_EDEVICE = -3,  /* a HIP runtime call failed                        */
+  MRTLB_ENUMERIC = -4  /* a weight <= 0, singular Hermite Gram matrix, or a
+                          non-finite value found in a solve's state         */
+} mrtlb_status;
+
+typedef struct mrtlb_ctx mrtlb_ctx;
+typedef struct mrtlb_lattice mrtlb_lattice;
+typedef struct mrtlb_solve mrtlb_solve;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mrtlb_last_error(void);
+
+/* ABI version, (major << 16) | minor. */
+int mrtlb_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Context: one device, one stream, one HBM budget.
+ *   device            HIP device ordinal.
+ *   stream            hipStream_t to enqueue on (borrowed, may be NULL for the
+ *                     default stream).
+ *   hbm_budget_bytes  upper bound on the device memory all solves of this
+ *                     context may hold; 0 = 90% of the device's free memory.
+ * ------------------------------------------------------------------------- */
+mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t hbm_budget_bytes, mrtlb_ctx** out);
+void mrtlb_ctx_destroy(mrtlb_ctx* ctx);
+/* Bytes held by the context's solves and the budget. */
+mrtlb_status mrtlb_ctx_memory(const mrtlb_ctx* ctx, size_t* used, size_t* budget);
+/* Block until all work enqueued by the context has finished. */
+mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Lattice (host only, FP64).  Velocity sets and weights follow the paper:
+ *   MRTLB_RD2Q25  Sec. V eq. (3-1), weights eq. (WeightQ25), free weights
+ *                 free_w = {w13, w17, w18, w21}.
+ *   MRTLB_RD2Q13  Sec. V eq. (Q13lattice), closed-form weights, no free w.
+ *   MRTLB_RD3Q53  App. D, weights with free_w = {w33, w37, w41, w45}
+ *                 (d0a = cs^2 / c_a^2).
+ *   MRTLB_RD3Q33  App. D, weights unique for a given cs^2, no free w.
+ * c[0..d-1] = c_a = dx_a/dt; cs2 = sound speed squared (direction
+ * independent, Remark 2).  The Hermite rows of orders 0..3 are
+ * H0 = 1, H1 = c, H2 = cc - cs^2 I, H3 = c_a(c_b^2 - cs^2), c_x c_y c_z and
+ * c_a(c_a^2 - 3 cs^2) minus its W-projection on span{c_a(c_b^2 - cs^2)}
+ * (eq. CorrectQ25 and its App. D analogue).
+ * Errors: EINVAL (unknown kind, c <= 0, cs2 <= 0, wrong n_free),
+ *         ENUMERIC (some weight <= 0 or a singular correction system).
+ * ------------------------------------------------------------------------- */
+typedef enum { MRTLB_RD2Q25 = 0, MRTLB_RD2Q13 = 1, MRTLB_RD3Q53 = 2, MRTLB_RD3Q33 = 3 } mrtlb_lattice_kind;
+
+typedef struct {
+  int kind;          /* mrtlb_lattice_kind */
+  double c[3];       /* c_a; c[2] ignored in 2D */
+  double cs2;
+  double free_w[4];  /* free weights, see above */
+  int n_free;        /* 4 for RD2Q25 and RD3Q53, 0 otherwise */
+} mrtlb_lattice_desc;
+
+mrtlb_status mrtlb_lattice_create(const mrtlb_lattice_desc* desc, mrtlb_lattice** out);
+void mrtlb_lattice_destroy(mrtlb_lattice* lat);
+/* Query: b, d, e (b*d ints, integer multiples, row j = velocity j), w (b),
+ * nlow (number of Hermite rows of order <= 3: 10 in 2D, 20 in 3D),
+ * H (nlow*b, row-major, component rows 1, x, y, [z], xx, yy, [zz], xy, [xz, yz],
+ * then x yy, [x zz], y xx, [y zz], [z xx, z yy], [xyz], xxx, yyy, [zzz] with the
+ * pure rows corrected) and norms (nlow) = H_r W H_r^T.  Any output pointer
+ * may be NULL. */
+mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* lat, int* b, int* d, int* e, double* w, int* nlow,
+                                 double* H, double* norms);
+
+/* ---------------------------------------------------------------------------
+ * Model.  Relaxation rates are the diagonal of S in Hermite space:
+ *   s0 (order 0), s1 (order 1), s_shear (off-diagonal and deviatoric normal
+ *   order-2 rows), s_bulk (trace of order 2), s3 (order 3), s_high (every
+ *   row above order 3).  Shear viscosity nu = cs^2 (1/s_shear - 1/2) dt,
+ *   bulk nu_b = (2/d) cs^2 (1/s_bulk - 1/2) dt (eq. 4-29, k = 0).
+ * MRTLB_NSE_INC   M0 = rho_bar, M1 = rho0 u, M2 = rho0 uu + cs^2 rho_bar I,
+ *                 M3 = rho0 cs^2 Delta.u + M30 (Sec. III, multispeed case);
+ *                 rho_bar carries the pressure p = cs^2 rho_bar.
+ * MRTLB_NSE_COMP  isothermal compressible: M0 = rho, M1 = rho u,
+ *                 M2 = rho uu + p I, M3 = p Delta.u + M30, p = cs^2 rho.
+ *   Both: M30 = rho uuu when m30 != 0; a body force F enters as
+ *   M1F = F (eq. M-NSEs-5) with the auxiliary
+ *   M2G = (I - S2/2)(uF + Fu) (eq. M2G-1, S = 0); u = (sum c f + F/2)/rho.
+ * MRTLB_NCDE      phi_t + div(phi u) = div(D(phi) grad phi),
+ *                 D = D0 (1 + D2 phi^2), constant advection adv_u:
+ *                 M0 = phi, M1 = phi u, M2 = cs^2 Phi(phi) I + phi uu,
+ *                 K Phi' = D with K = cs^2 (1/s1 - 1/2), and the auxiliary
+ *                 first moment (I - S1/2) u [(phi^n - phi^{n-1}) +
+ *                 u . grad phi^{n-1}] (eq. M-NCDE-6, case (1); central
+ *                 differences, phi^{-1} = phi^0).
+ * ------------------------------------------------------------------------- */
+typedef enum { MRTLB_NSE_INC = 0, MRTLB_NSE_COMP = 1, MRTLB_NCDE = 2 } mrtlb_model;
+
+typedef struct {
+  int model;         /* mrtlb_model */
+  double rho0;       /* NSE_INC reference density; deviation reference */
+  double s0, s1, s_shear, s_bulk, s3, s_high;
+  int m30;           /* NSE: include M30 = rho uuu */
+  double D0, D2;     /* NCDE */
+  double adv_u[3];   /* NCDE */
+} mrtlb_model_desc;
+
+/* Population storage in HBM (compute is FP64 for MRTLB_FP64, FP32 otherwise):
+ *   FP64      f_bar, double
+ *   FP32      f_bar, float
+ *   FP32_DEV  f_bar - w_j rho_ref, float
+ *   FP16_DEV  (f_bar - w_j rho_ref) * scale / w_j, IEEE half (RNE)
+ *   BF16_DEV  same, bfloat16 (RNE)
+ * rho_ref = rho0 (NSE) or 0 (NCDE); scale = 2^7. */
+typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DEV = 3, MRTLB_BF16_DEV = 4 } mrtlb_storage;
+
+/* Create a solve on a periodic grid n[0] x n[1] (x n[2] in 3D; n[2] = 1 in
+ * 2D).  Allocates two population buffers (pull streaming, double-buffered),
+ * the force field if has_force, and for the NCDE two phi history fields.
+ * The lattice is copied; it may be destroyed afterwards.
+ * Errors: EINVAL (sizes < 1, node count >= 2^31, rates outside (0, 2),
+ * unknown model or storage, NSE_INC with rho0 <= 0), ENOMEM (footprint over
+ * the remaining budget; nothing allocated), EDEVICE. */
+mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
+                                const int64_t n[3], int storage, int has_force, mrtlb_solve** out);
+/* Device bytes mrtlb_solve_create would allocate. */
+mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3], int storage, int model,
+                                   int has_force, size_t* bytes);
+/* Destroy every solve before its context. */
+void mrtlb_solve_destroy(mrtlb_solve* s);
+
+/* Initial state: f_bar(x, 0) = f_eq(rho_or_phi, u) - F/2 (NSE) or
+ * f_eq(phi) (NCDE).  rho_or_phi: N values (rho_bar for NSE_INC, rho for
+ * NSE_COMP, phi for NCDE); u: d*N values (ignored for NCDE, may be NULL);
+ * force: d*N values or NULL (required iff the solve has a force field).
+ * Resets the step counter.  Synchronous. */
+mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho_or_phi, const double* u, const double* force);
+
+/* Enqueue nsteps >= 0 collide-and-stream steps (asynchronous). */
+mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);
+
+/* Same, and return the device time of those steps in *ms, measured with HIP
+ * events recorded on the context stream around the launches (synchronous). */
+mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms);
+
+/* Advance every solve of the array by nsteps, with one kernel launch per
+ * step for each group of solves that share lattice, model and storage.
+ * Solves must belong to the same context.  Each solve's result equals
+ * mrtlb_step on it alone, bit for bit. */
+mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, int64_t nsteps);
+
+/* rho_or_phi (N) and u (d*N, may be NULL) at the current time, eq. (2-4-2)
+ * / (2-4-1): rho_bar = sum f_bar, u = (sum c f_bar + F/2)/rho_m.
+ * Synchronous. */
+mrtlb_status mrtlb_read_moments(mrtlb_solve* s, double* rho_or_phi, double* u);
+
+/* Domain totals in FP64 with a fixed reduction order: mass = sum rho_bar
+ * (or phi), momentum[d] = sum (sum c f_bar + F/2).  Returns ENUMERIC if a
+ * stored value is not finite.  Synchronous. */
+mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum);
+
+/* Checkpoint / restore of f_bar at the current time (b*N values). */
+mrtlb_status mrtlb_read_populations(mrtlb_solve* s, double* f);
+mrtlb_status mrtlb_write_populations(mrtlb_solve* s, const double* f);
+
+/* Steps taken since the last init (or write_populations keeps the count). */
+int64_t mrtlb_solve_steps(const mrtlb_solve* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRTLB_H */

@@ -1,0 +1,244 @@
+// Host-side lattice builder: weights from the paper's weight equations,
+// Hermite rows of order <= 3 with the rectangular-lattice correction of the
+// pure third-order rows, and their W-norms.  All FP64.
+#include "host_lattice.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include "lattices.h"
+
+namespace mrtlb {
+
+namespace {
+
+template <class L>
+void copy_velocities(HostLattice* out) {
+  out->D = L::D;
+  out->B = L::B;
+  out->e.assign(L::B * L::D, 0);
+  for (int j = 0; j < L::B; ++j) {
+    out->e[j * L::D + 0] = L::EX[j];
+    out->e[j * L::D + 1] = L::EY[j];
+    if (L::D == 3) out->e[j * L::D + 2] = ez<L>(j);
+  }
+}
+
+// Layer (max |e_a|) and the set of non-zero axes as a bit mask.
+void classify(const int* ej, int D, int* layer, int* mask) {
+  *layer = 0;
+  *mask = 0;
+  for (int a = 0; a < D; ++a) {
+    int v = std::abs(ej[a]);
+    if (v > *layer) *layer = v;
+    if (v) *mask |= 1 << a;
+  }
+}
+
+// rD2Q25 weights, Sec. V eq. (WeightQ25); free = {w13, w17, w18, w21}.
+void weights_rd2q25(const double* c, double cs2, const double* fr, HostLattice* out) {
+  const double d1 = cs2 / (c[0] * c[0]), d2 = cs2 / (c[1] * c[1]);
+  const double w13 = fr[0], w17 = fr[1], w18 = fr[2], w21 = fr[3];
+  const double w5 = (d1 * d2 - 64 * w13 - 324 * w21) / 4;
+  const double w9 = (d1 * (3 * d1 - 1) - 48 * w13 - 144 * w17 - 288 * w21) / 24;
+  const double w10 = (d2 * (3 * d2 - 1) - 48 * w13 - 144 * w18 - 288 * w21) / 24;
+  const double w1 = d1 / 2 - (2 * w5 + 4 * w9 + 8 * w13 + 9 * w17 + 18 * w21);
+  const double w2 = d2 / 2 - (2 * w5 + 4 * w10 + 8 * w13 + 9 * w18 + 18 * w21);
+  const double w0 = 1 - 2 * (w1 + w2 + w9 + w10 + w17 + w18) - 4 * (w5 + w13 + w21);
+  // [layer][mask]: mask 1 = x axis, 2 = y axis, 3 = diagonal
+  const double tab[4][4] = {{w0, 0, 0, 0}, {0, w1, w2, w5}, {0, w9, w10, w13}, {0, w17, w18, w21}};
+  out->w.resize(out->B);
+  for (int j = 0; j < out->B; ++j) {
+    int layer, mask;
+    classify(&out->e[j * 2], 2, &layer, &mask);
+    out->w[j] = tab[layer][mask];
+  }
+}
+
+// rD2Q13 closed-form weights printed with Sec. V eq. (Q13lattice).
+void weights_rd2q13(const double* c, double cs2, HostLattice* out) {
+  const double d1 = cs2 / (c[0] * c[0]), d2 = cs2 / (c[1] * c[1]);
+  const double w9 = d1 * (3 * d1 - 1) / 24, w10 = d2 * (3 * d2 - 1) / 24;
+  const double w0 = (1 - d1) * (1 - d2) + 6 * (w9 + w10);
+  const double w1 = d1 * (1 - d2) / 2 - 4 * w9, w2 = d2 * (1 - d1) / 2 - 4 * w10;
+  const double w5 = d1 * d2 / 4;
+  const double tab[3][4] = {{w0, 0, 0, 0}, {0, w1, w2, w5}, {0, w9, w10, 0}};
+  out->w.resize(out->B);
+  for (int j = 0; j < out->B; ++j) {
+    int layer, mask;
+    classify(&out->e[j * 2], 2, &layer, &mask);
+    out->w[j] = tab[layer][mask];
+  }
+}
+
+// rD3Q53 (free = {w33, w37, w41, w45}) and rD3Q33 (no free weights), App. D,
+// with d0a = cs^2 / c_a^2 as required by eq. (new11).
+void weights_3d(const double* c, double cs2, const double* fr, bool q53, HostLattice* out) {
+  const double d1 = cs2 / (c[0] * c[0]), d2 = cs2 / (c[1] * c[1]), d3 = cs2 / (c[2] * c[2]);
+  const double w33 = q53 ? fr[0] : 0, w37 = q53 ? fr[1] : 0, w41 = q53 ? fr[2] : 0, w45 = q53 ? fr[3] : 0;
+  const double w19 = d1 * d2 * d3 / 8 - 64 * w45;
+  const double w7 = d1 * d2 / 4 - 2 * w19 - 16 * w33 - 32 * w45;
+  const double w11 = d1 * d3 / 4 - 2 * w19 - 16 * w37 - 32 * w45;
+  const double w15 = d2 * d3 / 4 - 2 * w19 - 16 * w41 - 32 * w45;
+  const double w27 = d1 * (3 * d1 - 1) / 24 - 2 * (w33 + w37) - 4 * w45;
+  const double w28 = d2 * (3 * d2 - 1) / 24 - 2 * (w33 + w41) - 4 * w45;
+  const double w29 = d3 * (3 * d3 - 1) / 24 - 2 * (w41 + w37) - 4 * w45;
+  const double w1 = d1 / 2 - 2 * (w7 + w11) - 4 * w19 - 4 * w27 - 8 * (w33 + w37) - 16 * w45;
+  const double w2 = d2 / 2 - 2 * (w7 + w15) - 4 * w19 - 4 * w28 - 8 * (w33 + w41) - 16 * w45;
+  const double w3 = d3 / 2 - 2 * (w11 + w15) - 4 * w19 - 4 * w29 - 8 * (w41 + w37) - 16 * w45;
+  const double w0 = 1 - 2 * (w1 + w2 + w3 + w27 + w28 + w29) - 4 * (w7 + w11 + w15 + w33 + w37 + w41) -
+                    8 * (w19 + w45);
+  // [layer][mask]: mask bits x=1, y=2, z=4
+  double tab[3][8] = {};
+  tab[0][0] = w0;
+  tab[1][1] = w1; tab[1][2] = w2; tab[1][4] = w3; tab[1][3] = w7; tab[1][5] = w11; tab[1][6] = w15; tab[1][7] = w19;
+  tab[2][1] = w27; tab[2][2] = w28; tab[2][4] = w29; tab[2][3] = w33; tab[2][5] = w37; tab[2][6] = w41; tab[2][7] = w45;
+  out->w.resize(out->B);
+  for (int j = 0; j < out->B; ++j) {
+    int layer, mask;
+    classify(&out->e[j * 3], 3, &layer, &mask);
+    out->w[j] = tab[layer][mask];
+  }
+}
+
+double wdot(const HostLattice& L, const std::vector<double>& p, const std::vector<double>& q) {
+  double s = 0;
+  for (int j = 0; j < L.B; ++j) s += L.w[j] * p[j] * q[j];
+  return s;
+}
+
+}  // namespace
+
+int row_j(int, int a) { return 1 + a; }
+int row_nn(int D, int a) { return 1 + D + a; }
+int row_off(int D, int a, int b) {
+  // 2D: xy -> 5; 3D: xy -> 7, xz -> 8, yz -> 9
+  if (D == 2) return 5;
+  const int k = (a == 0) ? (b == 1 ? 0 : 1) : 2;
+  return 7 + k;
+}
+int row_abb(int D, int a, int b) {
+  // 2D: xyy 6, yxx 7.  3D: xyy 10, xzz 11, yxx 12, yzz 13, zxx 14, zyy 15
+  if (D == 2) return a == 0 ? 6 : 7;
+  int k = 0;
+  for (int aa = 0; aa < 3; ++aa)
+    for (int bb = 0; bb < 3; ++bb) {
+      if (aa == bb) continue;
+      if (aa == a && bb == b) return 10 + k;
+      ++k;
+    }
+  return -1;
+}
+int row_xyz() { return 16; }
+int row_aaa(int D, int a) { return D == 2 ? 8 + a : 17 + a; }
+
+mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std::string* err) {
+  char buf[256];
+  HostLattice L;
+  L.kind = desc.kind;
+  switch (desc.kind) {
+    case kRD2Q25: copy_velocities<LatRD2Q25>(&L); break;
+    case kRD2Q13: copy_velocities<LatRD2Q13>(&L); break;
+    case kRD3Q53: copy_velocities<LatRD3Q53>(&L); break;
+    case kRD3Q33: copy_velocities<LatRD3Q33>(&L); break;
+    default:
+      snprintf(buf, sizeof buf, "unknown lattice kind %d", desc.kind);
+      *err = buf;
+      return MRTLB_EINVAL;
+  }
+  const int D = L.D, B = L.B;
+  const int need_free = (desc.kind == kRD2Q25 || desc.kind == kRD3Q53) ? 4 : 0;
+  if (desc.n_free != need_free) {
+    snprintf(buf, sizeof buf, "lattice kind %d takes %d free weights, got %d", desc.kind, need_free, desc.n_free);
+    *err = buf;
+    return MRTLB_EINVAL;
+  }
+  if (!(desc.cs2 > 0) || !std::isfinite(desc.cs2)) {
+    *err = "cs2 must be positive and finite";
+    return MRTLB_EINVAL;
+  }
+  for (int a = 0; a < D; ++a) {
+    if (!(desc.c[a] > 0) || !std::isfinite(desc.c[a])) {
+      *err = "c_a must be positive and finite";
+      return MRTLB_EINVAL;
+    }
+    L.c[a] = desc.c[a];
+  }
+  L.cs2 = desc.cs2;
+  switch (desc.kind) {
+    case kRD2Q25: weights_rd2q25(L.c, L.cs2, desc.free_w, &L); break;
+    case kRD2Q13: weights_rd2q13(L.c, L.cs2, &L); break;
+    case kRD3Q53: weights_3d(L.c, L.cs2, desc.free_w, true, &L); break;
+    case kRD3Q33: weights_3d(L.c, L.cs2, nullptr, false, &L); break;
+  }
+  for (int j = 0; j < B; ++j) {
+    if (!(L.w[j] > 0)) {
+      snprintf(buf, sizeof buf, "weight w[%d] = %.6g is not positive for these c, cs2 and free weights", j, L.w[j]);
+      *err = buf;
+      return MRTLB_ENUMERIC;
+    }
+  }
+
+  // Physical velocities.
+  std::vector<double> cv(B * D);
+  for (int j = 0; j < B; ++j)
+    for (int a = 0; a < D; ++a) cv[j * D + a] = L.c[a] * L.e[j * D + a];
+  auto cc = [&](int j, int a) { return cv[j * D + a]; };
+  const double cs2 = L.cs2;
+
+  L.nlow = D == 2 ? 10 : 20;
+  std::vector<std::vector<double>> rows(L.nlow, std::vector<double>(B, 0.0));
+  for (int j = 0; j < B; ++j) {
+    rows[0][j] = 1.0;
+    for (int a = 0; a < D; ++a) {
+      rows[row_j(D, a)][j] = cc(j, a);
+      rows[row_nn(D, a)][j] = cc(j, a) * cc(j, a) - cs2;
+      for (int b = a + 1; b < D; ++b) rows[row_off(D, a, b)][j] = cc(j, a) * cc(j, b);
+      for (int b = 0; b < D; ++b)
+        if (b != a) rows[row_abb(D, a, b)][j] = cc(j, a) * (cc(j, b) * cc(j, b) - cs2);
+      rows[row_aaa(D, a)][j] = cc(j, a) * (cc(j, a) * cc(j, a) - 3 * cs2);
+    }
+    if (D == 3) rows[row_xyz()][j] = cc(j, 0) * cc(j, 1) * cc(j, 2);
+  }
+  // Correction: remove from each pure row its W-projection on the span of
+  // the mixed rows c_a (c_b^2 - cs^2), b != a.  The Gram system is at most
+  // 2 x 2 and solved directly.
+  for (int a = 0; a < D; ++a) {
+    int bs[2], nb = 0;
+    for (int b = 0; b < D; ++b)
+      if (b != a) bs[nb++] = b;
+    const std::vector<double>& p = rows[row_aaa(D, a)];
+    double G[2][2], r[2], x[2];
+    for (int i = 0; i < nb; ++i) {
+      r[i] = wdot(L, p, rows[row_abb(D, a, bs[i])]);
+      for (int k = 0; k < nb; ++k) G[i][k] = wdot(L, rows[row_abb(D, a, bs[i])], rows[row_abb(D, a, bs[k])]);
+    }
+    if (nb == 1) {
+      if (!(std::fabs(G[0][0]) > 0)) { *err = "singular correction system"; return MRTLB_ENUMERIC; }
+      x[0] = r[0] / G[0][0];
+    } else {
+      const double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+      if (!(std::fabs(det) > 1e-300)) { *err = "singular correction system"; return MRTLB_ENUMERIC; }
+      x[0] = (r[0] * G[1][1] - r[1] * G[0][1]) / det;
+      x[1] = (r[1] * G[0][0] - r[0] * G[1][0]) / det;
+    }
+    std::vector<double>& pr = rows[row_aaa(D, a)];
+    for (int i = 0; i < nb; ++i) {
+      L.corr[a][bs[i]] = x[i];
+      const std::vector<double>& m = rows[row_abb(D, a, bs[i])];
+      for (int j = 0; j < B; ++j) pr[j] -= x[i] * m[j];
+    }
+  }
+  L.H.assign(L.nlow * B, 0.0);
+  L.norms.assign(L.nlow, 0.0);
+  for (int r = 0; r < L.nlow; ++r) {
+    for (int j = 0; j < B; ++j) L.H[r * B + j] = rows[r][j];
+    L.norms[r] = wdot(L, rows[r], rows[r]);
+    if (!(L.norms[r] > 0)) { *err = "zero Hermite norm"; return MRTLB_ENUMERIC; }
+  }
+  *out = std::move(L);
+  return MRTLB_OK;
+}
+
+}  // namespace mrtlb

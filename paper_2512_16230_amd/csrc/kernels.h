@@ -1,0 +1,59 @@
+// Device-side data structures shared by the kernels and the ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mrtlb {
+
+constexpr int kMaxB = 53;
+constexpr int kBlock = 256;         // threads per workgroup of every node kernel
+constexpr int kNumXcd = 8;          // MI355X: 8 XCDs, workgroups dealt round-robin
+
+enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4 };
+enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2 };
+
+// Per-solve constants of the collision, in the compute precision.  Row
+// constants refer to the component-form Hermite rows of order <= 3.
+template <class Real>
+struct KParams {
+  int nx, ny, nz;
+  uint32_t N;               // nodes
+  int inc;                  // NSE: incompressible (rho_m = rho0) or compressible (rho_m = rho)
+  int m30;                  // NSE: third-order equilibrium moments rho uuu
+  Real cs2;
+  Real c1[3], c2[3], c3[3]; // c_a, c_a^2, c_a^3
+  Real cab[3];              // c_x c_y, c_x c_z, c_y c_z
+  Real cabb[3][3];          // c_a c_b^2
+  Real cxyz;
+  Real w[kMaxB];            // weights
+  Real wsc[kMaxB];          // 16-bit deviation storage: value = stored * wsc[j]
+  Real iwsc[kMaxB];         //                           stored = value * iwsc[j]
+  Real corr[3][3];          // correction coefficients of the pure third-order rows
+  Real k3[3];               // -3 cs^2 + cs^2 sum_b corr[a][b]
+  Real in0, in1[3], in2n[3], in2o[3], in3m[3][3], in3p[3], inxyz;  // 1 / norms
+  Real s1, ss, sb, s3, sh;  // rates (s0 never acts: order-0 moment is conserved)
+  Real rho_ref;             // deviation reference: stored = f_bar - w rho_ref
+  Real rho0;
+  Real phi_coef, D2;        // NCDE: Phi = phi_coef (phi + D2 phi^3 / 3)
+  Real adv[3];              // NCDE advection velocity
+};
+
+// One solve's share of a (possibly batched) step launch.
+template <class Real>
+struct Job {
+  KParams<Real> P;
+  const void* fin;          // populations at t (post-collision, pre-propagation)
+  void* fout;               // populations at t + 1
+  const Real* force;        // d x N, or nullptr
+  const Real* phi_prev;     // NCDE: phi^{n-1}
+  Real* phi_out;            // NCDE: phi^n
+  uint32_t block_begin;     // first linear workgroup of this job
+  uint32_t nblocks;
+  int gx;                   // workgroups along x per row group
+  int bx_shift;             // log2 of the x-width of a workgroup tile (6, 7 or 8)
+  int nrowgroups;           // ceil(ny / rows per tile) * nz
+};
+
+}  // namespace mrtlb

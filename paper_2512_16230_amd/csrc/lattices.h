@@ -1,0 +1,84 @@
+// Velocity sets of the supported lattices as compile-time tables, shared by
+// the host lattice builder and the kernels (integer multiples e_j; the
+// physical velocity is c_j = diag(c) e_j).  Column orders follow the paper:
+//   rD2Q25  Sec. V, eq. (3-1): rest, then the D2Q9 ring scaled by 1, 2, 3
+//   rD2Q13  Sec. V, eq. (Q13lattice)
+//   rD3Q53  App. D: D3Q27 in the printed order, then 2x its 26 moving columns
+//   rD3Q33  App. D: D3Q27, then (+-2,0,0), (0,+-2,0), (0,0,+-2)
+#pragma once
+
+namespace mrtlb {
+
+enum LatticeKind { kRD2Q25 = 0, kRD2Q13 = 1, kRD3Q53 = 2, kRD3Q33 = 3 };
+
+struct LatRD2Q25 {
+  static constexpr int kind = kRD2Q25, D = 2, B = 25, MAXE = 3;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0, 2, -2, -2, 2, 3, 0, -3, 0, 3, -3, -3, 3};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2, 2, 2, -2, -2, 0, 3, 0, -3, 3, 3, -3, -3};
+  static constexpr int EZ[B] = {};
+};
+
+struct LatRD2Q13 {
+  static constexpr int kind = kRD2Q13, D = 2, B = 13, MAXE = 2;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2};
+  static constexpr int EZ[B] = {};
+};
+
+#define MRTLB_D3Q27_X 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1
+#define MRTLB_D3Q27_Y 0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, 1, -1, -1, 1, 1, -1
+#define MRTLB_D3Q27_Z 0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1
+
+struct LatRD3Q53 {
+  static constexpr int kind = kRD3Q53, D = 3, B = 53, MAXE = 2;
+  static constexpr int EX[B] = {MRTLB_D3Q27_X, 2, -2, 0, 0, 0, 0, 2, -2, -2, 2, 2, -2, -2, 2, 0, 0, 0, 0, 2, -2, 2, -2, 2, -2, -2, 2};
+  static constexpr int EY[B] = {MRTLB_D3Q27_Y, 0, 0, 2, -2, 0, 0, 2, -2, 2, -2, 0, 0, 0, 0, 2, -2, -2, 2, 2, -2, 2, -2, -2, 2, 2, -2};
+  static constexpr int EZ[B] = {MRTLB_D3Q27_Z, 0, 0, 0, 0, 2, -2, 0, 0, 0, 0, 2, -2, 2, -2, 2, -2, 2, -2, 2, -2, -2, 2, 2, -2, 2, -2};
+};
+
+struct LatRD3Q33 {
+  static constexpr int kind = kRD3Q33, D = 3, B = 33, MAXE = 2;
+  static constexpr int EX[B] = {MRTLB_D3Q27_X, 2, -2, 0, 0, 0, 0};
+  static constexpr int EY[B] = {MRTLB_D3Q27_Y, 0, 0, 2, -2, 0, 0};
+  static constexpr int EZ[B] = {MRTLB_D3Q27_Z, 0, 0, 0, 0, 2, -2};
+};
+
+#undef MRTLB_D3Q27_X
+#undef MRTLB_D3Q27_Y
+#undef MRTLB_D3Q27_Z
+
+// Index of the population with velocity -e_j.
+template <class L>
+constexpr int opposite(int j) {
+  for (int k = 0; k < L::B; ++k) {
+    bool same = L::EX[k] == -L::EX[j] && L::EY[k] == -L::EY[j];
+    if (L::D == 3) same = same && L::EZ[k] == -L::EZ[j];
+    if (same) return k;
+  }
+  return -1;
+}
+
+template <class L>
+constexpr int ez(int j) {
+  if constexpr (L::D == 3) return L::EZ[j];
+  return 0;
+}
+
+// Pair list: the p-th pair is (pair_first<L>(p), opposite of it), taken in
+// increasing order of the first index with first < opposite.
+template <class L>
+constexpr int pair_first(int p) {
+  int count = 0;
+  for (int j = 1; j < L::B; ++j) {
+    if (j < opposite<L>(j)) {
+      if (count == p) return j;
+      ++count;
+    }
+  }
+  return -1;
+}
+
+template <class L>
+constexpr int n_pairs() { return (L::B - 1) / 2; }
+
+}  // namespace mrtlb

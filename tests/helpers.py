@@ -1,0 +1,39 @@
+"""Shared helpers of the parity tests: build the oracle and the HIP solve
+from the same workload parameters and compare them."""
+
+import numpy as np
+
+from oracle import lattice as OL
+from oracle import model as OM
+
+
+def oracle_for(card, eq, rates, rho0=1.0, D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), m30=True):
+    lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
+    mdl = OM.Model(eq=eq, rho0=rho0, s0=rates.s0, s1=rates.s1, s_shear=rates.s_shear, s_bulk=rates.s_bulk,
+                   s3=rates.s3, s_h=rates.s_h, m30=m30, D0=D0, D2=D2, adv_u=tuple(adv))
+    return lat, mdl
+
+
+def hip_model(eq, rates, rho0=1.0, D0=0.0, D2=0.0, adv=(0.0, 0.0, 0.0), m30=True):
+    from paper_2512_16230_amd import _mrtlb as H
+    return H.model_desc(eq, rho0=rho0, s0=rates.s0, s1=rates.s1, s_shear=rates.s_shear, s_bulk=rates.s_bulk,
+                        s3=rates.s3, s_high=rates.s_h, m30=m30, D0=D0, D2=D2, adv_u=adv)
+
+
+def hip_lattice(card):
+    from paper_2512_16230_amd import _mrtlb as H
+    return H.Lattice(card.kind, card.c, card.cs2, card.free)
+
+
+def max_rel(a, b):
+    """max |a - b| / max |b| (vector fields: magnitude over the components)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if a.ndim > 2 and a.shape[0] in (2, 3) and a.shape == b.shape and a.ndim in (3, 4):
+        return float(np.sqrt(((a - b) ** 2).sum(0)).max() / np.sqrt((b ** 2).sum(0)).max())
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def max_rel_dev(a, b, ref):
+    """max |a - b| / max |b - ref| for fields close to a constant ref."""
+    return float(np.abs(a - b).max() / np.abs(b - ref).max())

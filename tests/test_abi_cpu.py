@@ -1,0 +1,88 @@
+"""CPU checks of the C-ABI library: it is built, loads, exports every
+symbol declared in include/mrtlb.h, and its host-side lattice builder
+(no GPU involved) agrees with the oracle's independent construction."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lattice as OL
+from paper_2512_16230_amd import _mrtlb as H
+from paper_2512_16230_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mrtlb.h")).read()
+    decl = r"^(?:mrtlb_status|void|int|int64_t|const char\*)\s+\**(mrtlb_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(H.LIB_PATH), "libmrtlb.so not built"
+    lib = ctypes.CDLL(H.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 20
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert missing == []
+    assert sorted(H.EXPORTED) == syms
+
+
+def test_version():
+    assert H.lib().mrtlb_version() >> 16 == 1
+
+
+@pytest.mark.parametrize("card", [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC], ids=lambda c: c.kind)
+def test_host_lattice_matches_oracle(card):
+    q = H.Lattice(card.kind, card.c, card.cs2, card.free).query()
+    lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
+    assert np.array_equal(q["e"], lat.e)
+    assert np.allclose(q["w"], lat.w, rtol=0, atol=1e-15)
+    Hm = q["H"]
+    G = (Hm * q["w"]) @ Hm.T
+    assert np.abs(G - np.diag(np.diag(G))).max() < 1e-13 * np.abs(np.diag(G)).max()
+    assert np.allclose(np.diag(G), q["norms"], rtol=1e-14)
+    # the library's component rows span the same space as the oracle's rows
+    # (rotated second-order rows there), order by order
+    Ho = lat.H()
+    for order in range(4):
+        A = Ho[[r.order == order for r in lat.rows]]
+        rank_A = np.linalg.matrix_rank(A)
+        idx = {0: [0], 1: list(range(1, 1 + lat.d))}
+        if order >= 2:
+            n2 = lat.d * (lat.d + 1) // 2
+            idx[2] = list(range(1 + lat.d, 1 + lat.d + n2))
+            idx[3] = list(range(1 + lat.d + n2, Hm.shape[0]))
+        Bm = Hm[idx[order]]
+        assert np.linalg.matrix_rank(np.vstack([A, Bm]), tol=1e-9) == rank_A == Bm.shape[0]
+    # corrected pure third-order rows are identical (same definition)
+    pure_o = Ho[[r.name in ("xxx", "yyy", "zzz") for r in lat.rows]]
+    pure_h = Hm[-lat.d:]
+    assert np.allclose(pure_o, pure_h, atol=1e-12)
+
+
+def test_lattice_errors():
+    with pytest.raises(H.MrtlbError) as e:
+        H.Lattice(7, (1, 1), 0.5)
+    assert e.value.status == H.MRTLB_EINVAL
+    with pytest.raises(H.MrtlbError) as e:
+        H.Lattice("rD2Q25", (1.5, 1.0), 1.5, (0.0, 0.0, 0.0))
+    assert e.value.status == H.MRTLB_EINVAL
+    with pytest.raises(H.MrtlbError) as e:      # infeasible: w1 < 0
+        H.Lattice("rD2Q25", (1.5, 1.0), 1.5, (1e-3, 1e-3, 2e-2, 1e-3))
+    assert e.value.status == H.MRTLB_ENUMERIC
+    with pytest.raises(H.MrtlbError) as e:
+        H.Lattice("rD2Q13", (1.0, -1.0), 0.5)
+    assert e.value.status == H.MRTLB_EINVAL
+
+
+def test_footprint():
+    lat = H.Lattice(W.Q25_RECT.kind, W.Q25_RECT.c, W.Q25_RECT.cs2, W.Q25_RECT.free)
+    b32 = H.footprint(lat, (4096, 4096), "fp32", "NSE_INC")
+    b16 = H.footprint(lat, (4096, 4096), "fp16_dev", "NSE_INC")
+    assert b32 >= 2 * 25 * 4 * 4096 * 4096
+    assert b16 < 0.51 * b32

@@ -1,0 +1,339 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (max relative error, see tests/helpers.max_rel):
+  * FP64 storage/compute: the two sides differ only in rounding order;
+    1e-11 on rho and 1e-9 on u after hundreds of steps.
+  * FP32: every step rounds each stored population to 2^-24 of its size.
+    A velocity of size |u| is carried by populations of size ~w_j rho, so
+    one step perturbs u by ~2^-24 (rho/|u|) relative; the errors random-walk
+    and the momentum modes at k = 0 and the lowest k decay slower than a
+    decaying flow.  Plain FP32 therefore meets 1e-6 on rho and phi on short
+    runs but not on u; storing deviations f - w rho0 (fp32_dev) removes the
+    rho/|u| factor from the population part.  The bounds below are that
+    floor with a margin, measured on the box.
+  * 16-bit deviation storage: FP16 and BF16 bounded as measured.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import model as OM
+from paper_2512_16230_amd import _mrtlb as H
+from paper_2512_16230_amd import workloads as W
+
+from helpers import hip_lattice, hip_model, max_rel, max_rel_dev, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = H.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle_run(card, eq, rates, rho, u, steps, force=None, **kw):
+    lat, mdl = oracle_for(card, eq, rates, **kw)
+    st = OM.init_state(lat, mdl, rho, u, force)
+    st = OM.run(lat, mdl, st, steps, force)
+    r, v = OM.moments(lat, mdl, st, force)
+    return r, v, st
+
+
+def _gpu_run(ctx, card, eq, rates, shape, storage, rho, u, steps, force=None, **kw):
+    s = H.Solve(ctx, hip_lattice(card), hip_model(eq, rates, **kw), shape, storage, has_force=force is not None)
+    s.init_fields(rho, u, force)
+    s.step(steps)
+    r, v = s.read_moments()
+    return r, v, s
+
+
+def _random_fields(card, shape, seed, amp=0.03):
+    rng = np.random.default_rng(seed)
+    d = card.d
+    rho = 1 + amp * rng.normal(size=shape)
+    u = amp * rng.normal(size=(d,) + tuple(shape))
+    return rho, u
+
+
+# --------------------------------------------------------------------------
+# the small Taylor-Green workload: rD2Q25, 64 x 64, dx/dy = 1.5, 500 steps
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def tgv_oracle():
+    wl = W.tgv_small(0)
+    r, v, st = _oracle_run(wl.card, wl.eq, wl.rates, wl.rho_or_phi, wl.u, wl.steps)
+    return wl, r, v, st
+
+
+def test_tgv_fp64_matches_oracle(ctx, tgv_oracle):
+    wl, r_o, u_o, st_o = tgv_oracle
+    print("case: tgv-rD2Q25-64x64 fp64 500 steps", flush=True)
+    r, u, s = _gpu_run(ctx, wl.card, wl.eq, wl.rates, wl.shape, "fp64", wl.rho_or_phi, wl.u, wl.steps)
+    assert s.steps == wl.steps
+    assert max_rel(r, r_o) < 1e-11
+    assert max_rel_dev(r, r_o, 1.0) < 1e-6
+    assert max_rel(u, u_o) < 1e-9
+    f = s.read_populations()
+    assert np.abs(f - st_o.f).max() / np.abs(st_o.f).max() < 1e-11
+
+
+def test_tgv_fp32_matches_oracle(ctx, tgv_oracle):
+    wl, r_o, u_o, _ = tgv_oracle
+    print("case: tgv-rD2Q25-64x64 fp32 500 steps", flush=True)
+    errs = {}
+    for storage in ("fp32", "fp32_dev"):
+        r, u, _ = _gpu_run(ctx, wl.card, wl.eq, wl.rates, wl.shape, storage, wl.rho_or_phi, wl.u, wl.steps)
+        errs[storage] = (max_rel(r, r_o), max_rel(u, u_o))
+    print("fp32 errors (rho, u):", errs, flush=True)
+    assert errs["fp32"][0] < 2e-5 and errs["fp32"][1] < 5e-4
+    assert errs["fp32_dev"][0] < 1e-8 and errs["fp32_dev"][1] < 5e-5
+
+
+def test_dev16_storage(ctx):
+    wl = W.tgv_small(1, steps=200)
+    r_o, u_o, _ = _oracle_run(wl.card, wl.eq, wl.rates, wl.rho_or_phi, wl.u, wl.steps)
+    res = {}
+    for storage in ("fp16_dev", "bf16_dev"):
+        print("case: tgv-rD2Q25-64x64 %s 200 steps" % storage, flush=True)
+        r, u, _ = _gpu_run(ctx, wl.card, wl.eq, wl.rates, wl.shape, storage, wl.rho_or_phi, wl.u, wl.steps)
+        res[storage] = (max_rel(r, r_o), max_rel(u, u_o))
+    print("16-bit errors (rho, u):", res, flush=True)
+    assert res["fp16_dev"][0] < 1e-4 and res["fp16_dev"][1] < 1e-2
+    assert res["bf16_dev"][0] < 1e-2 and res["bf16_dev"][1] < 2e-1
+
+
+# --------------------------------------------------------------------------
+# ragged tiles, every lattice and model
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(7, 300), (70, 50), (3, 130)])
+@pytest.mark.parametrize("eq", ["NSE_INC", "NSE_COMP"])
+def test_rd2q25_ragged(ctx, shape, eq):
+    card = W.Q25_RECT
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    rho, u = _random_fields(card, shape, 3)
+    steps = 12
+    r_o, u_o, _ = _oracle_run(card, eq, rates, rho, u, steps)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4), ("fp32_dev", 1e-6, 2e-5)):
+        print("case: rD2Q25 %s %s %s" % (eq, shape, storage), flush=True)
+        r, v, _ = _gpu_run(ctx, card, eq, rates, shape, storage, rho, u, steps)
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+
+
+@pytest.mark.parametrize("shape", [(48, 136), (9, 70)])
+def test_rd2q13_ncde(ctx, shape):
+    card = W.Q13_SQUARE
+    wl = W.ncde_hill(shape, adv_u=(0.04, -0.03), D0=0.1, D2=1.0)
+    steps = 25
+    kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u)
+    phi_o, _, _ = _oracle_run(card, "NCDE", wl.rates, wl.rho_or_phi, None, steps, **kw)
+    for storage, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        print("case: rD2Q13 NCDE %s %s" % (shape, storage), flush=True)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, **kw), shape, storage)
+        s.init_fields(wl.rho_or_phi)
+        s.step(steps)
+        phi = s.read_moments(with_u=False)
+        assert max_rel(phi, phi_o) < tol
+
+
+@pytest.mark.parametrize("card,shape", [(W.Q53_RECT, (6, 10, 70)), (W.Q33_CUBIC, (5, 9, 66))],
+                         ids=["rD3Q53", "rD3Q33"])
+def test_3d_comp(ctx, card, shape):
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    rho, u = _random_fields(card, shape, 5)
+    steps = 6
+    r_o, u_o, _ = _oracle_run(card, "NSE_COMP", rates, rho, u, steps)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4), ("fp32_dev", 1e-6, 2e-5)):
+        print("case: %s NSE_COMP %s %s" % (card.kind, shape, storage), flush=True)
+        r, v, _ = _gpu_run(ctx, card, "NSE_COMP", rates, shape, storage, rho, u, steps)
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+
+
+@pytest.mark.parametrize("card,shape,eq", [(W.Q33_CUBIC, (8, 9, 10), "NSE_COMP"), (W.Q25_RECT, (12, 20), "NSE_INC"),
+                                           (W.Q53_RECT, (4, 5, 6), "NSE_INC")], ids=["rD3Q33", "rD2Q25", "rD3Q53"])
+def test_body_force(ctx, card, shape, eq):
+    rates = W.rates_tau(0.7)
+    rho, u = _random_fields(card, shape, 7, amp=0.01)
+    F = W.sinusoidal_force(card, shape, 1e-4, seed=3)
+    steps = 8
+    r_o, u_o, _ = _oracle_run(card, eq, rates, rho, u, steps, force=F)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4), ("fp32_dev", 1e-6, 2e-5)):
+        print("case: force %s %s %s" % (card.kind, eq, storage), flush=True)
+        r, v, s = _gpu_run(ctx, card, eq, rates, shape, storage, rho, u, steps, force=F)
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+    # momentum grows by exactly sum F per step (FP64 sums of the FP64 state)
+    s = H.Solve(ctx, hip_lattice(card), hip_model(eq, rates), shape, "fp64", has_force=True)
+    s.init_fields(rho, u, F)
+    m0, p0 = s.conserved()
+    s.step(5)
+    m1, p1 = s.conserved()
+    Fs = F.reshape(card.d, -1).sum(1)
+    assert abs(m1 - m0) < 1e-11 * abs(m0)
+    assert np.allclose(p1 - p0, 5 * Fs, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# conserved sums, checkpoints, batching, zero steps, errors
+# --------------------------------------------------------------------------
+
+def test_conserved_matches_oracle(ctx):
+    card = W.Q25_RECT
+    rates = W.rates_tau(0.8)
+    shape = (16, 33)
+    rho, u = _random_fields(card, shape, 9)
+    lat, mdl = oracle_for(card, "NSE_COMP", rates)
+    st = OM.init_state(lat, mdl, rho, u)
+    m_o, p_o = OM.conserved(lat, mdl, st)
+    for storage in ("fp64", "fp32", "fp32_dev", "fp16_dev"):
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NSE_COMP", rates), shape, storage)
+        s.init_fields(rho, u)
+        m0, p0 = s.conserved()
+        s.step(20)
+        m1, p1 = s.conserved()
+        tol = 1e-12 if storage == "fp64" else 1e-5
+        assert abs(m0 - m_o) < tol * abs(m_o), storage
+        assert np.allclose(p0, p_o, atol=tol * abs(m_o)), storage
+        if storage == "fp64":
+            assert abs(m1 - m0) < 1e-12 * abs(m0)
+            assert np.allclose(p1, p0, atol=1e-12)
+
+
+def test_checkpoint_roundtrip(ctx):
+    card = W.Q25_RECT
+    rates = W.rates_tau(0.8)
+    shape = (20, 40)
+    rho, u = _random_fields(card, shape, 11)
+    for storage in ("fp64", "fp32", "fp16_dev"):
+        a = H.Solve(ctx, hip_lattice(card), hip_model("NSE_INC", rates), shape, storage)
+        a.init_fields(rho, u)
+        a.step(7)
+        f = a.read_populations()
+        b = H.Solve(ctx, hip_lattice(card), hip_model("NSE_INC", rates), shape, storage)
+        b.write_populations(f)
+        a.step(5)
+        b.step(5)
+        fa, fb = a.read_populations(), b.read_populations()
+        if storage == "fp16_dev":
+            # the restore converts through FP64 and FP32 before rounding to
+            # half again; it reproduces the stored values up to ties
+            assert np.abs(fa - fb).max() <= 1e-6 * np.abs(fa).max()
+        else:
+            assert np.array_equal(fa, fb)
+
+
+def test_populations_match_oracle_after_steps(ctx):
+    card = W.Q13_SQUARE
+    wl = W.ncde_hill((20, 24), adv_u=(0.02, 0.01), D0=0.05, D2=0.5)
+    kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u)
+    lat, mdl = oracle_for(card, "NCDE", wl.rates, **kw)
+    st = OM.run(lat, mdl, OM.init_state(lat, mdl, wl.rho_or_phi), 9)
+    s = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, **kw), (20, 24), "fp64")
+    s.init_fields(wl.rho_or_phi)
+    s.step(9)
+    assert np.abs(s.read_populations() - st.f).max() < 1e-13
+
+
+def test_batch_equals_single(ctx):
+    cases = []
+    for i, N in enumerate([64, 96, 130]):
+        wl = W.ncde_hill((N, N), adv_u=(0.03 * (i - 1), 0.02), D0=0.1, D2=1.0)
+        cases.append((W.Q13_SQUARE, "NCDE", wl.rates, (N, N), wl.rho_or_phi, None,
+                      dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u)))
+    for shape in [(40, 70), (33, 257)]:
+        rho, u = _random_fields(W.Q25_RECT, shape, 13)
+        cases.append((W.Q25_RECT, "NSE_INC", W.rates_tau(0.8), shape, rho, u, {}))
+    for storage in ("fp32", "fp16_dev"):
+        solo, batch = [], []
+        for card, eq, rates, shape, r, u, kw in cases:
+            for lst in (solo, batch):
+                s = H.Solve(ctx, hip_lattice(card), hip_model(eq, rates, **kw), shape, storage)
+                s.init_fields(r, u)
+                lst.append(s)
+        for s in solo:
+            s.step(11)
+        H.batch_step(batch, 11)
+        for a, b in zip(solo, batch):
+            assert b.steps == 11
+            assert np.array_equal(a.read_populations(), b.read_populations())
+
+
+def test_zero_steps_and_errors(ctx):
+    card = W.Q25_RECT
+    rates = W.rates_tau(0.8)
+    rho, u = _random_fields(card, (8, 9), 15)
+    s = H.Solve(ctx, hip_lattice(card), hip_model("NSE_INC", rates), (8, 9), "fp32")
+    s.init_fields(rho, u)
+    f0 = s.read_populations()
+    s.step(0)
+    assert np.array_equal(s.read_populations(), f0)
+    with pytest.raises(H.MrtlbError) as e:
+        H.Solve(ctx, hip_lattice(card), hip_model("NSE_INC", rates), (2, 9), "fp32")   # ny < 3
+    assert e.value.status == H.MRTLB_EINVAL
+    with pytest.raises(H.MrtlbError) as e:
+        s.init_fields(rho, None)
+    assert e.value.status == H.MRTLB_EINVAL
+    with pytest.raises(H.MrtlbError) as e:
+        H.Solve(ctx, hip_lattice(card), hip_model("NSE_INC", W.Rates(1.2, 1.2, 2.5, 1.2, 1.2, 1.2)), (8, 9), "fp32")
+    assert e.value.status == H.MRTLB_EINVAL
+    small = H.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(H.MrtlbError) as e:
+        H.Solve(small, hip_lattice(card), hip_model("NSE_INC", rates), (512, 512), "fp32")
+    assert e.value.status == H.MRTLB_ENOMEM
+    assert small.memory()[0] == 0
+
+
+def test_nonfinite_state_is_reported(ctx):
+    """A density far outside the FP16 range overflows the stored deviation;
+    the conserved-sum pass reports it (the kernels just carry inf)."""
+    card = W.Q25_RECT
+    rates = W.rates_tau(0.8)
+    rho, u = _random_fields(card, (8, 9), 17)
+    rho[3, 4] = 1e6
+    s = H.Solve(ctx, hip_lattice(card), hip_model("NSE_INC", rates), (8, 9), "fp16_dev")
+    s.init_fields(rho, u)
+    with pytest.raises(H.MrtlbError) as e:
+        s.conserved()
+    assert e.value.status == H.MRTLB_ENUMERIC
+
+
+# --------------------------------------------------------------------------
+# full-size workload (4096 x 4096, launch configuration of the benchmark):
+# sampled nodes against the oracle on their light cone
+# --------------------------------------------------------------------------
+
+def _crop(a, iy, ix, r):
+    ny, nx = a.shape[-2:]
+    ys = (np.arange(iy - r, iy + r + 1)) % ny
+    xs = (np.arange(ix - r, ix + r + 1)) % nx
+    return a[..., ys[:, None], xs[None, :]]
+
+
+def test_full_size_sampled(ctx):
+    wl = W.tgv_large(0)
+    steps = 3
+    print("case: tgv-rD2Q25-4096x4096 fp32 sampled", flush=True)
+    s = H.Solve(ctx, hip_lattice(wl.card), hip_model(wl.eq, wl.rates), wl.shape, "fp32")
+    s.init_fields(wl.rho_or_phi, wl.u)
+    s.step(steps)
+    r, v = s.read_moments()
+    m_after, _ = s.conserved()
+    s.close()
+    rng = np.random.default_rng(0)
+    R = 3 * steps + 2
+    lat, mdl = oracle_for(wl.card, wl.eq, wl.rates)
+    pts = [(0, 0), (4095, 4095), (2048, 17)] + [tuple(rng.integers(0, 4096, 2)) for _ in range(5)]
+    for iy, ix in pts:
+        rho_c = _crop(wl.rho_or_phi, iy, ix, R)
+        u_c = _crop(wl.u, iy, ix, R)
+        st = OM.run(lat, mdl, OM.init_state(lat, mdl, rho_c, u_c), steps)
+        ro, uo = OM.moments(lat, mdl, st)
+        assert abs(r[iy, ix] - ro[R, R]) < 1e-6 * abs(ro[R, R])
+        assert np.abs(v[:, iy, ix] - uo[:, R, R]).max() < 1e-6 * 0.1 * np.sqrt(wl.card.cs2)
+    # mass is conserved to FP32 storage rounding
+    assert abs(m_after - wl.rho_or_phi.sum()) < 1e-6 * wl.rho_or_phi.sum()
