@@ -157,7 +157,8 @@ typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DE
  * 2D).  Allocates two population buffers (pull streaming, double-buffered),
  * the force field if has_force, and for the NCDE two phi history fields.
  * The lattice is copied; it may be destroyed afterwards.
- * Errors: EINVAL (sizes < 1, node count >= 2^31, rates outside (0, 2),
+ * Errors: EINVAL (sizes < 1, a size below the largest lattice offset, a
+ * population buffer of 4 GiB or more, rates outside (0, 2),
  * unknown model or storage, NSE_INC with rho0 <= 0), ENOMEM (footprint over
  * the remaining budget; nothing allocated), EDEVICE. */
 mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,

@@ -17,7 +17,8 @@ from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int64, c_size_t,
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmrtlb.so")
+# MRTLB_LIB points at another build of the library (tuning comparisons)
+LIB_PATH = os.environ.get("MRTLB_LIB", os.path.join(_HERE, "libmrtlb.so"))
 
 MRTLB_OK, MRTLB_EINVAL, MRTLB_ENOMEM, MRTLB_EDEVICE, MRTLB_ENUMERIC = 0, -1, -2, -3, -4
 MRTLB_RD2Q25, MRTLB_RD2Q13, MRTLB_RD3Q53, MRTLB_RD3Q33 = 0, 1, 2, 3

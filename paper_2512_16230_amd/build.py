@@ -1,39 +1,64 @@
-"""Build the HIP library libmrtlb.so in-tree for gfx950 with hipcc."""
+"""Build the HIP library libmrtlb.so in-tree for gfx950 with hipcc.
+
+Every translation unit compiles to an object in parallel (one per lattice
+plus the ABI layer), then hipcc links the shared library.
+"""
 
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrtlb.so")
-SOURCES = ["mrtlb.hip", "host_lattice.cpp"]
+SOURCES = ["abi.hip", "host_lattice.cpp", "inst_common.hip", "inst_rd2q25.hip", "inst_rd2q13.hip",
+           "inst_rd3q53.hip", "inst_rd3q33.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed FP32 instructions stay off: ordinary scalar FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",
+    "-Wno-unused-local-typedef",
 ]
+# extra flags for tuning builds, e.g. MRTLB_EXTRA_FLAGS="-DMRTLB_NT=0"
+FLAGS += os.environ.get("MRTLB_EXTRA_FLAGS", "").split()
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 8, out: str = LIB) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    outdir = tempfile.mkdtemp(prefix="mrtlb_build_")
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(outdir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+        objs.append(obj)
+        if len([p for p in procs if p.poll() is None]) >= jobs:
+            procs[0].wait()
+    failed = [src for src, p in zip(SOURCES, procs) if p.wait() != 0]
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(failed))
+    tmp = out + ".tmp"
+    link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
+    os.replace(tmp, out)
+    for o in objs:
+        os.remove(o)
+    os.rmdir(outdir)
+    return out
 
 
 if __name__ == "__main__":

@@ -1,0 +1,678 @@
+// C ABI of the Hermite-matrix MRT lattice Boltzmann library: contexts,
+// lattices, solves, and the host side of every entry point.  Kernels live in
+// device.h and are instantiated per lattice in inst_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mrtlb.h"
+#include "host_lattice.h"
+#include "kernels.h"
+#include "lattices.h"
+#include "launch.h"
+
+namespace mrtlb {
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+thread_local std::string g_last_error;
+
+static mrtlb_status fail(mrtlb_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(MRTLB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));    \
+  } while (0)
+
+}  // namespace mrtlb
+
+using namespace mrtlb;
+
+struct mrtlb_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t used = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct mrtlb_lattice {
+  HostLattice L;
+};
+
+struct mrtlb_solve {
+  mrtlb_ctx* ctx = nullptr;
+  HostLattice L;
+  mrtlb_model_desc model{};
+  int storage = 0;
+  int has_force = 0;
+  int nx = 1, ny = 1, nz = 1;
+  uint32_t N = 0;
+  size_t bytes = 0;
+  void* f[2] = {nullptr, nullptr};
+  void* force = nullptr;        // Real, d x N
+  void* phi[2] = {nullptr, nullptr};
+  void* jobs = nullptr;         // two Job<Real> (parity 0, 1)
+  void* pd = nullptr;           // KParams<double>
+  int cur = 0;
+  int64_t steps = 0;
+  KParams<double> Pd{};
+  KParams<float> Pf{};
+  int bx_shift = 8, gx = 1, nrowgroups = 1, vec = 1;
+  uint32_t nblocks = 0;         // workgroups of one step launch
+  uint32_t nblocks_node = 0;    // workgroups of the one-thread-per-node kernels
+};
+
+namespace mrtlb {
+
+static bool is_double(int storage) { return storage == kFP64; }
+static size_t elem_bytes(int storage) {
+  switch (storage) {
+    case kFP64: return 8;
+    case kFP32: case kFP32Dev: return 4;
+    default: return 2;
+  }
+}
+static int lattice_maxe(int kind) { return kind == kRD2Q25 ? 3 : 2; }
+
+// Nodes per thread of the step kernel: two consecutive x-nodes, i.e. 8-byte
+// (FP32), 16-byte (FP64) or 4-byte (16-bit) vector accesses per population;
+// one node when nx is odd or small.  Measured on rD2Q25 4096^2: two nodes
+// per thread match four for FP32 and beat it for FP16 (lower register
+// pressure).  MRTLB_STEP_VEC (1, 2 or 4) overrides it for tuning runs.
+static int pick_vec(int storage, int nx) {
+  (void)storage;
+  int v = 2;
+  if (const char* e = std::getenv("MRTLB_STEP_VEC")) {
+    const int o = std::atoi(e);
+    if (o == 1 || o == 2 || o == 4) v = o;
+  }
+  while (v > 1 && (nx % v != 0 || nx < 4 * v)) v >>= 1;
+  return v;
+}
+
+template <class Real>
+static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
+  const HostLattice& L = s.L;
+  const int D = L.D;
+  std::memset(&P, 0, sizeof P);
+  P.nx = s.nx; P.ny = s.ny; P.nz = s.nz; P.N = s.N;
+  P.inc = s.model.model == MRTLB_NSE_INC;
+  P.m30 = s.model.m30 != 0;
+  P.cs2 = (Real)L.cs2;
+  for (int a = 0; a < 3; ++a) {
+    const double c = a < D ? L.c[a] : 1.0;
+    P.c1[a] = (Real)c; P.c2[a] = (Real)(c * c); P.c3[a] = (Real)(c * c * c);
+  }
+  P.cab[0] = (Real)(L.c[0] * L.c[1]);
+  if (D == 3) { P.cab[1] = (Real)(L.c[0] * L.c[2]); P.cab[2] = (Real)(L.c[1] * L.c[2]); }
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) P.cabb[a][b] = (Real)(L.c[a] * L.c[b] * L.c[b]);
+  P.cxyz = D == 3 ? (Real)(L.c[0] * L.c[1] * L.c[2]) : (Real)0;
+  const double scale = 128.0;
+  for (int j = 0; j < L.B; ++j) {
+    P.w[j] = (Real)L.w[j];
+    P.wsc[j] = (Real)(L.w[j] / scale);
+    P.iwsc[j] = (Real)(scale / L.w[j]);
+  }
+  for (int a = 0; a < D; ++a) {
+    double ksum = 0;
+    for (int b = 0; b < D; ++b) {
+      P.corr[a][b] = (Real)L.corr[a][b];
+      ksum += L.corr[a][b];
+    }
+    P.k3[a] = (Real)(-3 * L.cs2 + L.cs2 * ksum);
+  }
+  P.in0 = (Real)(1.0 / L.norms[0]);
+  for (int a = 0; a < D; ++a) {
+    P.in1[a] = (Real)(1.0 / L.norms[row_j(D, a)]);
+    P.in2n[a] = (Real)(1.0 / L.norms[row_nn(D, a)]);
+    P.in3p[a] = (Real)(1.0 / L.norms[row_aaa(D, a)]);
+    for (int b = 0; b < D; ++b) {
+      if (b != a) P.in3m[a][b] = (Real)(1.0 / L.norms[row_abb(D, a, b)]);
+      if (b > a) P.in2o[off_index(a, b)] = (Real)(1.0 / L.norms[row_off(D, a, b)]);
+    }
+  }
+  if (D == 3) P.inxyz = (Real)(1.0 / L.norms[row_xyz()]);
+  const mrtlb_model_desc& m = s.model;
+  P.s1 = (Real)m.s1; P.ss = (Real)m.s_shear; P.sb = (Real)m.s_bulk; P.s3 = (Real)m.s3; P.sh = (Real)m.s_high;
+  const bool dev = s.storage == kFP32Dev || s.storage == kFP16Dev || s.storage == kBF16Dev;
+  P.rho_ref = (Real)(dev && m.model != MRTLB_NCDE ? m.rho0 : 0.0);
+  P.rho0 = (Real)m.rho0;
+  if (m.model == MRTLB_NCDE) {
+    const double K = L.cs2 * (1.0 / m.s1 - 0.5);
+    P.phi_coef = (Real)(m.D0 / K);
+    P.D2 = (Real)m.D2;
+  }
+  for (int a = 0; a < 3; ++a) P.adv[a] = (Real)(a < D ? m.adv_u[a] : 0.0);
+}
+
+template <class Real>
+static Job<Real> make_job(const mrtlb_solve& s, int parity, const KParams<Real>& P) {
+  Job<Real> J;
+  std::memset(&J, 0, sizeof J);
+  J.P = P;
+  J.fin = s.f[parity];
+  J.fout = s.f[parity ^ 1];
+  J.force = static_cast<const Real*>(s.force);
+  J.phi_prev = static_cast<const Real*>(s.phi[parity]);
+  J.phi_out = static_cast<Real*>(s.phi[parity ^ 1]);
+  J.block_begin = 0;
+  J.nblocks = s.nblocks;
+  J.gx = s.gx;
+  J.bx_shift = s.bx_shift;
+  J.nrowgroups = s.nrowgroups;
+  J.vec = s.vec;
+  return J;
+}
+
+// --- kernel dispatch -------------------------------------------------------
+
+static hipError_t dispatch(int kind, const LaunchReq& r) {
+  switch (kind) {
+    case kRD2Q25: return launch_rd2q25(r);
+    case kRD2Q13: return launch_rd2q13(r);
+    case kRD3Q53: return launch_rd3q53(r);
+    case kRD3Q33: return launch_rd3q33(r);
+  }
+  return hipErrorInvalidValue;
+}
+
+static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
+  LaunchReq r;
+  r.op = op;
+  r.storage = s.storage;
+  r.model = s.model.model;
+  r.force = s.has_force != 0;
+  r.vec = s.vec;
+  r.jobs = jobs;
+  r.njobs = 1;
+  r.blocks = op == kOpStep ? s.nblocks : s.nblocks_node;
+  r.stream = s.ctx->stream;
+  r.pd = s.pd;
+  return r;
+}
+
+static const void* job_ptr(const mrtlb_solve& s, int parity) {
+  const size_t jsz = is_double(s.storage) ? sizeof(Job<double>) : sizeof(Job<float>);
+  return static_cast<const char*>(s.jobs) + jsz * parity;
+}
+
+}  // namespace mrtlb
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+// Entry points keep the C linkage of their declarations in mrtlb.h.
+
+const char* mrtlb_last_error(void) { return g_last_error.c_str(); }
+
+int mrtlb_version(void) { return (1 << 16) | 0; }
+
+mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx** out) {
+  if (!out) return fail(MRTLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(MRTLB_EINVAL, "device ordinal out of range");
+  HIP_TRY(hipSetDevice(device));
+  size_t freeb = 0, total = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &total));
+  auto* c = new (std::nothrow) mrtlb_ctx;
+  if (!c) return fail(MRTLB_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return fail(MRTLB_EDEVICE, "hipEventCreate failed");
+  }
+  *out = c;
+  return MRTLB_OK;
+}
+
+void mrtlb_ctx_destroy(mrtlb_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+mrtlb_status mrtlb_ctx_memory(const mrtlb_ctx* c, size_t* used, size_t* budget) {
+  if (!c) return fail(MRTLB_EINVAL, "ctx is NULL");
+  if (used) *used = c->used;
+  if (budget) *budget = c->budget;
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* c) {
+  if (!c) return fail(MRTLB_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_lattice_create(const mrtlb_lattice_desc* desc, mrtlb_lattice** out) {
+  if (!desc || !out) return fail(MRTLB_EINVAL, "NULL argument");
+  *out = nullptr;
+  auto* l = new (std::nothrow) mrtlb_lattice;
+  if (!l) return fail(MRTLB_ENOMEM, "host allocation failed");
+  std::string err;
+  mrtlb_status st = build_lattice(*desc, &l->L, &err);
+  if (st != MRTLB_OK) {
+    delete l;
+    return fail(st, err);
+  }
+  *out = l;
+  return MRTLB_OK;
+}
+
+void mrtlb_lattice_destroy(mrtlb_lattice* l) { delete l; }
+
+mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* l, int* b, int* d, int* e, double* w, int* nlow, double* H,
+                                 double* norms) {
+  if (!l) return fail(MRTLB_EINVAL, "lattice is NULL");
+  const HostLattice& L = l->L;
+  if (b) *b = L.B;
+  if (d) *d = L.D;
+  if (nlow) *nlow = L.nlow;
+  if (e) std::copy(L.e.begin(), L.e.end(), e);
+  if (w) std::copy(L.w.begin(), L.w.end(), w);
+  if (H) std::copy(L.H.begin(), L.H.end(), H);
+  if (norms) std::copy(L.norms.begin(), L.norms.end(), norms);
+  return MRTLB_OK;
+}
+
+static mrtlb_status check_model(const mrtlb_model_desc& m, int D, int kind) {
+  if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP && m.model != MRTLB_NCDE)
+    return fail(MRTLB_EINVAL, "unknown model");
+  const double r[6] = {m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high};
+  for (double v : r)
+    if (!(v > 0 && v < 2)) return fail(MRTLB_EINVAL, "relaxation rates must lie in (0, 2)");
+  if (m.model == MRTLB_NSE_INC && !(m.rho0 > 0)) return fail(MRTLB_EINVAL, "rho0 must be positive");
+  if (m.model == MRTLB_NCDE && D != 2) return fail(MRTLB_EINVAL, "the NCDE model is built for 2D lattices");
+  (void)kind;
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3], int storage, int model,
+                                   int has_force, size_t* bytes) {
+  if (!lat || !n || !bytes) return fail(MRTLB_EINVAL, "NULL argument");
+  if (storage < kFP64 || storage > kBF16Dev) return fail(MRTLB_EINVAL, "unknown storage");
+  const int D = lat->L.D;
+  const int64_t nz = D == 3 ? n[2] : 1;
+  if (n[0] < 1 || n[1] < 1 || nz < 1) return fail(MRTLB_EINVAL, "grid sizes must be >= 1");
+  const int64_t N = n[0] * n[1] * nz;
+  const size_t real = is_double(storage) ? 8 : 4;
+  size_t b = 2 * (size_t)lat->L.B * (size_t)N * elem_bytes(storage);
+  if (has_force) b += (size_t)D * (size_t)N * real;
+  if (model == MRTLB_NCDE) b += 2 * (size_t)N * real;
+  b += 2 * sizeof(Job<double>) + sizeof(KParams<double>);
+  *bytes = b;
+  return MRTLB_OK;
+}
+
+static void release(mrtlb_solve* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->ctx->device);
+  for (void* p : {s->f[0], s->f[1], s->force, s->phi[0], s->phi[1], s->jobs, s->pd})
+    if (p) (void)hipFree(p);
+}
+
+static mrtlb_status upload_jobs(mrtlb_solve* s) {
+  if (is_double(s->storage)) {
+    Job<double> j[2] = {make_job(*s, 0, s->Pd), make_job(*s, 1, s->Pd)};
+    HIP_TRY(hipMemcpyAsync(s->jobs, j, sizeof j, hipMemcpyHostToDevice, s->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+  } else {
+    Job<float> j[2] = {make_job(*s, 0, s->Pf), make_job(*s, 1, s->Pf)};
+    HIP_TRY(hipMemcpyAsync(s->jobs, j, sizeof j, hipMemcpyHostToDevice, s->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+  }
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
+                                const int64_t n[3], int storage, int has_force, mrtlb_solve** out) {
+  if (!ctx || !lat || !model || !n || !out) return fail(MRTLB_EINVAL, "NULL argument");
+  *out = nullptr;
+  const int D = lat->L.D;
+  mrtlb_status st = check_model(*model, D, lat->L.kind);
+  if (st != MRTLB_OK) return st;
+  if (has_force && model->model == MRTLB_NCDE) return fail(MRTLB_EINVAL, "the NCDE model takes no force field");
+  size_t bytes = 0;
+  st = mrtlb_solve_footprint(lat, n, storage, model->model, has_force, &bytes);
+  if (st != MRTLB_OK) return st;
+  const int64_t nz = D == 3 ? n[2] : 1;
+  const int maxe = lattice_maxe(lat->L.kind);
+  if (n[0] < maxe || n[1] < maxe || (D == 3 && nz < maxe))
+    return fail(MRTLB_EINVAL, "every grid size must be at least the largest lattice offset");
+  if (n[0] * n[1] * nz >= ((int64_t)1 << 31)) return fail(MRTLB_EINVAL, "node count must be below 2^31");
+  // kernels address a population buffer with 32-bit byte offsets
+  if ((uint64_t)(n[0] * n[1] * nz) * (uint64_t)lat->L.B * elem_bytes(storage) >= ((uint64_t)1 << 32))
+    return fail(MRTLB_EINVAL, "one population buffer (b * N * element size) must be smaller than 4 GiB");
+  if (n[0] > (1 << 24) || n[1] > (1 << 24)) return fail(MRTLB_EINVAL, "grid size too large");
+  if (ctx->used + bytes > ctx->budget)
+    return fail(MRTLB_ENOMEM, "footprint " + std::to_string(bytes) + " B exceeds the remaining HBM budget");
+  auto* s = new (std::nothrow) mrtlb_solve;
+  if (!s) return fail(MRTLB_ENOMEM, "host allocation failed");
+  s->ctx = ctx;
+  s->L = lat->L;
+  s->model = *model;
+  s->storage = storage;
+  s->has_force = has_force ? 1 : 0;
+  s->nx = (int)n[0]; s->ny = (int)n[1]; s->nz = (int)nz;
+  s->N = (uint32_t)(n[0] * n[1] * nz);
+  s->bytes = bytes;
+  // step tile: each thread owns vec consecutive x-nodes (vector loads and
+  // stores of 8-16 bytes per lane); 64/128/256 threads along x per
+  // workgroup of 256 threads
+  s->vec = pick_vec(storage, s->nx);
+  const int tx = s->nx / s->vec;
+  s->bx_shift = tx > 128 ? 8 : (tx > 64 ? 7 : 6);
+  const int rows = kBlock >> s->bx_shift;
+  s->gx = (tx + (1 << s->bx_shift) - 1) >> s->bx_shift;
+  s->nrowgroups = ((s->ny + rows - 1) / rows) * s->nz;
+  s->nblocks_node = (s->N + kBlock - 1) / kBlock;
+  s->nblocks = (uint32_t)s->gx * (uint32_t)s->nrowgroups;
+  (void)hipSetDevice(ctx->device);
+  const size_t pop = (size_t)s->L.B * s->N * elem_bytes(storage);
+  const size_t real = is_double(storage) ? 8 : 4;
+  auto alloc = [&](void** p, size_t sz) { return hipMalloc(p, sz) == hipSuccess; };
+  bool ok = alloc(&s->f[0], pop) && alloc(&s->f[1], pop) &&
+            alloc(&s->jobs, 2 * std::max(sizeof(Job<double>), sizeof(Job<float>))) &&
+            alloc(&s->pd, sizeof(KParams<double>));
+  if (ok && has_force) ok = alloc(&s->force, (size_t)D * s->N * real);
+  if (ok && model->model == MRTLB_NCDE) ok = alloc(&s->phi[0], s->N * real) && alloc(&s->phi[1], s->N * real);
+  if (!ok) {
+    release(s);
+    delete s;
+    (void)hipGetLastError();
+    return fail(MRTLB_ENOMEM, "device allocation failed");
+  }
+  fill_params(*s, s->Pd);
+  fill_params(*s, s->Pf);
+  if (hipMemcpy(s->pd, &s->Pd, sizeof s->Pd, hipMemcpyHostToDevice) != hipSuccess || upload_jobs(s) != MRTLB_OK) {
+    release(s);
+    delete s;
+    return fail(MRTLB_EDEVICE, "parameter upload failed");
+  }
+  ctx->used += bytes;
+  *out = s;
+  return MRTLB_OK;
+}
+
+void mrtlb_solve_destroy(mrtlb_solve* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->ctx->stream);
+  release(s);
+  s->ctx->used -= s->bytes;
+  delete s;
+}
+
+int64_t mrtlb_solve_steps(const mrtlb_solve* s) { return s ? s->steps : -1; }
+
+// Staging: device FP64 copies of host fields.
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* u, const double* force) {
+  if (!s || !rho) return fail(MRTLB_EINVAL, "NULL argument");
+  const int D = s->L.D;
+  const bool ncde = s->model.model == MRTLB_NCDE;
+  if (!ncde && !u) return fail(MRTLB_EINVAL, "u is required for the NSE models");
+  if ((force != nullptr) != (s->has_force != 0)) return fail(MRTLB_EINVAL, "force must be given iff the solve has a force field");
+  for (uint32_t i = 0; i < s->N; ++i)
+    if (!std::isfinite(rho[i])) return fail(MRTLB_ENUMERIC, "non-finite initial density/phi");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  DevBuf dr, du, df;
+  HIP_TRY(hipMalloc(&dr.p, (size_t)s->N * 8));
+  HIP_TRY(hipMemcpyAsync(dr.p, rho, (size_t)s->N * 8, hipMemcpyHostToDevice, st));
+  if (!ncde) {
+    HIP_TRY(hipMalloc(&du.p, (size_t)D * s->N * 8));
+    HIP_TRY(hipMemcpyAsync(du.p, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
+  }
+  if (force) {
+    HIP_TRY(hipMalloc(&df.p, (size_t)D * s->N * 8));
+    HIP_TRY(hipMemcpyAsync(df.p, force, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
+    // the stepping kernels read the force in the compute precision
+    if (is_double(s->storage)) {
+      HIP_TRY(hipMemcpyAsync(s->force, df.p, (size_t)D * s->N * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+      std::vector<float> tmp((size_t)D * s->N);
+      for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)force[i];
+      HIP_TRY(hipMemcpyAsync(s->force, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+  }
+  s->cur = 0;
+  s->steps = 0;
+  // the init kernel writes f into buffer cur^1 and phi into both history
+  // slots; run it with the parity-1 job so that fout = f[0]
+  mrtlb_status rs = upload_jobs(s);
+  if (rs != MRTLB_OK) return rs;
+  LaunchReq r = base_req(*s, kOpInit, job_ptr(*s, 1));
+  r.in0 = (const double*)dr.p;
+  r.in1 = (const double*)du.p;
+  r.in2 = (const double*)df.p;
+  hipError_t err = dispatch(s->L.kind, r);
+  if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("init launch: ") + hipGetErrorString(err));
+  HIP_TRY(hipStreamSynchronize(st));
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps) {
+  if (!s) return fail(MRTLB_EINVAL, "solve is NULL");
+  if (nsteps < 0) return fail(MRTLB_EINVAL, "nsteps must be >= 0");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hipError_t e = dispatch(s->L.kind, base_req(*s, kOpStep, job_ptr(*s, s->cur)));
+    if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    s->cur ^= 1;
+    s->steps += 1;
+  }
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms) {
+  if (!s || !ms) return fail(MRTLB_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  HIP_TRY(hipEventRecord(s->ctx->ev0, s->ctx->stream));
+  mrtlb_status st = mrtlb_step(s, nsteps);
+  if (st != MRTLB_OK) return st;
+  HIP_TRY(hipEventRecord(s->ctx->ev1, s->ctx->stream));
+  HIP_TRY(hipEventSynchronize(s->ctx->ev1));
+  float t = 0;
+  HIP_TRY(hipEventElapsedTime(&t, s->ctx->ev0, s->ctx->ev1));
+  *ms = t;
+  return MRTLB_OK;
+}
+
+template <class Real>
+static mrtlb_status batch_group(mrtlb_solve* const* g, int n, int64_t nsteps, void* dev_jobs) {
+  // jobs for both parities of every member, laid out [parity][member]
+  std::vector<Job<Real>> jobs(2 * (size_t)n);
+  uint32_t begin = 0;
+  for (int i = 0; i < n; ++i) {
+    const mrtlb_solve& s = *g[i];
+    const KParams<Real>& P = *reinterpret_cast<const KParams<Real>*>(is_double(s.storage) ? (const void*)&s.Pd
+                                                                                          : (const void*)&s.Pf);
+    for (int par = 0; par < 2; ++par) {
+      Job<Real> J = make_job(s, s.cur ^ par, P);
+      J.block_begin = begin;
+      jobs[(size_t)par * n + i] = J;
+    }
+    begin += s.nblocks;
+  }
+  hipStream_t st = g[0]->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(dev_jobs, jobs.data(), jobs.size() * sizeof(Job<Real>), hipMemcpyHostToDevice, st));
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const void* jp = static_cast<const char*>(dev_jobs) + (size_t)(k & 1) * n * sizeof(Job<Real>);
+    LaunchReq r = base_req(*g[0], kOpStep, jp);
+    r.njobs = n;
+    r.blocks = begin;
+    hipError_t e = dispatch(g[0]->L.kind, r);
+    if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+  }
+  // the staging buffer must outlive the launches
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i) {
+    g[i]->cur ^= (int)(nsteps & 1);
+    g[i]->steps += nsteps;
+  }
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, int64_t nsteps) {
+  if (!solves || n < 0 || nsteps < 0) return fail(MRTLB_EINVAL, "bad argument");
+  if (n == 0 || nsteps == 0) return MRTLB_OK;
+  for (int i = 0; i < n; ++i) {
+    if (!solves[i]) return fail(MRTLB_EINVAL, "NULL solve in batch");
+    if (solves[i]->ctx != solves[0]->ctx) return fail(MRTLB_EINVAL, "solves of a batch must share a context");
+    for (int k = 0; k < i; ++k)
+      if (solves[k] == solves[i]) return fail(MRTLB_EINVAL, "a solve appears twice in the batch");
+  }
+  HIP_TRY(hipSetDevice(solves[0]->ctx->device));
+  // group by (lattice kind, storage, model, force); order of first appearance
+  std::vector<int> done(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (done[i]) continue;
+    std::vector<mrtlb_solve*> grp;
+    const mrtlb_solve* a = solves[i];
+    for (int k = i; k < n; ++k) {
+      const mrtlb_solve* b = solves[k];
+      if (!done[k] && b->L.kind == a->L.kind && b->storage == a->storage && b->model.model == a->model.model &&
+          b->has_force == a->has_force && b->vec == a->vec) {
+        grp.push_back(solves[k]);
+        done[k] = 1;
+      }
+    }
+    // one launch covers at most 2^31 workgroups; the job table lives in a
+    // temporary device buffer
+    const size_t jsz = is_double(a->storage) ? sizeof(Job<double>) : sizeof(Job<float>);
+    DevBuf jb;
+    HIP_TRY(hipMalloc(&jb.p, 2 * grp.size() * jsz));
+    mrtlb_status st = is_double(a->storage) ? batch_group<double>(grp.data(), (int)grp.size(), nsteps, jb.p)
+                                            : batch_group<float>(grp.data(), (int)grp.size(), nsteps, jb.p);
+    if (st != MRTLB_OK) return st;
+  }
+  return MRTLB_OK;
+}
+
+static mrtlb_status gather_launch(mrtlb_solve* s, int what, double* d0, double* d1) {
+  LaunchReq r = base_req(*s, what == 1 ? kOpPopulations : kOpMoments, job_ptr(*s, s->cur));
+  r.out0 = d0;
+  r.out1 = d1;
+  hipError_t err = dispatch(s->L.kind, r);
+  if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("gather launch: ") + hipGetErrorString(err));
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_read_moments(mrtlb_solve* s, double* rho, double* u) {
+  if (!s || !rho) return fail(MRTLB_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  const int D = s->L.D;
+  DevBuf dr, du;
+  HIP_TRY(hipMalloc(&dr.p, (size_t)s->N * 8));
+  if (u) HIP_TRY(hipMalloc(&du.p, (size_t)D * s->N * 8));
+  mrtlb_status st = gather_launch(s, 0, (double*)dr.p, (double*)du.p);
+  if (st != MRTLB_OK) return st;
+  HIP_TRY(hipMemcpyAsync(rho, dr.p, (size_t)s->N * 8, hipMemcpyDeviceToHost, s->ctx->stream));
+  if (u) HIP_TRY(hipMemcpyAsync(u, du.p, (size_t)D * s->N * 8, hipMemcpyDeviceToHost, s->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_read_populations(mrtlb_solve* s, double* f) {
+  if (!s || !f) return fail(MRTLB_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  DevBuf d;
+  const size_t n = (size_t)s->L.B * s->N;
+  HIP_TRY(hipMalloc(&d.p, n * 8));
+  mrtlb_status st = gather_launch(s, 1, (double*)d.p, nullptr);
+  if (st != MRTLB_OK) return st;
+  HIP_TRY(hipMemcpyAsync(f, d.p, n * 8, hipMemcpyDeviceToHost, s->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_write_populations(mrtlb_solve* s, const double* f) {
+  if (!s || !f) return fail(MRTLB_EINVAL, "NULL argument");
+  const size_t n = (size_t)s->L.B * s->N;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(f[i])) return fail(MRTLB_ENUMERIC, "non-finite population");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  DevBuf d;
+  HIP_TRY(hipMalloc(&d.p, n * 8));
+  HIP_TRY(hipMemcpyAsync(d.p, f, n * 8, hipMemcpyHostToDevice, st));
+  // write into the current buffer: the parity-(cur^1) job has fout = f[cur]
+  LaunchReq r = base_req(*s, kOpScatter, job_ptr(*s, s->cur ^ 1));
+  r.in0 = (const double*)d.p;
+  hipError_t err = dispatch(s->L.kind, r);
+  if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("scatter launch: ") + hipGetErrorString(err));
+  HIP_TRY(hipStreamSynchronize(st));
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum) {
+  if (!s || !mass) return fail(MRTLB_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  const int B = s->L.B, D = s->L.D;
+  const int nf = s->force ? D : 0;
+  const int planes = B + nf;
+  const uint32_t chunk = kBlock * kChunkIters;
+  const uint32_t nchunks = (s->N + chunk - 1) / chunk;
+  DevBuf part;
+  HIP_TRY(hipMalloc(&part.p, (size_t)planes * nchunks * 8));
+  hipStream_t st = s->ctx->stream;
+  // KParams is the first member of the job in device memory
+  const void* params = job_ptr(*s, s->cur);
+  hipError_t err = launch_plane_sums(s->storage, s->f[s->cur], s->N, B, s->force, nf, params, (double*)part.p,
+                                     nchunks, st);
+  if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("sum launch: ") + hipGetErrorString(err));
+  std::vector<double> h((size_t)planes * nchunks);
+  HIP_TRY(hipMemcpyAsync(h.data(), part.p, h.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<double> plane(planes, 0.0);
+  for (int p = 0; p < planes; ++p)
+    for (uint32_t c = 0; c < nchunks; ++c) plane[p] += h[(size_t)p * nchunks + c];
+  double m = 0, mom[3] = {0, 0, 0};
+  const double ref = (s->storage == kFP32Dev || s->storage == kFP16Dev || s->storage == kBF16Dev) &&
+                             s->model.model != MRTLB_NCDE
+                         ? s->model.rho0
+                         : 0.0;
+  for (int j = 0; j < B; ++j) {
+    m += plane[j];
+    for (int a = 0; a < D; ++a) mom[a] += s->L.c[a] * s->L.e[j * D + a] * plane[j];
+  }
+  m += ref * (double)s->N;
+  for (int a = 0; a < nf; ++a) mom[a] += 0.5 * plane[B + a];
+  bool finite = std::isfinite(m);
+  for (int a = 0; a < D; ++a) finite = finite && std::isfinite(mom[a]);
+  *mass = m;
+  if (momentum)
+    for (int a = 0; a < D; ++a) momentum[a] = mom[a];
+  if (!finite) return fail(MRTLB_ENUMERIC, "non-finite value in the solve's state");
+  return MRTLB_OK;
+}
+

@@ -1,0 +1,934 @@
+// Device code of the Hermite-matrix MRT lattice Boltzmann library: the
+// fused pull collide-and-stream kernel and its helpers (initialisation,
+// read-out, restore, FP64 plane sums), plus the host-side launchers that
+// instantiate them for one lattice.  Included by one translation unit per
+// lattice (inst_*.hip) so the instantiations compile in parallel.
+//
+// MI355X (gfx950) kernels and C ABI of the Hermite-matrix MRT lattice
+// Boltzmann method (arXiv 2512.16230): fused pull collide-and-stream,
+// initialisation, moment read-out, checkpoint and FP64 conserved sums.
+//
+// Layout in HBM: populations structure-of-arrays, f[j][z][y][x] (x fastest),
+// two buffers (pull propagation, double-buffered).  The buffer holds the
+// post-collision populations of the previous step, so f_bar_j(x, t) =
+// buf_j(x - e_j): a step gathers along -e_j, collides in registers and
+// writes every population at its own node (coalesced stores).
+//
+// Collision (per node, registers only).  With the component Hermite rows of
+// order <= 3 (H0 = 1, H1 = c, H2 = cc - cs^2, H3 mixed / xyz / corrected
+// pure) and every row above third order relaxing at the single rate s_h,
+// the update of eq. (2-3) with Lambda = H^-1 S H is
+//     f* = (1 - s_h) f + W sum_{r<=3} H_r (m*_r - (1 - s_h) m_r) / n_r
+// (the reduced form of eq. H-MRT-LB-1).  The forward moments are taken as
+// raw monomial sums over symmetric velocity pairs (even monomials from
+// f_p + f_q, odd ones from f_p - f_q) and the back-transform as a monomial
+// polynomial evaluated per pair, so each population costs a few FMAs and no
+// b x b matrix is formed.  The normal second-order rows relax their trace at
+// s_bulk and their deviator at s_shear.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+#include "kernels.h"
+#include "lattices.h"
+#include "launch.h"
+
+namespace mrtlb {
+
+// ---------------------------------------------------------------------------
+// compile-time helpers
+// ---------------------------------------------------------------------------
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+template <class L>
+constexpr int evel(int j, int a) {
+  return a == 0 ? L::EX[j] : (a == 1 ? L::EY[j] : ez<L>(j));
+}
+
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------------------
+// storage formats
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <int ST>
+struct StoreT;
+template <>
+struct StoreT<kFP64> { using T = double; using Real = double; };
+template <>
+struct StoreT<kFP32> { using T = float; using Real = float; };
+template <>
+struct StoreT<kFP32Dev> { using T = float; using Real = float; };
+template <>
+struct StoreT<kFP16Dev> { using T = _Float16; using Real = float; };
+template <>
+struct StoreT<kBF16Dev> { using T = uint16_t; using Real = float; };
+
+// Global-address-space access with a 32-bit byte offset from a uniform base:
+// the base stays in SGPRs and each lane supplies one 32-bit offset
+// (global_load/store with saddr), instead of flat accesses with a 64-bit
+// address per lane.  Every population plane is smaller than 4 GiB.
+#define MRTLB_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ T gload(const void* base, uint32_t byteoff) {
+  const MRTLB_GLOBAL char* p = (const MRTLB_GLOBAL char*)base;
+  return *(const MRTLB_GLOBAL T*)(p + byteoff);
+}
+
+template <class T>
+__device__ __forceinline__ void gstore(void* base, uint32_t byteoff, T v) {
+  MRTLB_GLOBAL char* p = (MRTLB_GLOBAL char*)base;
+  *(MRTLB_GLOBAL T*)(p + byteoff) = v;
+}
+
+template <int ST, class Real>
+__device__ __forceinline__ Real load_pop(const void* plane, uint32_t i, const KParams<Real>& P, int j) {
+  using T = typename StoreT<ST>::T;
+  const T v = gload<T>(plane, i * (uint32_t)sizeof(T));
+  if constexpr (ST == kFP16Dev) {
+    return (Real)(float)v * P.wsc[j];
+  } else if constexpr (ST == kBF16Dev) {
+    return (Real)bf16_to_f32(v) * P.wsc[j];
+  } else {
+    return (Real)v;
+  }
+}
+
+template <int ST, class Real>
+__device__ __forceinline__ void store_pop(void* plane, uint32_t i, Real v, const KParams<Real>& P, int j) {
+  using T = typename StoreT<ST>::T;
+  T out;
+  if constexpr (ST == kFP16Dev) {
+    out = (_Float16)(float)(v * P.iwsc[j]);
+  } else if constexpr (ST == kBF16Dev) {
+    out = f32_to_bf16_rne((float)(v * P.iwsc[j]));
+  } else {
+    out = (T)v;
+  }
+  gstore<T>(plane, i * (uint32_t)sizeof(T), out);
+}
+
+// ---------------------------------------------------------------------------
+// node geometry: wrapped row offsets for -MAXE..MAXE along y and z
+// ---------------------------------------------------------------------------
+
+// Population layout in HBM (row-blocked): element (j, x, y, z) of a buffer
+// sits at ((r * b + j) * nx + x) with node row r = z * ny + y, i.e. every
+// row of nx nodes stores its b population rows back to back.  A step then
+// reads each population from 2*MAXE+1 (2D) neighbouring row blocks and
+// writes one row block, instead of touching b planes that lie a whole
+// domain apart.  Scalar node fields (phi, force) are plain [r][x].
+template <class L>
+struct RowGeom {
+  static constexpr int M = L::MAXE;
+  uint32_t yo[2 * M + 1];   // wrap(iy - s)
+  uint32_t zo[2 * M + 1];   // wrap(iz - s) * ny
+  int nx;
+
+  __device__ __forceinline__ void init(int iy, int iz, int nx_, int ny, int nz) {
+    nx = nx_;
+#pragma unroll
+    for (int s = -M; s <= M; ++s) {
+      yo[s + M] = (uint32_t)wrap(iy - s, ny);
+      if constexpr (L::D == 3) zo[s + M] = (uint32_t)wrap(iz - s, nz) * (uint32_t)ny;
+    }
+  }
+  // node row of the source of population j (pull: row of x - e_j)
+  template <int J>
+  __device__ __forceinline__ uint32_t row() const {
+    uint32_t r = yo[L::EY[J] + M];
+    if constexpr (L::D == 3) r += zo[ez<L>(J) + M];
+    return r;
+  }
+  __device__ __forceinline__ uint32_t own_row() const { return yo[M] + (L::D == 3 ? zo[M] : 0u); }
+  // first element of population J's source row
+  template <int J>
+  __device__ __forceinline__ uint32_t prow() const { return (row<J>() * (uint32_t)L::B + J) * (uint32_t)nx; }
+  // first element of population j's own row
+  __device__ __forceinline__ uint32_t pown(int j) const { return (own_row() * (uint32_t)L::B + j) * (uint32_t)nx; }
+  // element of the source of population J for node ix (periodic in x)
+  template <int J>
+  __device__ __forceinline__ uint32_t src(int ix) const { return prow<J>() + (uint32_t)wrap(ix - L::EX[J], nx); }
+  // node index (scalar fields) of the own node ix
+  __device__ __forceinline__ uint32_t node(int ix) const { return own_row() * (uint32_t)nx + (uint32_t)ix; }
+  // node index of the node ix shifted by s = +-1 along axis a
+  __device__ __forceinline__ uint32_t shifted(int ix, int a, int s) const {
+    uint32_t xi = (uint32_t)ix, yi = yo[M], zi = (L::D == 3 ? zo[M] : 0u);
+    if (a == 0) xi = (uint32_t)wrap(ix + s, nx);
+    if (a == 1) yi = yo[M - s];
+    if constexpr (L::D == 3) {
+      if (a == 2) zi = zo[M - s];
+    }
+    return (yi + zi) * (uint32_t)nx + xi;
+  }
+};
+
+// Vectors of VEC consecutive stored elements.  Loads start at any element
+// (alignment of one element: the pull shift), stores at own nodes are
+// aligned to the whole vector.
+template <class T, int VEC, int ALIGN>
+struct VecT {
+  typedef T type __attribute__((ext_vector_type(VEC), aligned(ALIGN)));
+};
+
+// Populations are streamed once per step: the step kernel's loads and
+// stores carry the nontemporal hint (MRTLB_NT=0 at build time turns it off).
+#ifndef MRTLB_NT
+#define MRTLB_NT 1
+#endif
+
+template <class T>
+__device__ __forceinline__ T gload_nt(const void* base, uint32_t byteoff) {
+  const MRTLB_GLOBAL char* p = (const MRTLB_GLOBAL char*)base;
+#if MRTLB_NT
+  return __builtin_nontemporal_load((const MRTLB_GLOBAL T*)(p + byteoff));
+#else
+  return *(const MRTLB_GLOBAL T*)(p + byteoff);
+#endif
+}
+
+template <class T>
+__device__ __forceinline__ void gstore_nt(void* base, uint32_t byteoff, T v) {
+  MRTLB_GLOBAL char* p = (MRTLB_GLOBAL char*)base;
+#if MRTLB_NT
+  __builtin_nontemporal_store(v, (MRTLB_GLOBAL T*)(p + byteoff));
+#else
+  *(MRTLB_GLOBAL T*)(p + byteoff) = v;
+#endif
+}
+
+template <int ST, int VEC>
+__device__ __forceinline__ void load_vec(const void* buf, uint32_t i, typename StoreT<ST>::T (&out)[VEC]) {
+  using T = typename StoreT<ST>::T;
+  if constexpr (VEC == 1) {
+    out[0] = gload_nt<T>(buf, i * (uint32_t)sizeof(T));
+  } else {
+    using V = typename VecT<T, VEC, sizeof(T)>::type;
+    const V v = gload_nt<V>(buf, i * (uint32_t)sizeof(T));
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) out[k] = v[k];
+  }
+}
+
+template <int ST, int VEC>
+__device__ __forceinline__ void store_vec(void* buf, uint32_t i, const typename StoreT<ST>::T (&in)[VEC]) {
+  using T = typename StoreT<ST>::T;
+  if constexpr (VEC == 1) {
+    gstore_nt<T>(buf, i * (uint32_t)sizeof(T), in[0]);
+  } else {
+    using V = typename VecT<T, VEC, VEC * sizeof(T)>::type;
+    V v;
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) v[k] = in[k];
+    gstore_nt<V>(buf, i * (uint32_t)sizeof(T), v);
+  }
+}
+
+template <int ST, class Real>
+__device__ __forceinline__ Real decode(typename StoreT<ST>::T v, const KParams<Real>& P, int j) {
+  if constexpr (ST == kFP16Dev) {
+    return (Real)(float)v * P.wsc[j];
+  } else if constexpr (ST == kBF16Dev) {
+    return (Real)bf16_to_f32(v) * P.wsc[j];
+  } else {
+    return (Real)v;
+  }
+}
+
+template <int ST, class Real>
+__device__ __forceinline__ typename StoreT<ST>::T encode(Real v, const KParams<Real>& P, int j) {
+  using T = typename StoreT<ST>::T;
+  if constexpr (ST == kFP16Dev) {
+    return (_Float16)(float)(v * P.iwsc[j]);
+  } else if constexpr (ST == kBF16Dev) {
+    return f32_to_bf16_rne((float)(v * P.iwsc[j]));
+  } else {
+    return (T)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// moments of a node
+// ---------------------------------------------------------------------------
+
+template <class Real>
+struct Moments {
+  Real R0;
+  Real m1[3], m2n[3], m2o[3], m3m[3][3], m3p[3], mxyz;
+};
+
+// Hermite moments (component rows, physical units) of x[0..B-1].
+template <class L, class Real>
+__device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Real>& P, Moments<Real>& M) {
+  constexpr int D = L::D;
+  Real R0 = x[0];
+  Real R1[3] = {0, 0, 0}, R2n[3] = {0, 0, 0}, R2o[3] = {0, 0, 0}, R3p[3] = {0, 0, 0};
+  Real R3m[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  Real Rxyz = 0;
+  static_for<0, n_pairs<L>()>([&](auto kk) {
+    constexpr int p = pair_first<L>(decltype(kk)::value);
+    constexpr int q = opposite<L>(p);
+    const Real s = x[p] + x[q];
+    const Real d = x[p] - x[q];
+    R0 += s;
+    static_for<0, D>([&](auto aa) {
+      constexpr int a = decltype(aa)::value;
+      constexpr int ea = evel<L>(p, a);
+      if constexpr (ea != 0) {
+        R1[a] += Real(ea) * d;
+        R2n[a] += Real(ea * ea) * s;
+        R3p[a] += Real(ea * ea * ea) * d;
+        static_for<0, D>([&](auto bb) {
+          constexpr int b = decltype(bb)::value;
+          constexpr int eb = evel<L>(p, b);
+          if constexpr (b != a && eb != 0) R3m[a][b] += Real(ea * eb * eb) * d;
+          if constexpr (b > a && eb != 0) R2o[off_index(a, b)] += Real(ea * eb) * s;
+        });
+      }
+    });
+    if constexpr (D == 3) {
+      constexpr int exyz = evel<L>(p, 0) * evel<L>(p, 1) * evel<L>(p, 2);
+      if constexpr (exyz != 0) Rxyz += Real(exyz) * d;
+    }
+  });
+  M.R0 = R0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    M.m1[a] = P.c1[a] * R1[a];
+    M.m2n[a] = P.c2[a] * R2n[a] - P.cs2 * R0;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a + 1; b < D; ++b) M.m2o[off_index(a, b)] = P.cab[off_index(a, b)] * R2o[off_index(a, b)];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    Real pure = P.c3[a] * R3p[a] - 3 * P.cs2 * M.m1[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == a) continue;
+      M.m3m[a][b] = P.cabb[a][b] * R3m[a][b] - P.cs2 * M.m1[a];
+      pure -= P.corr[a][b] * M.m3m[a][b];
+    }
+    M.m3p[a] = pure;
+  }
+  if constexpr (D == 3) M.mxyz = P.cxyz * Rxyz;
+}
+
+// Per-row coefficients delta_r = (target_r) / n_r turned into monomial
+// coefficients in lattice units, then evaluated per velocity pair:
+//   x_j <- kx * x_j + w_j * sum_P beta_P e_j^P
+template <class L, class Real>
+__device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P, Real kx, Real d0, const Real* d1,
+                                         const Real* d2n, const Real* d2o, const Real (*d3m)[3], const Real* d3p,
+                                         Real dxyz) {
+  constexpr int D = L::D;
+  Real b0 = d0;
+  Real b1[3], b2n[3], b2o[3], b3m[3][3], b3p[3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) b0 -= P.cs2 * d2n[a];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    Real t = d1[a] + P.k3[a] * d3p[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == a) continue;
+      t -= P.cs2 * d3m[a][b];
+      b3m[a][b] = P.cabb[a][b] * (d3m[a][b] - P.corr[a][b] * d3p[a]);
+    }
+    b1[a] = P.c1[a] * t;
+    b2n[a] = P.c2[a] * d2n[a];
+    b3p[a] = P.c3[a] * d3p[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a + 1; b < D; ++b) b2o[off_index(a, b)] = P.cab[off_index(a, b)] * d2o[off_index(a, b)];
+  Real bxyz = 0;
+  if constexpr (D == 3) bxyz = P.cxyz * dxyz;
+  x[0] = kx * x[0] + P.w[0] * b0;
+  static_for<0, n_pairs<L>()>([&](auto kk) {
+    constexpr int p = pair_first<L>(decltype(kk)::value);
+    constexpr int q = opposite<L>(p);
+    Real even = b0, odd = 0;
+    static_for<0, D>([&](auto aa) {
+      constexpr int a = decltype(aa)::value;
+      constexpr int ea = evel<L>(p, a);
+      if constexpr (ea != 0) {
+        even += Real(ea * ea) * b2n[a];
+        odd += Real(ea) * b1[a] + Real(ea * ea * ea) * b3p[a];
+        static_for<0, D>([&](auto bb) {
+          constexpr int b = decltype(bb)::value;
+          constexpr int eb = evel<L>(p, b);
+          if constexpr (b != a && eb != 0) odd += Real(ea * eb * eb) * b3m[a][b];
+          if constexpr (b > a && eb != 0) even += Real(ea * eb) * b2o[off_index(a, b)];
+        });
+      }
+    });
+    if constexpr (D == 3) {
+      constexpr int exyz = evel<L>(p, 0) * evel<L>(p, 1) * evel<L>(p, 2);
+      if constexpr (exyz != 0) odd += Real(exyz) * bxyz;
+    }
+    const Real wp = P.w[p];
+    x[p] = kx * x[p] + wp * (even + odd);
+    x[q] = kx * x[q] + wp * (even - odd);
+  });
+}
+
+// Equilibrium Hermite moments (orders 1..3) from the conserved variables.
+template <class L, class Real, int MODEL>
+struct Equilibrium {
+  Real e1[3], e2n[3], e2o[3], e3m[3][3], e3p[3], exyz;
+
+  // NSE: j = rho_m u (momentum incl. the half force), u = j / rho_m.
+  // NCDE: phi, u = advection velocity.
+  __device__ __forceinline__ void build(const KParams<Real>& P, Real rho_or_phi, const Real* j, const Real* u) {
+    constexpr int D = L::D;
+    if constexpr (MODEL == kNcde) {
+      const Real phi = rho_or_phi;
+      const Real Phi = P.phi_coef * (phi + P.D2 * phi * phi * phi * Real(1.0 / 3.0));
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        e1[a] = phi * u[a];
+        e2n[a] = P.cs2 * (Phi - phi) + e1[a] * u[a];
+        e3p[a] = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) e3m[a][b] = 0;
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a + 1; b < D; ++b) e2o[off_index(a, b)] = e1[a] * u[b];
+      exyz = 0;
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        e1[a] = j[a];
+        e2n[a] = j[a] * u[a];
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a + 1; b < D; ++b) e2o[off_index(a, b)] = j[a] * u[b];
+      // M30 = rho uuu (m30 = 1) or 0: a multiplier keeps this branch-free
+      const Real g30 = P.m30 ? Real(1) : Real(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        Real pure = e2n[a] * u[a];
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          if (b == a) continue;
+          e3m[a][b] = e2n[b] * u[a];  // rho u_a u_b^2
+          pure -= P.corr[a][b] * e3m[a][b];
+        }
+        e3p[a] = g30 * pure;
+#pragma unroll
+        for (int b = 0; b < D; ++b) e3m[a][b] *= g30;
+      }
+      exyz = 0;
+      if constexpr (D == 3) exyz = g30 * (j[0] * u[1] * u[2]);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// the fused collide-and-stream step
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t lin, uint32_t total) {
+  // Workgroups are dealt to the XCDs round-robin; give every XCD a
+  // contiguous range of tiles so that neighbouring tiles (which share
+  // partially-read cache lines and halo rows) meet in the same L2.
+  const uint32_t q = total / kNumXcd;
+  if (lin >= q * kNumXcd) return lin;
+  return (lin % kNumXcd) * q + lin / kNumXcd;
+}
+
+template <class Real>
+__device__ __forceinline__ int find_job(const Job<Real>* jobs, int njobs, uint32_t lin) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_begin <= lin) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Tile of a step workgroup: (1 << bx_shift) threads along x, each owning VEC
+// consecutive nodes, times (kBlock >> bx_shift) rows.
+template <int VEC, class Real>
+__device__ __forceinline__ bool tile_node(const Job<Real>& J, uint32_t local, int& ix0, int& iy, int& iz) {
+  const int bxs = J.bx_shift;
+  const int rows = kBlock >> bxs;
+  const uint32_t tx = local % (uint32_t)J.gx;
+  const uint32_t rg = local / (uint32_t)J.gx;
+  const int ny = J.P.ny;
+  const uint32_t rgy = (uint32_t)((ny + rows - 1) / rows);
+  const int tid = threadIdx.x;
+  ix0 = ((int)(tx << bxs) + (tid & ((1 << bxs) - 1))) * VEC;
+  iy = (int)(rg % rgy) * rows + (tid >> bxs);
+  iz = (int)(rg / rgy);
+  return ix0 < J.P.nx && iy < ny;
+}
+
+// One node of the method after the gather: a2-a7 in registers.
+// x[] holds the pre-collision populations on entry, post-collision on exit.
+template <class L, int ST, int MODEL, bool FORCE>
+__device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B],
+                                             const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix) {
+  using Real = typename StoreT<ST>::Real;
+  constexpr int D = L::D;
+  const KParams<Real>& P = J.P;
+  const uint32_t self = g.node(ix);
+  const uint32_t N = P.N;
+
+  // a3: forward Hermite moments
+  Moments<Real> M;
+  forward<L>(x, P, M);
+
+  // a2: conserved variables, a5: sources
+  Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
+  Real u[3] = {0, 0, 0}, jm[3] = {0, 0, 0};
+  const Real R = M.R0 + P.rho_ref;
+  if constexpr (MODEL == kNcde) {
+    const Real phi_prev = gload<Real>(J.phi_prev, self * (uint32_t)sizeof(Real));
+    Real adv = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      u[a] = P.adv[a];
+      const Real grad = (gload<Real>(J.phi_prev, g.shifted(ix, a, 1) * (uint32_t)sizeof(Real)) -
+                         gload<Real>(J.phi_prev, g.shifted(ix, a, -1) * (uint32_t)sizeof(Real))) /
+                        (2 * P.c1[a]);
+      adv += u[a] * grad;
+    }
+    const Real scal = (R - phi_prev) + adv;
+#pragma unroll
+    for (int a = 0; a < D; ++a) src1[a] = u[a] * scal;
+    gstore<Real>(J.phi_out, self * (uint32_t)sizeof(Real), R);
+  } else {
+    if constexpr (FORCE) {
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        F[a] = gload<Real>(static_cast<const char*>(static_cast<const void*>(J.force)) + (size_t)a * N * sizeof(Real),
+                           self * (uint32_t)sizeof(Real));
+    }
+    const Real rho_m = P.inc ? P.rho0 : R;
+    const Real inv = Real(1) / rho_m;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      jm[a] = M.m1[a] + Real(0.5) * F[a];
+      u[a] = jm[a] * inv;
+      src1[a] = F[a];
+    }
+    if constexpr (FORCE) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) T2n[a] = 2 * u[a] * F[a];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a + 1; b < D; ++b) T2o[off_index(a, b)] = u[a] * F[b] + u[b] * F[a];
+    }
+  }
+
+  // a4: equilibrium moments
+  Equilibrium<L, Real, MODEL> E;
+  E.build(P, R, jm, u);
+
+  // a6: relaxation; targets t_r = m*_r - (1 - s_h) m_r, scaled by 1/n_r
+  const Real kx = Real(1) - P.sh;
+  Real d1[3], d2n[3], d2o[3], d3m[3][3], d3p[3], dxyz = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const Real ms = M.m1[a] - P.s1 * (M.m1[a] - E.e1[a]) + (Real(1) - Real(0.5) * P.s1) * src1[a];
+    d1[a] = (ms - kx * M.m1[a]) * P.in1[a];
+  }
+  {
+    Real neq[3], tn = 0, tT = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      neq[a] = M.m2n[a] - E.e2n[a];
+      tn += neq[a];
+      tT += T2n[a];
+    }
+    tn *= Real(1.0 / D);
+    tT *= Real(1.0 / D);
+    const Real kb = Real(1) - P.sb, ks = Real(1) - P.ss;
+    const Real gb = Real(1) - Real(0.5) * P.sb, gs = Real(1) - Real(0.5) * P.ss;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const Real ms = E.e2n[a] + kb * tn + ks * (neq[a] - tn) + gb * tT + gs * (T2n[a] - tT);
+      d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = a + 1; b < D; ++b) {
+        const int o = off_index(a, b);
+        const Real ms = E.e2o[o] + ks * (M.m2o[o] - E.e2o[o]) + gs * T2o[o];
+        d2o[o] = (ms - kx * M.m2o[o]) * P.in2o[o];
+      }
+  }
+  {
+    const Real k3 = Real(1) - P.s3;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      d3p[a] = (E.e3p[a] + k3 * (M.m3p[a] - E.e3p[a]) - kx * M.m3p[a]) * P.in3p[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        if (b == a) continue;
+        d3m[a][b] = (E.e3m[a][b] + k3 * (M.m3m[a][b] - E.e3m[a][b]) - kx * M.m3m[a][b]) * P.in3m[a][b];
+      }
+    }
+    if constexpr (D == 3) dxyz = (E.exyz + k3 * (M.mxyz - E.exyz) - kx * M.mxyz) * P.inxyz;
+  }
+  // order 0 is conserved: m*_0 = m_0
+  const Real d0 = P.sh * M.R0 * P.in0;
+
+  // a7: back to populations
+  backward<L>(x, P, kx, d0, d1, d2n, d2o, d3m, d3p, dxyz);
+}
+
+// ---------------------------------------------------------------------------
+// the fused collide-and-stream step: every thread owns VEC consecutive nodes
+// along x.  a1: each population is gathered with one VEC-wide load from the
+// row of x - e_j (element-aligned: the pull shift); at the periodic x-edges
+// the wrapped elements are loaded one by one.  a8: VEC-wide aligned stores at
+// the own nodes.
+// ---------------------------------------------------------------------------
+
+template <class L, int ST, int MODEL, bool FORCE, int VEC>
+__global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::Real>* __restrict__ jobs, int njobs,
+                                                uint32_t total_blocks) {
+  using Real = typename StoreT<ST>::Real;
+  using T = typename StoreT<ST>::T;
+  constexpr int B = L::B;
+  constexpr int M = L::MAXE;
+  const uint32_t lin = xcd_remap(blockIdx.x, total_blocks);
+  const int jb = njobs > 1 ? find_job(jobs, njobs, lin) : 0;
+  const Job<Real>& J = jobs[jb];
+  const KParams<Real>& P = J.P;
+  int ix0, iy, iz;
+  if (!tile_node<VEC>(J, lin - J.block_begin, ix0, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.ny, P.nz);
+  const uint32_t N = P.N;
+
+  // a1: gather along -e_j
+  T raw[B][VEC];
+  const bool interior = ix0 >= M && ix0 + VEC - 1 + M < P.nx;
+  if (interior) {
+    static_for<0, B>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      load_vec<ST, VEC>(J.fin, g.template prow<j>() + (uint32_t)(ix0 - L::EX[j]), raw[j]);
+    });
+  } else {
+    static_for<0, B>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) {
+        T one[1];
+        load_vec<ST, 1>(J.fin, g.template src<j>(ix0 + k), one);
+        raw[j][k] = one[0];
+      }
+    });
+  }
+
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) {
+    Real x[B];
+    static_for<0, B>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      x[j] = decode<ST>(raw[j][k], P, j);
+    });
+    collide_node<L, ST, MODEL, FORCE>(x, J, g, ix0 + k);
+    static_for<0, B>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      raw[j][k] = encode<ST>(x[j], P, j);
+    });
+  }
+
+  // a8: store at the own nodes
+  static_for<0, B>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    store_vec<ST, VEC>(J.fout, g.pown(j) + (uint32_t)ix0, raw[j]);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// initialisation, read-out and restore: one thread per node (1D over nodes),
+// computed in FP64 regardless of the storage.
+// ---------------------------------------------------------------------------
+
+template <class L>
+__device__ __forceinline__ bool node_of_thread(const KParams<double>& P, int& ix, int& iy, int& iz) {
+  const uint32_t n = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+  if (n >= P.N) return false;
+  const uint32_t nx = (uint32_t)P.nx, ny = (uint32_t)P.ny;
+  ix = (int)(n % nx);
+  iy = (int)((n / nx) % ny);
+  iz = (int)(n / (nx * ny));
+  return true;
+}
+
+// f_bar(x,0) = f_eq - F/2, written at x - e_j (inverse of the pull gather).
+template <class L, int ST, int MODEL>
+__global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                const KParams<double>* __restrict__ PD, const double* __restrict__ rho,
+                                                const double* __restrict__ uin, const double* __restrict__ fin,
+                                                uint32_t total_blocks) {
+  using Real = typename StoreT<ST>::Real;
+  constexpr int B = L::B, D = L::D;
+  const Job<Real>& J = jobs[0];
+  const KParams<double>& P = *PD;
+  int ix, iy, iz;
+  if (!node_of_thread<L>(P, ix, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.ny, P.nz);
+  const uint32_t self = g.node(ix);
+  const uint32_t N = P.N;
+  const double R = rho[self];
+  double u[3] = {0, 0, 0}, jm[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+  if constexpr (MODEL == kNcde) {
+    for (int a = 0; a < D; ++a) u[a] = P.adv[a];
+    static_cast<Real*>(J.phi_out)[self] = (Real)R;
+    const_cast<Real*>(J.phi_prev)[self] = (Real)R;
+  } else {
+    const double rho_m = P.inc ? P.rho0 : R;
+    for (int a = 0; a < D; ++a) {
+      u[a] = uin[(size_t)a * N + self];
+      jm[a] = rho_m * u[a];
+      if (fin) F[a] = fin[(size_t)a * N + self];
+    }
+  }
+  Equilibrium<L, double, MODEL> E;
+  E.build(P, R, jm, u);
+  double d1[3], d2n[3], d2o[3], d3m[3][3], d3p[3], dxyz = 0;
+  for (int a = 0; a < D; ++a) {
+    d1[a] = (E.e1[a] - 0.5 * F[a]) * P.in1[a];
+    d2n[a] = E.e2n[a] * P.in2n[a];
+    d3p[a] = E.e3p[a] * P.in3p[a];
+    for (int b = 0; b < D; ++b)
+      if (b != a) d3m[a][b] = E.e3m[a][b] * P.in3m[a][b];
+    for (int b = a + 1; b < D; ++b) d2o[off_index(a, b)] = E.e2o[off_index(a, b)] * P.in2o[off_index(a, b)];
+  }
+  if constexpr (D == 3) dxyz = E.exyz * P.inxyz;
+  double x[B];
+  for (int j = 0; j < B; ++j) x[j] = 0;
+  const double d0 = R * P.in0 - P.rho_ref;
+  backward<L>(x, P, 0.0, d0, d1, d2n, d2o, d3m, d3p, dxyz);
+  const KParams<Real>& PR = J.P;
+  static_for<0, B>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    // buf_j(x - e_j) = f_bar_j(x): the source index of the pull gather
+    store_pop<ST>(J.fout, g.template src<j>(ix), (Real)x[j], PR, j);
+  });
+}
+
+// read-out: gather f_bar(x, t) and compute moments (WHAT 0) or copy the
+// populations (WHAT 1)
+template <class L, int ST, int MODEL, int WHAT>
+__global__ __launch_bounds__(kBlock) void k_gather(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                  const KParams<double>* __restrict__ PD, double* __restrict__ out0,
+                                                  double* __restrict__ out1) {
+  constexpr int B = L::B, D = L::D;
+  const auto& J = jobs[0];
+  const KParams<double>& P = *PD;
+  int ix, iy, iz;
+  if (!node_of_thread<L>(P, ix, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.ny, P.nz);
+  const uint32_t self = g.node(ix);
+  const uint32_t N = P.N;
+  double x[B];
+  static_for<0, B>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    x[j] = (double)load_pop<ST>(J.fin, g.template src<j>(ix), J.P, j);
+  });
+  if constexpr (WHAT == 1) {
+    for (int j = 0; j < B; ++j) out0[(size_t)j * N + self] = x[j] + P.w[j] * P.rho_ref;
+  } else {
+    double R = 0, m1[3] = {0, 0, 0};
+    static_for<0, B>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      R += x[j];
+      static_for<0, D>([&](auto aa) {
+        constexpr int a = decltype(aa)::value;
+        if constexpr (evel<L>(j, a) != 0) m1[a] += double(evel<L>(j, a)) * x[j];
+      });
+    });
+    R += P.rho_ref;
+    out0[self] = R;
+    if (out1) {
+      if constexpr (MODEL == kNcde) {
+        for (int a = 0; a < D; ++a) out1[(size_t)a * N + self] = P.adv[a];
+      } else {
+        const double rho_m = P.inc ? P.rho0 : R;
+        for (int a = 0; a < D; ++a) {
+          double jmom = P.c1[a] * m1[a];
+          if (J.force) jmom += 0.5 * (double)J.force[(size_t)a * N + self];
+          out1[(size_t)a * N + self] = jmom / rho_m;
+        }
+      }
+    }
+  }
+}
+
+// Restore: buf_j(x - e_j) = f_bar_j(x) - w_j rho_ref.
+template <class L, int ST>
+__global__ __launch_bounds__(kBlock) void k_scatter(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                   const KParams<double>* __restrict__ PD, const double* __restrict__ in) {
+  using Real = typename StoreT<ST>::Real;
+  constexpr int B = L::B;
+  const Job<Real>& J = jobs[0];
+  const KParams<double>& P = *PD;
+  int ix, iy, iz;
+  if (!node_of_thread<L>(P, ix, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.ny, P.nz);
+  const uint32_t self = g.node(ix);
+  const uint32_t N = P.N;
+  static_for<0, B>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    const double v = in[(size_t)j * N + self] - P.w[j] * P.rho_ref;
+    store_pop<ST>(J.fout, g.template src<j>(ix), (Real)v, J.P, j);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// FP64 plane sums (conserved quantities): partial[plane][chunk] over chunks
+// of kBlock * kChunkIters elements, wavefront shuffles then a fixed LDS tree.
+// ---------------------------------------------------------------------------
+
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_plane_sums(const void* __restrict__ base, uint32_t N, int nplanes_pop,
+                                                      const typename StoreT<ST>::Real* __restrict__ force, int nforce,
+                                                      const KParams<typename StoreT<ST>::Real>* __restrict__ PR,
+                                                      double* __restrict__ partial, uint32_t nchunks) {
+  using Real = typename StoreT<ST>::Real;
+  using T = typename StoreT<ST>::T;
+  const uint32_t chunk = blockIdx.x;
+  const int plane = blockIdx.y;
+  const uint32_t begin = chunk * (uint32_t)(kBlock * kChunkIters);
+  double acc = 0;
+  for (int it = 0; it < kChunkIters; ++it) {
+    const uint32_t i = begin + (uint32_t)it * kBlock + threadIdx.x;
+    if (i < N) {
+      if (plane < nplanes_pop) {
+        const uint32_t nx = (uint32_t)PR->nx;
+        const uint32_t e = ((i / nx) * (uint32_t)nplanes_pop + (uint32_t)plane) * nx + i % nx;
+        acc += (double)load_pop<ST>(base, e, *PR, plane);
+      } else {
+        acc += (double)force[(size_t)(plane - nplanes_pop) * N + i];
+      }
+    }
+  }
+  // wavefront reduction (64 lanes), fixed butterfly order
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  __shared__ double red[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int k = 0; k < kBlock / 64; ++k) s += red[k];
+    partial[(size_t)plane * nchunks + chunk] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers for one lattice
+// ---------------------------------------------------------------------------
+
+template <class F>
+inline bool with_storage(int st, F&& f) {
+  switch (st) {
+    case kFP64: f(std::integral_constant<int, kFP64>{}); return true;
+    case kFP32: f(std::integral_constant<int, kFP32>{}); return true;
+    case kFP32Dev: f(std::integral_constant<int, kFP32Dev>{}); return true;
+    case kFP16Dev: f(std::integral_constant<int, kFP16Dev>{}); return true;
+    case kBF16Dev: f(std::integral_constant<int, kBF16Dev>{}); return true;
+  }
+  return false;
+}
+
+// The NCDE kernels are instantiated for the 2D lattices only.
+template <class L>
+hipError_t launch_lattice(const LaunchReq& r) {
+  hipError_t err = hipErrorInvalidValue;
+  const dim3 grid(r.blocks), block(kBlock);
+  with_storage(r.storage, [&](auto stc) {
+    constexpr int ST = decltype(stc)::value;
+    using Real = typename StoreT<ST>::Real;
+    const auto* J = static_cast<const Job<Real>*>(r.jobs);
+    const auto* PD = static_cast<const KParams<double>*>(r.pd);
+    const bool ncde = r.model == kNcde;
+    if (ncde && L::D != 2) return;
+    switch (r.op) {
+      case kOpStep: {
+        auto step = [&](auto vc) {
+          constexpr int V = decltype(vc)::value;
+          if (ncde) {
+            if constexpr (L::D == 2)
+              hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+          } else if (r.force) {
+            hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+          } else {
+            hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+          }
+        };
+        if (r.vec == 4) step(std::integral_constant<int, 4>{});
+        else if (r.vec == 2) step(std::integral_constant<int, 2>{});
+        else step(std::integral_constant<int, 1>{});
+        break;
+      }
+      case kOpInit:
+        if (ncde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kNcde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+        } else {
+          hipLaunchKernelGGL((k_init<L, ST, kNseComp>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+        }
+        break;
+      case kOpMoments:
+        if (ncde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kNcde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        } else {
+          hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        }
+        break;
+      case kOpPopulations:
+        hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 1>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        break;
+      case kOpScatter:
+        hipLaunchKernelGGL((k_scatter<L, ST>), grid, block, 0, r.stream, J, PD, r.in0);
+        break;
+      default:
+        return;
+    }
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+}  // namespace mrtlb

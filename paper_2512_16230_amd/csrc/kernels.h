@@ -11,6 +11,11 @@ constexpr int kMaxB = 53;
 constexpr int kBlock = 256;         // threads per workgroup of every node kernel
 constexpr int kNumXcd = 8;          // MI355X: 8 XCDs, workgroups dealt round-robin
 
+constexpr int kChunkIters = 16;    // elements per thread of one plane-sum chunk
+
+// Index of the off-diagonal pair (a, b), a < b: xy -> 0, xz -> 1, yz -> 2.
+constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
+
 enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4 };
 enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2 };
 
@@ -52,7 +57,8 @@ struct Job {
   uint32_t block_begin;     // first linear workgroup of this job
   uint32_t nblocks;
   int gx;                   // workgroups along x per row group
-  int bx_shift;             // log2 of the x-width of a workgroup tile (6, 7 or 8)
+  int bx_shift;             // log2 of the threads along x of a workgroup tile (6, 7 or 8)
+  int vec;                  // nodes per thread along x
   int nrowgroups;           // ceil(ny / rows per tile) * nz
 };
 

@@ -1,0 +1,40 @@
+// Host-side launch interface between the ABI layer and the per-lattice
+// translation units that instantiate the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mrtlb {
+
+enum LaunchOp { kOpStep = 0, kOpInit = 1, kOpMoments = 2, kOpPopulations = 3, kOpScatter = 4 };
+
+struct LaunchReq {
+  int op = kOpStep;
+  int storage = 0;
+  int model = 0;             // ModelKind
+  bool force = false;        // NSE with a body-force field
+  int vec = 1;               // step kernel: nodes per thread along x (1, 2, 4)
+  const void* jobs = nullptr;
+  int njobs = 1;
+  uint32_t blocks = 0;
+  hipStream_t stream = nullptr;
+  const void* pd = nullptr;  // device KParams<double>
+  const double* in0 = nullptr;   // init: rho_or_phi; scatter: populations
+  const double* in1 = nullptr;   // init: u
+  const double* in2 = nullptr;   // init: force
+  double* out0 = nullptr;        // gather: rho_or_phi or populations
+  double* out1 = nullptr;        // gather: u
+};
+
+hipError_t launch_rd2q25(const LaunchReq& r);
+hipError_t launch_rd2q13(const LaunchReq& r);
+hipError_t launch_rd3q53(const LaunchReq& r);
+hipError_t launch_rd3q33(const LaunchReq& r);
+
+// FP64 sums of every population plane (and force plane) in chunks.
+hipError_t launch_plane_sums(int storage, const void* base, uint32_t N, int npop, const void* force, int nforce,
+                             const void* params, double* partial, uint32_t nchunks, hipStream_t stream);
+
+}  // namespace mrtlb

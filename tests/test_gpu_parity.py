@@ -337,3 +337,21 @@ def test_full_size_sampled(ctx):
         assert np.abs(v[:, iy, ix] - uo[:, R, R]).max() < 1e-6 * 0.1 * np.sqrt(wl.card.cs2)
     # mass is conserved to FP32 storage rounding
     assert abs(m_after - wl.rho_or_phi.sum()) < 1e-6 * wl.rho_or_phi.sum()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16_dev", "fp64"])
+def test_launch_shape_invariance(ctx, storage, monkeypatch):
+    """1, 2 or 4 nodes per thread change only the memory access pattern of
+    the step kernel: results are bit-identical (and match the oracle)."""
+    card = W.Q25_RECT
+    rates = W.rates_tau(0.7)
+    shape = (24, 136)           # 136 = 4 * 34: every width is usable
+    rho, u = _random_fields(card, shape, 19)
+    outs = []
+    for v in ("1", "2", "4"):
+        monkeypatch.setenv("MRTLB_STEP_VEC", v)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NSE_COMP", rates), shape, storage)
+        s.init_fields(rho, u)
+        s.step(9)
+        outs.append(s.read_populations())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
