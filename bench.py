@@ -35,7 +35,7 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_dev": "f32", "fp16_dev": "f32 (fp16
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("mrtlb.hip", "kernels.h", "lattices.h"):
+    for name in ("device.h", "kernels.h", "lattices.h", "launch.h", "abi.hip"):
         with open(os.path.join(ROOT, "paper_2512_16230_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -54,7 +54,7 @@ def measured_traffic(storage, launch_bytes):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(sample_shape=(512, 512), steps=30):
+def cpu_baseline(sample_shape=(512, 512), steps=200):
     """The FP64 oracle on a bounded sample of the same workload."""
     from oracle import lattice as OL
     from oracle import model as OM

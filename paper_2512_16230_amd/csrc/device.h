@@ -102,33 +102,6 @@ __device__ __forceinline__ void gstore(void* base, uint32_t byteoff, T v) {
   *(MRTLB_GLOBAL T*)(p + byteoff) = v;
 }
 
-template <int ST, class Real>
-__device__ __forceinline__ Real load_pop(const void* plane, uint32_t i, const KParams<Real>& P, int j) {
-  using T = typename StoreT<ST>::T;
-  const T v = gload<T>(plane, i * (uint32_t)sizeof(T));
-  if constexpr (ST == kFP16Dev) {
-    return (Real)(float)v * P.wsc[j];
-  } else if constexpr (ST == kBF16Dev) {
-    return (Real)bf16_to_f32(v) * P.wsc[j];
-  } else {
-    return (Real)v;
-  }
-}
-
-template <int ST, class Real>
-__device__ __forceinline__ void store_pop(void* plane, uint32_t i, Real v, const KParams<Real>& P, int j) {
-  using T = typename StoreT<ST>::T;
-  T out;
-  if constexpr (ST == kFP16Dev) {
-    out = (_Float16)(float)(v * P.iwsc[j]);
-  } else if constexpr (ST == kBF16Dev) {
-    out = f32_to_bf16_rne((float)(v * P.iwsc[j]));
-  } else {
-    out = (T)v;
-  }
-  gstore<T>(plane, i * (uint32_t)sizeof(T), out);
-}
-
 // ---------------------------------------------------------------------------
 // node geometry: wrapped row offsets for -MAXE..MAXE along y and z
 // ---------------------------------------------------------------------------
@@ -245,12 +218,23 @@ __device__ __forceinline__ void store_vec(void* buf, uint32_t i, const typename 
   }
 }
 
+// Storage conversions are never fused with neighbouring arithmetic: the
+// scaled value is rounded to FP32 first, then RNE to the 16-bit format,
+// whatever code shape the compiler picks for the surrounding kernel (LLVM
+// otherwise turns fptrunc(fmul) into a single-rounding v_fma_mixlo_f16 in
+// some unrollings and not in others).  pin() is an empty asm statement that
+// makes its operand an opaque FP32 register value.
+__device__ __forceinline__ float pin(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <int ST, class Real>
 __device__ __forceinline__ Real decode(typename StoreT<ST>::T v, const KParams<Real>& P, int j) {
   if constexpr (ST == kFP16Dev) {
-    return (Real)(float)v * P.wsc[j];
+    return (Real)pin((float)v * (float)P.wsc[j]);
   } else if constexpr (ST == kBF16Dev) {
-    return (Real)bf16_to_f32(v) * P.wsc[j];
+    return (Real)pin(bf16_to_f32(v) * (float)P.wsc[j]);
   } else {
     return (Real)v;
   }
@@ -260,12 +244,24 @@ template <int ST, class Real>
 __device__ __forceinline__ typename StoreT<ST>::T encode(Real v, const KParams<Real>& P, int j) {
   using T = typename StoreT<ST>::T;
   if constexpr (ST == kFP16Dev) {
-    return (_Float16)(float)(v * P.iwsc[j]);
+    return (_Float16)pin((float)v * (float)P.iwsc[j]);
   } else if constexpr (ST == kBF16Dev) {
-    return f32_to_bf16_rne((float)(v * P.iwsc[j]));
+    return f32_to_bf16_rne(pin((float)v * (float)P.iwsc[j]));
   } else {
     return (T)v;
   }
+}
+
+template <int ST, class Real>
+__device__ __forceinline__ Real load_pop(const void* buf, uint32_t i, const KParams<Real>& P, int j) {
+  using T = typename StoreT<ST>::T;
+  return decode<ST>(gload<T>(buf, i * (uint32_t)sizeof(T)), P, j);
+}
+
+template <int ST, class Real>
+__device__ __forceinline__ void store_pop(void* buf, uint32_t i, Real v, const KParams<Real>& P, int j) {
+  using T = typename StoreT<ST>::T;
+  gstore<T>(buf, i * (uint32_t)sizeof(T), encode<ST>(v, P, j));
 }
 
 // ---------------------------------------------------------------------------
