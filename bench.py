@@ -99,6 +99,84 @@ def copy_probe(torch, dev, steps, warmup):
                       "GB_per_s": round(2 * 4 * n / ms / 1e6, 1)}), flush=True)
 
 
+def _line(metric, value, unit, args, wall, workload_cfg, storage, launch_bytes, per_launch_s, peak=HBM_PEAK_GBS):
+    achieved = launch_bytes / per_launch_s / 1e9
+    return {"metric": metric, "value": round(value, 1), "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[storage], "data": "synthetic",
+            "config": workload_cfg,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
+                         "frac": round(achieved / peak, 4), "traffic": None,
+                         "kernel_ms_per_launch": round(per_launch_s * 1e3, 5),
+                         "algorithmic_bytes_per_launch": launch_bytes}}
+
+
+def bench_tgv3d(torch, H, W, stream, args):
+    """rD3Q53 (1 : 1.25 : 1.5) compressible isothermal 3D Taylor-Green, 256^3."""
+    n = args.size if args.size != 4096 else 256
+    shape = (n, n, n)
+    card3 = W.Q53_RECT if args.lattice3d == "rD3Q53" else W.Q33_CUBIC
+    wl = W.tgv3d(shape=shape, steps=args.steps, card=card3)
+    card, r = wl.card, wl.rates
+    ctx = H.Context(0, stream=stream.cuda_stream)
+    lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
+    md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h)
+    s = H.Solve(ctx, lat, md, shape, args.storage)
+    s.init_fields(wl.rho_or_phi, wl.u)
+    del wl
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = s.step_timed(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nodes = n ** 3
+    bq = 53 if card.kind == "rD3Q53" else 33
+    launch_bytes = 2 * bq * STORE_BYTES[args.storage] * nodes
+    out = _line("%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline" % card.kind,
+                nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
+                {"workload": "tgv3d-%s-%dx%dx%d" % (card.kind, n, n, n), "lattice": card.kind,
+                                      "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes},
+                args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
+    s.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_ncde_batch(torch, H, W, stream, args):
+    """256 rD2Q13 NCDE solves, sides log-uniform in [128, 1024], one launch per step."""
+    wls = W.ncde_batch(256, steps=args.steps)
+    ctx = H.Context(0, stream=stream.cuda_stream)
+    card = wls[0].card
+    lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
+    solves = []
+    for wl in wls:
+        r = wl.rates
+        md = H.model_desc("NCDE", s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
+                          D0=wl.D0, D2=wl.D2, adv_u=wl.adv_u)
+        s = H.Solve(ctx, lat, md, wl.shape, args.storage)
+        s.init_fields(wl.rho_or_phi)
+        solves.append(s)
+    nodes = sum(w.shape[0] * w.shape[1] for w in wls)
+    del wls
+    H.batch_step(solves, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.batch_step(solves, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    real = 8 if args.storage == "fp64" else 4
+    launch_bytes = (2 * 13 * STORE_BYTES[args.storage] + 2 * real) * nodes
+    out = _line("rD2Q13 NCDE batch MLUPS (256 solves, one launch per step), % of HBM roofline",
+                nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
+                {"workload": "ncde-batch-rD2Q13-256-solves", "lattice": "rD2Q13", "storage": args.storage,
+                 "nodes": nodes, "solves": len(solves)}, args.storage, launch_bytes, wall / args.steps)
+    for s in solves:
+        s.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +185,11 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=sorted(STORE_BYTES))
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="tgv2d", choices=["tgv2d", "tgv3d", "ncde-batch"],
+                    help="tgv2d: rD2Q25 4096^2 (default); tgv3d: rD3Q53 256^3 compressible; "
+                         "ncde-batch: 256 rD2Q13 NCDE solves advanced by one batched launch per step")
+    ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q33"],
+                    help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of 2 x 1.68 GB instead (HBM reference and counter calibration)")
     args = ap.parse_args()
@@ -126,6 +209,10 @@ def main():
         copy_probe(torch, dev, args.steps, args.warmup)
         return
     stream = torch.cuda.current_stream(dev)
+    if args.workload == "tgv3d":
+        return bench_tgv3d(torch, H, W, stream, args)
+    if args.workload == "ncde-batch":
+        return bench_ncde_batch(torch, H, W, stream, args)
     shape = (args.size, args.size)
     wl = W.tgv_large(0, shape=shape, steps=args.steps)
     card, r = wl.card, wl.rates

@@ -89,14 +89,16 @@ static size_t elem_bytes(int storage) {
 }
 static int lattice_maxe(int kind) { return kind == kRD2Q25 ? 3 : 2; }
 
-// Nodes per thread of the step kernel: two consecutive x-nodes, i.e. 8-byte
-// (FP32), 16-byte (FP64) or 4-byte (16-bit) vector accesses per population;
-// one node when nx is odd or small.  Measured on rD2Q25 4096^2: two nodes
-// per thread match four for FP32 and beat it for FP16 (lower register
-// pressure).  MRTLB_STEP_VEC (1, 2 or 4) overrides it for tuning runs.
-static int pick_vec(int storage, int nx) {
+// Nodes per thread of the step kernel: two consecutive x-nodes on the 2D
+// lattices, i.e. 8-byte (FP32), 16-byte (FP64) or 4-byte (16-bit) vector
+// accesses per population, and one node on the 3D lattices (b = 33, 53:
+// two nodes double a register file that already limits occupancy); one
+// node when nx is odd or small.  Measured: rD2Q25 4096^2 two nodes match
+// four (FP32) and beat it (FP16); rD3Q53 256^3 one node beats two by 7%.
+// MRTLB_STEP_VEC (1, 2 or 4) overrides it for tuning runs.
+static int pick_vec(int storage, int kind, int nx) {
   (void)storage;
-  int v = 2;
+  int v = (kind == kRD3Q53 || kind == kRD3Q33) ? 1 : 2;
   if (const char* e = std::getenv("MRTLB_STEP_VEC")) {
     const int o = std::atoi(e);
     if (o == 1 || o == 2 || o == 4) v = o;
@@ -383,9 +385,20 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   // step tile: each thread owns vec consecutive x-nodes (vector loads and
   // stores of 8-16 bytes per lane); 64/128/256 threads along x per
   // workgroup of 256 threads
-  s->vec = pick_vec(storage, s->nx);
+  s->vec = pick_vec(storage, s->L.kind, s->nx);
   const int tx = s->nx / s->vec;
-  s->bx_shift = tx > 128 ? 8 : (tx > 64 ? 7 : 6);
+  // threads along x per workgroup: the width (64, 128, 256) that leaves the
+  // fewest idle lanes across a row, the widest on ties
+  s->bx_shift = 8;
+  int best = 1 << 30;
+  for (int b = 8; b >= 6; --b) {
+    const int w = 1 << b;
+    const int idle = ((tx + w - 1) / w) * w - tx;
+    if (idle < best) {
+      best = idle;
+      s->bx_shift = b;
+    }
+  }
   const int rows = kBlock >> s->bx_shift;
   s->gx = (tx + (1 << s->bx_shift) - 1) >> s->bx_shift;
   s->nrowgroups = ((s->ny + rows - 1) / rows) * s->nz;
