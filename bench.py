@@ -177,6 +177,39 @@ def bench_ncde_batch(torch, H, W, stream, args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(stream, args):
+    """Served stream: Poisson arrivals mixing rD2Q25 NSE (64^2-2048^2), rD2Q13
+    NCDE (128^2-1024^2) and rD3Q33 NSE with body force (32^3-128^3), 200-2000
+    steps, 16-bit deviation storage; continuous batching."""
+    from paper_2512_16230_amd import serving as S
+
+    storage = args.storage if args.storage != "fp32" else "bf16_dev"
+    reqs = S.request_stream(args.requests, args.rate, seed=0, storage=storage)
+    ex = S.GpuExecutor(stream=stream.cuda_stream)
+    warm = S.request_stream(6, 1000.0, seed=99, storage=storage, steps=(10, 20), q25=(64, 128), q13=(128, 160),
+                            q33=(24, 32))
+    S.Server(ex).run(warm)
+    st = S.Server(ex).run(reqs)
+    ex.close()
+    s = st.summary()
+    work = sum(r.nodes * r.steps for r in st.results if r.error is None)
+    window = reqs[-1].arrival - reqs[0].arrival
+    busy_rate = s["mlups"] * 1e6
+    out = {"metric": "served-batch latency p50/p99 (continuous batching) and aggregate MLUPS",
+           "value": round(s["p99_s"] * 1e3, 2), "unit": "ms (p99)", "n_gpus": 1, "steps": None, "warmup": None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[storage],
+           "data": "synthetic",
+           "config": {"workload": "served-stream-rD2Q25-rD2Q13-rD3Q33", "rate_per_s": args.rate,
+                      "requests": args.requests, "storage": storage},
+           "p50_ms": round(s["p50_s"] * 1e3, 2), "p99_ms": round(s["p99_s"] * 1e3, 2),
+           "mean_ms": round(s["mean_s"] * 1e3, 2), "aggregate_mlups": round(s["mlups"], 1),
+           "wall_s": round(s["wall_s"], 3), "arrival_window_s": round(window, 3),
+           "offered_load_vs_measured_capacity": round(work / busy_rate / window, 3) if window > 0 else None,
+           "max_resident": s["max_resident"], "failed": s["failed"],
+           "host_split_s": {k: round(s[k], 3) for k in ("t_create_s", "t_step_s", "t_read_s", "t_wait_s")}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,9 +218,11 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=sorted(STORE_BYTES))
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tgv2d", choices=["tgv2d", "tgv3d", "ncde-batch"],
+    ap.add_argument("--workload", default="tgv2d", choices=["tgv2d", "tgv3d", "ncde-batch", "serve"],
                     help="tgv2d: rD2Q25 4096^2 (default); tgv3d: rD3Q53 256^3 compressible; "
                          "ncde-batch: 256 rD2Q13 NCDE solves advanced by one batched launch per step")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--requests", type=int, default=300, help="serve: requests in the measured window")
     ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q33"],
                     help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -213,6 +248,8 @@ def main():
         return bench_tgv3d(torch, H, W, stream, args)
     if args.workload == "ncde-batch":
         return bench_ncde_batch(torch, H, W, stream, args)
+    if args.workload == "serve":
+        return bench_serve(stream, args)
     shape = (args.size, args.size)
     wl = W.tgv_large(0, shape=shape, steps=args.steps)
     card, r = wl.card, wl.rates

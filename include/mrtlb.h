@@ -183,11 +183,13 @@ mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);
  * events recorded on the context stream around the launches (synchronous). */
 mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms);
 
-/* Advance every solve of the array by nsteps, with one kernel launch per
- * step for each group of solves that share lattice, model and storage.
- * Solves must belong to the same context.  Each solve's result equals
- * mrtlb_step on it alone, bit for bit. */
-mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, int64_t nsteps);
+/* Advance solve i of the array by nsteps[i] >= 0 steps.  Solves that share
+ * lattice, model, storage and force go into one kernel launch per step (the
+ * ones that have finished drop out of later launches); groups run one after
+ * the other on the context stream.  Solves must belong to the same context
+ * and appear once.  Each solve's result equals mrtlb_step on it alone, bit
+ * for bit.  Synchronous (returns when the steps have run). */
+mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* nsteps);
 
 /* rho_or_phi (N) and u (d*N, may be NULL) at the current time, eq. (2-4-2)
  * / (2-4-1): rho_bar = sum f_bar, u = (sum c f_bar + F/2)/rho_m.

@@ -78,7 +78,7 @@ def lib():
         "mrtlb_init_fields": (c_int, [c_void_p, _DP, _DP, _DP]),
         "mrtlb_step": (c_int, [c_void_p, c_int64]),
         "mrtlb_step_timed": (c_int, [c_void_p, c_int64, _DP]),
-        "mrtlb_batch_step": (c_int, [POINTER(c_void_p), c_int, c_int64]),
+        "mrtlb_batch_step": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int64)]),
         "mrtlb_read_moments": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_read_populations": (c_int, [c_void_p, _DP]),
@@ -301,5 +301,10 @@ class Solve:
 
 
 def batch_step(solves, nsteps):
-    arr = (c_void_p * len(solves))(*[s.h for s in solves])
-    _check(lib().mrtlb_batch_step(arr, len(solves), int(nsteps)))
+    """Advance solve i by nsteps[i] (or every solve by the same int)."""
+    n = len(solves)
+    if isinstance(nsteps, (int, np.integer)):
+        nsteps = [int(nsteps)] * n
+    arr = (c_void_p * n)(*[s.h for s in solves])
+    cnt = (c_int64 * n)(*[int(k) for k in nsteps])
+    _check(lib().mrtlb_batch_step(arr, n, cnt))

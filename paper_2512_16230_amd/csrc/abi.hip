@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -48,6 +49,11 @@ struct mrtlb_ctx {
   size_t budget = 0;
   size_t used = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // job tables of batched launches: a device buffer and its pinned host
+  // staging copy, grown on demand and reused (no allocation per call)
+  void* job_dev = nullptr;
+  void* job_host = nullptr;
+  size_t job_cap = 0;
 };
 
 struct mrtlb_lattice {
@@ -61,6 +67,7 @@ struct mrtlb_solve {
   int storage = 0;
   int has_force = 0;
   int nx = 1, ny = 1, nz = 1;
+  int nxp = 1;                  // population row pitch (elements)
   uint32_t N = 0;
   size_t bytes = 0;
   void* f[2] = {nullptr, nullptr};
@@ -72,7 +79,7 @@ struct mrtlb_solve {
   int64_t steps = 0;
   KParams<double> Pd{};
   KParams<float> Pf{};
-  int bx_shift = 8, gx = 1, nrowgroups = 1, vec = 1;
+  int vec = 1;
   uint32_t nblocks = 0;         // workgroups of one step launch
   uint32_t nblocks_node = 0;    // workgroups of the one-thread-per-node kernels
 };
@@ -89,16 +96,28 @@ static size_t elem_bytes(int storage) {
 }
 static int lattice_maxe(int kind) { return kind == kRD2Q25 ? 3 : 2; }
 
+// Population row pitch: nx rounded up to 32 nodes.  Rows start on a 32-element
+// boundary and the step kernel's wavefronts cover whole 32-node runs of a row
+// (128 B for FP32), so a wavefront access never straddles an extra cache line
+// whatever nx is.
+static int64_t row_pitch(int64_t nx, int storage) {
+  (void)storage;
+  return (nx + 31) / 32 * 32;
+}
+
 // Nodes per thread of the step kernel: two consecutive x-nodes on the 2D
-// lattices, i.e. 8-byte (FP32), 16-byte (FP64) or 4-byte (16-bit) vector
-// accesses per population, and one node on the 3D lattices (b = 33, 53:
-// two nodes double a register file that already limits occupancy); one
-// node when nx is odd or small.  Measured: rD2Q25 4096^2 two nodes match
-// four (FP32) and beat it (FP16); rD3Q53 256^3 one node beats two by 7%.
-// MRTLB_STEP_VEC (1, 2 or 4) overrides it for tuning runs.
+// lattices when rows hold at least 512 nodes, i.e. 8-byte (FP32), 16-byte
+// (FP64) or 4-byte (16-bit) vector accesses per population, and one node
+// otherwise.  With one node per lane the periodic wrap is a per-lane index,
+// so short rows (where every wavefront holds row-edge lanes) run no
+// divergent gather; the 3D lattices (b = 33, 53) stay at one node, where two
+// would double a register file that already limits occupancy.  Measured:
+// rD2Q25 4096^2 two nodes match four (FP32) and beat it (FP16); rD3Q53 256^3
+// one node beats two by 7%.  MRTLB_STEP_VEC (1, 2 or 4) overrides it for
+// tuning runs.
 static int pick_vec(int storage, int kind, int nx) {
   (void)storage;
-  int v = (kind == kRD3Q53 || kind == kRD3Q33) ? 1 : 2;
+  int v = (kind == kRD3Q53 || kind == kRD3Q33 || nx < 512) ? 1 : 2;
   if (const char* e = std::getenv("MRTLB_STEP_VEC")) {
     const int o = std::atoi(e);
     if (o == 1 || o == 2 || o == 4) v = o;
@@ -113,6 +132,7 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   const int D = L.D;
   std::memset(&P, 0, sizeof P);
   P.nx = s.nx; P.ny = s.ny; P.nz = s.nz; P.N = s.N;
+  P.nxp = s.nxp;
   P.inc = s.model.model == MRTLB_NSE_INC;
   P.m30 = s.model.m30 != 0;
   P.cs2 = (Real)L.cs2;
@@ -175,9 +195,6 @@ static Job<Real> make_job(const mrtlb_solve& s, int parity, const KParams<Real>&
   J.phi_out = static_cast<Real*>(s.phi[parity ^ 1]);
   J.block_begin = 0;
   J.nblocks = s.nblocks;
-  J.gx = s.gx;
-  J.bx_shift = s.bx_shift;
-  J.nrowgroups = s.nrowgroups;
   J.vec = s.vec;
   return J;
 }
@@ -251,6 +268,9 @@ mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx
 void mrtlb_ctx_destroy(mrtlb_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->job_dev) (void)hipFree(c->job_dev);
+  if (c->job_host) (void)hipHostFree(c->job_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
@@ -322,7 +342,8 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
   if (n[0] < 1 || n[1] < 1 || nz < 1) return fail(MRTLB_EINVAL, "grid sizes must be >= 1");
   const int64_t N = n[0] * n[1] * nz;
   const size_t real = is_double(storage) ? 8 : 4;
-  size_t b = 2 * (size_t)lat->L.B * (size_t)N * elem_bytes(storage);
+  const int64_t rows = N / n[0];
+  size_t b = 2 * (size_t)lat->L.B * (size_t)(rows * row_pitch(n[0], storage)) * elem_bytes(storage);
   if (has_force) b += (size_t)D * (size_t)N * real;
   if (model == MRTLB_NCDE) b += 2 * (size_t)N * real;
   b += 2 * sizeof(Job<double>) + sizeof(KParams<double>);
@@ -367,7 +388,8 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
     return fail(MRTLB_EINVAL, "every grid size must be at least the largest lattice offset");
   if (n[0] * n[1] * nz >= ((int64_t)1 << 31)) return fail(MRTLB_EINVAL, "node count must be below 2^31");
   // kernels address a population buffer with 32-bit byte offsets
-  if ((uint64_t)(n[0] * n[1] * nz) * (uint64_t)lat->L.B * elem_bytes(storage) >= ((uint64_t)1 << 32))
+  if ((uint64_t)(n[1] * nz * row_pitch(n[0], storage)) * (uint64_t)lat->L.B * elem_bytes(storage) >=
+      ((uint64_t)1 << 32))
     return fail(MRTLB_EINVAL, "one population buffer (b * N * element size) must be smaller than 4 GiB");
   if (n[0] > (1 << 24) || n[1] > (1 << 24)) return fail(MRTLB_EINVAL, "grid size too large");
   if (ctx->used + bytes > ctx->budget)
@@ -381,31 +403,16 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   s->has_force = has_force ? 1 : 0;
   s->nx = (int)n[0]; s->ny = (int)n[1]; s->nz = (int)nz;
   s->N = (uint32_t)(n[0] * n[1] * nz);
+  s->nxp = (int)row_pitch(n[0], storage);
   s->bytes = bytes;
-  // step tile: each thread owns vec consecutive x-nodes (vector loads and
-  // stores of 8-16 bytes per lane); 64/128/256 threads along x per
-  // workgroup of 256 threads
+  // step kernel: each thread owns vec consecutive x-slots of the padded rows,
+  // a workgroup kBlock * vec consecutive slots
   s->vec = pick_vec(storage, s->L.kind, s->nx);
-  const int tx = s->nx / s->vec;
-  // threads along x per workgroup: the width (64, 128, 256) that leaves the
-  // fewest idle lanes across a row, the widest on ties
-  s->bx_shift = 8;
-  int best = 1 << 30;
-  for (int b = 8; b >= 6; --b) {
-    const int w = 1 << b;
-    const int idle = ((tx + w - 1) / w) * w - tx;
-    if (idle < best) {
-      best = idle;
-      s->bx_shift = b;
-    }
-  }
-  const int rows = kBlock >> s->bx_shift;
-  s->gx = (tx + (1 << s->bx_shift) - 1) >> s->bx_shift;
-  s->nrowgroups = ((s->ny + rows - 1) / rows) * s->nz;
+  const uint32_t slots = (uint32_t)s->ny * (uint32_t)s->nz * (uint32_t)s->nxp;
+  s->nblocks = (slots + (uint32_t)(kBlock * s->vec) - 1) / (uint32_t)(kBlock * s->vec);
   s->nblocks_node = (s->N + kBlock - 1) / kBlock;
-  s->nblocks = (uint32_t)s->gx * (uint32_t)s->nrowgroups;
   (void)hipSetDevice(ctx->device);
-  const size_t pop = (size_t)s->L.B * s->N * elem_bytes(storage);
+  const size_t pop = (size_t)s->L.B * (size_t)s->ny * s->nz * s->nxp * elem_bytes(storage);
   const size_t real = is_double(storage) ? 8 : 4;
   auto alloc = [&](void** p, size_t sz) { return hipMalloc(p, sz) == hipSuccess; };
   bool ok = alloc(&s->f[0], pop) && alloc(&s->f[1], pop) &&
@@ -520,72 +527,94 @@ mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms) {
   return MRTLB_OK;
 }
 
+static mrtlb_status reserve_jobs(mrtlb_ctx* c, size_t bytes) {
+  if (bytes <= c->job_cap) return MRTLB_OK;
+  size_t cap = std::max<size_t>(bytes, 2 * c->job_cap);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->job_dev) HIP_TRY(hipFree(c->job_dev));
+  if (c->job_host) HIP_TRY(hipHostFree(c->job_host));
+  c->job_dev = c->job_host = nullptr;
+  c->job_cap = 0;
+  HIP_TRY(hipMalloc(&c->job_dev, cap));
+  HIP_TRY(hipHostMalloc(&c->job_host, cap, hipHostMallocDefault));
+  c->job_cap = cap;
+  return MRTLB_OK;
+}
+
+// One group (same lattice, storage, model, force, nodes per thread).  Members
+// are ordered by decreasing step count, so the solves still running at step
+// k form a prefix of the job table: launch k covers jobs [0, m_k).  Two
+// tables (one per parity of the ping-pong buffers) hold each member's job for
+// its even and odd steps of this call.
 template <class Real>
-static mrtlb_status batch_group(mrtlb_solve* const* g, int n, int64_t nsteps, void* dev_jobs) {
-  // jobs for both parities of every member, laid out [parity][member]
-  std::vector<Job<Real>> jobs(2 * (size_t)n);
-  uint32_t begin = 0;
+static mrtlb_status batch_group(std::vector<std::pair<mrtlb_solve*, int64_t>>& g) {
+  std::stable_sort(g.begin(), g.end(), [](const auto& a, const auto& b) { return a.second > b.second; });
+  const int n = (int)g.size();
+  mrtlb_ctx* c = g[0].first->ctx;
+  mrtlb_status rs = reserve_jobs(c, 2 * (size_t)n * sizeof(Job<Real>));
+  if (rs != MRTLB_OK) return rs;
+  // the previous call's copy out of the staging buffer has completed: every
+  // batched call ends with a stream synchronization
+  Job<Real>* jobs = static_cast<Job<Real>*>(c->job_host);
+  std::vector<uint32_t> prefix(n + 1, 0);
   for (int i = 0; i < n; ++i) {
-    const mrtlb_solve& s = *g[i];
+    const mrtlb_solve& s = *g[i].first;
     const KParams<Real>& P = *reinterpret_cast<const KParams<Real>*>(is_double(s.storage) ? (const void*)&s.Pd
                                                                                           : (const void*)&s.Pf);
     for (int par = 0; par < 2; ++par) {
       Job<Real> J = make_job(s, s.cur ^ par, P);
-      J.block_begin = begin;
+      J.block_begin = prefix[i];
       jobs[(size_t)par * n + i] = J;
     }
-    begin += s.nblocks;
+    prefix[i + 1] = prefix[i] + s.nblocks;
   }
-  hipStream_t st = g[0]->ctx->stream;
-  HIP_TRY(hipMemcpyAsync(dev_jobs, jobs.data(), jobs.size() * sizeof(Job<Real>), hipMemcpyHostToDevice, st));
-  for (int64_t k = 0; k < nsteps; ++k) {
-    const void* jp = static_cast<const char*>(dev_jobs) + (size_t)(k & 1) * n * sizeof(Job<Real>);
-    LaunchReq r = base_req(*g[0], kOpStep, jp);
-    r.njobs = n;
-    r.blocks = begin;
-    hipError_t e = dispatch(g[0]->L.kind, r);
+  hipStream_t st = c->stream;
+  HIP_TRY(hipMemcpyAsync(c->job_dev, jobs, 2 * (size_t)n * sizeof(Job<Real>), hipMemcpyHostToDevice, st));
+  int m = n;
+  for (int64_t k = 0; k < g[0].second; ++k) {
+    while (m > 0 && g[m - 1].second <= k) --m;
+    const void* jp = static_cast<const char*>(c->job_dev) + (size_t)(k & 1) * n * sizeof(Job<Real>);
+    LaunchReq r = base_req(*g[0].first, kOpStep, jp);
+    r.njobs = m;
+    r.blocks = prefix[m];
+    hipError_t e = dispatch(g[0].first->L.kind, r);
     if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
   }
-  // the staging buffer must outlive the launches
   HIP_TRY(hipStreamSynchronize(st));
-  for (int i = 0; i < n; ++i) {
-    g[i]->cur ^= (int)(nsteps & 1);
-    g[i]->steps += nsteps;
+  for (auto& p : g) {
+    p.first->cur ^= (int)(p.second & 1);
+    p.first->steps += p.second;
   }
   return MRTLB_OK;
 }
 
-mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, int64_t nsteps) {
-  if (!solves || n < 0 || nsteps < 0) return fail(MRTLB_EINVAL, "bad argument");
-  if (n == 0 || nsteps == 0) return MRTLB_OK;
+mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* nsteps) {
+  if (!solves || n < 0 || (n > 0 && !nsteps)) return fail(MRTLB_EINVAL, "bad argument");
   for (int i = 0; i < n; ++i) {
     if (!solves[i]) return fail(MRTLB_EINVAL, "NULL solve in batch");
+    if (nsteps[i] < 0) return fail(MRTLB_EINVAL, "nsteps must be >= 0");
     if (solves[i]->ctx != solves[0]->ctx) return fail(MRTLB_EINVAL, "solves of a batch must share a context");
     for (int k = 0; k < i; ++k)
       if (solves[k] == solves[i]) return fail(MRTLB_EINVAL, "a solve appears twice in the batch");
   }
+  if (n == 0) return MRTLB_OK;
   HIP_TRY(hipSetDevice(solves[0]->ctx->device));
-  // group by (lattice kind, storage, model, force); order of first appearance
+  // group by (lattice kind, storage, model, force, nodes per thread) in order
+  // of first appearance; solves with nsteps == 0 are left alone
   std::vector<int> done(n, 0);
   for (int i = 0; i < n; ++i) {
-    if (done[i]) continue;
-    std::vector<mrtlb_solve*> grp;
+    if (done[i] || nsteps[i] == 0) continue;
+    std::vector<std::pair<mrtlb_solve*, int64_t>> grp;
     const mrtlb_solve* a = solves[i];
     for (int k = i; k < n; ++k) {
       const mrtlb_solve* b = solves[k];
-      if (!done[k] && b->L.kind == a->L.kind && b->storage == a->storage && b->model.model == a->model.model &&
-          b->has_force == a->has_force && b->vec == a->vec) {
-        grp.push_back(solves[k]);
+      if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->storage == a->storage &&
+          b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec) {
+        grp.emplace_back(solves[k], nsteps[k]);
         done[k] = 1;
       }
     }
-    // one launch covers at most 2^31 workgroups; the job table lives in a
-    // temporary device buffer
-    const size_t jsz = is_double(a->storage) ? sizeof(Job<double>) : sizeof(Job<float>);
-    DevBuf jb;
-    HIP_TRY(hipMalloc(&jb.p, 2 * grp.size() * jsz));
-    mrtlb_status st = is_double(a->storage) ? batch_group<double>(grp.data(), (int)grp.size(), nsteps, jb.p)
-                                            : batch_group<float>(grp.data(), (int)grp.size(), nsteps, jb.p);
+    mrtlb_status st = is_double(a->storage) ? batch_group<double>(grp) : batch_group<float>(grp);
     if (st != MRTLB_OK) return st;
   }
   return MRTLB_OK;

@@ -107,8 +107,9 @@ __device__ __forceinline__ void gstore(void* base, uint32_t byteoff, T v) {
 // ---------------------------------------------------------------------------
 
 // Population layout in HBM (row-blocked): element (j, x, y, z) of a buffer
-// sits at ((r * b + j) * nx + x) with node row r = z * ny + y, i.e. every
-// row of nx nodes stores its b population rows back to back.  A step then
+// sits at ((r * b + j) * nxp + x) with node row r = z * ny + y and the row
+// pitch nxp = nx rounded up to 32 nodes, i.e. every row of nx nodes stores
+// its b population rows back to back, each starting on a 32-element boundary.  A step then
 // reads each population from 2*MAXE+1 (2D) neighbouring row blocks and
 // writes one row block, instead of touching b planes that lie a whole
 // domain apart.  Scalar node fields (phi, force) are plain [r][x].
@@ -117,10 +118,11 @@ struct RowGeom {
   static constexpr int M = L::MAXE;
   uint32_t yo[2 * M + 1];   // wrap(iy - s)
   uint32_t zo[2 * M + 1];   // wrap(iz - s) * ny
-  int nx;
+  int nx, nxp;
 
-  __device__ __forceinline__ void init(int iy, int iz, int nx_, int ny, int nz) {
+  __device__ __forceinline__ void init(int iy, int iz, int nx_, int nxp_, int ny, int nz) {
     nx = nx_;
+    nxp = nxp_;
 #pragma unroll
     for (int s = -M; s <= M; ++s) {
       yo[s + M] = (uint32_t)wrap(iy - s, ny);
@@ -137,9 +139,9 @@ struct RowGeom {
   __device__ __forceinline__ uint32_t own_row() const { return yo[M] + (L::D == 3 ? zo[M] : 0u); }
   // first element of population J's source row
   template <int J>
-  __device__ __forceinline__ uint32_t prow() const { return (row<J>() * (uint32_t)L::B + J) * (uint32_t)nx; }
+  __device__ __forceinline__ uint32_t prow() const { return (row<J>() * (uint32_t)L::B + J) * (uint32_t)nxp; }
   // first element of population j's own row
-  __device__ __forceinline__ uint32_t pown(int j) const { return (own_row() * (uint32_t)L::B + j) * (uint32_t)nx; }
+  __device__ __forceinline__ uint32_t pown(int j) const { return (own_row() * (uint32_t)L::B + j) * (uint32_t)nxp; }
   // element of the source of population J for node ix (periodic in x)
   template <int J>
   __device__ __forceinline__ uint32_t src(int ix) const { return prow<J>() + (uint32_t)wrap(ix - L::EX[J], nx); }
@@ -471,21 +473,21 @@ __device__ __forceinline__ int find_job(const Job<Real>* jobs, int njobs, uint32
   return lo;
 }
 
-// Tile of a step workgroup: (1 << bx_shift) threads along x, each owning VEC
-// consecutive nodes, times (kBlock >> bx_shift) rows.
+// Mapping of a step workgroup: the node slots of a solve are its rows laid
+// end to end at the padded pitch nxp (a multiple of 32 nodes), cut into
+// runs of kBlock * VEC slots; thread t of workgroup w owns the VEC
+// consecutive slots starting at (w * kBlock + t) * VEC.  Every wavefront
+// therefore starts on a 32-node boundary of a row (its accesses cover whole
+// cache lines whatever nx is); slots past nx in a row are idle.
 template <int VEC, class Real>
 __device__ __forceinline__ bool tile_node(const Job<Real>& J, uint32_t local, int& ix0, int& iy, int& iz) {
-  const int bxs = J.bx_shift;
-  const int rows = kBlock >> bxs;
-  const uint32_t tx = local % (uint32_t)J.gx;
-  const uint32_t rg = local / (uint32_t)J.gx;
-  const int ny = J.P.ny;
-  const uint32_t rgy = (uint32_t)((ny + rows - 1) / rows);
-  const int tid = threadIdx.x;
-  ix0 = ((int)(tx << bxs) + (tid & ((1 << bxs) - 1))) * VEC;
-  iy = (int)(rg % rgy) * rows + (tid >> bxs);
-  iz = (int)(rg / rgy);
-  return ix0 < J.P.nx && iy < ny;
+  const uint32_t n0 = (local * (uint32_t)kBlock + threadIdx.x) * (uint32_t)VEC;
+  const uint32_t nxp = (uint32_t)J.P.nxp, ny = (uint32_t)J.P.ny;
+  const uint32_t r = n0 / nxp;
+  ix0 = (int)(n0 - r * nxp);
+  iy = (int)(r % ny);
+  iz = (int)(r / ny);
+  return ix0 < J.P.nx && r < ny * (uint32_t)J.P.nz;
 }
 
 // One node of the method after the gather: a2-a7 in registers.
@@ -627,13 +629,20 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   int ix0, iy, iz;
   if (!tile_node<VEC>(J, lin - J.block_begin, ix0, iy, iz)) return;
   RowGeom<L> g;
-  g.init(iy, iz, P.nx, P.ny, P.nz);
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t N = P.N;
 
   // a1: gather along -e_j
   T raw[B][VEC];
-  const bool interior = ix0 >= M && ix0 + VEC - 1 + M < P.nx;
-  if (interior) {
+  if constexpr (VEC == 1) {
+    // one node per lane: every lane wraps its own index, no divergent path
+    static_for<0, B>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      T one[1];
+      load_vec<ST, 1>(J.fin, g.template src<j>(ix0), one);
+      raw[j][0] = one[0];
+    });
+  } else if (ix0 >= M && ix0 + VEC - 1 + M < P.nx) {
     static_for<0, B>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
       load_vec<ST, VEC>(J.fin, g.template prow<j>() + (uint32_t)(ix0 - L::EX[j]), raw[j]);
@@ -700,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   int ix, iy, iz;
   if (!node_of_thread<L>(P, ix, iy, iz)) return;
   RowGeom<L> g;
-  g.init(iy, iz, P.nx, P.ny, P.nz);
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t self = g.node(ix);
   const uint32_t N = P.N;
   const double R = rho[self];
@@ -753,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const Job<typename StoreT<ST>
   int ix, iy, iz;
   if (!node_of_thread<L>(P, ix, iy, iz)) return;
   RowGeom<L> g;
-  g.init(iy, iz, P.nx, P.ny, P.nz);
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t self = g.node(ix);
   const uint32_t N = P.N;
   double x[B];
@@ -801,7 +810,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Job<typename StoreT<ST
   int ix, iy, iz;
   if (!node_of_thread<L>(P, ix, iy, iz)) return;
   RowGeom<L> g;
-  g.init(iy, iz, P.nx, P.ny, P.nz);
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t self = g.node(ix);
   const uint32_t N = P.N;
   static_for<0, B>([&](auto jj) {
@@ -833,7 +842,7 @@ __global__ __launch_bounds__(kBlock) void k_plane_sums(const void* __restrict__ 
     if (i < N) {
       if (plane < nplanes_pop) {
         const uint32_t nx = (uint32_t)PR->nx;
-        const uint32_t e = ((i / nx) * (uint32_t)nplanes_pop + (uint32_t)plane) * nx + i % nx;
+        const uint32_t e = ((i / nx) * (uint32_t)nplanes_pop + (uint32_t)plane) * (uint32_t)PR->nxp + i % nx;
         acc += (double)load_pop<ST>(base, e, *PR, plane);
       } else {
         acc += (double)force[(size_t)(plane - nplanes_pop) * N + i];

@@ -24,6 +24,7 @@ enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2 };
 template <class Real>
 struct KParams {
   int nx, ny, nz;
+  int nxp;                  // population row pitch in elements (nx padded to 128 bytes)
   uint32_t N;               // nodes
   int inc;                  // NSE: incompressible (rho_m = rho0) or compressible (rho_m = rho)
   int m30;                  // NSE: third-order equilibrium moments rho uuu
@@ -56,10 +57,7 @@ struct Job {
   Real* phi_out;            // NCDE: phi^n
   uint32_t block_begin;     // first linear workgroup of this job
   uint32_t nblocks;
-  int gx;                   // workgroups along x per row group
-  int bx_shift;             // log2 of the threads along x of a workgroup tile (6, 7 or 8)
   int vec;                  // nodes per thread along x
-  int nrowgroups;           // ceil(ny / rows per tile) * nz
 };
 
 }  // namespace mrtlb

@@ -59,17 +59,18 @@ def rates_tau(tau_shear: float, other: float = 1.2) -> Rates:
 # fields
 # ---------------------------------------------------------------------------
 
+def axis_coords(card: Card, shape, a):
+    """Physical coordinates along axis a (x = 0), shaped to broadcast."""
+    d = card.d
+    n = shape[d - 1 - a]                   # x is the last array axis
+    sh = [1] * d
+    sh[d - 1 - a] = n
+    return (np.arange(n, dtype=np.float64) * card.c[a]).reshape(sh)
+
+
 def grid_coords(card: Card, shape):
     """Physical coordinates, one array per axis, broadcast to ``shape``."""
-    d = card.d
-    axes = []
-    for a in range(d):
-        n = shape[d - 1 - a]               # x is the last array axis
-        coord = np.arange(n, dtype=np.float64) * card.c[a]
-        sh = [1] * d
-        sh[d - 1 - a] = n
-        axes.append(np.broadcast_to(coord.reshape(sh), shape))
-    return axes
+    return [np.broadcast_to(axis_coords(card, shape, a), shape) for a in range(card.d)]
 
 
 def taylor_green_2d(card: Card, shape, U0, rho0=1.0, t=0.0, nu=0.0):
@@ -79,15 +80,17 @@ def taylor_green_2d(card: Card, shape, U0, rho0=1.0, t=0.0, nu=0.0):
     u = -U0 sqrt(ky/kx) cos(kx x) sin(ky y) F, v = U0 sqrt(kx/ky) sin(kx x) cos(ky y) F,
     p = -(rho0 U0^2 / 4) [ (ky/kx) cos(2 kx x) + (kx/ky) cos(2 ky y) ] F^2,
     F = exp(-nu (kx^2 + ky^2) t).  Returns (p, u) with u of shape (2, Ny, Nx).
+    Separable factors are evaluated on the axes and combined by broadcasting.
     """
     Ny, Nx = shape
     kx = 2 * pi / (Nx * card.c[0])
     ky = 2 * pi / (Ny * card.c[1])
-    x, y = grid_coords(card, shape)
+    x = axis_coords(card, shape, 0)
+    y = axis_coords(card, shape, 1)
     F = np.exp(-nu * (kx * kx + ky * ky) * t)
-    u = -U0 * np.sqrt(ky / kx) * np.cos(kx * x) * np.sin(ky * y) * F
-    v = U0 * np.sqrt(kx / ky) * np.sin(kx * x) * np.cos(ky * y) * F
-    p = -(rho0 * U0 * U0 / 4) * ((ky / kx) * np.cos(2 * kx * x) + (kx / ky) * np.cos(2 * ky * y)) * F * F
+    u = (-U0 * np.sqrt(ky / kx) * F) * np.cos(kx * x) * np.sin(ky * y)
+    v = (U0 * np.sqrt(kx / ky) * F) * np.sin(kx * x) * np.cos(ky * y)
+    p = (-(rho0 * U0 * U0 / 4) * F * F) * ((ky / kx) * np.cos(2 * kx * x) + (kx / ky) * np.cos(2 * ky * y))
     return p, np.stack([u, v])
 
 
@@ -99,31 +102,31 @@ def taylor_green_3d(card: Card, shape, U0, drho=1e-2):
     kx = 2 * pi / (Nx * card.c[0])
     ky = 2 * pi / (Ny * card.c[1])
     kz = 2 * pi / (Nz * card.c[2])
-    x, y, z = grid_coords(card, shape)
-    u = U0 * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)
-    v = -U0 * (kx / ky) * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)
-    w = np.zeros_like(u)
-    rho = 1.0 + drho * np.cos(kx * x) * np.cos(ky * y) * np.cos(kz * z)
+    x, y, z = (axis_coords(card, shape, a) for a in range(3))
+    cz = np.cos(kz * z)
+    u = (U0 * np.sin(kx * x)) * (np.cos(ky * y) * cz)
+    v = (-U0 * (kx / ky) * np.cos(kx * x)) * (np.sin(ky * y) * cz)
+    w = np.zeros(shape)
+    rho = 1.0 + (drho * np.cos(kx * x)) * (np.cos(ky * y) * cz)
     return rho, np.stack([u, v, w])
 
 
 def gaussian_hill(card: Card, shape, amplitude=1.0, sigma0=None, center=None):
     """phi0 = A exp(-|x - x0|^2 / (2 sigma0^2)) with periodic images summed
-    (images at +-1 period in each axis), sigma0 in physical units."""
+    (images at +-1 period in each axis), sigma0 in physical units.  The
+    Gaussian and its image sum factor over the axes."""
     d = card.d
     L = [shape[d - 1 - a] * card.c[a] for a in range(d)]
     if sigma0 is None:
         sigma0 = min(L) / 16.0
     if center is None:
         center = [0.5 * La for La in L]
-    X = grid_coords(card, shape)
-    out = np.zeros(shape)
-    for shift in np.ndindex(*([3] * d)):
-        r2 = np.zeros(shape)
-        for a in range(d):
-            r2 = r2 + (X[a] - center[a] + (shift[a] - 1) * L[a]) ** 2
-        out += np.exp(-r2 / (2 * sigma0 ** 2))
-    return amplitude * out
+    out = amplitude
+    for a in range(d):
+        xa = axis_coords(card, shape, a)
+        g = sum(np.exp(-(xa - center[a] + k * L[a]) ** 2 / (2 * sigma0 ** 2)) for k in (-1, 0, 1))
+        out = out * g
+    return np.broadcast_to(out, shape).copy()
 
 
 def sinusoidal_force(card: Card, shape, F0, seed, modes=3):
@@ -132,15 +135,18 @@ def sinusoidal_force(card: Card, shape, F0, seed, modes=3):
     rng = np.random.default_rng(seed)
     d = card.d
     L = [shape[d - 1 - a] * card.c[a] for a in range(d)]
-    X = grid_coords(card, shape)
     F = np.zeros((d,) + tuple(shape))
     for _ in range(modes):
         n = rng.normal(size=d)
         n /= np.linalg.norm(n)
         k = rng.integers(1, 3, size=d) * rng.choice([-1, 1], size=d)
         ph = rng.uniform(0, 2 * pi)
-        arg = sum(2 * pi * k[a] / L[a] * X[a] for a in range(d)) + ph
-        F += F0 * n.reshape((d,) + (1,) * d) * np.sin(arg)[None]
+        # sin(sum_a t_a + ph) expanded with complex exponentials per axis
+        e = np.exp(1j * ph)
+        for a in range(d):
+            e = e * np.exp(1j * 2 * pi * k[a] / L[a] * axis_coords(card, shape, a))
+        arg_sin = np.broadcast_to(e.imag, shape)
+        F += F0 * n.reshape((d,) + (1,) * d) * arg_sin[None]
     return F
 
 

@@ -255,11 +255,18 @@ def test_batch_equals_single(ctx):
                 s = H.Solve(ctx, hip_lattice(card), hip_model(eq, rates, **kw), shape, storage)
                 s.init_fields(r, u)
                 lst.append(s)
+        counts = [11, 4, 11, 0, 7]
+        for s, k in zip(solo, counts):
+            s.step(k)
+        H.batch_step(batch, counts)
+        for a, b, k in zip(solo, batch, counts):
+            assert b.steps == k
+            assert np.array_equal(a.read_populations(), b.read_populations())
+        # a second call continues from the new parities
         for s in solo:
-            s.step(11)
-        H.batch_step(batch, 11)
+            s.step(3)
+        H.batch_step(batch, 3)
         for a, b in zip(solo, batch):
-            assert b.steps == 11
             assert np.array_equal(a.read_populations(), b.read_populations())
 
 
