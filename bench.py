@@ -28,9 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2}
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2, "i16_dev": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_dev": "f32", "fp16_dev": "f32 (fp16 storage)",
-         "bf16_dev": "f32 (bf16 storage)"}
+         "bf16_dev": "f32 (bf16 storage)", "i16_dev": "f32 (int16 fixed-point storage)"}
 
 
 def kernel_source_hash():
@@ -99,6 +99,14 @@ def copy_probe(torch, dev, steps, warmup):
                       "GB_per_s": round(2 * 4 * n / ms / 1e6, 1)}), flush=True)
 
 
+def _bounds(W, storage, wl):
+    """Flow bounds that size the int16 storage's ranges (only that storage uses them)."""
+    if storage != "i16_dev":
+        return {}
+    ub, db = W.flow_bounds(wl.eq, wl.rho_or_phi, wl.u, wl.force, wl.steps, wl.rho0, wl.adv_u)
+    return {"u_bound": ub, "dev_bound": db}
+
+
 def _line(metric, value, unit, args, wall, workload_cfg, storage, launch_bytes, per_launch_s, peak=HBM_PEAK_GBS):
     achieved = launch_bytes / per_launch_s / 1e9
     return {"metric": metric, "value": round(value, 1), "unit": unit, "n_gpus": 1, "steps": args.steps,
@@ -120,7 +128,8 @@ def bench_tgv3d(torch, H, W, stream, args):
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
-    md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h)
+    md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
+                      **_bounds(W, args.storage, wl))
     s = H.Solve(ctx, lat, md, shape, args.storage)
     s.init_fields(wl.rho_or_phi, wl.u)
     del wl
@@ -153,7 +162,7 @@ def bench_ncde_batch(torch, H, W, stream, args):
     for wl in wls:
         r = wl.rates
         md = H.model_desc("NCDE", s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                          D0=wl.D0, D2=wl.D2, adv_u=wl.adv_u)
+                          D0=wl.D0, D2=wl.D2, adv_u=wl.adv_u, **_bounds(W, args.storage, wl))
         s = H.Solve(ctx, lat, md, wl.shape, args.storage)
         s.init_fields(wl.rho_or_phi)
         solves.append(s)
@@ -180,10 +189,10 @@ def bench_ncde_batch(torch, H, W, stream, args):
 def bench_serve(stream, args):
     """Served stream: Poisson arrivals mixing rD2Q25 NSE (64^2-2048^2), rD2Q13
     NCDE (128^2-1024^2) and rD3Q33 NSE with body force (32^3-128^3), 200-2000
-    steps, 16-bit deviation storage; continuous batching."""
+    steps, int16 deviation storage (bf16_dev/fp16_dev by --storage); continuous batching."""
     from paper_2512_16230_amd import serving as S
 
-    storage = args.storage if args.storage != "fp32" else "bf16_dev"
+    storage = args.storage if args.storage != "fp32" else "i16_dev"
     reqs = S.request_stream(args.requests, args.rate, seed=0, storage=storage)
     ex = S.GpuExecutor(stream=stream.cuda_stream)
     warm = S.request_stream(6, 1000.0, seed=99, storage=storage, steps=(10, 20), q25=(64, 128), q13=(128, 160),
@@ -255,7 +264,8 @@ def main():
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
-    md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h)
+    md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
+                      **_bounds(W, args.storage, wl))
     s = H.Solve(ctx, lat, md, shape, args.storage)
     s.init_fields(wl.rho_or_phi, wl.u)
     del wl

@@ -142,23 +142,39 @@ typedef struct {
   int m30;           /* NSE: include M30 = rho uuu */
   double D0, D2;     /* NCDE */
   double adv_u[3];   /* NCDE */
+  /* Bounds the caller guarantees over the whole run, used only by
+   * MRTLB_I16_DEV to size its fixed-point ranges: u_bound >= max |u|,
+   * dev_bound >= max |rho - rho0| / rho0 (NSE) or max |phi| (NCDE).
+   * Both 0 (the default) selects the uniform range |f_bar - w rho_ref| <= 2 w. */
+  double u_bound, dev_bound;
 } mrtlb_model_desc;
 
 /* Population storage in HBM (compute is FP64 for MRTLB_FP64, FP32 otherwise):
  *   FP64      f_bar, double
  *   FP32      f_bar, float
  *   FP32_DEV  f_bar - w_j rho_ref, float
- *   FP16_DEV  (f_bar - w_j rho_ref) * scale / w_j, IEEE half (RNE)
+ *   FP16_DEV  (f_bar - w_j rho_ref) * 128 / w_j, IEEE half (RNE)
  *   BF16_DEV  same, bfloat16 (RNE)
- * rho_ref = rho0 (NSE) or 0 (NCDE); scale = 2^7. */
-typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DEV = 3, MRTLB_BF16_DEV = 4 } mrtlb_storage;
+ *   I16_DEV   (f_bar - w_j rho_ref) * 32767 / (A_j w_j), int16 fixed point
+ *             (RNE, saturating at +-A_j w_j).  A_j = 2 when u_bound and
+ *             dev_bound are 0; otherwise, with t_j = |c_j| u_bound / cs^2,
+ *             r = dev_bound and U = u_bound,
+ *               A_j = 2 [r + (1 + r)(exp(t_j) - 1 + U^2 / (2 cs^2))],
+ *             twice a bound on |f_eq,j - w_j rho_ref| / w_j (the equilibrium
+ *             is a truncated series in c_j.u / cs^2 whose terms the exp
+ *             series dominates); the factor 2 covers the non-equilibrium part.
+ * rho_ref = rho0 (NSE) or 0 (NCDE).  Each FP32 value is rounded once to
+ * the 16-bit format. */
+typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DEV = 3, MRTLB_BF16_DEV = 4,
+               MRTLB_I16_DEV = 5 } mrtlb_storage;
 
 /* Create a solve on a periodic grid n[0] x n[1] (x n[2] in 3D; n[2] = 1 in
  * 2D).  Allocates two population buffers (pull streaming, double-buffered),
  * the force field if has_force, and for the NCDE two phi history fields.
  * The lattice is copied; it may be destroyed afterwards.
  * Errors: EINVAL (sizes < 1, a size below the largest lattice offset, a
- * population buffer of 4 GiB or more, rates outside (0, 2),
+ * population buffer of 4 GiB or more, rates outside (0, 2), negative or
+ * non-finite u_bound / dev_bound,
  * unknown model or storage, NSE_INC with rho0 <= 0), ENOMEM (footprint over
  * the remaining budget; nothing allocated), EDEVICE. */
 mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,

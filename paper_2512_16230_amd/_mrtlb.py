@@ -23,12 +23,12 @@ LIB_PATH = os.environ.get("MRTLB_LIB", os.path.join(_HERE, "libmrtlb.so"))
 MRTLB_OK, MRTLB_EINVAL, MRTLB_ENOMEM, MRTLB_EDEVICE, MRTLB_ENUMERIC = 0, -1, -2, -3, -4
 MRTLB_RD2Q25, MRTLB_RD2Q13, MRTLB_RD3Q53, MRTLB_RD3Q33 = 0, 1, 2, 3
 MRTLB_NSE_INC, MRTLB_NSE_COMP, MRTLB_NCDE = 0, 1, 2
-MRTLB_FP64, MRTLB_FP32, MRTLB_FP32_DEV, MRTLB_FP16_DEV, MRTLB_BF16_DEV = 0, 1, 2, 3, 4
+MRTLB_FP64, MRTLB_FP32, MRTLB_FP32_DEV, MRTLB_FP16_DEV, MRTLB_BF16_DEV, MRTLB_I16_DEV = 0, 1, 2, 3, 4, 5
 
 KINDS = {"rD2Q25": MRTLB_RD2Q25, "rD2Q13": MRTLB_RD2Q13, "rD3Q53": MRTLB_RD3Q53, "rD3Q33": MRTLB_RD3Q33}
 MODELS = {"NSE_INC": MRTLB_NSE_INC, "NSE_COMP": MRTLB_NSE_COMP, "NCDE": MRTLB_NCDE}
 STORAGES = {"fp64": MRTLB_FP64, "fp32": MRTLB_FP32, "fp32_dev": MRTLB_FP32_DEV, "fp16_dev": MRTLB_FP16_DEV,
-            "bf16_dev": MRTLB_BF16_DEV}
+            "bf16_dev": MRTLB_BF16_DEV, "i16_dev": MRTLB_I16_DEV}
 
 
 class MrtlbError(RuntimeError):
@@ -45,7 +45,7 @@ class mrtlb_lattice_desc(ctypes.Structure):
 class mrtlb_model_desc(ctypes.Structure):
     _fields_ = [("model", c_int), ("rho0", c_double), ("s0", c_double), ("s1", c_double), ("s_shear", c_double),
                 ("s_bulk", c_double), ("s3", c_double), ("s_high", c_double), ("m30", c_int), ("D0", c_double),
-                ("D2", c_double), ("adv_u", c_double * 3)]
+                ("D2", c_double), ("adv_u", c_double * 3), ("u_bound", c_double), ("dev_bound", c_double)]
 
 
 _lib = None
@@ -205,7 +205,9 @@ class Lattice:
 
 
 def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s_high=1.2, m30=True, D0=0.0,
-               D2=0.0, adv_u=(0.0, 0.0, 0.0)):
+               D2=0.0, adv_u=(0.0, 0.0, 0.0), u_bound=0.0, dev_bound=0.0):
+    """Model parameters; u_bound / dev_bound size the int16 storage's ranges
+    (max |u| and max |rho - rho0| / rho0, or max |phi| for the NCDE)."""
     m = mrtlb_model_desc()
     m.model = MODELS[eq] if isinstance(eq, str) else int(eq)
     m.rho0, m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high = rho0, s0, s1, s_shear, s_bulk, s3, s_high
@@ -213,6 +215,7 @@ def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s
     m.D0, m.D2 = D0, D2
     for a in range(3):
         m.adv_u[a] = float(adv_u[a]) if a < len(adv_u) else 0.0
+    m.u_bound, m.dev_bound = float(u_bound), float(dev_bound)
     return m
 
 

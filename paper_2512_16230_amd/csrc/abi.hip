@@ -145,8 +145,25 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   for (int a = 0; a < D; ++a)
     for (int b = 0; b < D; ++b) P.cabb[a][b] = (Real)(L.c[a] * L.c[b] * L.c[b]);
   P.cxyz = D == 3 ? (Real)(L.c[0] * L.c[1] * L.c[2]) : (Real)0;
-  const double scale = 128.0;
+  // 16-bit deviation storage, value f - w rho_ref = stored * wsc[j]:
+  // FP16/BF16 store 128 (f - w rho_ref) / w; the int16 fixed point spans
+  // |f - w rho_ref| <= A_j w with 32767 steps (A_j from the caller's flow
+  // bounds, else the uniform kI16Range).
+  const mrtlb_model_desc& md = s.model;
+  const bool bounded = md.u_bound > 0 || md.dev_bound > 0;
   for (int j = 0; j < L.B; ++j) {
+    double scale = 128.0;
+    if (s.storage == kI16Dev) {
+      double A = kI16Range;
+      if (bounded) {
+        double cn = 0;
+        for (int a = 0; a < D; ++a) cn += L.c[a] * L.c[a] * L.e[j * D + a] * L.e[j * D + a];
+        const double t = std::sqrt(cn) * md.u_bound / L.cs2;
+        const double r = md.dev_bound;
+        A = 2.0 * (r + (1.0 + r) * (std::expm1(t) + md.u_bound * md.u_bound / (2.0 * L.cs2)));
+      }
+      scale = 32767.0 / A;
+    }
     P.w[j] = (Real)L.w[j];
     P.wsc[j] = (Real)(L.w[j] / scale);
     P.iwsc[j] = (Real)(scale / L.w[j]);
@@ -172,7 +189,7 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   if (D == 3) P.inxyz = (Real)(1.0 / L.norms[row_xyz()]);
   const mrtlb_model_desc& m = s.model;
   P.s1 = (Real)m.s1; P.ss = (Real)m.s_shear; P.sb = (Real)m.s_bulk; P.s3 = (Real)m.s3; P.sh = (Real)m.s_high;
-  const bool dev = s.storage == kFP32Dev || s.storage == kFP16Dev || s.storage == kBF16Dev;
+  const bool dev = s.storage != kFP64 && s.storage != kFP32;
   P.rho_ref = (Real)(dev && m.model != MRTLB_NCDE ? m.rho0 : 0.0);
   P.rho0 = (Real)m.rho0;
   if (m.model == MRTLB_NCDE) {
@@ -329,6 +346,8 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, int D, int kind) {
     if (!(v > 0 && v < 2)) return fail(MRTLB_EINVAL, "relaxation rates must lie in (0, 2)");
   if (m.model == MRTLB_NSE_INC && !(m.rho0 > 0)) return fail(MRTLB_EINVAL, "rho0 must be positive");
   if (m.model == MRTLB_NCDE && D != 2) return fail(MRTLB_EINVAL, "the NCDE model is built for 2D lattices");
+  if (!(m.u_bound >= 0 && m.u_bound < 1e3) || !(m.dev_bound >= 0 && m.dev_bound < 1e3))
+    return fail(MRTLB_EINVAL, "u_bound and dev_bound must be finite and >= 0");
   (void)kind;
   return MRTLB_OK;
 }
@@ -336,7 +355,7 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, int D, int kind) {
 mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3], int storage, int model,
                                    int has_force, size_t* bytes) {
   if (!lat || !n || !bytes) return fail(MRTLB_EINVAL, "NULL argument");
-  if (storage < kFP64 || storage > kBF16Dev) return fail(MRTLB_EINVAL, "unknown storage");
+  if (storage < kFP64 || storage > kI16Dev) return fail(MRTLB_EINVAL, "unknown storage");
   const int D = lat->L.D;
   const int64_t nz = D == 3 ? n[2] : 1;
   if (n[0] < 1 || n[1] < 1 || nz < 1) return fail(MRTLB_EINVAL, "grid sizes must be >= 1");
@@ -699,8 +718,7 @@ mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum) {
   for (int p = 0; p < planes; ++p)
     for (uint32_t c = 0; c < nchunks; ++c) plane[p] += h[(size_t)p * nchunks + c];
   double m = 0, mom[3] = {0, 0, 0};
-  const double ref = (s->storage == kFP32Dev || s->storage == kFP16Dev || s->storage == kBF16Dev) &&
-                             s->model.model != MRTLB_NCDE
+  const double ref = s->storage != kFP64 && s->storage != kFP32 && s->model.model != MRTLB_NCDE
                          ? s->model.rho0
                          : 0.0;
   for (int j = 0; j < B; ++j) {

@@ -83,6 +83,8 @@ template <>
 struct StoreT<kFP16Dev> { using T = _Float16; using Real = float; };
 template <>
 struct StoreT<kBF16Dev> { using T = uint16_t; using Real = float; };
+template <>
+struct StoreT<kI16Dev> { using T = int16_t; using Real = float; };
 
 // Global-address-space access with a 32-bit byte offset from a uniform base:
 // the base stays in SGPRs and each lane supplies one 32-bit offset
@@ -237,6 +239,8 @@ __device__ __forceinline__ Real decode(typename StoreT<ST>::T v, const KParams<R
     return (Real)pin((float)v * (float)P.wsc[j]);
   } else if constexpr (ST == kBF16Dev) {
     return (Real)pin(bf16_to_f32(v) * (float)P.wsc[j]);
+  } else if constexpr (ST == kI16Dev) {
+    return (Real)pin((float)(int)v * (float)P.wsc[j]);
   } else {
     return (Real)v;
   }
@@ -249,6 +253,10 @@ __device__ __forceinline__ typename StoreT<ST>::T encode(Real v, const KParams<R
     return (_Float16)pin((float)v * (float)P.iwsc[j]);
   } else if constexpr (ST == kBF16Dev) {
     return f32_to_bf16_rne(pin((float)v * (float)P.iwsc[j]));
+  } else if constexpr (ST == kI16Dev) {
+    // fixed point: round to nearest even, saturate at +-32767
+    const float q = __builtin_rintf(pin((float)v * (float)P.iwsc[j]));
+    return (int16_t)(int)fminf(fmaxf(q, -32767.0f), 32767.0f);
   } else {
     return (T)v;
   }
@@ -874,6 +882,7 @@ inline bool with_storage(int st, F&& f) {
     case kFP32Dev: f(std::integral_constant<int, kFP32Dev>{}); return true;
     case kFP16Dev: f(std::integral_constant<int, kFP16Dev>{}); return true;
     case kBF16Dev: f(std::integral_constant<int, kBF16Dev>{}); return true;
+    case kI16Dev: f(std::integral_constant<int, kI16Dev>{}); return true;
   }
   return false;
 }

@@ -11,12 +11,13 @@ constexpr int kMaxB = 53;
 constexpr int kBlock = 256;         // threads per workgroup of every node kernel
 constexpr int kNumXcd = 8;          // MI355X: 8 XCDs, workgroups dealt round-robin
 
-constexpr int kChunkIters = 16;    // elements per thread of one plane-sum chunk
+constexpr int kChunkIters = 16;
+constexpr double kI16Range = 2.0;   // int16 deviation storage spans |f - w rho_ref| <= 2 w    // elements per thread of one plane-sum chunk
 
 // Index of the off-diagonal pair (a, b), a < b: xy -> 0, xz -> 1, yz -> 2.
 constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
 
-enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4 };
+enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4, kI16Dev = 5 };
 enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2 };
 
 // Per-solve constants of the collision, in the compute precision.  Row

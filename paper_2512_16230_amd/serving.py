@@ -31,7 +31,7 @@ import numpy as np
 
 from . import workloads as W
 
-STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2}
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2, "i16_dev": 2}
 B_OF = {"rD2Q25": 25, "rD2Q13": 13, "rD3Q53": 53, "rD3Q33": 33}
 
 
@@ -70,7 +70,7 @@ def make_payload(req: Request) -> dict:
     return {"rho_or_phi": rho, "u": u, "force": F}
 
 
-def request_stream(n, rate, seed=0, storage="bf16_dev", mix=(1 / 3, 1 / 3, 1 / 3), steps=(200, 2000),
+def request_stream(n, rate, seed=0, storage="i16_dev", mix=(1 / 3, 1 / 3, 1 / 3), steps=(200, 2000),
                    q25=(64, 2048), q13=(128, 1024), q33=(32, 128)):
     """Poisson arrivals at ``rate`` per second mixing rD2Q25 NSE (sides in
     ``q25``), rD2Q13 NCDE (``q13``) and rD3Q33 NSE with a body force
@@ -138,10 +138,13 @@ class GpuExecutor:
     def create(self, req):
         H = self.H
         r = req.rates
-        md = H.model_desc(req.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                          D0=req.D0, D2=req.D2, adv_u=req.adv_u)
-        s = H.Solve(self.ctx, self._lattice(req.card), md, req.shape, req.storage, has_force=req.with_force)
         p = req.payload
+        ub = db = 0.0
+        if req.storage == "i16_dev":
+            ub, db = W.flow_bounds(req.eq, p["rho_or_phi"], p["u"], p["force"], req.steps, adv_u=req.adv_u)
+        md = H.model_desc(req.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
+                          D0=req.D0, D2=req.D2, adv_u=req.adv_u, u_bound=ub, dev_bound=db)
+        s = H.Solve(self.ctx, self._lattice(req.card), md, req.shape, req.storage, has_force=req.with_force)
         s.init_fields(p["rho_or_phi"], p["u"], p["force"])
         return s
 

@@ -100,9 +100,15 @@ def test_dev16_storage(ctx):
         print("case: tgv-rD2Q25-64x64 %s 200 steps" % storage, flush=True)
         r, u, _ = _gpu_run(ctx, wl.card, wl.eq, wl.rates, wl.shape, storage, wl.rho_or_phi, wl.u, wl.steps)
         res[storage] = (max_rel(r, r_o), max_rel(u, u_o))
+    ub, db = W.flow_bounds(wl.eq, wl.rho_or_phi, wl.u)
+    print("case: tgv-rD2Q25-64x64 i16_dev 200 steps, u_bound %.4f dev_bound %.2e" % (ub, db), flush=True)
+    r, u, _ = _gpu_run(ctx, wl.card, wl.eq, wl.rates, wl.shape, "i16_dev", wl.rho_or_phi, wl.u, wl.steps,
+                       u_bound=ub, dev_bound=db)
+    res["i16_dev"] = (max_rel(r, r_o), max_rel(u, u_o))
     print("16-bit errors (rho, u):", res, flush=True)
     assert res["fp16_dev"][0] < 1e-4 and res["fp16_dev"][1] < 1e-2
     assert res["bf16_dev"][0] < 1e-2 and res["bf16_dev"][1] < 2e-1
+    assert res["i16_dev"][0] < 1e-4 and res["i16_dev"][1] < 1e-3
 
 
 # --------------------------------------------------------------------------
@@ -209,7 +215,7 @@ def test_checkpoint_roundtrip(ctx):
     rates = W.rates_tau(0.8)
     shape = (20, 40)
     rho, u = _random_fields(card, shape, 11)
-    for storage in ("fp64", "fp32", "fp16_dev"):
+    for storage in ("fp64", "fp32", "fp16_dev", "i16_dev"):
         a = H.Solve(ctx, hip_lattice(card), hip_model("NSE_INC", rates), shape, storage)
         a.init_fields(rho, u)
         a.step(7)
@@ -248,7 +254,7 @@ def test_batch_equals_single(ctx):
     for shape in [(40, 70), (33, 257)]:
         rho, u = _random_fields(W.Q25_RECT, shape, 13)
         cases.append((W.Q25_RECT, "NSE_INC", W.rates_tau(0.8), shape, rho, u, {}))
-    for storage in ("fp32", "fp16_dev"):
+    for storage in ("fp32", "fp16_dev", "i16_dev"):
         solo, batch = [], []
         for card, eq, rates, shape, r, u, kw in cases:
             for lst in (solo, batch):
@@ -346,7 +352,7 @@ def test_full_size_sampled(ctx):
     assert abs(m_after - wl.rho_or_phi.sum()) < 1e-6 * wl.rho_or_phi.sum()
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16_dev", "fp64"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16_dev", "i16_dev", "fp64"])
 def test_launch_shape_invariance(ctx, storage, monkeypatch):
     """1, 2 or 4 nodes per thread change only the memory access pattern of
     the step kernel: results are bit-identical (and match the oracle)."""

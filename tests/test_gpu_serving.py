@@ -9,7 +9,7 @@ from paper_2512_16230_amd import serving as S
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("storage", ["bf16_dev", "fp32"])
+@pytest.mark.parametrize("storage", ["i16_dev", "bf16_dev", "fp32"])
 def test_served_results_equal_solo_runs(storage):
     reqs = S.request_stream(10, rate=2000.0, seed=11, storage=storage, steps=(20, 80),
                             q25=(64, 160), q13=(128, 200), q33=(24, 40))
