@@ -115,9 +115,12 @@ static int64_t row_pitch(int64_t nx, int storage) {
 // rD2Q25 4096^2 two nodes match four (FP32) and beat it (FP16); rD3Q53 256^3
 // one node beats two by 7%.  MRTLB_STEP_VEC (1, 2 or 4) overrides it for
 // tuning runs.
-static int pick_vec(int storage, int kind, int nx) {
-  (void)storage;
-  int v = (kind == kRD3Q53 || kind == kRD3Q33 || nx < 512) ? 1 : 2;
+static int pick_vec(int storage, int kind, int model, int nx) {
+  // Measured on MI355X: one node per lane on the 3D lattices (register
+  // pressure), for rows under 512 nodes and for the NCDE; otherwise 2 nodes
+  // (FP32/FP64) or 4 nodes (16-bit storage, 8-byte accesses per lane).
+  const bool small = storage != kFP64 && storage != kFP32 && storage != kFP32Dev;
+  int v = (kind == kRD3Q53 || kind == kRD3Q33 || nx < 512 || model == MRTLB_NCDE) ? 1 : (small ? 4 : 2);
   if (const char* e = std::getenv("MRTLB_STEP_VEC")) {
     const int o = std::atoi(e);
     if (o == 1 || o == 2 || o == 4) v = o;
@@ -133,6 +136,7 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   std::memset(&P, 0, sizeof P);
   P.nx = s.nx; P.ny = s.ny; P.nz = s.nz; P.N = s.N;
   P.nxp = s.nxp;
+  P.pop_bytes = (uint32_t)((size_t)L.B * (size_t)s.ny * (size_t)s.nz * (size_t)s.nxp * elem_bytes(s.storage));
   P.inc = s.model.model == MRTLB_NSE_INC;
   P.m30 = s.model.m30 != 0;
   P.cs2 = (Real)L.cs2;
@@ -145,15 +149,18 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   for (int a = 0; a < D; ++a)
     for (int b = 0; b < D; ++b) P.cabb[a][b] = (Real)(L.c[a] * L.c[b] * L.c[b]);
   P.cxyz = D == 3 ? (Real)(L.c[0] * L.c[1] * L.c[2]) : (Real)0;
-  // 16-bit deviation storage, value f - w rho_ref = stored * wsc[j]:
-  // FP16/BF16 store 128 (f - w rho_ref) / w; the int16 fixed point spans
-  // |f - w rho_ref| <= A_j w with 32767 steps (A_j from the caller's flow
-  // bounds, else the uniform kI16Range).
+  // 16-bit deviation storage (see KParams): FP16/BF16 hold
+  // (f - w rho_ref) * 128 / w; int16 holds (f - w rho_ref) / (A_j w) as a
+  // signed 16-bit fraction, A_j from the caller's flow bounds, else the
+  // uniform kI16Range.  Opposite populations share one scale.
   const mrtlb_model_desc& md = s.model;
   const bool bounded = md.u_bound > 0 || md.dev_bound > 0;
+  std::vector<double> unit(L.B, 1.0), inv(L.B, 1.0);
   for (int j = 0; j < L.B; ++j) {
-    double scale = 128.0;
-    if (s.storage == kI16Dev) {
+    if (s.storage == kFP16Dev || s.storage == kBF16Dev) {
+      unit[j] = L.w[j] / 128.0;
+      inv[j] = 128.0 / L.w[j];
+    } else if (s.storage == kI16Dev) {
       double A = kI16Range;
       if (bounded) {
         double cn = 0;
@@ -162,12 +169,25 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
         const double r = md.dev_bound;
         A = 2.0 * (r + (1.0 + r) * (std::expm1(t) + md.u_bound * md.u_bound / (2.0 * L.cs2)));
       }
-      scale = 32767.0 / A;
+      unit[j] = A * L.w[j] / 32767.0;
+      inv[j] = 1.0 / (A * L.w[j]);
     }
-    P.w[j] = (Real)L.w[j];
-    P.wsc[j] = (Real)(L.w[j] / scale);
-    P.iwsc[j] = (Real)(scale / L.w[j]);
   }
+  for (int j = 0; j < L.B; ++j) {
+    int q = j;
+    for (int k = 0; k < L.B; ++k) {
+      bool opp = true;
+      for (int a = 0; a < D; ++a) opp = opp && L.e[k * D + a] == -L.e[j * D + a];
+      if (opp) q = k;
+    }
+    const int src = q < j ? q : j;
+    P.w[j] = (Real)L.w[j];
+    P.wsc[j] = (Real)unit[src];
+    P.iwsc[j] = (Real)inv[src];
+    P.wo[j] = (Real)(s.storage == kFP16Dev || s.storage == kBF16Dev || s.storage == kI16Dev ? L.w[src] * inv[src]
+                                                                                            : L.w[j]);
+  }
+  P.kin = (Real)(s.storage == kI16Dev ? 1.0 / 32767.0 : 1.0);
   for (int a = 0; a < D; ++a) {
     double ksum = 0;
     for (int b = 0; b < D; ++b) {
@@ -426,7 +446,7 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   s->bytes = bytes;
   // step kernel: each thread owns vec consecutive x-slots of the padded rows,
   // a workgroup kBlock * vec consecutive slots
-  s->vec = pick_vec(storage, s->L.kind, s->nx);
+  s->vec = pick_vec(storage, s->L.kind, s->model.model, s->nx);
   const uint32_t slots = (uint32_t)s->ny * (uint32_t)s->nz * (uint32_t)s->nxp;
   s->nblocks = (slots + (uint32_t)(kBlock * s->vec) - 1) / (uint32_t)(kBlock * s->vec);
   s->nblocks_node = (s->N + kBlock - 1) / kBlock;

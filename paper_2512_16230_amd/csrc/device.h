@@ -8,11 +8,12 @@
 // Boltzmann method (arXiv 2512.16230): fused pull collide-and-stream,
 // initialisation, moment read-out, checkpoint and FP64 conserved sums.
 //
-// Layout in HBM: populations structure-of-arrays, f[j][z][y][x] (x fastest),
-// two buffers (pull propagation, double-buffered).  The buffer holds the
-// post-collision populations of the previous step, so f_bar_j(x, t) =
-// buf_j(x - e_j): a step gathers along -e_j, collides in registers and
-// writes every population at its own node (coalesced stores).
+// Layout in HBM: populations row-blocked (see RowGeom: every grid row holds
+// its b population rows back to back, x fastest), two buffers (pull
+// propagation, double-buffered).  The buffer holds the post-collision
+// populations of the previous step, so f_bar_j(x, t) = buf_j(x - e_j): a
+// step gathers along -e_j, collides in registers and writes every
+// population at its own node (coalesced stores).
 //
 // Collision (per node, registers only).  With the component Hermite rows of
 // order <= 3 (H0 = 1, H1 = c, H2 = cc - cs^2, H3 mixed / xyz / corrected
@@ -144,6 +145,18 @@ struct RowGeom {
   __device__ __forceinline__ uint32_t prow() const { return (row<J>() * (uint32_t)L::B + J) * (uint32_t)nxp; }
   // first element of population j's own row
   __device__ __forceinline__ uint32_t pown(int j) const { return (own_row() * (uint32_t)L::B + j) * (uint32_t)nxp; }
+  // The step kernel splits an element index into a wave-uniform part, added
+  // to the buffer pointer in scalar registers, and a per-lane part that
+  // depends on the source row only (plus, at the periodic x-edges, on e_x):
+  //   source of population J (J >= 1):  uni = J nxp - e_Jx - M,
+  //                                     lane = row_J b nxp + (x_src + e_Jx + M)
+  //   own row:                          uni = J nxp, lane = own b nxp + x.
+  // Both parts are non-negative (nxp >= 32 > 2M) and sum to the index.
+  template <int J>
+  __device__ __forceinline__ uint32_t lrow() const { return row<J>() * (uint32_t)L::B * (uint32_t)nxp; }
+  __device__ __forceinline__ uint32_t lown() const { return own_row() * (uint32_t)L::B * (uint32_t)nxp; }
+  template <int J>
+  __device__ __forceinline__ uint32_t uni_src() const { return (uint32_t)(J * nxp - L::EX[J] - M); }
   // element of the source of population J for node ix (periodic in x)
   template <int J>
   __device__ __forceinline__ uint32_t src(int ix) const { return prow<J>() + (uint32_t)wrap(ix - L::EX[J], nx); }
@@ -175,50 +188,81 @@ struct VecT {
 #define MRTLB_NT 1
 #endif
 
-template <class T>
-__device__ __forceinline__ T gload_nt(const void* base, uint32_t byteoff) {
-  const MRTLB_GLOBAL char* p = (const MRTLB_GLOBAL char*)base;
-#if MRTLB_NT
-  return __builtin_nontemporal_load((const MRTLB_GLOBAL T*)(p + byteoff));
-#else
-  return *(const MRTLB_GLOBAL T*)(p + byteoff);
-#endif
+// The step kernel reads and writes population buffers through buffer
+// resources (MUBUF): the base address lives in the resource, the wave-uniform
+// part of an offset in soffset (SGPR) and each lane supplies one 32-bit byte
+// offset, so per population no per-lane address arithmetic is needed.
+// Accesses beyond the resource's size read 0 / are dropped.
+constexpr int kBufFlags = 0x00020000;   // dword 3 of a raw buffer resource (gfx9 family)
+constexpr int kAuxNT = MRTLB_NT ? 2 : 0; // cache policy: nontemporal (gfx94x/gfx950 encoding)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kBufFlags);
 }
 
-template <class T>
-__device__ __forceinline__ void gstore_nt(void* base, uint32_t byteoff, T v) {
-  MRTLB_GLOBAL char* p = (MRTLB_GLOBAL char*)base;
-#if MRTLB_NT
-  __builtin_nontemporal_store(v, (MRTLB_GLOBAL T*)(p + byteoff));
-#else
-  *(MRTLB_GLOBAL T*)(p + byteoff) = v;
-#endif
+template <int BYTES>
+struct RawChunk;
+template <>
+struct RawChunk<2> { using T = unsigned short; };
+template <>
+struct RawChunk<4> { using T = unsigned int; };
+template <>
+struct RawChunk<8> { typedef unsigned int T __attribute__((ext_vector_type(2))); };
+template <>
+struct RawChunk<16> { typedef unsigned int T __attribute__((ext_vector_type(4))); };
+
+template <int BYTES>
+__device__ __forceinline__ typename RawChunk<BYTES>::T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (BYTES == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kAuxNT);
+  else if constexpr (BYTES == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kAuxNT);
+  else if constexpr (BYTES == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, kAuxNT);
+  else return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, kAuxNT);
 }
 
+template <int BYTES>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, typename RawChunk<BYTES>::T v, uint32_t voff,
+                                          uint32_t soff) {
+  if constexpr (BYTES == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, (int)soff, kAuxNT);
+  else if constexpr (BYTES == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, kAuxNT);
+  else if constexpr (BYTES == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, kAuxNT);
+  else __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, kAuxNT);
+}
+
+// VEC consecutive stored elements starting at element (uni + lane): uni is
+// wave-uniform, lane per lane.  Loads start at any element (the pull shift);
+// vectors wider than 16 bytes are split into 16-byte pieces.
 template <int ST, int VEC>
-__device__ __forceinline__ void load_vec(const void* buf, uint32_t i, typename StoreT<ST>::T (&out)[VEC]) {
+__device__ __forceinline__ void load_vec(__amdgpu_buffer_rsrc_t r, uint32_t uni, uint32_t lane,
+                                         typename StoreT<ST>::T (&out)[VEC]) {
   using T = typename StoreT<ST>::T;
-  if constexpr (VEC == 1) {
-    out[0] = gload_nt<T>(buf, i * (uint32_t)sizeof(T));
-  } else {
-    using V = typename VecT<T, VEC, sizeof(T)>::type;
-    const V v = gload_nt<V>(buf, i * (uint32_t)sizeof(T));
+  constexpr int BYTES = VEC * (int)sizeof(T);
+  constexpr int PIECE = BYTES > 16 ? 16 : BYTES;
+  constexpr int PER = PIECE / (int)sizeof(T);
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) out[k] = v[k];
+  for (int c = 0; c < VEC / PER; ++c) {
+    const auto v = buf_load<PIECE>(r, lane * (uint32_t)sizeof(T), (uni + (uint32_t)(c * PER)) * (uint32_t)sizeof(T));
+    struct Elems { T e[PER]; };
+    const Elems el = __builtin_bit_cast(Elems, v);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) out[c * PER + k] = el.e[k];
   }
 }
 
 template <int ST, int VEC>
-__device__ __forceinline__ void store_vec(void* buf, uint32_t i, const typename StoreT<ST>::T (&in)[VEC]) {
+__device__ __forceinline__ void store_vec(__amdgpu_buffer_rsrc_t r, uint32_t uni, uint32_t lane,
+                                          const typename StoreT<ST>::T (&in)[VEC]) {
   using T = typename StoreT<ST>::T;
-  if constexpr (VEC == 1) {
-    gstore_nt<T>(buf, i * (uint32_t)sizeof(T), in[0]);
-  } else {
-    using V = typename VecT<T, VEC, VEC * sizeof(T)>::type;
-    V v;
+  constexpr int BYTES = VEC * (int)sizeof(T);
+  constexpr int PIECE = BYTES > 16 ? 16 : BYTES;
+  constexpr int PER = PIECE / (int)sizeof(T);
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) v[k] = in[k];
-    gstore_nt<V>(buf, i * (uint32_t)sizeof(T), v);
+  for (int c = 0; c < VEC / PER; ++c) {
+    struct Elems { T e[PER]; };
+    Elems el;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) el.e[k] = in[c * PER + k];
+    buf_store<PIECE>(r, __builtin_bit_cast(typename RawChunk<PIECE>::T, el), lane * (uint32_t)sizeof(T),
+                     (uni + (uint32_t)(c * PER)) * (uint32_t)sizeof(T));
   }
 }
 
@@ -233,14 +277,56 @@ __device__ __forceinline__ float pin(float v) {
   return v;
 }
 
+// Storage with a per-population scale (the 16-bit deviation formats).
+template <int ST>
+constexpr bool scaled_storage() { return ST == kFP16Dev || ST == kBF16Dev || ST == kI16Dev; }
+
+// The number a stored element reads as (before its scale).
+template <int ST>
+__device__ __forceinline__ typename StoreT<ST>::Real units(typename StoreT<ST>::T v) {
+  using Real = typename StoreT<ST>::Real;
+  if constexpr (ST == kFP16Dev) {
+    return (float)v;
+  } else if constexpr (ST == kBF16Dev) {
+    return bf16_to_f32(v);
+  } else if constexpr (ST == kI16Dev) {
+    return (float)(int)v;
+  } else {
+    return (Real)v;
+  }
+}
+
+// int16 fixed point: round(clamp(o, -1, 1) * 32767) to the nearest integer
+// of the exact product, two values per instruction (v_cvt_pknorm_i16_f32).
+typedef short mrtlb_short2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void snorm16x2(float a, float b, int16_t& qa, int16_t& qb) {
+  const mrtlb_short2 r = __builtin_amdgcn_cvt_pknorm_i16(a, b);
+  qa = r[0];
+  qb = r[1];
+}
+
+// Output number -> stored element.  FP16/BF16 round the FP32 value to
+// nearest even; int16 as snorm16x2.
+template <int ST>
+__device__ __forceinline__ typename StoreT<ST>::T to_stored(typename StoreT<ST>::Real o) {
+  using T = typename StoreT<ST>::T;
+  if constexpr (ST == kFP16Dev) {
+    return (_Float16)pin(o);
+  } else if constexpr (ST == kBF16Dev) {
+    return f32_to_bf16_rne(o);
+  } else if constexpr (ST == kI16Dev) {
+    int16_t q, unused;
+    snorm16x2(o, 0.0f, q, unused);
+    return q;
+  } else {
+    return (T)o;
+  }
+}
+
 template <int ST, class Real>
 __device__ __forceinline__ Real decode(typename StoreT<ST>::T v, const KParams<Real>& P, int j) {
-  if constexpr (ST == kFP16Dev) {
-    return (Real)pin((float)v * (float)P.wsc[j]);
-  } else if constexpr (ST == kBF16Dev) {
-    return (Real)pin(bf16_to_f32(v) * (float)P.wsc[j]);
-  } else if constexpr (ST == kI16Dev) {
-    return (Real)pin((float)(int)v * (float)P.wsc[j]);
+  if constexpr (scaled_storage<ST>()) {
+    return (Real)pin(units<ST>(v) * (float)P.wsc[j]);
   } else {
     return (Real)v;
   }
@@ -249,14 +335,8 @@ __device__ __forceinline__ Real decode(typename StoreT<ST>::T v, const KParams<R
 template <int ST, class Real>
 __device__ __forceinline__ typename StoreT<ST>::T encode(Real v, const KParams<Real>& P, int j) {
   using T = typename StoreT<ST>::T;
-  if constexpr (ST == kFP16Dev) {
-    return (_Float16)pin((float)v * (float)P.iwsc[j]);
-  } else if constexpr (ST == kBF16Dev) {
-    return f32_to_bf16_rne(pin((float)v * (float)P.iwsc[j]));
-  } else if constexpr (ST == kI16Dev) {
-    // fixed point: round to nearest even, saturate at +-32767
-    const float q = __builtin_rintf(pin((float)v * (float)P.iwsc[j]));
-    return (int16_t)(int)fminf(fmaxf(q, -32767.0f), 32767.0f);
+  if constexpr (scaled_storage<ST>()) {
+    return to_stored<ST>(pin((float)v * (float)P.iwsc[j]));
   } else {
     return (T)v;
   }
@@ -284,19 +364,24 @@ struct Moments {
   Real m1[3], m2n[3], m2o[3], m3m[3][3], m3p[3], mxyz;
 };
 
-// Hermite moments (component rows, physical units) of x[0..B-1].
-template <class L, class Real>
+// Hermite moments (component rows, physical units) of x[0..B-1].  SCALED:
+// x holds read numbers, population j is x_j * wsc[j] (one scale per pair).
+template <class L, bool SCALED, class Real>
 __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Real>& P, Moments<Real>& M) {
   constexpr int D = L::D;
-  Real R0 = x[0];
+  Real R0 = SCALED ? x[0] * P.wsc[0] : x[0];
   Real R1[3] = {0, 0, 0}, R2n[3] = {0, 0, 0}, R2o[3] = {0, 0, 0}, R3p[3] = {0, 0, 0};
   Real R3m[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   Real Rxyz = 0;
   static_for<0, n_pairs<L>()>([&](auto kk) {
     constexpr int p = pair_first<L>(decltype(kk)::value);
     constexpr int q = opposite<L>(p);
-    const Real s = x[p] + x[q];
-    const Real d = x[p] - x[q];
+    Real s = x[p] + x[q];
+    Real d = x[p] - x[q];
+    if constexpr (SCALED) {
+      s *= P.wsc[p];
+      d *= P.wsc[p];
+    }
     R0 += s;
     static_for<0, D>([&](auto aa) {
       constexpr int a = decltype(aa)::value;
@@ -344,11 +429,13 @@ __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Rea
 
 // Per-row coefficients delta_r = (target_r) / n_r turned into monomial
 // coefficients in lattice units, then evaluated per velocity pair:
-//   x_j <- kx * x_j + w_j * sum_P beta_P e_j^P
+//   x_j <- kx * x_j + wo_j * sum_P beta_P e_j^P
+// (wo = w for populations in physical units; see KParams for the 16-bit
+// storages, whose output numbers it writes directly).
 template <class L, class Real>
-__device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P, Real kx, Real d0, const Real* d1,
-                                         const Real* d2n, const Real* d2o, const Real (*d3m)[3], const Real* d3p,
-                                         Real dxyz) {
+__device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P, Real kx, const Real* wo, Real d0,
+                                         const Real* d1, const Real* d2n, const Real* d2o, const Real (*d3m)[3],
+                                         const Real* d3p, Real dxyz) {
   constexpr int D = L::D;
   Real b0 = d0;
   Real b1[3], b2n[3], b2o[3], b3m[3][3], b3p[3];
@@ -373,7 +460,7 @@ __device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P
     for (int b = a + 1; b < D; ++b) b2o[off_index(a, b)] = P.cab[off_index(a, b)] * d2o[off_index(a, b)];
   Real bxyz = 0;
   if constexpr (D == 3) bxyz = P.cxyz * dxyz;
-  x[0] = kx * x[0] + P.w[0] * b0;
+  x[0] = kx * x[0] + wo[0] * b0;
   static_for<0, n_pairs<L>()>([&](auto kk) {
     constexpr int p = pair_first<L>(decltype(kk)::value);
     constexpr int q = opposite<L>(p);
@@ -396,7 +483,7 @@ __device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P
       constexpr int exyz = evel<L>(p, 0) * evel<L>(p, 1) * evel<L>(p, 2);
       if constexpr (exyz != 0) odd += Real(exyz) * bxyz;
     }
-    const Real wp = P.w[p];
+    const Real wp = wo[p];
     x[p] = kx * x[p] + wp * (even + odd);
     x[q] = kx * x[q] + wp * (even - odd);
   });
@@ -511,7 +598,7 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
 
   // a3: forward Hermite moments
   Moments<Real> M;
-  forward<L>(x, P, M);
+  forward<L, scaled_storage<ST>()>(x, P, M);
 
   // a2: conserved variables, a5: sources
   Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
@@ -611,8 +698,8 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   // order 0 is conserved: m*_0 = m_0
   const Real d0 = P.sh * M.R0 * P.in0;
 
-  // a7: back to populations
-  backward<L>(x, P, kx, d0, d1, d2n, d2o, d3m, d3p, dxyz);
+  // a7: back to populations (output numbers of the storage)
+  backward<L>(x, P, kx * P.kin, P.wo, d0, d1, d2n, d2o, d3m, d3p, dxyz);
 }
 
 // ---------------------------------------------------------------------------
@@ -640,51 +727,74 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t N = P.N;
 
-  // a1: gather along -e_j
+  // a1: gather along -e_j.  The rest population (e = 0) is read at the
+  // own node; population j >= 1 at uniform base + lane offset (RowGeom).
+  static_assert(L::EX[0] == 0 && L::EY[0] == 0, "population 0 is the rest velocity");
+  const auto rin = make_rsrc(J.fin, P.pop_bytes);
   T raw[B][VEC];
-  if constexpr (VEC == 1) {
-    // one node per lane: every lane wraps its own index, no divergent path
-    static_for<0, B>([&](auto jj) {
+  // one node per lane: a wave-uniform choice, so no wave runs both paths
+  const bool inside = ix0 >= M && ix0 + VEC - 1 + M < P.nx;
+  const bool interior = VEC == 1 ? __all(inside) != 0 : inside;
+  if (interior) {
+    // whole VEC-runs inside the row: the lane part depends on the row only
+    const uint32_t lx = (uint32_t)(ix0 + M);
+    load_vec<ST, VEC>(rin, 0u, g.lown() + (uint32_t)ix0, raw[0]);
+    static_for<1, B>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
-      T one[1];
-      load_vec<ST, 1>(J.fin, g.template src<j>(ix0), one);
-      raw[j][0] = one[0];
-    });
-  } else if (ix0 >= M && ix0 + VEC - 1 + M < P.nx) {
-    static_for<0, B>([&](auto jj) {
-      constexpr int j = decltype(jj)::value;
-      load_vec<ST, VEC>(J.fin, g.template prow<j>() + (uint32_t)(ix0 - L::EX[j]), raw[j]);
+      load_vec<ST, VEC>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx, raw[j]);
     });
   } else {
-    static_for<0, B>([&](auto jj) {
-      constexpr int j = decltype(jj)::value;
+    // per node: x_src = wrap(x - e_x); one lane offset per distinct e_x
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        T one[1];
-        load_vec<ST, 1>(J.fin, g.template src<j>(ix0 + k), one);
+    for (int k = 0; k < VEC; ++k) {
+      uint32_t lx[2 * M + 1];
+#pragma unroll
+      for (int e = -M; e <= M; ++e) lx[e + M] = (uint32_t)(wrap(ix0 + k - e, P.nx) + e + M);
+      T one[1];
+      load_vec<ST, 1>(rin, 0u, g.lown() + (uint32_t)(ix0 + k), one);
+      raw[0][k] = one[0];
+      static_for<1, B>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        load_vec<ST, 1>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx[L::EX[j] + M], one);
         raw[j][k] = one[0];
-      }
-    });
+      });
+    }
   }
 
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) {
+  // a2-a7 in registers: x holds the numbers the storage reads as, the
+  // back-transform leaves the numbers it writes (equal for FP32/FP64).  The
+  // int16 format converts two nodes per instruction: an even node's output
+  // waits in keep[] for the odd one.
+  Real keep[ST == kI16Dev && VEC > 1 ? B : 1];
+  static_for<0, VEC>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
     Real x[B];
     static_for<0, B>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
-      x[j] = decode<ST>(raw[j][k], P, j);
+      x[j] = units<ST>(raw[j][k]);
     });
     collide_node<L, ST, MODEL, FORCE>(x, J, g, ix0 + k);
     static_for<0, B>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
-      raw[j][k] = encode<ST>(x[j], P, j);
+      if constexpr (ST == kI16Dev && VEC == 1) {
+        int16_t unused;
+        snorm16x2(x[j], 0.0f, raw[j][0], unused);
+      } else if constexpr (ST == kI16Dev && k % 2 == 0) {
+        keep[j] = x[j];
+      } else if constexpr (ST == kI16Dev) {
+        snorm16x2(keep[j], x[j], raw[j][k - 1], raw[j][k]);
+      } else {
+        raw[j][k] = to_stored<ST>(x[j]);
+      }
     });
-  }
+  });
 
   // a8: store at the own nodes
+  const auto rout = make_rsrc(J.fout, P.pop_bytes);
+  const uint32_t lo = g.lown() + (uint32_t)ix0;
   static_for<0, B>([&](auto jj) {
     constexpr int j = decltype(jj)::value;
-    store_vec<ST, VEC>(J.fout, g.pown(j) + (uint32_t)ix0, raw[j]);
+    store_vec<ST, VEC>(rout, (uint32_t)j * (uint32_t)P.nxp, lo, raw[j]);
   });
 }
 
@@ -749,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   double x[B];
   for (int j = 0; j < B; ++j) x[j] = 0;
   const double d0 = R * P.in0 - P.rho_ref;
-  backward<L>(x, P, 0.0, d0, d1, d2n, d2o, d3m, d3p, dxyz);
+  backward<L>(x, P, 0.0, P.w, d0, d1, d2n, d2o, d3m, d3p, dxyz);
   const KParams<Real>& PR = J.P;
   static_for<0, B>([&](auto jj) {
     constexpr int j = decltype(jj)::value;

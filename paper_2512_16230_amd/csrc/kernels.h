@@ -11,8 +11,8 @@ constexpr int kMaxB = 53;
 constexpr int kBlock = 256;         // threads per workgroup of every node kernel
 constexpr int kNumXcd = 8;          // MI355X: 8 XCDs, workgroups dealt round-robin
 
-constexpr int kChunkIters = 16;
-constexpr double kI16Range = 2.0;   // int16 deviation storage spans |f - w rho_ref| <= 2 w    // elements per thread of one plane-sum chunk
+constexpr int kChunkIters = 16;      // elements per thread of one plane-sum chunk
+constexpr double kI16Range = 2.0;    // default int16 range: |f - w rho_ref| <= 2 w
 
 // Index of the off-diagonal pair (a, b), a < b: xy -> 0, xz -> 1, yz -> 2.
 constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
@@ -27,6 +27,7 @@ struct KParams {
   int nx, ny, nz;
   int nxp;                  // population row pitch in elements (nx padded to 128 bytes)
   uint32_t N;               // nodes
+  uint32_t pop_bytes;       // bytes of one population buffer (< 4 GiB)
   int inc;                  // NSE: incompressible (rho_m = rho0) or compressible (rho_m = rho)
   int m30;                  // NSE: third-order equilibrium moments rho uuu
   Real cs2;
@@ -35,8 +36,19 @@ struct KParams {
   Real cabb[3][3];          // c_a c_b^2
   Real cxyz;
   Real w[kMaxB];            // weights
-  Real wsc[kMaxB];          // 16-bit deviation storage: value = stored * wsc[j]
-  Real iwsc[kMaxB];         //                           stored = value * iwsc[j]
+  // 16-bit deviation storage.  A stored element s_j reads as the number
+  // u_j (FP16/BF16: its value; int16: the integer) and means the deviation
+  // f_j - w_j rho_ref = u_j * wsc[j]; it is written from an output number o_j
+  // (FP16/BF16: o_j = u_j; int16: o_j = u_j / 32767 in [-1, 1]) with
+  // o_j = (f_j - w_j rho_ref) * iwsc[j].  Opposite populations share wsc and
+  // iwsc.  The step kernel's back-transform writes output numbers directly:
+  // o_j = kin * kx * u_j + wo[j] * (...) with wo[j] = w_j * iwsc[j] and kin
+  // = output numbers per read number (1, or 1/32767 for int16).  For the
+  // other storages wsc = iwsc = kin = 1 and wo = w.
+  Real wsc[kMaxB];
+  Real iwsc[kMaxB];
+  Real wo[kMaxB];
+  Real kin;
   Real corr[3][3];          // correction coefficients of the pure third-order rows
   Real k3[3];               // -3 cs^2 + cs^2 sum_b corr[a][b]
   Real in0, in1[3], in2n[3], in2o[3], in3m[3][3], in3p[3], inxyz;  // 1 / norms
