@@ -199,6 +199,21 @@ mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);
  * events recorded on the context stream around the launches (synchronous). */
 mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms);
 
+/* Drift correction of the conserved totals.  The collision conserves mass,
+ * and momentum without a force, exactly (Sec. II, eq. M-NSEs-1); the
+ * rounding of the stored populations does not.  With every > 0, after each
+ * `every` steps of mrtlb_step / mrtlb_batch_step the library takes the FP64
+ * totals of the populations (mass: rho_bar, rho or phi; momentum for the NSE
+ * models without a force) and adds their difference to the totals recorded
+ * at the reference point, spread evenly over the nodes, to the zeroth and
+ * first moments of the next step's collision.  The reference point is the
+ * latest of mrtlb_init_fields, mrtlb_write_populations and this call.  Each
+ * check costs one FP64 reduction pass over the populations and a host
+ * synchronisation.  every = 0 (the default) turns it off.
+ * Errors: EINVAL (NULL solve, every < 0), EDEVICE, ENUMERIC (non-finite
+ * state at the reference point). */
+mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every);
+
 /* Advance solve i of the array by nsteps[i] >= 0 steps.  Solves that share
  * lattice, model, storage and force go into one kernel launch per step (the
  * ones that have finished drop out of later launches); groups run one after

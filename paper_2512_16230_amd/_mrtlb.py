@@ -81,6 +81,7 @@ def lib():
         "mrtlb_batch_step": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int64)]),
         "mrtlb_read_moments": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
+        "mrtlb_set_drift_correction": (c_int, [c_void_p, c_int64]),
         "mrtlb_read_populations": (c_int, [c_void_p, _DP]),
         "mrtlb_write_populations": (c_int, [c_void_p, _DP]),
         "mrtlb_solve_steps": (c_int64, [c_void_p]),
@@ -97,7 +98,7 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_ctx_synchronize", "mrtlb_lattice_create", "mrtlb_lattice_destroy", "mrtlb_lattice_query",
             "mrtlb_solve_create", "mrtlb_solve_footprint", "mrtlb_solve_destroy", "mrtlb_init_fields",
             "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
-            "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps"]
+            "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction"]
 
 
 def _check(status):
@@ -270,6 +271,11 @@ class Solve:
         _check(lib().mrtlb_read_moments(self.h, _ptr(r), _ptr(u)))
         r = r.reshape(self.shape)
         return (r, u.reshape((self.d,) + self.shape)) if with_u else r
+
+    def set_drift_correction(self, every):
+        """FP64 check of the conserved totals every ``every`` steps, the
+        difference applied on the next step (0 turns it off)."""
+        _check(lib().mrtlb_set_drift_correction(self.h, int(every)))
 
     def conserved(self):
         m = c_double()

@@ -24,6 +24,10 @@ FLAGS = [
     "-fPIC",
     # packed FP32 instructions stay off: ordinary scalar FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a * b + c is fused only inside one source expression, never across
+    # statements: every unrolled copy of the collision rounds the same way,
+    # so results do not depend on the nodes-per-thread launch shape
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",

@@ -82,6 +82,17 @@ struct mrtlb_solve {
   int vec = 1;
   uint32_t nblocks = 0;         // workgroups of one step launch
   uint32_t nblocks_node = 0;    // workgroups of the one-thread-per-node kernels
+  // drift correction: FP64 check every drift_every steps against the sums
+  // recorded at the reference point; a pending correction rides on the next
+  // step (job slot 2)
+  int64_t drift_every = 0;
+  int64_t since_check = 0;
+  bool have_ref = false;
+  double ref_mass = 0, ref_mom[3] = {0, 0, 0};
+  bool pending = false;
+  double dm0 = 0, dm1[3] = {0, 0, 0};
+  void* part = nullptr;         // FP64 partial sums of the plane-sum kernel
+  size_t part_bytes = 0;
 };
 
 namespace mrtlb {
@@ -385,7 +396,7 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
   size_t b = 2 * (size_t)lat->L.B * (size_t)(rows * row_pitch(n[0], storage)) * elem_bytes(storage);
   if (has_force) b += (size_t)D * (size_t)N * real;
   if (model == MRTLB_NCDE) b += 2 * (size_t)N * real;
-  b += 2 * sizeof(Job<double>) + sizeof(KParams<double>);
+  b += 3 * sizeof(Job<double>) + sizeof(KParams<double>);
   *bytes = b;
   return MRTLB_OK;
 }
@@ -393,7 +404,7 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
 static void release(mrtlb_solve* s) {
   if (!s) return;
   (void)hipSetDevice(s->ctx->device);
-  for (void* p : {s->f[0], s->f[1], s->force, s->phi[0], s->phi[1], s->jobs, s->pd})
+  for (void* p : {s->f[0], s->f[1], s->force, s->phi[0], s->phi[1], s->jobs, s->pd, s->part})
     if (p) (void)hipFree(p);
 }
 
@@ -455,7 +466,7 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   const size_t real = is_double(storage) ? 8 : 4;
   auto alloc = [&](void** p, size_t sz) { return hipMalloc(p, sz) == hipSuccess; };
   bool ok = alloc(&s->f[0], pop) && alloc(&s->f[1], pop) &&
-            alloc(&s->jobs, 2 * std::max(sizeof(Job<double>), sizeof(Job<float>))) &&
+            alloc(&s->jobs, 3 * std::max(sizeof(Job<double>), sizeof(Job<float>))) &&
             alloc(&s->pd, sizeof(KParams<double>));
   if (ok && has_force) ok = alloc(&s->force, (size_t)D * s->N * real);
   if (ok && model->model == MRTLB_NCDE) ok = alloc(&s->phi[0], s->N * real) && alloc(&s->phi[1], s->N * real);
@@ -492,6 +503,110 @@ struct DevBuf {
   void* p = nullptr;
   ~DevBuf() { if (p) (void)hipFree(p); }
 };
+
+// FP64 mass and momentum of the solve's current state: per-plane partial
+// sums on the device (fixed order), then a fixed-order sum on the host.
+static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
+  const int B = s->L.B, D = s->L.D;
+  const int nf = s->force ? D : 0;
+  const int planes = B + nf;
+  const uint32_t chunk = kBlock * kChunkIters;
+  const uint32_t nchunks = (s->N + chunk - 1) / chunk;
+  const size_t need = (size_t)planes * nchunks * 8;
+  if (need > s->part_bytes) {
+    if (s->part) HIP_TRY(hipFree(s->part));
+    s->part = nullptr;
+    s->part_bytes = 0;
+    HIP_TRY(hipMalloc(&s->part, need));
+    s->part_bytes = need;
+  }
+  hipStream_t st = s->ctx->stream;
+  // KParams is the first member of the job in device memory
+  const void* params = job_ptr(*s, s->cur);
+  hipError_t err = launch_plane_sums(s->storage, s->f[s->cur], s->N, B, s->force, nf, params, (double*)s->part,
+                                     nchunks, st);
+  if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("sum launch: ") + hipGetErrorString(err));
+  std::vector<double> h((size_t)planes * nchunks);
+  HIP_TRY(hipMemcpyAsync(h.data(), s->part, h.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<double> plane(planes, 0.0);
+  for (int p = 0; p < planes; ++p)
+    for (uint32_t c = 0; c < nchunks; ++c) plane[p] += h[(size_t)p * nchunks + c];
+  double m = 0, mom[3] = {0, 0, 0};
+  const double ref = s->storage != kFP64 && s->storage != kFP32 && s->model.model != MRTLB_NCDE
+                         ? s->model.rho0
+                         : 0.0;
+  for (int j = 0; j < B; ++j) {
+    m += plane[j];
+    for (int a = 0; a < D; ++a) mom[a] += s->L.c[a] * s->L.e[j * D + a] * plane[j];
+  }
+  m += ref * (double)s->N;
+  for (int a = 0; a < nf; ++a) mom[a] += 0.5 * plane[B + a];
+  bool finite = std::isfinite(m);
+  for (int a = 0; a < D; ++a) finite = finite && std::isfinite(mom[a]);
+  *mass = m;
+  if (momentum)
+    for (int a = 0; a < 3; ++a) momentum[a] = a < D ? mom[a] : 0.0;
+  if (!finite) return fail(MRTLB_ENUMERIC, "non-finite value in the solve's state");
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum) {
+  if (!s || !mass) return fail(MRTLB_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  double m = 0, mom[3] = {0, 0, 0};
+  mrtlb_status st = state_sums(s, &m, mom);
+  *mass = m;
+  if (momentum)
+    for (int a = 0; a < s->L.D; ++a) momentum[a] = mom[a];
+  return st;
+}
+
+// Momentum is a conserved total only for the NSE models without a force.
+static bool corrects_momentum(const mrtlb_solve* s) { return s->model.model != MRTLB_NCDE && !s->has_force; }
+
+static mrtlb_status record_reference(mrtlb_solve* s) {
+  s->have_ref = false;
+  s->pending = false;
+  s->since_check = 0;
+  if (s->drift_every <= 0) return MRTLB_OK;
+  mrtlb_status st = state_sums(s, &s->ref_mass, s->ref_mom);
+  if (st != MRTLB_OK) return st;
+  s->have_ref = true;
+  return MRTLB_OK;
+}
+
+// After drift_every steps: FP64 totals against the reference; the per-node
+// difference is applied on the next step.
+static mrtlb_status drift_check(mrtlb_solve* s) {
+  s->since_check = 0;
+  if (!s->have_ref) return record_reference(s);
+  double m = 0, mom[3] = {0, 0, 0};
+  mrtlb_status st = state_sums(s, &m, mom);
+  if (st != MRTLB_OK) return st;
+  const double n = (double)s->N;
+  s->dm0 = (s->ref_mass - m) / n;
+  for (int a = 0; a < 3; ++a) s->dm1[a] = corrects_momentum(s) && a < s->L.D ? (s->ref_mom[a] - mom[a]) / n : 0.0;
+  s->pending = true;
+  return MRTLB_OK;
+}
+
+template <class Real>
+static KParams<Real> with_drift(const mrtlb_solve& s, KParams<Real> P) {
+  if (s.pending) {
+    P.dm0 = (Real)s.dm0;
+    for (int a = 0; a < 3; ++a) P.dm1[a] = (Real)s.dm1[a];
+  }
+  return P;
+}
+
+mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every) {
+  if (!s) return fail(MRTLB_EINVAL, "solve is NULL");
+  if (every < 0) return fail(MRTLB_EINVAL, "every must be >= 0");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  s->drift_every = every;
+  return record_reference(s);
+}
 
 mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* u, const double* force) {
   if (!s || !rho) return fail(MRTLB_EINVAL, "NULL argument");
@@ -536,7 +651,7 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
   hipError_t err = dispatch(s->L.kind, r);
   if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("init launch: ") + hipGetErrorString(err));
   HIP_TRY(hipStreamSynchronize(st));
-  return MRTLB_OK;
+  return record_reference(s);
 }
 
 mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps) {
@@ -544,10 +659,30 @@ mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps) {
   if (nsteps < 0) return fail(MRTLB_EINVAL, "nsteps must be >= 0");
   HIP_TRY(hipSetDevice(s->ctx->device));
   for (int64_t k = 0; k < nsteps; ++k) {
-    hipError_t e = dispatch(s->L.kind, base_req(*s, kOpStep, job_ptr(*s, s->cur)));
+    const void* jp = job_ptr(*s, s->cur);
+    if (s->pending) {
+      // the corrected step runs from job slot 2
+      void* slot = static_cast<char*>(s->jobs) + 2 * (is_double(s->storage) ? sizeof(Job<double>) : sizeof(Job<float>));
+      if (is_double(s->storage)) {
+        const Job<double> J = make_job(*s, s->cur, with_drift(*s, s->Pd));
+        HIP_TRY(hipMemcpyAsync(slot, &J, sizeof J, hipMemcpyHostToDevice, s->ctx->stream));
+        HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+      } else {
+        const Job<float> J = make_job(*s, s->cur, with_drift(*s, s->Pf));
+        HIP_TRY(hipMemcpyAsync(slot, &J, sizeof J, hipMemcpyHostToDevice, s->ctx->stream));
+        HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+      }
+      jp = slot;
+      s->pending = false;
+    }
+    hipError_t e = dispatch(s->L.kind, base_req(*s, kOpStep, jp));
     if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     s->cur ^= 1;
     s->steps += 1;
+    if (s->drift_every > 0 && ++s->since_check >= s->drift_every) {
+      mrtlb_status st = drift_check(s);
+      if (st != MRTLB_OK) return st;
+    }
   }
   return MRTLB_OK;
 }
@@ -582,47 +717,71 @@ static mrtlb_status reserve_jobs(mrtlb_ctx* c, size_t bytes) {
 
 // One group (same lattice, storage, model, force, nodes per thread).  Members
 // are ordered by decreasing step count, so the solves still running at step
-// k form a prefix of the job table: launch k covers jobs [0, m_k).  Two
-// tables (one per parity of the ping-pong buffers) hold each member's job for
-// its even and odd steps of this call.
+// k form a prefix of the job table: launch k covers jobs [0, m_k).  The call
+// runs in segments that end where a member with drift correction is due for
+// its FP64 check (one segment without drift correction).  Per segment three
+// tables are uploaded: the first launch (pending corrections applied) and
+// one per parity of the ping-pong buffers for the later launches.
 template <class Real>
 static mrtlb_status batch_group(std::vector<std::pair<mrtlb_solve*, int64_t>>& g) {
   std::stable_sort(g.begin(), g.end(), [](const auto& a, const auto& b) { return a.second > b.second; });
   const int n = (int)g.size();
   mrtlb_ctx* c = g[0].first->ctx;
-  mrtlb_status rs = reserve_jobs(c, 2 * (size_t)n * sizeof(Job<Real>));
+  mrtlb_status rs = reserve_jobs(c, 3 * (size_t)n * sizeof(Job<Real>));
   if (rs != MRTLB_OK) return rs;
-  // the previous call's copy out of the staging buffer has completed: every
-  // batched call ends with a stream synchronization
-  Job<Real>* jobs = static_cast<Job<Real>*>(c->job_host);
-  std::vector<uint32_t> prefix(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    const mrtlb_solve& s = *g[i].first;
-    const KParams<Real>& P = *reinterpret_cast<const KParams<Real>*>(is_double(s.storage) ? (const void*)&s.Pd
-                                                                                          : (const void*)&s.Pf);
-    for (int par = 0; par < 2; ++par) {
-      Job<Real> J = make_job(s, s.cur ^ par, P);
-      J.block_begin = prefix[i];
-      jobs[(size_t)par * n + i] = J;
-    }
-    prefix[i + 1] = prefix[i] + s.nblocks;
-  }
   hipStream_t st = c->stream;
-  HIP_TRY(hipMemcpyAsync(c->job_dev, jobs, 2 * (size_t)n * sizeof(Job<Real>), hipMemcpyHostToDevice, st));
-  int m = n;
-  for (int64_t k = 0; k < g[0].second; ++k) {
-    while (m > 0 && g[m - 1].second <= k) --m;
-    const void* jp = static_cast<const char*>(c->job_dev) + (size_t)(k & 1) * n * sizeof(Job<Real>);
-    LaunchReq r = base_req(*g[0].first, kOpStep, jp);
-    r.njobs = m;
-    r.blocks = prefix[m];
-    hipError_t e = dispatch(g[0].first->L.kind, r);
-    if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
-  }
-  HIP_TRY(hipStreamSynchronize(st));
-  for (auto& p : g) {
-    p.first->cur ^= (int)(p.second & 1);
-    p.first->steps += p.second;
+  std::vector<uint32_t> prefix(n + 1, 0);
+  for (int i = 0; i < n; ++i) prefix[i + 1] = prefix[i] + g[i].first->nblocks;
+  const int64_t total = g[0].second;
+  int64_t done = 0;
+  while (done < total) {
+    int64_t seg = total - done;
+    for (int i = 0; i < n; ++i) {
+      const mrtlb_solve& s = *g[i].first;
+      if (s.drift_every > 0 && g[i].second > done) seg = std::min(seg, s.drift_every - s.since_check);
+    }
+    // the previous segment's copy out of the staging buffer has completed:
+    // every segment ends with a stream synchronization
+    Job<Real>* jobs = static_cast<Job<Real>*>(c->job_host);
+    for (int i = 0; i < n; ++i) {
+      const mrtlb_solve& s = *g[i].first;
+      const KParams<Real>& P = *reinterpret_cast<const KParams<Real>*>(is_double(s.storage) ? (const void*)&s.Pd
+                                                                                            : (const void*)&s.Pf);
+      Job<Real> J0 = make_job(s, s.cur, with_drift(s, P));
+      J0.block_begin = prefix[i];
+      jobs[i] = J0;
+      for (int par = 0; par < 2; ++par) {
+        Job<Real> J = make_job(s, s.cur ^ par, P);
+        J.block_begin = prefix[i];
+        jobs[(size_t)(1 + par) * n + i] = J;
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(c->job_dev, jobs, 3 * (size_t)n * sizeof(Job<Real>), hipMemcpyHostToDevice, st));
+    int m = n;
+    for (int64_t k = 0; k < seg; ++k) {
+      while (m > 0 && g[m - 1].second <= done + k) --m;
+      const size_t table = k == 0 ? 0 : 1 + (size_t)(k & 1);
+      const void* jp = static_cast<const char*>(c->job_dev) + table * n * sizeof(Job<Real>);
+      LaunchReq r = base_req(*g[0].first, kOpStep, jp);
+      r.njobs = m;
+      r.blocks = prefix[m];
+      hipError_t e = dispatch(g[0].first->L.kind, r);
+      if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+      mrtlb_solve* s = g[i].first;
+      const int64_t adv = std::max<int64_t>(0, std::min(g[i].second, done + seg) - done);
+      if (adv == 0) continue;
+      s->pending = false;
+      s->cur ^= (int)(adv & 1);
+      s->steps += adv;
+      if (s->drift_every > 0 && (s->since_check += adv) >= s->drift_every) {
+        mrtlb_status r2 = drift_check(s);
+        if (r2 != MRTLB_OK) return r2;
+      }
+    }
+    done += seg;
   }
   return MRTLB_OK;
 }
@@ -712,47 +871,7 @@ mrtlb_status mrtlb_write_populations(mrtlb_solve* s, const double* f) {
   hipError_t err = dispatch(s->L.kind, r);
   if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("scatter launch: ") + hipGetErrorString(err));
   HIP_TRY(hipStreamSynchronize(st));
-  return MRTLB_OK;
+  return record_reference(s);
 }
 
-mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum) {
-  if (!s || !mass) return fail(MRTLB_EINVAL, "NULL argument");
-  HIP_TRY(hipSetDevice(s->ctx->device));
-  const int B = s->L.B, D = s->L.D;
-  const int nf = s->force ? D : 0;
-  const int planes = B + nf;
-  const uint32_t chunk = kBlock * kChunkIters;
-  const uint32_t nchunks = (s->N + chunk - 1) / chunk;
-  DevBuf part;
-  HIP_TRY(hipMalloc(&part.p, (size_t)planes * nchunks * 8));
-  hipStream_t st = s->ctx->stream;
-  // KParams is the first member of the job in device memory
-  const void* params = job_ptr(*s, s->cur);
-  hipError_t err = launch_plane_sums(s->storage, s->f[s->cur], s->N, B, s->force, nf, params, (double*)part.p,
-                                     nchunks, st);
-  if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("sum launch: ") + hipGetErrorString(err));
-  std::vector<double> h((size_t)planes * nchunks);
-  HIP_TRY(hipMemcpyAsync(h.data(), part.p, h.size() * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  std::vector<double> plane(planes, 0.0);
-  for (int p = 0; p < planes; ++p)
-    for (uint32_t c = 0; c < nchunks; ++c) plane[p] += h[(size_t)p * nchunks + c];
-  double m = 0, mom[3] = {0, 0, 0};
-  const double ref = s->storage != kFP64 && s->storage != kFP32 && s->model.model != MRTLB_NCDE
-                         ? s->model.rho0
-                         : 0.0;
-  for (int j = 0; j < B; ++j) {
-    m += plane[j];
-    for (int a = 0; a < D; ++a) mom[a] += s->L.c[a] * s->L.e[j * D + a] * plane[j];
-  }
-  m += ref * (double)s->N;
-  for (int a = 0; a < nf; ++a) mom[a] += 0.5 * plane[B + a];
-  bool finite = std::isfinite(m);
-  for (int a = 0; a < D; ++a) finite = finite && std::isfinite(mom[a]);
-  *mass = m;
-  if (momentum)
-    for (int a = 0; a < D; ++a) momentum[a] = mom[a];
-  if (!finite) return fail(MRTLB_ENUMERIC, "non-finite value in the solve's state");
-  return MRTLB_OK;
-}
 

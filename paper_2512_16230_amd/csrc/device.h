@@ -599,6 +599,10 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   // a3: forward Hermite moments
   Moments<Real> M;
   forward<L, scaled_storage<ST>()>(x, P, M);
+  // a8 drift correction (zero except on the step after an FP64 check)
+  M.R0 += P.dm0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) M.m1[a] += P.dm1[a];
 
   // a2: conserved variables, a5: sources
   Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};

@@ -57,6 +57,10 @@ struct KParams {
   Real rho0;
   Real phi_coef, D2;        // NCDE: Phi = phi_coef (phi + D2 phi^3 / 3)
   Real adv[3];              // NCDE advection velocity
+  // Drift correction: added to every node's zeroth and first Hermite moments
+  // before the collision of one step (zero otherwise); the collision keeps
+  // them, so the step moves the totals by N * dm0 and N * dm1.
+  Real dm0, dm1[3];
 };
 
 // One solve's share of a (possibly batched) step launch.
