@@ -232,6 +232,8 @@ def main():
                          "ncde-batch: 256 rD2Q13 NCDE solves advanced by one batched launch per step")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests in the measured window")
+    ap.add_argument("--lattice2d", default="rD2Q25", choices=["rD2Q25", "rD2Q21", "D2Q21K"],
+                    help="lattice of the tgv2d workload (rD2Q21: rD2Q25 subgroup; D2Q21K: knight-move D2Q21)")
     ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q33"],
                     help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -260,7 +262,8 @@ def main():
     if args.workload == "serve":
         return bench_serve(stream, args)
     shape = (args.size, args.size)
-    wl = W.tgv_large(0, shape=shape, steps=args.steps)
+    card2 = {"rD2Q25": W.Q25_RECT, "rD2Q21": W.Q21_RECT, "D2Q21K": W.Q21K_RECT}[args.lattice2d]
+    wl = W.tgv_large(0, shape=shape, steps=args.steps, card=card2)
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
@@ -277,13 +280,13 @@ def main():
     wall = time.perf_counter() - t0
     mass, _ = s.conserved()
     nodes = shape[0] * shape[1]
-    b = 25
+    b = {"rD2Q25": 25, "rD2Q21": 21, "D2Q21K": 21}[card.kind]
     launch_bytes = 2 * b * STORE_BYTES[args.storage] * nodes
     per_launch_s = kernel_ms / 1e3 / args.steps
     achieved = launch_bytes / per_launch_s / 1e9
     value = nodes * args.steps / wall / 1e6
     out = {
-        "metric": "rD2Q25 MRT-LB MLUPS (fused collide-and-stream), % of HBM roofline",
+        "metric": "%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline" % card.kind,
         "value": round(value, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -295,11 +298,12 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic",
-        "config": {"workload": "tgv-rD2Q25-%dx%d" % (shape[1], shape[0]), "lattice": "rD2Q25",
+        "config": {"workload": "tgv-%s-%dx%d" % (card.kind, shape[1], shape[0]), "lattice": card.kind,
                    "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes,
                    "tau_shear": 0.6, "mass_check": mass},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.storage, launch_bytes),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.storage, launch_bytes) if card.kind == "rD2Q25" else None,
                      "kernel_ms_per_launch": round(per_launch_s * 1e3, 5),
                      "algorithmic_bytes_per_launch": launch_bytes},
     }

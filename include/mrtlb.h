@@ -82,6 +82,12 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  *   MRTLB_RD3Q53  App. D, weights with free_w = {w33, w37, w41, w45}
  *                 (d0a = cs^2 / c_a^2).
  *   MRTLB_RD3Q33  App. D, weights unique for a given cs^2, no free w.
+ *   MRTLB_RD2Q21  the rD2Q25 subgroup without the (+-3, +-3) velocities
+ *                 (Sec. V item (i): w21 = 0), the first 21 columns of
+ *                 eq. (3-1); free_w = {w13, w17, w18}.
+ *   MRTLB_D2Q21K  App. C, the D2Q21 with knight-move velocities (+-2, +-1),
+ *                 (+-1, +-2) and (+-3, 0), (0, +-3) (not an rD2Q25
+ *                 subgroup); free_w = {w9}.
  * c[0..d-1] = c_a = dx_a/dt; cs2 = sound speed squared (direction
  * independent, Remark 2).  The Hermite rows of orders 0..3 are
  * H0 = 1, H1 = c, H2 = cc - cs^2 I, H3 = c_a(c_b^2 - cs^2), c_x c_y c_z and
@@ -90,7 +96,8 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  * Errors: EINVAL (unknown kind, c <= 0, cs2 <= 0, wrong n_free),
  *         ENUMERIC (some weight <= 0 or a singular correction system).
  * ------------------------------------------------------------------------- */
-typedef enum { MRTLB_RD2Q25 = 0, MRTLB_RD2Q13 = 1, MRTLB_RD3Q53 = 2, MRTLB_RD3Q33 = 3 } mrtlb_lattice_kind;
+typedef enum { MRTLB_RD2Q25 = 0, MRTLB_RD2Q13 = 1, MRTLB_RD3Q53 = 2, MRTLB_RD3Q33 = 3, MRTLB_RD2Q21 = 4,
+               MRTLB_D2Q21K = 5 } mrtlb_lattice_kind;
 
 typedef struct {
   int kind;          /* mrtlb_lattice_kind */

@@ -75,6 +75,8 @@ def velocity_set(kind: str) -> np.ndarray:
         "rD3Q53": _rd3q53,
         "rD3Q33": _rd3q33,
         "D2Q21K": lambda: _KNIGHT21,
+        # Sec. V item (i): rD2Q25 without its (+-3, +-3) group (w21 = 0)
+        "rD2Q21": lambda: _rd2q25()[:21],
     }
     return np.array(table[kind](), dtype=np.int64)
 
@@ -384,6 +386,8 @@ def make_lattice(kind: str, c=(1.0, 1.0), cs2=None, free=None) -> Lattice:
         w = weights_rd3q33(c, cs2)
     elif kind == "D2Q21K":
         w = weights_knight21(c, cs2, free[0])
+    elif kind == "rD2Q21":
+        w = weights_rd2q25(c, cs2, tuple(free) + (0.0,))[:21]
     else:
         raise ValueError(kind)
     return custom_lattice(kind, c, cs2, e, w)

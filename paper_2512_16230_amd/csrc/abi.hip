@@ -105,7 +105,7 @@ static size_t elem_bytes(int storage) {
     default: return 2;
   }
 }
-static int lattice_maxe(int kind) { return kind == kRD2Q25 ? 3 : 2; }
+static int lattice_maxe(int kind) { return kind == kRD2Q25 || kind == kRD2Q21 || kind == kD2Q21K ? 3 : 2; }
 
 // Population row pitch: nx rounded up to 32 nodes.  Rows start on a 32-element
 // boundary and the step kernel's wavefronts cover whole 32-node runs of a row
@@ -255,6 +255,8 @@ static hipError_t dispatch(int kind, const LaunchReq& r) {
     case kRD2Q13: return launch_rd2q13(r);
     case kRD3Q53: return launch_rd3q53(r);
     case kRD3Q33: return launch_rd3q33(r);
+    case kRD2Q21: return launch_rd2q21(r);
+    case kD2Q21K: return launch_d2q21k(r);
   }
   return hipErrorInvalidValue;
 }

@@ -56,6 +56,27 @@ void weights_rd2q25(const double* c, double cs2, const double* fr, HostLattice* 
   }
 }
 
+// App. C knight-move D2Q21 weights, free w9: w5, w17, w18, w1, w2, w0 in
+// that order from eq. (new11); w9 on all eight knight moves.
+void weights_d2q21k(const double* c, double cs2, double w9, HostLattice* out) {
+  const double d1 = cs2 / (c[0] * c[0]), d2 = cs2 / (c[1] * c[1]);
+  const double w5 = d1 * d2 / 4 - 8 * w9;
+  const double w17 = (d1 * (3 * d1 - 1) - 48 * w9) / 144;
+  const double w18 = (d2 * (3 * d2 - 1) - 48 * w9) / 144;
+  const double w1 = d1 / 2 - 2 * w5 - 10 * w9 - 9 * w17;
+  const double w2 = d2 / 2 - 2 * w5 - 10 * w9 - 9 * w18;
+  const double w0 = 1 - 2 * (w1 + w2 + 2 * w5 + 4 * w9 + w17 + w18);
+  // [layer][mask]: the knight moves are the layer-2 velocities, (+-3, 0) and
+  // (0, +-3) the layer-3 ones
+  const double tab[4][4] = {{w0, 0, 0, 0}, {0, w1, w2, w5}, {0, 0, 0, w9}, {0, w17, w18, 0}};
+  out->w.resize(out->B);
+  for (int j = 0; j < out->B; ++j) {
+    int layer, mask;
+    classify(&out->e[j * 2], 2, &layer, &mask);
+    out->w[j] = tab[layer][mask];
+  }
+}
+
 // rD2Q13 closed-form weights printed with Sec. V eq. (Q13lattice).
 void weights_rd2q13(const double* c, double cs2, HostLattice* out) {
   const double d1 = cs2 / (c[0] * c[0]), d2 = cs2 / (c[1] * c[1]);
@@ -142,13 +163,16 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
     case kRD2Q13: copy_velocities<LatRD2Q13>(&L); break;
     case kRD3Q53: copy_velocities<LatRD3Q53>(&L); break;
     case kRD3Q33: copy_velocities<LatRD3Q33>(&L); break;
+    case kRD2Q21: copy_velocities<LatRD2Q21>(&L); break;
+    case kD2Q21K: copy_velocities<LatD2Q21K>(&L); break;
     default:
       snprintf(buf, sizeof buf, "unknown lattice kind %d", desc.kind);
       *err = buf;
       return MRTLB_EINVAL;
   }
   const int D = L.D, B = L.B;
-  const int need_free = (desc.kind == kRD2Q25 || desc.kind == kRD3Q53) ? 4 : 0;
+  const int need_free =
+      (desc.kind == kRD2Q25 || desc.kind == kRD3Q53) ? 4 : desc.kind == kRD2Q21 ? 3 : desc.kind == kD2Q21K ? 1 : 0;
   if (desc.n_free != need_free) {
     snprintf(buf, sizeof buf, "lattice kind %d takes %d free weights, got %d", desc.kind, need_free, desc.n_free);
     *err = buf;
@@ -171,6 +195,13 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
     case kRD2Q13: weights_rd2q13(L.c, L.cs2, &L); break;
     case kRD3Q53: weights_3d(L.c, L.cs2, desc.free_w, true, &L); break;
     case kRD3Q33: weights_3d(L.c, L.cs2, nullptr, false, &L); break;
+    case kRD2Q21: {
+      // Sec. V item (i): the rD2Q25 weights with w21 = 0
+      const double fr[4] = {desc.free_w[0], desc.free_w[1], desc.free_w[2], 0.0};
+      weights_rd2q25(L.c, L.cs2, fr, &L);
+      break;
+    }
+    case kD2Q21K: weights_d2q21k(L.c, L.cs2, desc.free_w[0], &L); break;
   }
   for (int j = 0; j < B; ++j) {
     if (!(L.w[j] > 0)) {

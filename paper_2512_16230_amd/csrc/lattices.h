@@ -5,11 +5,13 @@
 //   rD2Q13  Sec. V, eq. (Q13lattice)
 //   rD3Q53  App. D: D3Q27 in the printed order, then 2x its 26 moving columns
 //   rD3Q33  App. D: D3Q27, then (+-2,0,0), (0,+-2,0), (0,0,+-2)
+//   rD2Q21  the first 21 columns of rD2Q25 (its (+-3,+-3) group removed)
+//   D2Q21K  App. C: rest, D2Q9 ring, the eight knight moves, (+-3,0), (0,+-3)
 #pragma once
 
 namespace mrtlb {
 
-enum LatticeKind { kRD2Q25 = 0, kRD2Q13 = 1, kRD3Q53 = 2, kRD3Q33 = 3 };
+enum LatticeKind { kRD2Q25 = 0, kRD2Q13 = 1, kRD3Q53 = 2, kRD3Q33 = 3, kRD2Q21 = 4, kD2Q21K = 5 };
 
 struct LatRD2Q25 {
   static constexpr int kind = kRD2Q25, D = 2, B = 25, MAXE = 3;
@@ -22,6 +24,20 @@ struct LatRD2Q13 {
   static constexpr int kind = kRD2Q13, D = 2, B = 13, MAXE = 2;
   static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0};
   static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2};
+  static constexpr int EZ[B] = {};
+};
+
+struct LatRD2Q21 {
+  static constexpr int kind = kRD2Q21, D = 2, B = 21, MAXE = 3;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0, 2, -2, -2, 2, 3, 0, -3, 0};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2, 2, 2, -2, -2, 0, 3, 0, -3};
+  static constexpr int EZ[B] = {};
+};
+
+struct LatD2Q21K {
+  static constexpr int kind = kD2Q21K, D = 2, B = 21, MAXE = 3;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 1, -1, -2, -2, -1, 1, 2, 3, 0, -3, 0};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 1, 2, 2, 1, -1, -2, -2, -1, 0, 3, 0, -3};
   static constexpr int EZ[B] = {};
 };
 

@@ -32,6 +32,8 @@ hipError_t launch_rd2q25(const LaunchReq& r);
 hipError_t launch_rd2q13(const LaunchReq& r);
 hipError_t launch_rd3q53(const LaunchReq& r);
 hipError_t launch_rd3q33(const LaunchReq& r);
+hipError_t launch_rd2q21(const LaunchReq& r);
+hipError_t launch_d2q21k(const LaunchReq& r);
 
 // FP64 sums of every population plane (and force plane) in chunks.
 hipError_t launch_plane_sums(int storage, const void* base, uint32_t N, int npop, const void* force, int nforce,

@@ -38,6 +38,9 @@ Q25_RECT = Card("rD2Q25", (1.5, 1.0), 1.5, (5.35e-3, 6.25e-4, 2.46e-2, 8.2e-4))
 Q13_SQUARE = Card("rD2Q13", (1.0, 1.0), 0.5)
 Q53_RECT = Card("rD3Q53", (1.0, 1.25, 1.5), 1.0, (6.56e-3, 2.05e-3, 3.0e-4, 2.3e-4))
 Q33_CUBIC = Card("rD3Q33", (1.0, 1.0, 1.0), 0.45)
+# subgroup rD2Q21 (w21 = 0) and the knight-move D2Q21 on the rD2Q25 aspect ratio
+Q21_RECT = Card("rD2Q21", (1.5, 1.0), 1.5, (8.0e-3, 1.6e-3, 3.3e-2))
+Q21K_RECT = Card("D2Q21K", (1.5, 1.0), 0.98, (7.0e-4,))
 
 
 @dataclass
@@ -200,16 +203,16 @@ def tgv_small(seed=0, shape=(64, 64), steps=500):
                     rates_tau(0.8), 1.0, rho_bar, u, meta={"U0": U0})
 
 
-def tgv_large(seed=0, shape=(4096, 4096), steps=1000, sigma=1e-3):
-    """rD2Q25 incompressible Taylor-Green vortex at Ma = 0.1 (U0 = 0.1 cs)
-    plus iid N(0, sigma^2) per velocity component, tau_shear = 0.6."""
+def tgv_large(seed=0, shape=(4096, 4096), steps=1000, sigma=1e-3, card=Q25_RECT):
+    """Incompressible Taylor-Green vortex at Ma = 0.1 (U0 = 0.1 cs) plus iid
+    N(0, sigma^2) per velocity component, tau_shear = 0.6 (rD2Q25 unless
+    another 2D card is given)."""
     rng = np.random.default_rng(seed)
-    card = Q25_RECT
     U0 = 0.1 * np.sqrt(card.cs2)
     p, u = taylor_green_2d(card, shape, U0)
     u = u + rng.normal(0.0, sigma, size=u.shape)
     rho_bar = 1.0 + p / card.cs2
-    return Workload("tgv-rD2Q25-%dx%d" % (shape[1], shape[0]), card, "NSE_INC", shape, steps,
+    return Workload("tgv-%s-%dx%d" % (card.kind, shape[1], shape[0]), card, "NSE_INC", shape, steps,
                     rates_tau(0.6), 1.0, rho_bar, u, meta={"U0": U0, "sigma": sigma})
 
 

@@ -36,7 +36,8 @@ def test_version():
     assert H.lib().mrtlb_version() >> 16 == 1
 
 
-@pytest.mark.parametrize("card", [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC], ids=lambda c: c.kind)
+@pytest.mark.parametrize("card", [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT],
+                         ids=lambda c: c.kind)
 def test_host_lattice_matches_oracle(card):
     q = H.Lattice(card.kind, card.c, card.cs2, card.free).query()
     lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)

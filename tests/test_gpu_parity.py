@@ -130,6 +130,37 @@ def test_rd2q25_ragged(ctx, shape, eq):
         assert max_rel(v, u_o) < tu
 
 
+@pytest.mark.parametrize("card", [W.Q21_RECT, W.Q21K_RECT], ids=lambda c: c.kind)
+@pytest.mark.parametrize("shape,eq", [((7, 300), "NSE_INC"), ((37, 66), "NSE_COMP")])
+def test_rd2q21_lattices(ctx, card, shape, eq):
+    """The rD2Q25 subgroup rD2Q21 and the knight-move D2Q21: NSE against the
+    oracle on ragged tiles, and a 16-bit storage run."""
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    rho, u = _random_fields(card, shape, 21)
+    steps = 12
+    r_o, u_o, _ = _oracle_run(card, eq, rates, rho, u, steps)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4), ("fp32_dev", 1e-6, 2e-5),
+                            ("i16_dev", 1e-4, 1e-2)):
+        print("case: %s %s %s %s" % (card.kind, eq, shape, storage), flush=True)
+        r, v, _ = _gpu_run(ctx, card, eq, rates, shape, storage, rho, u, steps)
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+
+
+@pytest.mark.parametrize("card", [W.Q21_RECT, W.Q21K_RECT], ids=lambda c: c.kind)
+def test_rd2q21_lattices_ncde(ctx, card):
+    wl = W.ncde_hill((40, 72), adv_u=(0.03, -0.02), D0=0.1, D2=1.0, card=card)
+    steps = 20
+    kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u)
+    phi_o, _, _ = _oracle_run(card, "NCDE", wl.rates, wl.rho_or_phi, None, steps, **kw)
+    for storage, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        print("case: %s NCDE %s" % (card.kind, storage), flush=True)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, **kw), wl.shape, storage)
+        s.init_fields(wl.rho_or_phi)
+        s.step(steps)
+        assert max_rel(s.read_moments(with_u=False), phi_o) < tol
+
+
 @pytest.mark.parametrize("shape", [(48, 136), (9, 70)])
 def test_rd2q13_ncde(ctx, shape):
     card = W.Q13_SQUARE

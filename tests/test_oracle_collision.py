@@ -20,7 +20,7 @@ from oracle import model as M
 from oracle import naive as N
 from paper_2512_16230_amd import workloads as W
 
-CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC]
+CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT]
 
 
 def card_lattice(card):
@@ -240,3 +240,25 @@ def test_mirror_symmetry_x():
     a = M.step(lat, mdl, M.State(mirror(st.f)))
     b = M.step(lat, mdl, st)
     assert np.abs(a.f - mirror(b.f)).max() < 1e-15
+
+
+def test_rd2q21_equals_rd2q25_with_zero_corner_weight():
+    """Sec. V item (i): rD2Q21 is rD2Q25 with w21 = 0.  Run on the full
+    25-velocity set with zero corner weights, the corner populations stay
+    zero and the other 21 evolve exactly as on the 21-velocity lattice."""
+    card = W.Q21_RECT
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    lat21 = L.make_lattice("rD2Q21", card.c, card.cs2, card.free)
+    w25 = L.weights_rd2q25(card.c, card.cs2, tuple(card.free) + (0.0,))
+    lat25 = L.custom_lattice("rD2Q25-w21=0", card.c, card.cs2, L.velocity_set("rD2Q25"), w25)
+    assert np.array_equal(lat25.e[:21], lat21.e) and np.all(w25[21:] == 0)
+    mdl = M.Model(eq="NSE_COMP", s0=rates.s0, s1=rates.s1, s_shear=rates.s_shear, s_bulk=rates.s_bulk,
+                  s3=rates.s3, s_h=rates.s_h)
+    rng = np.random.default_rng(5)
+    shape = (9, 11)
+    rho = 1 + 0.02 * rng.normal(size=shape)
+    u = 0.02 * rng.normal(size=(2,) + shape)
+    s21 = M.run(lat21, mdl, M.init_state(lat21, mdl, rho, u), 6)
+    s25 = M.run(lat25, mdl, M.init_state(lat25, mdl, rho, u), 6)
+    assert np.abs(s25.f[21:]).max() == 0
+    assert np.abs(s25.f[:21] - s21.f).max() < 1e-14

@@ -16,7 +16,7 @@ import pytest
 from oracle import lattice as L
 from paper_2512_16230_amd import workloads as W
 
-CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC]
+CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT]
 
 
 def card_lattice(card):
