@@ -123,7 +123,7 @@ def bench_tgv3d(torch, H, W, stream, args):
     """rD3Q53 (1 : 1.25 : 1.5) compressible isothermal 3D Taylor-Green, 256^3."""
     n = args.size if args.size != 4096 else 256
     shape = (n, n, n)
-    card3 = W.Q53_RECT if args.lattice3d == "rD3Q53" else W.Q33_CUBIC
+    card3 = {"rD3Q53": W.Q53_RECT, "rD3Q45": W.Q45_RECT, "rD3Q33": W.Q33_CUBIC}[args.lattice3d]
     wl = W.tgv3d(shape=shape, steps=args.steps, card=card3)
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
@@ -140,7 +140,7 @@ def bench_tgv3d(torch, H, W, stream, args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nodes = n ** 3
-    bq = 53 if card.kind == "rD3Q53" else 33
+    bq = {"rD3Q53": 53, "rD3Q45": 45, "rD3Q33": 33}[card.kind]
     launch_bytes = 2 * bq * STORE_BYTES[args.storage] * nodes
     out = _line("%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline" % card.kind,
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--requests", type=int, default=300, help="serve: requests in the measured window")
     ap.add_argument("--lattice2d", default="rD2Q25", choices=["rD2Q25", "rD2Q21", "D2Q21K"],
                     help="lattice of the tgv2d workload (rD2Q21: rD2Q25 subgroup; D2Q21K: knight-move D2Q21)")
-    ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q33"],
+    ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33"],
                     help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of 2 x 1.68 GB instead (HBM reference and counter calibration)")

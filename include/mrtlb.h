@@ -88,6 +88,14 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  *   MRTLB_D2Q21K  App. C, the D2Q21 with knight-move velocities (+-2, +-1),
  *                 (+-1, +-2) and (+-3, 0), (0, +-3) (not an rD2Q25
  *                 subgroup); free_w = {w9}.
+ *   MRTLB_RD3Q45  the rD3Q53 subgroup without the (+-2, +-2, +-2) velocities
+ *                 (w45 = 0), the first 45 columns of the App. D velocity
+ *                 matrix; free_w = {w33, w37, w41}.
+ *   MRTLB_RD2Q17_1 .. MRTLB_RD2Q17_5  App. C, D2Q17 cases 1-5 in their printed
+ *                 velocity order: rD2Q25 subgroups.  free_w = {w13, w17, w18,
+ *                 w21} of eq. (WeightQ25); with the given c and cs2 the weights
+ *                 of the case's dropped velocity groups must vanish (|w| <=
+ *                 1e-12, else EINVAL).
  * c[0..d-1] = c_a = dx_a/dt; cs2 = sound speed squared (direction
  * independent, Remark 2).  The Hermite rows of orders 0..3 are
  * H0 = 1, H1 = c, H2 = cc - cs^2 I, H3 = c_a(c_b^2 - cs^2), c_x c_y c_z and
@@ -97,7 +105,8 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  *         ENUMERIC (some weight <= 0 or a singular correction system).
  * ------------------------------------------------------------------------- */
 typedef enum { MRTLB_RD2Q25 = 0, MRTLB_RD2Q13 = 1, MRTLB_RD3Q53 = 2, MRTLB_RD3Q33 = 3, MRTLB_RD2Q21 = 4,
-               MRTLB_D2Q21K = 5 } mrtlb_lattice_kind;
+               MRTLB_D2Q21K = 5, MRTLB_RD3Q45 = 6, MRTLB_RD2Q17_1 = 7, MRTLB_RD2Q17_2 = 8, MRTLB_RD2Q17_3 = 9,
+               MRTLB_RD2Q17_4 = 10, MRTLB_RD2Q17_5 = 11 } mrtlb_lattice_kind;
 
 typedef struct {
   int kind;          /* mrtlb_lattice_kind */

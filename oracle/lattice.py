@@ -67,6 +67,26 @@ _KNIGHT21 = [(0, 0)] + _D2Q9_RING + [(2, 1), (1, 2), (-1, 2), (-2, 1), (-2, -1),
                                      (3, 0), (0, 3), (-3, 0), (0, -3)]
 
 
+# App. C, the printed velocity matrices of the D2Q17 cases 1-5 (square,
+# c = 1 there): each keeps the rest velocity and four of the rD2Q25 groups.
+_Q17_GROUPS = {
+    1: ["ring1", "diag1", "diag2", "axis3"],
+    2: ["ring1", "diag1", "axis3", "diag3"],
+    3: ["diag1", "axis2", "axis3", "diag3"],
+    4: ["diag1", "diag2", "axis3", "diag3"],
+    5: ["ring1", "diag1", "axis2", "diag2"],
+}
+
+
+def _q17(case):
+    axis = [(1, 0), (0, 1), (-1, 0), (0, -1)]
+    diag = [(1, 1), (-1, 1), (-1, -1), (1, -1)]
+    groups = {"ring1": axis, "diag1": diag, "axis2": [(2 * a, 2 * b) for a, b in axis],
+              "diag2": [(2 * a, 2 * b) for a, b in diag], "axis3": [(3 * a, 3 * b) for a, b in axis],
+              "diag3": [(3 * a, 3 * b) for a, b in diag]}
+    return [(0, 0)] + [v for g in _Q17_GROUPS[case] for v in groups[g]]
+
+
 def velocity_set(kind: str) -> np.ndarray:
     """Integer velocity multiples e_j (b x d) in the paper's column order."""
     table = {
@@ -77,6 +97,9 @@ def velocity_set(kind: str) -> np.ndarray:
         "D2Q21K": lambda: _KNIGHT21,
         # Sec. V item (i): rD2Q25 without its (+-3, +-3) group (w21 = 0)
         "rD2Q21": lambda: _rd2q25()[:21],
+        # the rD3Q53 subgroup without its (+-2, +-2, +-2) group (w45 = 0)
+        "rD3Q45": lambda: _rd3q53()[:45],
+        **{"rD2Q17-%d" % k: (lambda k=k: _q17(k)) for k in range(1, 6)},
     }
     return np.array(table[kind](), dtype=np.int64)
 
@@ -388,6 +411,18 @@ def make_lattice(kind: str, c=(1.0, 1.0), cs2=None, free=None) -> Lattice:
         w = weights_knight21(c, cs2, free[0])
     elif kind == "rD2Q21":
         w = weights_rd2q25(c, cs2, tuple(free) + (0.0,))[:21]
+    elif kind == "rD3Q45":
+        w = weights_rd3q53(c, cs2, tuple(free) + (0.0,))[:45]
+    elif kind.startswith("rD2Q17-"):
+        # eq. (WeightQ25) on the full rD2Q25 set; the dropped groups must vanish
+        e25 = velocity_set("rD2Q25")
+        w25 = weights_rd2q25(c, cs2, free)
+        keep = {tuple(v) for v in e.tolist()}
+        dropped = [w25[j] for j in range(len(e25)) if tuple(e25[j].tolist()) not in keep]
+        if max(abs(v) for v in dropped) > 1e-12:
+            raise ValueError("cs2 and the free weights do not give D2Q17 case " + kind)
+        index = {tuple(v): j for j, v in enumerate(e25.tolist())}
+        w = np.array([w25[index[tuple(v)]] for v in e.tolist()])
     else:
         raise ValueError(kind)
     return custom_lattice(kind, c, cs2, e, w)

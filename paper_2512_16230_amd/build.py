@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrtlb.so")
 SOURCES = ["abi.hip", "host_lattice.cpp", "inst_common.hip", "inst_rd2q25.hip", "inst_rd2q13.hip",
-           "inst_rd3q53.hip", "inst_rd3q33.hip", "inst_rd2q21.hip", "inst_d2q21k.hip"]
+           "inst_rd3q53.hip", "inst_rd3q33.hip", "inst_rd2q21.hip", "inst_d2q21k.hip",
+           "inst_rd3q45.hip"] + ["inst_rd2q17_%d.hip" % k for k in range(1, 6)]
 
 FLAGS = [
     "--offload-arch=gfx950",

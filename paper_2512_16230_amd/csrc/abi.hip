@@ -105,7 +105,9 @@ static size_t elem_bytes(int storage) {
     default: return 2;
   }
 }
-static int lattice_maxe(int kind) { return kind == kRD2Q25 || kind == kRD2Q21 || kind == kD2Q21K ? 3 : 2; }
+static int lattice_maxe(int kind) {
+  return kind == kRD2Q25 || kind == kRD2Q21 || kind == kD2Q21K || (kind >= kRD2Q17_1 && kind <= kRD2Q17_4) ? 3 : 2;
+}
 
 // Population row pitch: nx rounded up to 32 nodes.  Rows start on a 32-element
 // boundary and the step kernel's wavefronts cover whole 32-node runs of a row
@@ -131,7 +133,8 @@ static int pick_vec(int storage, int kind, int model, int nx) {
   // pressure), for rows under 512 nodes and for the NCDE; otherwise 2 nodes
   // (FP32/FP64) or 4 nodes (16-bit storage, 8-byte accesses per lane).
   const bool small = storage != kFP64 && storage != kFP32 && storage != kFP32Dev;
-  int v = (kind == kRD3Q53 || kind == kRD3Q33 || nx < 512 || model == MRTLB_NCDE) ? 1 : (small ? 4 : 2);
+  int v = (kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || nx < 512 || model == MRTLB_NCDE) ? 1
+                                                                                            : (small ? 4 : 2);
   if (const char* e = std::getenv("MRTLB_STEP_VEC")) {
     const int o = std::atoi(e);
     if (o == 1 || o == 2 || o == 4) v = o;
@@ -257,6 +260,12 @@ static hipError_t dispatch(int kind, const LaunchReq& r) {
     case kRD3Q33: return launch_rd3q33(r);
     case kRD2Q21: return launch_rd2q21(r);
     case kD2Q21K: return launch_d2q21k(r);
+    case kRD3Q45: return launch_rd3q45(r);
+    case kRD2Q17_1: return launch_rd2q17_1(r);
+    case kRD2Q17_2: return launch_rd2q17_2(r);
+    case kRD2Q17_3: return launch_rd2q17_3(r);
+    case kRD2Q17_4: return launch_rd2q17_4(r);
+    case kRD2Q17_5: return launch_rd2q17_5(r);
   }
   return hipErrorInvalidValue;
 }

@@ -165,6 +165,12 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
     case kRD3Q33: copy_velocities<LatRD3Q33>(&L); break;
     case kRD2Q21: copy_velocities<LatRD2Q21>(&L); break;
     case kD2Q21K: copy_velocities<LatD2Q21K>(&L); break;
+    case kRD3Q45: copy_velocities<LatRD3Q45>(&L); break;
+    case kRD2Q17_1: copy_velocities<LatRD2Q17_1>(&L); break;
+    case kRD2Q17_2: copy_velocities<LatRD2Q17_2>(&L); break;
+    case kRD2Q17_3: copy_velocities<LatRD2Q17_3>(&L); break;
+    case kRD2Q17_4: copy_velocities<LatRD2Q17_4>(&L); break;
+    case kRD2Q17_5: copy_velocities<LatRD2Q17_5>(&L); break;
     default:
       snprintf(buf, sizeof buf, "unknown lattice kind %d", desc.kind);
       *err = buf;
@@ -172,7 +178,9 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
   }
   const int D = L.D, B = L.B;
   const int need_free =
-      (desc.kind == kRD2Q25 || desc.kind == kRD3Q53) ? 4 : desc.kind == kRD2Q21 ? 3 : desc.kind == kD2Q21K ? 1 : 0;
+      (desc.kind == kRD2Q25 || desc.kind == kRD3Q53 || (desc.kind >= kRD2Q17_1 && desc.kind <= kRD2Q17_5)) ? 4
+      : (desc.kind == kRD2Q21 || desc.kind == kRD3Q45) ? 3
+      : desc.kind == kD2Q21K ? 1 : 0;
   if (desc.n_free != need_free) {
     snprintf(buf, sizeof buf, "lattice kind %d takes %d free weights, got %d", desc.kind, need_free, desc.n_free);
     *err = buf;
@@ -202,6 +210,35 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
       break;
     }
     case kD2Q21K: weights_d2q21k(L.c, L.cs2, desc.free_w[0], &L); break;
+    case kRD2Q17_1: case kRD2Q17_2: case kRD2Q17_3: case kRD2Q17_4: case kRD2Q17_5: {
+      // the rD2Q25 weights (free = {w13, w17, w18, w21}); the groups the case
+      // drops must come out zero
+      HostLattice full;
+      copy_velocities<LatRD2Q25>(&full);
+      weights_rd2q25(L.c, L.cs2, desc.free_w, &full);
+      L.w.assign(B, 0.0);
+      for (int k = 0; k < full.B; ++k) {
+        int hit = -1;
+        for (int j = 0; j < B; ++j)
+          if (L.e[j * 2] == full.e[k * 2] && L.e[j * 2 + 1] == full.e[k * 2 + 1]) hit = j;
+        if (hit >= 0) {
+          L.w[hit] = full.w[k];
+        } else if (std::fabs(full.w[k]) > 1e-12) {
+          snprintf(buf, sizeof buf,
+                   "the weight of dropped velocity (%d, %d) is %.3g, not 0: cs2 and the free weights do not give "
+                   "this D2Q17 case", full.e[k * 2], full.e[k * 2 + 1], full.w[k]);
+          *err = buf;
+          return MRTLB_EINVAL;
+        }
+      }
+      break;
+    }
+    case kRD3Q45: {
+      // the rD3Q53 weights with w45 = 0
+      const double fr[4] = {desc.free_w[0], desc.free_w[1], desc.free_w[2], 0.0};
+      weights_3d(L.c, L.cs2, fr, true, &L);
+      break;
+    }
   }
   for (int j = 0; j < B; ++j) {
     if (!(L.w[j] > 0)) {

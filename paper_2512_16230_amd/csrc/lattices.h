@@ -7,11 +7,17 @@
 //   rD3Q33  App. D: D3Q27, then (+-2,0,0), (0,+-2,0), (0,0,+-2)
 //   rD2Q21  the first 21 columns of rD2Q25 (its (+-3,+-3) group removed)
 //   D2Q21K  App. C: rest, D2Q9 ring, the eight knight moves, (+-3,0), (0,+-3)
+//   rD3Q45  the first 45 columns of rD3Q53 (its (+-2,+-2,+-2) group removed)
+//   rD2Q17-k  App. C, D2Q17 cases 1-5: the printed velocity matrices (rD2Q25
+//           subgroups whose dropped groups carry zero weight)
 #pragma once
 
 namespace mrtlb {
 
-enum LatticeKind { kRD2Q25 = 0, kRD2Q13 = 1, kRD3Q53 = 2, kRD3Q33 = 3, kRD2Q21 = 4, kD2Q21K = 5 };
+enum LatticeKind {
+  kRD2Q25 = 0, kRD2Q13 = 1, kRD3Q53 = 2, kRD3Q33 = 3, kRD2Q21 = 4, kD2Q21K = 5, kRD3Q45 = 6,
+  kRD2Q17_1 = 7, kRD2Q17_2 = 8, kRD2Q17_3 = 9, kRD2Q17_4 = 10, kRD2Q17_5 = 11
+};
 
 struct LatRD2Q25 {
   static constexpr int kind = kRD2Q25, D = 2, B = 25, MAXE = 3;
@@ -41,6 +47,41 @@ struct LatD2Q21K {
   static constexpr int EZ[B] = {};
 };
 
+struct LatRD2Q17_1 {
+  static constexpr int kind = kRD2Q17_1, D = 2, B = 17, MAXE = 3;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, -2, -2, 2, 3, 0, -3, 0};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 2, 2, -2, -2, 0, 3, 0, -3};
+  static constexpr int EZ[B] = {};
+};
+
+struct LatRD2Q17_2 {
+  static constexpr int kind = kRD2Q17_2, D = 2, B = 17, MAXE = 3;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 3, 0, -3, 0, 3, -3, -3, 3};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 3, 0, -3, 3, 3, -3, -3};
+  static constexpr int EZ[B] = {};
+};
+
+struct LatRD2Q17_3 {
+  static constexpr int kind = kRD2Q17_3, D = 2, B = 17, MAXE = 3;
+  static constexpr int EX[B] = {0, 1, -1, -1, 1, 2, 0, -2, 0, 3, 0, -3, 0, 3, -3, -3, 3};
+  static constexpr int EY[B] = {0, 1, 1, -1, -1, 0, 2, 0, -2, 0, 3, 0, -3, 3, 3, -3, -3};
+  static constexpr int EZ[B] = {};
+};
+
+struct LatRD2Q17_4 {
+  static constexpr int kind = kRD2Q17_4, D = 2, B = 17, MAXE = 3;
+  static constexpr int EX[B] = {0, 1, -1, -1, 1, 2, -2, -2, 2, 3, 0, -3, 0, 3, -3, -3, 3};
+  static constexpr int EY[B] = {0, 1, 1, -1, -1, 2, 2, -2, -2, 0, 3, 0, -3, 3, 3, -3, -3};
+  static constexpr int EZ[B] = {};
+};
+
+struct LatRD2Q17_5 {
+  static constexpr int kind = kRD2Q17_5, D = 2, B = 17, MAXE = 2;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0, 2, -2, -2, 2};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2, 2, 2, -2, -2};
+  static constexpr int EZ[B] = {};
+};
+
 #define MRTLB_D3Q27_X 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1
 #define MRTLB_D3Q27_Y 0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, 1, -1, -1, 1, 1, -1
 #define MRTLB_D3Q27_Z 0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1
@@ -50,6 +91,13 @@ struct LatRD3Q53 {
   static constexpr int EX[B] = {MRTLB_D3Q27_X, 2, -2, 0, 0, 0, 0, 2, -2, -2, 2, 2, -2, -2, 2, 0, 0, 0, 0, 2, -2, 2, -2, 2, -2, -2, 2};
   static constexpr int EY[B] = {MRTLB_D3Q27_Y, 0, 0, 2, -2, 0, 0, 2, -2, 2, -2, 0, 0, 0, 0, 2, -2, -2, 2, 2, -2, 2, -2, -2, 2, 2, -2};
   static constexpr int EZ[B] = {MRTLB_D3Q27_Z, 0, 0, 0, 0, 2, -2, 0, 0, 0, 0, 2, -2, 2, -2, 2, -2, 2, -2, 2, -2, -2, 2, 2, -2, 2, -2};
+};
+
+struct LatRD3Q45 {
+  static constexpr int kind = kRD3Q45, D = 3, B = 45, MAXE = 2;
+  static constexpr int EX[B] = {MRTLB_D3Q27_X, 2, -2, 0, 0, 0, 0, 2, -2, -2, 2, 2, -2, -2, 2, 0, 0, 0, 0};
+  static constexpr int EY[B] = {MRTLB_D3Q27_Y, 0, 0, 2, -2, 0, 0, 2, -2, 2, -2, 0, 0, 0, 0, 2, -2, -2, 2};
+  static constexpr int EZ[B] = {MRTLB_D3Q27_Z, 0, 0, 0, 0, 2, -2, 0, 0, 0, 0, 2, -2, 2, -2, 2, -2, 2, -2};
 };
 
 struct LatRD3Q33 {

@@ -34,6 +34,12 @@ hipError_t launch_rd3q53(const LaunchReq& r);
 hipError_t launch_rd3q33(const LaunchReq& r);
 hipError_t launch_rd2q21(const LaunchReq& r);
 hipError_t launch_d2q21k(const LaunchReq& r);
+hipError_t launch_rd3q45(const LaunchReq& r);
+hipError_t launch_rd2q17_1(const LaunchReq& r);
+hipError_t launch_rd2q17_2(const LaunchReq& r);
+hipError_t launch_rd2q17_3(const LaunchReq& r);
+hipError_t launch_rd2q17_4(const LaunchReq& r);
+hipError_t launch_rd2q17_5(const LaunchReq& r);
 
 // FP64 sums of every population plane (and force plane) in chunks.
 hipError_t launch_plane_sums(int storage, const void* base, uint32_t N, int npop, const void* force, int nforce,

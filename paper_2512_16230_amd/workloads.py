@@ -41,6 +41,20 @@ Q33_CUBIC = Card("rD3Q33", (1.0, 1.0, 1.0), 0.45)
 # subgroup rD2Q21 (w21 = 0) and the knight-move D2Q21 on the rD2Q25 aspect ratio
 Q21_RECT = Card("rD2Q21", (1.5, 1.0), 1.5, (8.0e-3, 1.6e-3, 3.3e-2))
 Q21K_RECT = Card("D2Q21K", (1.5, 1.0), 0.98, (7.0e-4,))
+# App. C, D2Q17 cases 1-5 (square): the printed cs^2 and, as rD2Q25 free
+# weights (w13, w17, w18, w21), the printed weights of the kept groups
+_R193, _R10 = 193 ** 0.5, 10 ** 0.5
+Q17_CASES = [
+    Card("rD2Q17-1", (1.0, 1.0), 72 / (125 + 5 * _R193),
+         ((685 - 49 * _R193) / 54000, (1445 - 101 * _R193) / 162000, (1445 - 101 * _R193) / 162000, 0.0)),
+    Card("rD2Q17-2", (1.0, 1.0), 3 / (5 + _R10),
+         (0.0, (295 - 92 * _R10) / 16200, (295 - 92 * _R10) / 16200, (130 - 41 * _R10) / 64800)),
+    Card("rD2Q17-3", (1.0, 1.0), 3 / 4, (0.0, 1 / 1440, 1 / 1440, 5 / 18432)),
+    Card("rD2Q17-4", (1.0, 1.0), 3 / 2, (9 / 640, 1 / 36, 1 / 36, 23 / 11520)),
+    Card("rD2Q17-5", (1.0, 1.0), 0.3740845, (0.0000891, 0.0, 0.0, 0.0)),
+]
+# subgroup rD3Q45 (w45 = 0) at the rD3Q53 aspect ratio
+Q45_RECT = Card("rD3Q45", (1.0, 1.25, 1.5), 0.86, (4.3e-3, 4.8e-4, 4.3e-4))
 
 
 @dataclass

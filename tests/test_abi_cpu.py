@@ -36,7 +36,8 @@ def test_version():
     assert H.lib().mrtlb_version() >> 16 == 1
 
 
-@pytest.mark.parametrize("card", [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT],
+@pytest.mark.parametrize("card", [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT,
+                                  W.Q45_RECT] + W.Q17_CASES,
                          ids=lambda c: c.kind)
 def test_host_lattice_matches_oracle(card):
     q = H.Lattice(card.kind, card.c, card.cs2, card.free).query()
@@ -64,6 +65,13 @@ def test_host_lattice_matches_oracle(card):
     pure_o = Ho[[r.name in ("xxx", "yyy", "zzz") for r in lat.rows]]
     pure_h = Hm[-lat.d:]
     assert np.allclose(pure_o, pure_h, atol=1e-12)
+
+
+def test_d2q17_case_needs_vanishing_dropped_weights():
+    card = W.Q17_CASES[0]
+    with pytest.raises(H.MrtlbError) as e:
+        H.Lattice(card.kind, card.c, card.cs2 * 1.01, card.free)
+    assert e.value.status == H.MRTLB_EINVAL
 
 
 def test_lattice_errors():

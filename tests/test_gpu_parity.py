@@ -147,6 +147,21 @@ def test_rd2q21_lattices(ctx, card, shape, eq):
         assert max_rel(v, u_o) < tu
 
 
+@pytest.mark.parametrize("card", W.Q17_CASES, ids=lambda c: c.kind)
+def test_d2q17_cases(ctx, card):
+    """App. C D2Q17 cases 1-5 through the generic kernel, NSE against the oracle."""
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    shape = (13, 70)
+    rho, u = _random_fields(card, shape, 23, amp=0.02)
+    steps = 10
+    r_o, u_o, _ = _oracle_run(card, "NSE_COMP", rates, rho, u, steps)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4)):
+        print("case: %s NSE_COMP %s %s" % (card.kind, shape, storage), flush=True)
+        r, v, _ = _gpu_run(ctx, card, "NSE_COMP", rates, shape, storage, rho, u, steps)
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+
+
 @pytest.mark.parametrize("card", [W.Q21_RECT, W.Q21K_RECT], ids=lambda c: c.kind)
 def test_rd2q21_lattices_ncde(ctx, card):
     wl = W.ncde_hill((40, 72), adv_u=(0.03, -0.02), D0=0.1, D2=1.0, card=card)
@@ -177,8 +192,8 @@ def test_rd2q13_ncde(ctx, shape):
         assert max_rel(phi, phi_o) < tol
 
 
-@pytest.mark.parametrize("card,shape", [(W.Q53_RECT, (6, 10, 70)), (W.Q33_CUBIC, (5, 9, 66))],
-                         ids=["rD3Q53", "rD3Q33"])
+@pytest.mark.parametrize("card,shape", [(W.Q53_RECT, (6, 10, 70)), (W.Q33_CUBIC, (5, 9, 66)),
+                                        (W.Q45_RECT, (7, 6, 40))], ids=["rD3Q53", "rD3Q33", "rD3Q45"])
 def test_3d_comp(ctx, card, shape):
     rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
     rho, u = _random_fields(card, shape, 5)

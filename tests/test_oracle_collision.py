@@ -20,7 +20,7 @@ from oracle import model as M
 from oracle import naive as N
 from paper_2512_16230_amd import workloads as W
 
-CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT]
+CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT, W.Q45_RECT] + W.Q17_CASES
 
 
 def card_lattice(card):
@@ -262,3 +262,25 @@ def test_rd2q21_equals_rd2q25_with_zero_corner_weight():
     s25 = M.run(lat25, mdl, M.init_state(lat25, mdl, rho, u), 6)
     assert np.abs(s25.f[21:]).max() == 0
     assert np.abs(s25.f[:21] - s21.f).max() < 1e-14
+
+
+def test_rd3q45_equals_rd3q53_with_zero_corner_weight():
+    """rD3Q45 is rD3Q53 with w45 = 0: on the full 53-velocity set with zero
+    weight on the (+-2, +-2, +-2) group those populations stay zero and the
+    other 45 evolve exactly as on the 45-velocity lattice."""
+    card = W.Q45_RECT
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    lat45 = L.make_lattice("rD3Q45", card.c, card.cs2, card.free)
+    w53 = L.weights_rd3q53(card.c, card.cs2, tuple(card.free) + (0.0,))
+    lat53 = L.custom_lattice("rD3Q53-w45=0", card.c, card.cs2, L.velocity_set("rD3Q53"), w53)
+    assert np.array_equal(lat53.e[:45], lat45.e) and np.all(w53[45:] == 0)
+    mdl = M.Model(eq="NSE_COMP", s0=rates.s0, s1=rates.s1, s_shear=rates.s_shear, s_bulk=rates.s_bulk,
+                  s3=rates.s3, s_h=rates.s_h)
+    rng = np.random.default_rng(6)
+    shape = (5, 6, 7)
+    rho = 1 + 0.02 * rng.normal(size=shape)
+    u = 0.02 * rng.normal(size=(3,) + shape)
+    s45 = M.run(lat45, mdl, M.init_state(lat45, mdl, rho, u), 4)
+    s53 = M.run(lat53, mdl, M.init_state(lat53, mdl, rho, u), 4)
+    assert np.abs(s53.f[45:]).max() == 0
+    assert np.abs(s53.f[:45] - s45.f).max() < 1e-14

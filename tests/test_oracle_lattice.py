@@ -16,7 +16,7 @@ import pytest
 from oracle import lattice as L
 from paper_2512_16230_amd import workloads as W
 
-CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT]
+CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT, W.Q45_RECT] + W.Q17_CASES
 
 
 def card_lattice(card):
@@ -67,6 +67,23 @@ def test_velocity_sets_match_printed(vsets, kind):
     s = set(map(tuple, e.tolist()))
     assert all(tuple(-v for v in t) in s for t in s)
     assert len(s) == len(e)
+
+
+@pytest.mark.parametrize("case", [1, 2, 3, 4, 5])
+def test_d2q17_case_lattices_match_printed(vsets, q17, case):
+    """The oracle's D2Q17 case lattices: printed velocity order, and the
+    printed weights from the case card's free weights."""
+    assert L.velocity_set("rD2Q17-%d" % case).tolist() == vsets["D2Q17-%d" % case]["e"]
+    card = W.Q17_CASES[case - 1]
+    lat = L.make_lattice(card.kind, card.c, card.cs2, card.free)
+    data = q17["cases"][str(case)]
+    tol = 1e-14 if data["exact"] else 5e-7
+    assert abs(card.cs2 - _expr(data["cs2"])) < 1e-15
+    groups = ["rest"] + [g for g in q17["groups"][1:] for _ in range(4)]
+    assert np.abs(lat.w - np.array([_expr(data[g]) for g in groups])).max() < tol
+    if case != 5:   # case 5 drops only groups whose weights are free (zero)
+        with pytest.raises(ValueError):
+            L.make_lattice(card.kind, card.c, card.cs2 * 1.01, card.free)
 
 
 @pytest.mark.parametrize("case", [1, 2, 3, 4, 5])
