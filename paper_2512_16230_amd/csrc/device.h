@@ -182,8 +182,8 @@ struct VecT {
   typedef T type __attribute__((ext_vector_type(VEC), aligned(ALIGN)));
 };
 
-// Populations are streamed once per step: the step kernel's loads and
-// stores carry the nontemporal hint (MRTLB_NT=0 at build time turns it off).
+// Populations are streamed once per step: the step kernel's stores carry the
+// nontemporal hint (MRTLB_NT=0 at build time turns it off).
 #ifndef MRTLB_NT
 #define MRTLB_NT 1
 #endif
@@ -194,7 +194,18 @@ struct VecT {
 // offset, so per population no per-lane address arithmetic is needed.
 // Accesses beyond the resource's size read 0 / are dropped.
 constexpr int kBufFlags = 0x00020000;   // dword 3 of a raw buffer resource (gfx9 family)
-constexpr int kAuxNT = MRTLB_NT ? 2 : 0; // cache policy: nontemporal (gfx94x/gfx950 encoding)
+// cache policy bits (gfx94x/gfx950 encoding: 2 = nontemporal).  Stores are
+// streamed; loads keep the default policy: a wavefront's shifted read spans
+// one partial cache line at each end, which the neighbouring wavefront reads
+// from L2 (measured: 3-6% faster than nontemporal loads, less HBM fetch).
+#ifndef MRTLB_LOAD_AUX
+#define MRTLB_LOAD_AUX 0
+#endif
+#ifndef MRTLB_STORE_AUX
+#define MRTLB_STORE_AUX (MRTLB_NT ? 2 : 0)
+#endif
+constexpr int kAuxLoad = MRTLB_LOAD_AUX;
+constexpr int kAuxStore = MRTLB_STORE_AUX;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kBufFlags);
@@ -213,19 +224,19 @@ struct RawChunk<16> { typedef unsigned int T __attribute__((ext_vector_type(4)))
 
 template <int BYTES>
 __device__ __forceinline__ typename RawChunk<BYTES>::T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (BYTES == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kAuxNT);
-  else if constexpr (BYTES == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kAuxNT);
-  else if constexpr (BYTES == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, kAuxNT);
-  else return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, kAuxNT);
+  if constexpr (BYTES == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kAuxLoad);
+  else if constexpr (BYTES == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kAuxLoad);
+  else if constexpr (BYTES == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, kAuxLoad);
+  else return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, kAuxLoad);
 }
 
 template <int BYTES>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, typename RawChunk<BYTES>::T v, uint32_t voff,
                                           uint32_t soff) {
-  if constexpr (BYTES == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, (int)soff, kAuxNT);
-  else if constexpr (BYTES == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, kAuxNT);
-  else if constexpr (BYTES == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, kAuxNT);
-  else __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, kAuxNT);
+  if constexpr (BYTES == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, (int)soff, kAuxStore);
+  else if constexpr (BYTES == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, kAuxStore);
+  else if constexpr (BYTES == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, kAuxStore);
+  else __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, kAuxStore);
 }
 
 // VEC consecutive stored elements starting at element (uni + lane): uni is
