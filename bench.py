@@ -152,6 +152,39 @@ def bench_tgv3d(torch, H, W, stream, args):
     print(json.dumps(out), flush=True)
 
 
+def bench_cde(torch, H, W, stream, args):
+    """rD2Q13 CDE special case (velocity field u(x), S_G = -u . grad phi):
+    Gaussian hill in a shear flow on a 4096^2 box."""
+    n = args.size
+    shape = (n, n)
+    card = W.Q13_SQUARE
+    wl = W.cde_hill(shape, args.steps, u=W.shear_field(card, shape, 0.04), D0=0.1, card=card)
+    r = wl.rates
+    ctx = H.Context(0, stream=stream.cuda_stream)
+    lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
+    md = H.model_desc("CDE", s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
+                      **_bounds(W, args.storage, wl))
+    s = H.Solve(ctx, lat, md, shape, args.storage)
+    s.init_fields(wl.rho_or_phi, wl.u)
+    del wl
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_ms = s.step_timed(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nodes = n * n
+    real = 8 if args.storage == "fp64" else 4
+    launch_bytes = (2 * 13 * STORE_BYTES[args.storage] + 2 * real) * nodes   # + the velocity field read
+    out = _line("rD2Q13 CDE MLUPS (velocity field, S_G = -u.grad phi), % of HBM roofline",
+                nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
+                {"workload": "cde-shear-rD2Q13-%dx%d" % (n, n), "lattice": "rD2Q13", "storage": args.storage,
+                 "nodes": nodes}, args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
+    s.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_ncde_batch(torch, H, W, stream, args):
     """256 rD2Q13 NCDE solves, sides log-uniform in [128, 1024], one launch per step."""
     wls = W.ncde_batch(256, steps=args.steps)
@@ -227,7 +260,7 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=sorted(STORE_BYTES))
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="tgv2d", choices=["tgv2d", "tgv3d", "ncde-batch", "serve"],
+    ap.add_argument("--workload", default="tgv2d", choices=["tgv2d", "tgv3d", "ncde-batch", "cde", "serve"],
                     help="tgv2d: rD2Q25 4096^2 (default); tgv3d: rD3Q53 256^3 compressible; "
                          "ncde-batch: 256 rD2Q13 NCDE solves advanced by one batched launch per step")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (requests/s)")
@@ -259,6 +292,8 @@ def main():
         return bench_tgv3d(torch, H, W, stream, args)
     if args.workload == "ncde-batch":
         return bench_ncde_batch(torch, H, W, stream, args)
+    if args.workload == "cde":
+        return bench_cde(torch, H, W, stream, args)
     if args.workload == "serve":
         return bench_serve(stream, args)
     shape = (args.size, args.size)

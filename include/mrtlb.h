@@ -148,8 +148,15 @@ mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* lat, int* b, int* d, int* 
  *                 first moment (I - S1/2) u [(phi^n - phi^{n-1}) +
  *                 u . grad phi^{n-1}] (eq. M-NCDE-6, case (1); central
  *                 differences, phi^{-1} = phi^0).
+ * MRTLB_CDE       phi_t + u . grad phi = div(K grad phi) with a velocity
+ *                 field u(x) given per node (the NCDE special case (3)):
+ *                 diffusion-type equilibrium M0 = phi, M1 = 0,
+ *                 M2 = cs^2 phi I, M3 = 0; source S_G = -u . grad phi with
+ *                 grad phi = -s1 sum_j c_j f_j / cs^2 and
+ *                 phi = sum_j f_j + S_G / 2 (eq. M-NCDE-3-00),
+ *                 M0G = (1 - s0/2) S_G; K = cs^2 (1/s1 - 1/2).  2D lattices.
  * ------------------------------------------------------------------------- */
-typedef enum { MRTLB_NSE_INC = 0, MRTLB_NSE_COMP = 1, MRTLB_NCDE = 2 } mrtlb_model;
+typedef enum { MRTLB_NSE_INC = 0, MRTLB_NSE_COMP = 1, MRTLB_NCDE = 2, MRTLB_CDE = 3 } mrtlb_model;
 
 typedef struct {
   int model;         /* mrtlb_model */
@@ -203,7 +210,8 @@ void mrtlb_solve_destroy(mrtlb_solve* s);
 
 /* Initial state: f_bar(x, 0) = f_eq(rho_or_phi, u) - F/2 (NSE) or
  * f_eq(phi) (NCDE).  rho_or_phi: N values (rho_bar for NSE_INC, rho for
- * NSE_COMP, phi for NCDE); u: d*N values (ignored for NCDE, may be NULL);
+ * NSE_COMP, phi for NCDE and CDE); u: d*N values (the velocity field for
+ * the CDE; ignored for NCDE, may be NULL);
  * force: d*N values or NULL (required iff the solve has a force field).
  * Resets the step counter.  Synchronous. */
 mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho_or_phi, const double* u, const double* force);
@@ -226,8 +234,8 @@ mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms);
  * latest of mrtlb_init_fields, mrtlb_write_populations and this call.  Each
  * check costs one FP64 reduction pass over the populations and a host
  * synchronisation.  every = 0 (the default) turns it off.
- * Errors: EINVAL (NULL solve, every < 0), EDEVICE, ENUMERIC (non-finite
- * state at the reference point). */
+ * Errors: EINVAL (NULL solve, every < 0, a CDE solve: its total changes),
+ * EDEVICE, ENUMERIC (non-finite state at the reference point). */
 mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every);
 
 /* Advance solve i of the array by nsteps[i] >= 0 steps.  Solves that share

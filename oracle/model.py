@@ -27,6 +27,16 @@ step is, in the paper's order:
      f* = (1 - s_h) f + W sum_{r<=3} H_r^T (m*_r - (1 - s_h) m_r) / n_r;
   7. propagation f_bar_j(x + c_j dt) = f*_j(x) (eq. 2-2), periodic.
 
+The convection-diffusion special case (3) of the NCDE section (model
+"CDE"): a diffusion-type equilibrium (M0 = phi, M1 = 0, M2 = cs^2 phi I,
+M3 = 0), lambda = 1, M1G = 0 and the source S_G = -u . grad(phi) with a
+known velocity field u(x); the gradient comes from the non-equilibrium first
+moment, grad(phi) = -S1 sum_j c_j f_j / (dt cs^2), and
+phi = sum_j f_j + dt S_G / 2 (eq. M-NCDE-3-00, read with c_j in the first
+sum); M0G = (1 - s0/2) S_G (eq. M-NCDE-4), so each step adds S_G to the
+zeroth moment.  It recovers d_t phi + u . grad(phi) = div(K grad(phi)),
+K = cs^2 (1/s1 - 1/2) dt.  The initial state is the equilibrium w_j phi.
+
 Readings of points the paper leaves open (all listed in the design notes):
 Hermite moments of F and G above their constrained orders are zero;
 the equilibrium has no Hermite component above third order (eq. feq-1 with
@@ -44,7 +54,7 @@ import numpy as np
 
 from .lattice import Lattice
 
-NSE_INC, NSE_COMP, NCDE = "NSE_INC", "NSE_COMP", "NCDE"
+NSE_INC, NSE_COMP, NCDE, CDE = "NSE_INC", "NSE_COMP", "NCDE", "CDE"
 
 
 @dataclass
@@ -122,9 +132,18 @@ def _uuu(u):
 # macroscopic variables (eq. 2-4-2 / 2-4-1)
 # --------------------------------------------------------------------------
 
+def cde_source(lat: Lattice, model: Model, f: np.ndarray, vel: np.ndarray):
+    """S_G = -u . grad(phi) with grad(phi) = -s1 sum_j c_j f_j / cs^2 (CDE)."""
+    grad = -model.s1 * (lat.E.T @ f) / lat.cs2
+    return -(vel * grad).sum(axis=0)
+
+
 def macroscopic(lat: Lattice, model: Model, f: np.ndarray, force=None):
-    """(rho_bar or phi, u, rho_m) from pre-collision f_bar of shape (b, n)."""
+    """(rho_bar or phi, u, rho_m) from pre-collision f_bar of shape (b, n).
+    For the CDE ``force`` carries the velocity field u (d, n)."""
     R0 = f.sum(axis=0)
+    if model.eq == CDE:
+        return R0 + 0.5 * cde_source(lat, model, f, force), force, None
     if model.eq == NCDE:
         u = np.repeat(np.asarray(model.adv_u[: lat.d], dtype=np.float64)[:, None], f.shape[1], axis=1)
         return R0, u, None
@@ -139,6 +158,10 @@ def equilibrium_raw(lat: Lattice, model: Model, R0, u, rho_m):
     """Raw moments M0..M3 of f_eq prescribed by the model (None = unconstrained)."""
     d, cs2 = lat.d, lat.cs2
     I = np.eye(d)[:, :, None]
+    if model.eq == CDE:
+        phi = R0
+        n = phi.shape[-1]
+        return [phi, np.zeros((d, n)), cs2 * phi * I, np.zeros((d, d, d, n))]
     if model.eq == NCDE:
         phi = R0
         K = cs2 * (1.0 / model.s1 - 0.5)
@@ -225,12 +248,20 @@ class State:
 def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None):
     """Post-collision populations f* (b, n) from pre-collision f_bar (b, n).
 
-    ``ncde_b`` is the NCDE field B^n (d, n) of the auxiliary first moment."""
+    ``ncde_b`` is the NCDE field B^n (d, n) of the auxiliary first moment;
+    for the CDE ``force`` is the velocity field (d, n)."""
     n = f.shape[1]
     s = rates(lat, model)
     R0, u, rho_m = macroscopic(lat, model, f, force)
     m = lat.H() @ f
     meq = equilibrium_hermite(lat, model, R0, u, rho_m)
+    if model.eq == CDE:
+        # M0G = (1 - s0/2) S_G on the zeroth row, nothing else
+        mF = np.zeros_like(m)
+        mG = np.zeros_like(m)
+        mG[[r.order == 0 for r in lat.rows]] = (1 - 0.5 * model.s0) * cde_source(lat, model, f, force)
+        mstar = m - s[:, None] * (m - meq) + mG
+        return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
     mF = force_hermite(lat, n, force) if model.eq != NCDE else np.zeros_like(m)
     mG = aux_hermite(lat, model, s, u, force, extra=ncde_b)
     mstar = m - s[:, None] * (m - meq) + mG + (1 - 0.5 * s)[:, None] * mF
@@ -271,10 +302,14 @@ def run(lat, model, st: State, steps: int, force=None) -> State:
 # --------------------------------------------------------------------------
 
 def init_state(lat: Lattice, model: Model, rho_or_phi: np.ndarray, u=None, force=None) -> State:
-    """f_bar(x, 0) = f_eq(rho, u) - dt/2 F (NSE) or f_eq(phi) (NCDE)."""
+    """f_bar(x, 0) = f_eq(rho, u) - dt/2 F (NSE) or f_eq(phi) (NCDE, CDE)."""
     grid = rho_or_phi.shape
     R0 = rho_or_phi.reshape(-1).astype(np.float64)
     n = R0.size
+    if model.eq == CDE:
+        meq = equilibrium_hermite(lat, model, R0, None, None)
+        f = populations_from_hermite(lat, meq)
+        return State(f.reshape((lat.b,) + grid), None)
     if model.eq == NCDE:
         uu = np.repeat(np.asarray(model.adv_u[: lat.d], dtype=np.float64)[:, None], n, axis=1)
         meq = equilibrium_hermite(lat, model, R0, uu, None)

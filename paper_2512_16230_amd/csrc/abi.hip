@@ -133,7 +133,8 @@ static int pick_vec(int storage, int kind, int model, int nx) {
   // pressure), for rows under 512 nodes and for the NCDE; otherwise 2 nodes
   // (FP32/FP64) or 4 nodes (16-bit storage, 8-byte accesses per lane).
   const bool small = storage != kFP64 && storage != kFP32 && storage != kFP32Dev;
-  int v = (kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || nx < 512 || model == MRTLB_NCDE) ? 1
+  int v = (kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || nx < 512 || model == MRTLB_NCDE ||
+           model == MRTLB_CDE) ? 1
                                                                                             : (small ? 4 : 2);
   if (const char* e = std::getenv("MRTLB_STEP_VEC")) {
     const int o = std::atoi(e);
@@ -224,7 +225,7 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   const mrtlb_model_desc& m = s.model;
   P.s1 = (Real)m.s1; P.ss = (Real)m.s_shear; P.sb = (Real)m.s_bulk; P.s3 = (Real)m.s3; P.sh = (Real)m.s_high;
   const bool dev = s.storage != kFP64 && s.storage != kFP32;
-  P.rho_ref = (Real)(dev && m.model != MRTLB_NCDE ? m.rho0 : 0.0);
+  P.rho_ref = (Real)(dev && m.model != MRTLB_NCDE && m.model != MRTLB_CDE ? m.rho0 : 0.0);
   P.rho0 = (Real)m.rho0;
   if (m.model == MRTLB_NCDE) {
     const double K = L.cs2 * (1.0 / m.s1 - 0.5);
@@ -381,13 +382,14 @@ mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* l, int* b, int* d, int* e,
 }
 
 static mrtlb_status check_model(const mrtlb_model_desc& m, int D, int kind) {
-  if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP && m.model != MRTLB_NCDE)
+  if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP && m.model != MRTLB_NCDE && m.model != MRTLB_CDE)
     return fail(MRTLB_EINVAL, "unknown model");
   const double r[6] = {m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high};
   for (double v : r)
     if (!(v > 0 && v < 2)) return fail(MRTLB_EINVAL, "relaxation rates must lie in (0, 2)");
   if (m.model == MRTLB_NSE_INC && !(m.rho0 > 0)) return fail(MRTLB_EINVAL, "rho0 must be positive");
   if (m.model == MRTLB_NCDE && D != 2) return fail(MRTLB_EINVAL, "the NCDE model is built for 2D lattices");
+  if (m.model == MRTLB_CDE && D != 2) return fail(MRTLB_EINVAL, "the CDE model is built for 2D lattices");
   if (!(m.u_bound >= 0 && m.u_bound < 1e3) || !(m.dev_bound >= 0 && m.dev_bound < 1e3))
     return fail(MRTLB_EINVAL, "u_bound and dev_bound must be finite and >= 0");
   (void)kind;
@@ -407,6 +409,7 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
   size_t b = 2 * (size_t)lat->L.B * (size_t)(rows * row_pitch(n[0], storage)) * elem_bytes(storage);
   if (has_force) b += (size_t)D * (size_t)N * real;
   if (model == MRTLB_NCDE) b += 2 * (size_t)N * real;
+  if (model == MRTLB_CDE) b += (size_t)D * (size_t)N * real;   // velocity field
   b += 3 * sizeof(Job<double>) + sizeof(KParams<double>);
   *bytes = b;
   return MRTLB_OK;
@@ -439,7 +442,8 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   const int D = lat->L.D;
   mrtlb_status st = check_model(*model, D, lat->L.kind);
   if (st != MRTLB_OK) return st;
-  if (has_force && model->model == MRTLB_NCDE) return fail(MRTLB_EINVAL, "the NCDE model takes no force field");
+  if (has_force && (model->model == MRTLB_NCDE || model->model == MRTLB_CDE))
+    return fail(MRTLB_EINVAL, "the NCDE and CDE models take no force field");
   size_t bytes = 0;
   st = mrtlb_solve_footprint(lat, n, storage, model->model, has_force, &bytes);
   if (st != MRTLB_OK) return st;
@@ -481,6 +485,8 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
             alloc(&s->pd, sizeof(KParams<double>));
   if (ok && has_force) ok = alloc(&s->force, (size_t)D * s->N * real);
   if (ok && model->model == MRTLB_NCDE) ok = alloc(&s->phi[0], s->N * real) && alloc(&s->phi[1], s->N * real);
+  // the CDE's velocity field lives where the NSE force field would
+  if (ok && model->model == MRTLB_CDE) ok = alloc(&s->force, (size_t)D * s->N * real);
   if (!ok) {
     release(s);
     delete s;
@@ -519,7 +525,7 @@ struct DevBuf {
 // sums on the device (fixed order), then a fixed-order sum on the host.
 static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
   const int B = s->L.B, D = s->L.D;
-  const int nf = s->force ? D : 0;
+  const int nf = s->force && s->model.model != MRTLB_CDE ? D : 0;
   const int planes = B + nf;
   const uint32_t chunk = kBlock * kChunkIters;
   const uint32_t nchunks = (s->N + chunk - 1) / chunk;
@@ -544,7 +550,8 @@ static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
   for (int p = 0; p < planes; ++p)
     for (uint32_t c = 0; c < nchunks; ++c) plane[p] += h[(size_t)p * nchunks + c];
   double m = 0, mom[3] = {0, 0, 0};
-  const double ref = s->storage != kFP64 && s->storage != kFP32 && s->model.model != MRTLB_NCDE
+  const double ref = s->storage != kFP64 && s->storage != kFP32 && s->model.model != MRTLB_NCDE &&
+                             s->model.model != MRTLB_CDE
                          ? s->model.rho0
                          : 0.0;
   for (int j = 0; j < B; ++j) {
@@ -614,6 +621,8 @@ static KParams<Real> with_drift(const mrtlb_solve& s, KParams<Real> P) {
 mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every) {
   if (!s) return fail(MRTLB_EINVAL, "solve is NULL");
   if (every < 0) return fail(MRTLB_EINVAL, "every must be >= 0");
+  if (every > 0 && s->model.model == MRTLB_CDE)
+    return fail(MRTLB_EINVAL, "the CDE does not conserve its total (S_G = -u . grad phi)");
   HIP_TRY(hipSetDevice(s->ctx->device));
   s->drift_every = every;
   return record_reference(s);
@@ -623,7 +632,8 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
   if (!s || !rho) return fail(MRTLB_EINVAL, "NULL argument");
   const int D = s->L.D;
   const bool ncde = s->model.model == MRTLB_NCDE;
-  if (!ncde && !u) return fail(MRTLB_EINVAL, "u is required for the NSE models");
+  const bool cde = s->model.model == MRTLB_CDE;
+  if (!ncde && !u) return fail(MRTLB_EINVAL, "u is required for the NSE models and the CDE");
   if ((force != nullptr) != (s->has_force != 0)) return fail(MRTLB_EINVAL, "force must be given iff the solve has a force field");
   for (uint32_t i = 0; i < s->N; ++i)
     if (!std::isfinite(rho[i])) return fail(MRTLB_ENUMERIC, "non-finite initial density/phi");
@@ -632,7 +642,20 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
   DevBuf dr, du, df;
   HIP_TRY(hipMalloc(&dr.p, (size_t)s->N * 8));
   HIP_TRY(hipMemcpyAsync(dr.p, rho, (size_t)s->N * 8, hipMemcpyHostToDevice, st));
-  if (!ncde) {
+  if (cde) {
+    // the velocity field, in the compute precision
+    for (size_t i = 0; i < (size_t)D * s->N; ++i)
+      if (!std::isfinite(u[i])) return fail(MRTLB_ENUMERIC, "non-finite velocity field");
+    if (is_double(s->storage)) {
+      HIP_TRY(hipMemcpyAsync(s->force, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    } else {
+      std::vector<float> tmp((size_t)D * s->N);
+      for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)u[i];
+      HIP_TRY(hipMemcpyAsync(s->force, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+  } else if (!ncde) {
     HIP_TRY(hipMalloc(&du.p, (size_t)D * s->N * 8));
     HIP_TRY(hipMemcpyAsync(du.p, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
   }

@@ -510,7 +510,17 @@ struct Equilibrium {
   // NCDE: phi, u = advection velocity.
   __device__ __forceinline__ void build(const KParams<Real>& P, Real rho_or_phi, const Real* j, const Real* u) {
     constexpr int D = L::D;
-    if constexpr (MODEL == kNcde) {
+    if constexpr (MODEL == kCde) {
+      // diffusion-type equilibrium w_j phi: no Hermite moment above order 0
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        e1[a] = 0; e2n[a] = 0; e2o[a] = 0; e3p[a] = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) e3m[a][b] = 0;
+      }
+      exyz = 0;
+      (void)P; (void)rho_or_phi; (void)j; (void)u;
+    } else if constexpr (MODEL == kNcde) {
       const Real phi = rho_or_phi;
       const Real Phi = P.phi_coef * (phi + P.D2 * phi * phi * phi * Real(1.0 / 3.0));
 #pragma unroll
@@ -620,7 +630,15 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
   Real u[3] = {0, 0, 0}, jm[3] = {0, 0, 0};
   const Real R = M.R0 + P.rho_ref;
-  if constexpr (MODEL == kNcde) {
+  Real sg = 0;   // CDE: S_G = -u . grad(phi), grad(phi) = -s1 sum_j c_j f_j / cs^2
+  if constexpr (MODEL == kCde) {
+    const char* vel = static_cast<const char*>(static_cast<const void*>(J.force));
+    Real dot = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      dot += gload<Real>(vel + (size_t)a * N * sizeof(Real), self * (uint32_t)sizeof(Real)) * M.m1[a];
+    sg = P.s1 * dot / P.cs2;
+  } else if constexpr (MODEL == kNcde) {
     const Real phi_prev = gload<Real>(J.phi_prev, self * (uint32_t)sizeof(Real));
     Real adv = 0;
 #pragma unroll
@@ -711,8 +729,9 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
     }
     if constexpr (D == 3) dxyz = (E.exyz + k3 * (M.mxyz - E.exyz) - kx * M.mxyz) * P.inxyz;
   }
-  // order 0 is conserved: m*_0 = m_0
-  const Real d0 = P.sh * M.R0 * P.in0;
+  // order 0 is conserved, m*_0 = m_0, except for the CDE source:
+  // m*_0 = m_0 + M0G + s0 S_G / 2 = m_0 + S_G (M0G = (1 - s0/2) S_G)
+  const Real d0 = (P.sh * M.R0 + sg) * P.in0;
 
   // a7: back to populations (output numbers of the storage)
   backward<L>(x, P, kx * P.kin, P.wo, d0, d1, d2n, d2o, d3m, d3p, dxyz);
@@ -848,7 +867,9 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   const uint32_t N = P.N;
   const double R = rho[self];
   double u[3] = {0, 0, 0}, jm[3] = {0, 0, 0}, F[3] = {0, 0, 0};
-  if constexpr (MODEL == kNcde) {
+  if constexpr (MODEL == kCde) {
+    // equilibrium w_j phi; the velocity field is stored by the host
+  } else if constexpr (MODEL == kNcde) {
     for (int a = 0; a < D; ++a) u[a] = P.adv[a];
     static_cast<Real*>(J.phi_out)[self] = (Real)R;
     const_cast<Real*>(J.phi_prev)[self] = (Real)R;
@@ -917,6 +938,15 @@ __global__ __launch_bounds__(kBlock) void k_gather(const Job<typename StoreT<ST>
       });
     });
     R += P.rho_ref;
+    if constexpr (MODEL == kCde) {
+      // phi = sum_j f_j + S_G / 2; u is the stored velocity field
+      double dot = 0;
+      for (int a = 0; a < D; ++a) dot += (double)J.force[(size_t)a * N + self] * P.c1[a] * m1[a];
+      out0[self] = R + 0.5 * P.s1 * dot / P.cs2;
+      if (out1)
+        for (int a = 0; a < D; ++a) out1[(size_t)a * N + self] = (double)J.force[(size_t)a * N + self];
+      return;
+    }
     out0[self] = R;
     if (out1) {
       if constexpr (MODEL == kNcde) {
@@ -1024,7 +1054,8 @@ hipError_t launch_lattice(const LaunchReq& r) {
     const auto* J = static_cast<const Job<Real>*>(r.jobs);
     const auto* PD = static_cast<const KParams<double>*>(r.pd);
     const bool ncde = r.model == kNcde;
-    if (ncde && L::D != 2) return;
+    const bool cde = r.model == kCde;
+    if ((ncde || cde) && L::D != 2) return;
     switch (r.op) {
       case kOpStep: {
         auto step = [&](auto vc) {
@@ -1032,6 +1063,9 @@ hipError_t launch_lattice(const LaunchReq& r) {
           if (ncde) {
             if constexpr (L::D == 2)
               hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+          } else if (cde) {
+            if constexpr (L::D == 2)
+              hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
           } else if (r.force) {
             hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
           } else {
@@ -1046,6 +1080,8 @@ hipError_t launch_lattice(const LaunchReq& r) {
       case kOpInit:
         if (ncde) {
           if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kNcde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+        } else if (cde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kCde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
         } else {
           hipLaunchKernelGGL((k_init<L, ST, kNseComp>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
         }
@@ -1053,6 +1089,8 @@ hipError_t launch_lattice(const LaunchReq& r) {
       case kOpMoments:
         if (ncde) {
           if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kNcde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        } else if (cde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kCde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
         } else {
           hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
         }

@@ -18,7 +18,7 @@ constexpr double kI16Range = 2.0;    // default int16 range: |f - w rho_ref| <= 
 constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
 
 enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4, kI16Dev = 5 };
-enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2 };
+enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2, kCde = 3 };
 
 // Per-solve constants of the collision, in the compute precision.  Row
 // constants refer to the component-form Hermite rows of order <= 3.
@@ -69,7 +69,7 @@ struct Job {
   KParams<Real> P;
   const void* fin;          // populations at t (post-collision, pre-propagation)
   void* fout;               // populations at t + 1
-  const Real* force;        // d x N, or nullptr
+  const Real* force;        // d x N, or nullptr (CDE: the velocity field)
   const Real* phi_prev;     // NCDE: phi^{n-1}
   Real* phi_out;            // NCDE: phi^n
   uint32_t block_begin;     // first linear workgroup of this job

@@ -169,13 +169,16 @@ def sinusoidal_force(card: Card, shape, F0, seed, modes=3):
 
 def flow_bounds(eq, rho_or_phi, u=None, force=None, steps=0, rho0=1.0, adv_u=(0.0, 0.0, 0.0), margin=1.5):
     """Run-long bounds (u_bound, dev_bound) on max |u| and on max |rho - rho0|
-    / rho0 (NSE) or max |phi| (NCDE), from the initial fields: ``margin``
+    / rho0 (NSE) or max |phi| (NCDE, CDE), from the initial fields: ``margin``
     times the initial maxima, which bound an unforced run (decaying kinetic
     energy; maximum principle of the convection-diffusion equation), plus for
     a body force the velocity it can add in ``steps`` steps, max |F| steps /
     min rho."""
     if eq == "NCDE":
         return margin * float(np.linalg.norm(adv_u)), margin * float(np.abs(rho_or_phi).max())
+    if eq == "CDE":
+        umax = float(np.sqrt((np.asarray(u) ** 2).sum(0)).max())
+        return margin * umax, margin * float(np.abs(rho_or_phi).max())
     rho = np.asarray(rho_or_phi)
     umax = float(np.sqrt((np.asarray(u) ** 2).sum(0)).max()) if u is not None else 0.0
     if force is not None:
@@ -246,6 +249,28 @@ def ncde_hill(shape=(128, 128), steps=1000, adv_u=(0.03, -0.02), D0=0.1, D2=1.0,
     phi = gaussian_hill(card, shape)
     return Workload("ncde-%s-%dx%d" % (card.kind, shape[1], shape[0]), card, "NCDE", shape, steps, r,
                     0.0, phi, None, adv_u=tuple(adv_u) + (0.0,) * (3 - len(adv_u)), D0=D0, D2=D2)
+
+
+def shear_field(card: Card, shape, U):
+    """Divergence-free velocity field u = (U sin(2 pi y / Ly), 0) on a 2D box."""
+    y = axis_coords(card, shape, 1)
+    Ly = shape[0] * card.c[1]
+    ux = np.broadcast_to(U * np.sin(2 * pi * y / Ly), shape)
+    return np.stack([ux, np.zeros(shape)])
+
+
+def cde_hill(shape=(128, 128), steps=1000, u=(0.03, -0.02), D0=0.1, card=Q13_SQUARE):
+    """Convection-diffusion (CDE special case of the NCDE) of a Gaussian hill
+    (amplitude 1, sigma0 = N/16) in a velocity field: ``u`` is a constant
+    vector or a (d, Ny, Nx) field; diffusivity D0 via s1 (K = D0)."""
+    s1 = 1.0 / (D0 / card.cs2 + 0.5)
+    r = Rates(1.2, s1, 1.2, 1.2, 1.2, 1.2)
+    phi = gaussian_hill(card, shape)
+    u = np.asarray(u, dtype=np.float64)
+    if u.ndim == 1:
+        u = np.broadcast_to(u.reshape((card.d,) + (1,) * card.d), (card.d,) + tuple(shape)).copy()
+    return Workload("cde-%s-%dx%d" % (card.kind, shape[1], shape[0]), card, "CDE", shape, steps, r,
+                    0.0, phi, u, D0=D0)
 
 
 def ncde_batch_sizes(n=256, lo=128, hi=1024, seed=0):

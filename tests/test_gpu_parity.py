@@ -176,6 +176,30 @@ def test_rd2q21_lattices_ncde(ctx, card):
         assert max_rel(s.read_moments(with_u=False), phi_o) < tol
 
 
+@pytest.mark.parametrize("card", [W.Q13_SQUARE, W.Q25_RECT], ids=lambda c: c.kind)
+@pytest.mark.parametrize("field", ["constant", "shear"])
+def test_cde(ctx, card, field):
+    """The CDE special case (velocity field, S_G = -u . grad phi) against the
+    oracle, FP64 and FP32, on ragged tiles."""
+    shape = (40, 72)
+    vel = (0.03, -0.02) if field == "constant" else W.shear_field(card, shape, 0.04)
+    wl = W.cde_hill(shape, 30, u=vel, D0=0.1, card=card)
+    lat, mdl = oracle_for(card, "CDE", wl.rates)
+    st = OM.run(lat, mdl, OM.init_state(lat, mdl, wl.rho_or_phi), 30, force=wl.u)
+    phi_o, u_o = OM.moments(lat, mdl, st, force=wl.u)
+    for storage, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        print("case: CDE %s %s %s" % (card.kind, field, storage), flush=True)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("CDE", wl.rates), shape, storage)
+        s.init_fields(wl.rho_or_phi, wl.u)
+        s.step(30)
+        phi, u = s.read_moments()
+        assert max_rel(phi, phi_o) < tol
+        assert np.abs(u - wl.u).max() <= 1e-7 * max(np.abs(wl.u).max(), 1e-30)
+        with pytest.raises(H.MrtlbError):
+            s.set_drift_correction(10)
+        s.close()
+
+
 @pytest.mark.parametrize("shape", [(48, 136), (9, 70)])
 def test_rd2q13_ncde(ctx, shape):
     card = W.Q13_SQUARE

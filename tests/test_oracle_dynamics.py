@@ -142,3 +142,73 @@ def test_nonlinear_diffusion_second_moment_identity():
     lhs = ((phis[20] * r2).sum() - (phis[0] * r2).sum()) / 20
     rhs = sum(2 * 2 * G(p).sum() * (0.5 if k in (0, 20) else 1.0) for k, p in enumerate(phis)) / 20
     assert abs(lhs / rhs - 1) < 3e-3
+
+
+# --------------------------------------------------------------------------
+# CDE special case (3): diffusion-type equilibrium, S_G = -u . grad(phi)
+# --------------------------------------------------------------------------
+
+def _cde_hill_error(N, steps, adv=(0.03, -0.02), D0=0.1):
+    wl = W.cde_hill((N, N), steps, u=adv, D0=D0)
+    lat, mdl = setup(wl)
+    st = M.init_state(lat, mdl, wl.rho_or_phi)
+    st = M.run(lat, mdl, st, steps, force=wl.u)
+    phi, _ = M.moments(lat, mdl, st, force=wl.u)
+    s0 = N / 16.0
+    s2 = s0 ** 2 + 2 * D0 * steps
+    x = np.arange(N)[None, :]
+    y = np.arange(N)[:, None]
+    ref = np.zeros((N, N))
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            ref += s0 ** 2 / s2 * np.exp(-((x - N / 2 - adv[0] * steps + i * N) ** 2
+                                           + (y - N / 2 - adv[1] * steps + j * N) ** 2) / (2 * s2))
+    return np.abs(phi - ref).max() / ref.max()
+
+
+def test_cde_gaussian_hill_closed_form():
+    """Constant u: the advected, spreading Gaussian; error falls ~4x when the
+    grid is refined 2x (acoustic scaling of time)."""
+    e64 = _cde_hill_error(64, 100)
+    e32 = _cde_hill_error(32, 25)
+    assert e64 < 2e-2
+    assert 3.0 < e32 / e64 < 5.5
+
+
+def test_cde_without_velocity_is_the_linear_ncde():
+    """u = 0: the CDE and the NCDE with D(phi) = K (D2 = 0, no advection) are
+    the same scheme (equilibrium w phi, no sources)."""
+    wl = W.cde_hill((24, 20), 10, u=(0.0, 0.0), D0=0.1)
+    lat, mdl = setup(wl)
+    K = lat.cs2 * (1 / mdl.s1 - 0.5)
+    ncde = M.Model(eq=M.NCDE, s0=mdl.s0, s1=mdl.s1, s_shear=mdl.s_shear, s_bulk=mdl.s_bulk, s3=mdl.s3,
+                   s_h=mdl.s_h, D0=K, D2=0.0, adv_u=(0.0, 0.0, 0.0))
+    a = M.run(lat, mdl, M.init_state(lat, mdl, wl.rho_or_phi), 10, force=wl.u)
+    b = M.run(lat, ncde, M.init_state(lat, ncde, wl.rho_or_phi), 10)
+    assert np.abs(a.f - b.f).max() < 1e-14
+
+
+def test_cde_shear_field_converges_at_second_order():
+    """Divergence-free shear u = (U sin(2 pi y / L), 0): solutions on N, 2N
+    and 4N grids (time scaled by 4 per refinement, diffusive scaling) converge
+    at second order, and the total of phi stays put (div u = 0)."""
+    out = []
+    for N, steps in ((16, 10), (32, 40), (64, 160)):
+        card = W.Q13_SQUARE
+        U = 0.04 * 16 / N          # fixed Peclet number under diffusive scaling
+        D0 = 0.1
+        vel = W.shear_field(card, (N, N), U)
+        wl = W.cde_hill((N, N), steps, u=vel, D0=D0, card=card)
+        lat, mdl = setup(wl)
+        st = M.run(lat, mdl, M.init_state(lat, mdl, wl.rho_or_phi), steps, force=wl.u)
+        phi, _ = M.moments(lat, mdl, st, force=wl.u)
+        out.append((N, phi, wl.rho_or_phi.sum()))
+    # restrict the finer solutions to the coarse grid's nodes
+    c16 = out[0][1]
+    c32 = out[1][1][::2, ::2]
+    c64 = out[2][1][::4, ::4]
+    e1 = np.abs(c16 - c32).max()
+    e2 = np.abs(c32 - c64).max()
+    assert 3.0 < e1 / e2 < 5.5
+    for N, phi, m0 in out:
+        assert abs(phi.sum() - m0) / m0 < 1e-3
