@@ -378,41 +378,63 @@ struct Moments {
 
 // Hermite moments (component rows, physical units) of x[0..B-1].  SCALED:
 // x holds read numbers, population j is x_j * wsc[j] (one scale per pair).
+// The monomial sums run over rays: the pairs of a ray have velocities
+// sign * k * b for one direction b, so a degree-n monomial of a pair is
+// (sign k)^n times that of b, and each ray needs the four partial sums
+//   S0 = sum s, S2 = sum k^2 s, D1 = sum sign k d, D3 = sum sign k^3 d
+// (s = f_p + f_q, d = f_p - f_q) before its monomials are added once.
+// Accumulators start at -0.0, the additive identity the compiler folds.
 template <class L, bool SCALED, class Real>
 __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Real>& P, Moments<Real>& M) {
   constexpr int D = L::D;
+  const Real z = Real(-0.0);
   Real R0 = SCALED ? x[0] * P.wsc[0] : x[0];
-  Real R1[3] = {0, 0, 0}, R2n[3] = {0, 0, 0}, R2o[3] = {0, 0, 0}, R3p[3] = {0, 0, 0};
-  Real R3m[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  Real Rxyz = 0;
-  static_for<0, n_pairs<L>()>([&](auto kk) {
-    constexpr int p = pair_first<L>(decltype(kk)::value);
-    constexpr int q = opposite<L>(p);
-    Real s = x[p] + x[q];
-    Real d = x[p] - x[q];
-    if constexpr (SCALED) {
-      s *= P.wsc[p];
-      d *= P.wsc[p];
-    }
-    R0 += s;
-    static_for<0, D>([&](auto aa) {
-      constexpr int a = decltype(aa)::value;
-      constexpr int ea = evel<L>(p, a);
-      if constexpr (ea != 0) {
-        R1[a] += Real(ea) * d;
-        R2n[a] += Real(ea * ea) * s;
-        R3p[a] += Real(ea * ea * ea) * d;
-        static_for<0, D>([&](auto bb) {
-          constexpr int b = decltype(bb)::value;
-          constexpr int eb = evel<L>(p, b);
-          if constexpr (b != a && eb != 0) R3m[a][b] += Real(ea * eb * eb) * d;
-          if constexpr (b > a && eb != 0) R2o[off_index(a, b)] += Real(ea * eb) * s;
-        });
+  Real R1[3] = {z, z, z}, R2n[3] = {z, z, z}, R2o[3] = {z, z, z}, R3p[3] = {z, z, z};
+  Real R3m[3][3] = {{z, z, z}, {z, z, z}, {z, z, z}};
+  Real Rxyz = z;
+  static_for<0, n_pairs<L>()>([&](auto ll) {
+    constexpr int lead = decltype(ll)::value;
+    if constexpr (ray_leader<L>(lead) == lead) {
+      Real S0 = z, S2 = z, D1 = z, D3 = z;
+      static_for<lead, n_pairs<L>()>([&](auto kk) {
+        constexpr int pp = decltype(kk)::value;
+        if constexpr (ray_leader<L>(pp) == lead) {
+          constexpr int p = pair_first<L>(pp);
+          constexpr int q = opposite<L>(p);
+          constexpr int k = ray_scale<L>(pp);
+          constexpr int sk = ray_sign<L>(pp) * k;
+          Real s = x[p] + x[q];
+          Real d = x[p] - x[q];
+          if constexpr (SCALED) {
+            s *= P.wsc[p];
+            d *= P.wsc[p];
+          }
+          S0 += s;
+          S2 += Real(k * k) * s;
+          D1 += Real(sk) * d;
+          D3 += Real(sk * k * k) * d;
+        }
+      });
+      R0 += S0;
+      static_for<0, D>([&](auto aa) {
+        constexpr int a = decltype(aa)::value;
+        constexpr int ba = ray_dir<L>(lead, a);
+        if constexpr (ba != 0) {
+          R1[a] += Real(ba) * D1;
+          R2n[a] += Real(ba * ba) * S2;
+          R3p[a] += Real(ba * ba * ba) * D3;
+          static_for<0, D>([&](auto bb) {
+            constexpr int b = decltype(bb)::value;
+            constexpr int bv = ray_dir<L>(lead, b);
+            if constexpr (b != a && bv != 0) R3m[a][b] += Real(ba * bv * bv) * D3;
+            if constexpr (b > a && bv != 0) R2o[off_index(a, b)] += Real(ba * bv) * S2;
+          });
+        }
+      });
+      if constexpr (D == 3) {
+        constexpr int bxyz = ray_dir<L>(lead, 0) * ray_dir<L>(lead, 1) * ray_dir<L>(lead, 2);
+        if constexpr (bxyz != 0) Rxyz += Real(bxyz) * D3;
       }
-    });
-    if constexpr (D == 3) {
-      constexpr int exyz = evel<L>(p, 0) * evel<L>(p, 1) * evel<L>(p, 2);
-      if constexpr (exyz != 0) Rxyz += Real(exyz) * d;
     }
   });
   M.R0 = R0;
@@ -443,12 +465,15 @@ __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Rea
 // coefficients in lattice units, then evaluated per velocity pair:
 //   x_j <- kx * x_j + wo_j * sum_P beta_P e_j^P
 // (wo = w for populations in physical units; see KParams for the 16-bit
-// storages, whose output numbers it writes directly).
+// storages, whose output numbers it writes directly).  Per ray the even and
+// odd parts are b0 + k^2 E2 and sign (k O1 + k^3 O3), with E2, O1, O3 the
+// degree-2, -1 and -3 polynomials at the ray direction.
 template <class L, class Real>
 __device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P, Real kx, const Real* wo, Real d0,
                                          const Real* d1, const Real* d2n, const Real* d2o, const Real (*d3m)[3],
                                          const Real* d3p, Real dxyz) {
   constexpr int D = L::D;
+  const Real z = Real(-0.0);
   Real b0 = d0;
   Real b1[3], b2n[3], b2o[3], b3m[3][3], b3p[3];
 #pragma unroll
@@ -473,31 +498,44 @@ __device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P
   Real bxyz = 0;
   if constexpr (D == 3) bxyz = P.cxyz * dxyz;
   x[0] = kx * x[0] + wo[0] * b0;
-  static_for<0, n_pairs<L>()>([&](auto kk) {
-    constexpr int p = pair_first<L>(decltype(kk)::value);
-    constexpr int q = opposite<L>(p);
-    Real even = b0, odd = 0;
-    static_for<0, D>([&](auto aa) {
-      constexpr int a = decltype(aa)::value;
-      constexpr int ea = evel<L>(p, a);
-      if constexpr (ea != 0) {
-        even += Real(ea * ea) * b2n[a];
-        odd += Real(ea) * b1[a] + Real(ea * ea * ea) * b3p[a];
-        static_for<0, D>([&](auto bb) {
-          constexpr int b = decltype(bb)::value;
-          constexpr int eb = evel<L>(p, b);
-          if constexpr (b != a && eb != 0) odd += Real(ea * eb * eb) * b3m[a][b];
-          if constexpr (b > a && eb != 0) even += Real(ea * eb) * b2o[off_index(a, b)];
-        });
+  static_for<0, n_pairs<L>()>([&](auto ll) {
+    constexpr int lead = decltype(ll)::value;
+    if constexpr (ray_leader<L>(lead) == lead) {
+      Real E2 = z, O1 = z, O3 = z;
+      static_for<0, D>([&](auto aa) {
+        constexpr int a = decltype(aa)::value;
+        constexpr int ba = ray_dir<L>(lead, a);
+        if constexpr (ba != 0) {
+          E2 += Real(ba * ba) * b2n[a];
+          O1 += Real(ba) * b1[a];
+          O3 += Real(ba * ba * ba) * b3p[a];
+          static_for<0, D>([&](auto bb) {
+            constexpr int b = decltype(bb)::value;
+            constexpr int bv = ray_dir<L>(lead, b);
+            if constexpr (b != a && bv != 0) O3 += Real(ba * bv * bv) * b3m[a][b];
+            if constexpr (b > a && bv != 0) E2 += Real(ba * bv) * b2o[off_index(a, b)];
+          });
+        }
+      });
+      if constexpr (D == 3) {
+        constexpr int b3 = ray_dir<L>(lead, 0) * ray_dir<L>(lead, 1) * ray_dir<L>(lead, 2);
+        if constexpr (b3 != 0) O3 += Real(b3) * bxyz;
       }
-    });
-    if constexpr (D == 3) {
-      constexpr int exyz = evel<L>(p, 0) * evel<L>(p, 1) * evel<L>(p, 2);
-      if constexpr (exyz != 0) odd += Real(exyz) * bxyz;
+      static_for<lead, n_pairs<L>()>([&](auto kk) {
+        constexpr int pp = decltype(kk)::value;
+        if constexpr (ray_leader<L>(pp) == lead) {
+          constexpr int p = pair_first<L>(pp);
+          constexpr int q = opposite<L>(p);
+          constexpr int k = ray_scale<L>(pp);
+          constexpr int sk = ray_sign<L>(pp) * k;
+          const Real even = b0 + Real(k * k) * E2;
+          const Real odd = Real(sk) * O1 + Real(sk * k * k) * O3;
+          const Real wp = wo[p];
+          x[p] = kx * x[p] + wp * (even + odd);
+          x[q] = kx * x[q] + wp * (even - odd);
+        }
+      });
     }
-    const Real wp = wo[p];
-    x[p] = kx * x[p] + wp * (even + odd);
-    x[q] = kx * x[q] + wp * (even - odd);
   });
 }
 

@@ -145,4 +145,49 @@ constexpr int pair_first(int p) {
 template <class L>
 constexpr int n_pairs() { return (L::B - 1) / 2; }
 
+// Rays: pairs whose velocities are multiples of one direction (e, 2e, 3e on
+// the multispeed lattices) form a ray.  Pair p's first velocity is
+// sign * scale * base, base being the ray's direction as given by its first
+// pair (the leader).
+constexpr int iabs(int v) { return v < 0 ? -v : v; }
+constexpr int igcd(int a, int b) { return b == 0 ? a : igcd(b, a % b); }
+
+template <class L>
+constexpr int ray_scale(int p) {
+  const int j = pair_first<L>(p);
+  return igcd(igcd(iabs(L::EX[j]), iabs(L::EY[j])), iabs(ez<L>(j)));
+}
+
+template <class L>
+constexpr int prim(int p, int a) {
+  const int j = pair_first<L>(p);
+  const int v = a == 0 ? L::EX[j] : (a == 1 ? L::EY[j] : ez<L>(j));
+  return v / ray_scale<L>(p);
+}
+
+// +1 / -1 if pair q's direction equals / opposes pair p's, 0 otherwise
+template <class L>
+constexpr int ray_relation(int p, int q) {
+  bool same = true, opp = true;
+  for (int a = 0; a < L::D; ++a) {
+    same = same && prim<L>(p, a) == prim<L>(q, a);
+    opp = opp && prim<L>(p, a) == -prim<L>(q, a);
+  }
+  return same ? 1 : (opp ? -1 : 0);
+}
+
+template <class L>
+constexpr int ray_leader(int p) {
+  for (int q = 0; q <= p; ++q)
+    if (ray_relation<L>(q, p) != 0) return q;
+  return p;
+}
+
+template <class L>
+constexpr int ray_sign(int p) { return ray_relation<L>(ray_leader<L>(p), p); }
+
+// component a of the ray direction (the leader's primitive velocity)
+template <class L>
+constexpr int ray_dir(int leader, int a) { return a < L::D ? prim<L>(leader, a) : 0; }
+
 }  // namespace mrtlb
