@@ -59,6 +59,13 @@ const char* mrtlb_last_error(void);
 /* ABI version, (major << 16) | minor. */
 int mrtlb_version(void);
 
+/* Page-locked host memory from the library's HIP runtime, for staging the
+ * host arrays of mrtlb_init_fields / mrtlb_read_moments (copies from and to
+ * it run at DMA speed).  The caller owns it; release with mrtlb_host_free.
+ * Errors: EINVAL (NULL out, bytes == 0), ENOMEM. */
+mrtlb_status mrtlb_host_alloc(size_t bytes, void** out);
+void mrtlb_host_free(void* p);
+
 /* ---------------------------------------------------------------------------
  * Context: one device, one stream, one HBM budget.
  *   device            HIP device ordinal.

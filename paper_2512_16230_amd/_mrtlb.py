@@ -85,6 +85,8 @@ def lib():
         "mrtlb_read_moments": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_set_drift_correction": (c_int, [c_void_p, c_int64]),
+        "mrtlb_host_alloc": (c_int, [c_size_t, POINTER(c_void_p)]),
+        "mrtlb_host_free": (None, [c_void_p]),
         "mrtlb_read_populations": (c_int, [c_void_p, _DP]),
         "mrtlb_write_populations": (c_int, [c_void_p, _DP]),
         "mrtlb_solve_steps": (c_int64, [c_void_p]),
@@ -101,7 +103,8 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_ctx_synchronize", "mrtlb_lattice_create", "mrtlb_lattice_destroy", "mrtlb_lattice_query",
             "mrtlb_solve_create", "mrtlb_solve_footprint", "mrtlb_solve_destroy", "mrtlb_init_fields",
             "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
-            "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction"]
+            "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
+            "mrtlb_host_alloc", "mrtlb_host_free"]
 
 
 def _check(status):
@@ -223,6 +226,30 @@ def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s
     return m
 
 
+class HostBuffer:
+    """Page-locked float64 host array from the library (mrtlb_host_alloc);
+    ``array`` is a NumPy view of it.  Freed by close() or at exit."""
+
+    def __init__(self, n):
+        p = c_void_p()
+        _check(lib().mrtlb_host_alloc(int(n) * 8, byref(p)))
+        self._p = p
+        self.n = int(n)
+        self.array = np.ctypeslib.as_array(ctypes.cast(p, POINTER(c_double)), shape=(self.n,))
+
+    def close(self):
+        if self._p is not None and self._p.value:
+            self.array = None
+            lib().mrtlb_host_free(self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def footprint(lattice, shape, storage, eq, has_force=False):
     n = (c_int64 * 3)(*_nxyz(shape))
     out = c_size_t()
@@ -268,9 +295,20 @@ class Solve:
         _check(lib().mrtlb_step_timed(self.h, int(n), byref(ms)))
         return ms.value
 
-    def read_moments(self, with_u=True):
-        r = np.empty(self.N)
-        u = np.empty(self.d * self.N) if with_u else None
+    def read_moments(self, with_u=True, out=None):
+        """(rho_or_phi, u) as arrays of the grid shape; ``out`` = (r, u) lets
+        the caller supply the destination (contiguous float64, e.g. in
+        page-locked memory), u may be None."""
+        if out is not None:
+            r, u = out
+            if r.dtype != np.float64 or not r.flags.c_contiguous or r.size != self.N:
+                raise ValueError("out[0] must be a contiguous float64 array of N values")
+            if u is not None and (u.dtype != np.float64 or not u.flags.c_contiguous or u.size != self.d * self.N):
+                raise ValueError("out[1] must be a contiguous float64 array of d*N values")
+            with_u = u is not None
+        else:
+            r = np.empty(self.N)
+            u = np.empty(self.d * self.N) if with_u else None
         _check(lib().mrtlb_read_moments(self.h, _ptr(r), _ptr(u)))
         r = r.reshape(self.shape)
         return (r, u.reshape((self.d,) + self.shape)) if with_u else r

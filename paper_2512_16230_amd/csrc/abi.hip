@@ -303,6 +303,21 @@ const char* mrtlb_last_error(void) { return g_last_error.c_str(); }
 
 int mrtlb_version(void) { return (1 << 16) | 0; }
 
+mrtlb_status mrtlb_host_alloc(size_t bytes, void** out) {
+  if (!out || bytes == 0) return fail(MRTLB_EINVAL, "NULL out or zero size");
+  *out = nullptr;
+  if (hipHostMalloc(out, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(MRTLB_ENOMEM, "page-locked host allocation failed");
+  }
+  return MRTLB_OK;
+}
+
+void mrtlb_host_free(void* p) {
+  if (p) (void)hipHostFree(p);
+}
+
 mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx** out) {
   if (!out) return fail(MRTLB_EINVAL, "out is NULL");
   *out = nullptr;
@@ -317,6 +332,13 @@ mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
   c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+  // keep the stream-ordered allocator's freed staging memory for reuse
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  (void)hipGetLastError();
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;
     return fail(MRTLB_EDEVICE, "hipEventCreate failed");
@@ -515,10 +537,17 @@ void mrtlb_solve_destroy(mrtlb_solve* s) {
 
 int64_t mrtlb_solve_steps(const mrtlb_solve* s) { return s ? s->steps : -1; }
 
-// Staging: device FP64 copies of host fields.
+// Staging: device FP64 copies of host fields, from the stream-ordered
+// allocator: allocation and release are ordered on the context stream and,
+// unlike hipFree, do not wait for the whole device.
 struct DevBuf {
   void* p = nullptr;
-  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipStream_t st = nullptr;
+  hipError_t alloc(size_t bytes, hipStream_t s) {
+    st = s;
+    return hipMallocAsync(&p, bytes, s);
+  }
+  ~DevBuf() { if (p) (void)hipFreeAsync(p, st); }
 };
 
 // FP64 mass and momentum of the solve's current state: per-plane partial
@@ -640,7 +669,7 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
   HIP_TRY(hipSetDevice(s->ctx->device));
   hipStream_t st = s->ctx->stream;
   DevBuf dr, du, df;
-  HIP_TRY(hipMalloc(&dr.p, (size_t)s->N * 8));
+  HIP_TRY(dr.alloc((size_t)s->N * 8, st));
   HIP_TRY(hipMemcpyAsync(dr.p, rho, (size_t)s->N * 8, hipMemcpyHostToDevice, st));
   if (cde) {
     // the velocity field, in the compute precision
@@ -656,11 +685,11 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
       HIP_TRY(hipStreamSynchronize(st));
     }
   } else if (!ncde) {
-    HIP_TRY(hipMalloc(&du.p, (size_t)D * s->N * 8));
+    HIP_TRY(du.alloc((size_t)D * s->N * 8, st));
     HIP_TRY(hipMemcpyAsync(du.p, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
   }
   if (force) {
-    HIP_TRY(hipMalloc(&df.p, (size_t)D * s->N * 8));
+    HIP_TRY(df.alloc((size_t)D * s->N * 8, st));
     HIP_TRY(hipMemcpyAsync(df.p, force, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
     // the stepping kernels read the force in the compute precision
     if (is_double(s->storage)) {
@@ -866,8 +895,8 @@ mrtlb_status mrtlb_read_moments(mrtlb_solve* s, double* rho, double* u) {
   HIP_TRY(hipSetDevice(s->ctx->device));
   const int D = s->L.D;
   DevBuf dr, du;
-  HIP_TRY(hipMalloc(&dr.p, (size_t)s->N * 8));
-  if (u) HIP_TRY(hipMalloc(&du.p, (size_t)D * s->N * 8));
+  HIP_TRY(dr.alloc((size_t)s->N * 8, s->ctx->stream));
+  if (u) HIP_TRY(du.alloc((size_t)D * s->N * 8, s->ctx->stream));
   mrtlb_status st = gather_launch(s, 0, (double*)dr.p, (double*)du.p);
   if (st != MRTLB_OK) return st;
   HIP_TRY(hipMemcpyAsync(rho, dr.p, (size_t)s->N * 8, hipMemcpyDeviceToHost, s->ctx->stream));
@@ -881,7 +910,7 @@ mrtlb_status mrtlb_read_populations(mrtlb_solve* s, double* f) {
   HIP_TRY(hipSetDevice(s->ctx->device));
   DevBuf d;
   const size_t n = (size_t)s->L.B * s->N;
-  HIP_TRY(hipMalloc(&d.p, n * 8));
+  HIP_TRY(d.alloc(n * 8, s->ctx->stream));
   mrtlb_status st = gather_launch(s, 1, (double*)d.p, nullptr);
   if (st != MRTLB_OK) return st;
   HIP_TRY(hipMemcpyAsync(f, d.p, n * 8, hipMemcpyDeviceToHost, s->ctx->stream));
@@ -897,7 +926,7 @@ mrtlb_status mrtlb_write_populations(mrtlb_solve* s, const double* f) {
   HIP_TRY(hipSetDevice(s->ctx->device));
   hipStream_t st = s->ctx->stream;
   DevBuf d;
-  HIP_TRY(hipMalloc(&d.p, n * 8));
+  HIP_TRY(d.alloc(n * 8, s->ctx->stream));
   HIP_TRY(hipMemcpyAsync(d.p, f, n * 8, hipMemcpyHostToDevice, st));
   // write into the current buffer: the parity-(cur^1) job has fout = f[cur]
   LaunchReq r = base_req(*s, kOpScatter, job_ptr(*s, s->cur ^ 1));

@@ -51,6 +51,7 @@ class Request:
     adv_u: tuple = (0.0, 0.0, 0.0)
     with_force: bool = False
     payload: dict = None           # rho_or_phi, u, force (filled by the producer)
+    payload_error: str = None      # set by the producer if the payload could not be made
 
     @property
     def nodes(self):
@@ -115,14 +116,81 @@ def footprint_bytes(req: Request) -> int:
 # executors
 # --------------------------------------------------------------------------
 
-class GpuExecutor:
-    """Runs solves on the HIP library."""
+class PinnedPool:
+    """Page-locked float64 host buffers from the library (mrtlb_host_alloc),
+    reused across requests in power-of-two size classes: uploads from them
+    and read-backs into them run at DMA speed instead of through the
+    runtime's pageable staging."""
 
-    def __init__(self, device=0, stream=None, hbm_budget=0):
+    def __init__(self, H):
+        self._H = H
+        self._free = {}
+        self._all = []
+        self._lock = threading.Lock()
+
+    def get(self, n):
+        cap = 1 << max(10, int(n - 1).bit_length())
+        with self._lock:
+            lst = self._free.get(cap)
+            b = lst.pop() if lst else None
+        if b is None:
+            b = self._H.HostBuffer(cap)
+            with self._lock:
+                self._all.append(b)
+        return b
+
+    def put(self, b):
+        with self._lock:
+            self._free.setdefault(b.n, []).append(b)
+
+    @staticmethod
+    def array(b, shape):
+        n = int(np.prod(shape))
+        return b.array[:n].reshape(shape)
+
+    def close(self):
+        with self._lock:
+            for b in self._all:
+                b.close()
+            self._all, self._free = [], {}
+
+
+class GpuExecutor:
+    """Runs solves on the HIP library.  The producer thread stages request
+    payloads in page-locked memory together with the flow bounds of the
+    int16 storage (``prepare``); results are read back into page-locked
+    buffers."""
+
+    def __init__(self, device=0, stream=None, hbm_budget=0, pinned=True):
         from . import _mrtlb as H
         self.H = H
         self.ctx = H.Context(device, stream=stream, hbm_budget=hbm_budget)
         self._lat = {}
+        self.pool = PinnedPool(H) if pinned else None
+
+    def prepare(self, req):
+        """Producer side: the payload (what a client uploads), its flow
+        bounds, and page-locked copies of its fields."""
+        p = make_payload(req)
+        if req.storage == "i16_dev":
+            p["bounds"] = W.flow_bounds(req.eq, p["rho_or_phi"], p["u"], p["force"], req.steps, adv_u=req.adv_u)
+        if self.pool is not None:
+            p["_pinned"] = []
+            for key in ("rho_or_phi", "u", "force"):
+                a = p[key]
+                if a is None:
+                    continue
+                t = self.pool.get(a.size)
+                view = self.pool.array(t, a.shape)
+                np.copyto(view, a)
+                p[key] = view
+                p["_pinned"].append(t)
+        return p
+
+    def recycle(self, payload):
+        if self.pool is not None:
+            for t in payload.get("_pinned", ()):
+                self.pool.put(t)
 
     def budget(self):
         return self.ctx.memory()[1]
@@ -141,7 +209,8 @@ class GpuExecutor:
         p = req.payload
         ub = db = 0.0
         if req.storage == "i16_dev":
-            ub, db = W.flow_bounds(req.eq, p["rho_or_phi"], p["u"], p["force"], req.steps, adv_u=req.adv_u)
+            ub, db = p.get("bounds") or W.flow_bounds(req.eq, p["rho_or_phi"], p["u"], p["force"], req.steps,
+                                                       adv_u=req.adv_u)
         md = H.model_desc(req.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
                           D0=req.D0, D2=req.D2, adv_u=req.adv_u, u_bound=ub, dev_bound=db)
         s = H.Solve(self.ctx, self._lattice(req.card), md, req.shape, req.storage, has_force=req.with_force)
@@ -151,10 +220,26 @@ class GpuExecutor:
     def step(self, handles, counts):
         self.H.batch_step(handles, counts)
 
-    def read(self, handle, req):
-        if req.eq == "NCDE":
-            return handle.read_moments(with_u=False), None
-        return handle.read_moments()
+    def read(self, handle, req, keep=True):
+        """Moments of a finished solve; with keep=False they land in reused
+        page-locked buffers and are not returned (the bench discards them)."""
+        with_u = req.eq != "NCDE"
+        if self.pool is None:
+            out = handle.read_moments(with_u=with_u)
+            return out if with_u else (out, None)
+        tr = self.pool.get(handle.N)
+        tu = self.pool.get(handle.d * handle.N) if with_u else None
+        r = tr.array[:handle.N]
+        u = tu.array[:handle.d * handle.N] if with_u else None
+        res = handle.read_moments(out=(r, u))
+        if keep:
+            res = (res[0].copy(), res[1].copy()) if with_u else (res.copy(), None)
+        else:
+            res = None
+        self.pool.put(tr)
+        if tu is not None:
+            self.pool.put(tu)
+        return res
 
     def release(self, handle):
         handle.close()
@@ -163,6 +248,8 @@ class GpuExecutor:
         return time.perf_counter()
 
     def close(self):
+        if self.pool is not None:
+            self.pool.close()
         self.ctx.close()
 
 
@@ -197,7 +284,7 @@ class SimExecutor:
         for h, n in zip(handles, counts):
             self.steps_done[h.rid] += n
 
-    def read(self, handle, req):
+    def read(self, handle, req, keep=True):
         return self.steps_done[handle.rid], None
 
     def release(self, handle):
@@ -262,30 +349,46 @@ class ServeStats:
 
 
 class Server:
-    def __init__(self, executor, max_chunk=64, keep_values=False, lookahead=32):
+    def __init__(self, executor, max_chunk=64, keep_values=False, lookahead=32, producers=4):
         self.ex = executor
         self.max_chunk = max_chunk
         self.keep_values = keep_values
         self.lookahead = lookahead
+        self.producers = producers
 
     def _start_producer(self, reqs):
-        """Fill request payloads ahead of their arrival (the clients' uploads),
-        at most ``lookahead`` requests ahead of admission."""
+        """Fill request payloads ahead of their arrival (the clients' uploads)
+        with ``producers`` threads, at most ``lookahead`` requests ahead of
+        admission."""
         events = {r.rid: threading.Event() for r in reqs}
         if not getattr(self.ex, "needs_payload", True):
             for e in events.values():
                 e.set()
             return events, None
         room = threading.Semaphore(self.lookahead)
+        nxt = iter(reqs)
+        take = threading.Lock()
 
         def produce():
-            for r in reqs:
+            while True:
                 room.acquire()
-                if r.payload is None:
-                    r.payload = make_payload(r)
-                events[r.rid].set()
+                with take:
+                    r = next(nxt, None)
+                if r is None:
+                    room.release()
+                    return
+                try:
+                    if r.payload is None:
+                        prepare = getattr(self.ex, "prepare", None)
+                        r.payload = prepare(r) if prepare is not None else make_payload(r)
+                except Exception as e:       # the request fails alone; admission must not wait forever
+                    r.payload = None
+                    r.payload_error = "payload: %s: %s" % (type(e).__name__, e)
+                finally:
+                    events[r.rid].set()
 
-        threading.Thread(target=produce, daemon=True).start()
+        for _ in range(self.producers):
+            threading.Thread(target=produce, daemon=True).start()
         return events, room
 
     def run(self, requests, real_time=True):
@@ -301,6 +404,9 @@ class Server:
         clock = (lambda: ex.now() - t0)
 
         def consumed(req):
+            recycle = getattr(ex, "recycle", None)
+            if recycle is not None and req.payload is not None:
+                recycle(req.payload)
             req.payload = None
             if room is not None:
                 room.release()
@@ -325,6 +431,11 @@ class Server:
                 events[req.rid].wait()
                 tc = clock()
                 stats.t_wait += tc - tw
+                if getattr(req, "payload_error", None):
+                    consumed(req)
+                    stats.results.append(Result(req.rid, req.arrival, now, clock(), req.nodes, 0,
+                                                error=req.payload_error))
+                    continue
                 try:
                     h = ex.create(req)
                 except Exception as e:           # the failing request only
@@ -360,7 +471,7 @@ class Server:
             for a in active:
                 if a[2] == 0:
                     h, req, _, adm, fp = a
-                    val = ex.read(h, req)
+                    val = ex.read(h, req, keep=self.keep_values)
                     ex.release(h)
                     used -= fp
                     stats.results.append(Result(req.rid, req.arrival, adm, clock(), req.nodes, req.steps,

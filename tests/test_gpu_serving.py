@@ -16,7 +16,7 @@ def test_served_results_equal_solo_runs(storage):
     print("case: serving 10 mixed requests, %s" % storage, flush=True)
     ex = S.GpuExecutor(hbm_budget=256 << 20)
     st = S.Server(ex, max_chunk=16, keep_values=True).run(reqs, real_time=True)
-    assert all(r.error is None for r in st.results)
+    assert all(r.error is None for r in st.results), [r.error for r in st.results if r.error]
     assert st.max_resident >= 2
     for q, r in zip(sorted(reqs, key=lambda q: q.rid), st.results):
         q.payload = S.make_payload(q)

@@ -90,3 +90,22 @@ def test_summary_percentiles():
     assert s["p50_s"] == float(np.percentile(lat, 50))
     assert s["p99_s"] == float(np.percentile(lat, 99))
     assert s["requests"] == 50 and s["failed"] == 0
+
+
+def test_payload_failure_fails_its_request_only():
+    """A payload that cannot be made (the producer thread raises) fails that
+    request; admission does not wait for it forever."""
+
+    class Faulty(S.SimExecutor):
+        needs_payload = True
+
+        def prepare(self, req):
+            if req.rid == 3:
+                raise RuntimeError("bad payload")
+            return {"rho_or_phi": None, "u": None, "force": None}
+
+    reqs = S.request_stream(8, rate=1000.0, seed=5, steps=(20, 40), q25=(64, 96), q13=(128, 160), q33=(24, 32))
+    st = S.Server(Faulty(hbm_budget=1 << 40), max_chunk=8).run(reqs, real_time=False)
+    assert len(st.results) == 8
+    bad = [r for r in st.results if r.error is not None]
+    assert [r.rid for r in bad] == [3] and "bad payload" in bad[0].error
