@@ -12,6 +12,8 @@ Paper references (arXiv 2512.16230):
   * rD3Q53 / rD3Q33 velocities and weights ... App. D
   * Hermite rows H0..H3 ...................... Sec. V (definition above eq. (new5)),
                                                App. C/D lists of H rows
+  * standard D2Q9 / D3Q27 (k = 1) ............. Sec. IV, eqs. (4-27), (4-27-1), and the
+                                               standard-lattice case of Sec. IV-B
 
 Everything here is the plain definition: weights from the printed formulas,
 Hermite rows as polynomials in the physical velocity, the third-order
@@ -87,6 +89,15 @@ def _q17(case):
     return [(0, 0)] + [v for g in _Q17_GROUPS[case] for v in groups[g]]
 
 
+def _d3q27():
+    return list(zip(_D3Q27_X, _D3Q27_Y, _D3Q27_Z))
+
+
+# Standard (single-layer) lattices: the k = 1 model of the standard-lattice
+# special case, with no pure third-order rows and a non-diagonal S2 block.
+STANDARD = ("D2Q9", "D3Q27")
+
+
 def velocity_set(kind: str) -> np.ndarray:
     """Integer velocity multiples e_j (b x d) in the paper's column order."""
     table = {
@@ -100,6 +111,9 @@ def velocity_set(kind: str) -> np.ndarray:
         # the rD3Q53 subgroup without its (+-2, +-2, +-2) group (w45 = 0)
         "rD3Q45": lambda: _rd3q53()[:45],
         **{"rD2Q17-%d" % k: (lambda k=k: _q17(k)) for k in range(1, 6)},
+        # the first layer of rD2Q25 / rD3Q53 (eq. 3-1, App. D)
+        "D2Q9": lambda: [(0, 0)] + _D2Q9_RING,
+        "D3Q27": _d3q27,
     }
     return np.array(table[kind](), dtype=np.int64)
 
@@ -137,6 +151,24 @@ def weights_rd2q25(c, cs2, free):
         return layer[2]
 
     return _group_weights(velocity_set("rD2Q25"), g)
+
+
+def weights_standard(e, c, cs2):
+    """Standard-lattice weights: the product of one D1Q3 weight per axis,
+    1 - d_a at rest and d_a / 2 at +-1, d_a = cs^2 / c_a^2.
+
+    On the single-layer set these are the only weights that meet the
+    conditions of Sec. V the lattice can meet: unit mass, Delta2 = cs^2 I and
+    the mixed fourth moments Delta4_aabb = cs^4 that make the second-order
+    rows W-orthogonal.  The pure fourth moments are c_a^2 cs^2, not 3 cs^4;
+    the k = 1 model absorbs that difference in its S2 block (eq. 4-27-1).
+    """
+    d = np.array([cs2 / ca ** 2 for ca in c])
+    w = np.ones(len(e))
+    for j, v in enumerate(e):
+        for a, t in enumerate(v):
+            w[j] *= d[a] / 2 if t != 0 else 1 - d[a]
+    return w
 
 
 def weights_rd2q13(c, cs2):
@@ -257,8 +289,9 @@ def poly_eval(p: Poly, E: np.ndarray) -> np.ndarray:
 class Row:
     name: str
     order: int
-    group: str          # relaxation group: rho, j, bulk, shear, third, high
+    group: str          # relaxation group: rho, j, bulk, shear, normal, third, high
     poly: Poly
+    axis: int = -1      # normal second-order component rows: their axis
 
 
 @dataclass
@@ -315,18 +348,26 @@ def hermite_rows(lat: Lattice) -> tuple[list, dict]:
     the pure rows c_a (c_a^2 - 3 cs^2) corrected by removing their W-weighted
     projection on span{c_a (c_b^2 - cs^2) : b != a} (eq. CorrectQ25 and its
     App. D analogue).  Returns (rows, correction coefficients).
+    Standard lattices keep the normal component rows c_a^2 - cs^2 (their S2
+    block is not diagonal, eq. 4-27) and have no pure third-order rows.
     """
     d, cs2 = lat.d, lat.cs2
+    standard = lat.kind in STANDARD
     one = {_mono(d): 1.0}
     ax = "xyz"[:d]
     rows = [Row("1", 0, "rho", one)]
     for a in range(d):
         rows.append(Row(ax[a], 1, "j", {_mono(d, a): 1.0}))
     hnorm = [poly_add((1.0, {_mono(d, a, a): 1.0}), (-cs2, one)) for a in range(d)]
-    rows.append(Row("trace", 2, "bulk", poly_add(*[(1.0, h) for h in hnorm])))
-    if d == 2:
+    if standard:
+        # component rows c_a^2 - cs^2, relaxed together by the S2 block
+        for a in range(d):
+            rows.append(Row(ax[a] * 2, 2, "normal", hnorm[a], axis=a))
+    elif d == 2:
+        rows.append(Row("trace", 2, "bulk", poly_add(*[(1.0, h) for h in hnorm])))
         rows.append(Row("xx-yy", 2, "shear", poly_add((1.0, hnorm[0]), (-1.0, hnorm[1]))))
     else:
+        rows.append(Row("trace", 2, "bulk", poly_add(*[(1.0, h) for h in hnorm])))
         rows.append(Row("xx-yy", 2, "shear", poly_add((1.0, hnorm[0]), (-1.0, hnorm[1]))))
         rows.append(Row("xx+yy-2zz", 2, "shear",
                         poly_add((1.0, hnorm[0]), (1.0, hnorm[1]), (-2.0, hnorm[2]))))
@@ -346,6 +387,11 @@ def hermite_rows(lat: Lattice) -> tuple[list, dict]:
     if d == 3:
         third.append(Row("xyz", 3, "third", {_mono(d, 0, 1, 2): 1.0}))
     corrections = {}
+    if standard:
+        # c_a^3 = c_a^2 c_a on a single layer: the pure rows are multiples of
+        # the first-order rows and are not part of the basis
+        rows += third
+        return rows, corrections
     for a in range(d):
         pure = poly_add((1.0, {_mono(d, a, a, a): 1.0}), (-3 * cs2, {_mono(d, a): 1.0}))
         basis = [mixed[(a, b)] for b in range(d) if b != a]
@@ -413,6 +459,8 @@ def make_lattice(kind: str, c=(1.0, 1.0), cs2=None, free=None) -> Lattice:
         w = weights_rd2q25(c, cs2, tuple(free) + (0.0,))[:21]
     elif kind == "rD3Q45":
         w = weights_rd3q53(c, cs2, tuple(free) + (0.0,))[:45]
+    elif kind in STANDARD:
+        w = weights_standard(e, c, cs2)
     elif kind.startswith("rD2Q17-"):
         # eq. (WeightQ25) on the full rD2Q25 set; the dropped groups must vanish
         e25 = velocity_set("rD2Q25")

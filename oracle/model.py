@@ -19,7 +19,8 @@ step is, in the paper's order:
      moment of G is (I - S2/2)(uF + Fu) (eq. M2G-1 with isothermal p, S = 0
      and M30 = rho uuu); for the NCDE the auxiliary first moment of G is
      (I - S1/2)(d_t M1 + div M20) (eq. M-NCDE-6, case (1));
-  5. relaxation with diagonal S in Hermite space and the update
+  5. relaxation with S in Hermite space (diagonal, except the normal
+     second-order block of the standard k = 1 lattices, eq. 4-27) and the update
      m* = m - S (m - m_eq) + m_G + (I - S/2) m_F (eq. 2-3 with
      Lambda = H^-1 S H, eq. H-MRT-LB);
   6. back to populations with the reduced form of eq. (H-MRT-LB-1): every row
@@ -77,8 +78,38 @@ class Model:
                 "third": self.s3, "high": self.s_h}[group]
 
 
-def rates(lat: Lattice, model: Model) -> np.ndarray:
-    return np.array([model.rate(r.group) for r in lat.rows])
+def s2_normal_block(lat: Lattice, model: Model) -> np.ndarray:
+    """S2 on the normal components (c_a^2 - cs^2 rows) of a standard lattice.
+
+    eqs. (4-27), (4-27-1): S2^-1 = diag(1/s_sa) + a b^T / d with
+    a_a = (1/s_ba - 1/s_sa)(c_a^2 - cs^2), b_b = 1/(c_b^2 - cs^2), and by
+    eq. (4-29) with k = 1 the rates give mu = (1/s_sa - 1/2) rho (c_a^2 - cs^2)/2
+    and mu_b = (1/s_ba - 1/2) rho (c_a^2 - cs^2)/d.  The model's s_shear and
+    s_bulk name the target viscosities of the multispeed lattices,
+    nu = cs^2 (1/s_shear - 1/2) and nu_b = (2/d) cs^2 (1/s_bulk - 1/2), so
+    1/s_sa = 1/2 + 2 nu / (c_a^2 - cs^2) and 1/s_ba = 1/2 + d nu_b / (c_a^2 - cs^2).
+    """
+    d, cs2 = lat.d, lat.cs2
+    nu = cs2 * (1.0 / model.s_shear - 0.5)
+    nu_b = (2.0 / d) * cs2 * (1.0 / model.s_bulk - 0.5)
+    g = np.array([lat.c[a] ** 2 - cs2 for a in range(d)])
+    inv_ss = 0.5 + 2 * nu / g
+    inv_sb = 0.5 + d * nu_b / g
+    a_vec = (inv_sb - inv_ss) * g
+    b_vec = 1.0 / g
+    return np.linalg.inv(np.diag(inv_ss) + np.outer(a_vec, b_vec) / d)
+
+
+def relaxation_matrix(lat: Lattice, model: Model) -> np.ndarray:
+    """S on the rows of order <= 3: diagonal with the group rates, except the
+    normal second-order block of a standard lattice (eq. 4-27).  The
+    off-diagonal rows keep s_shear there: 1/s_ab = 1/2 + nu / cs^2 (eq. 4-29)."""
+    S = np.diag([model.rate(r.group) if r.group != "normal" else 0.0 for r in lat.rows])
+    idx = [i for i, r in enumerate(lat.rows) if r.group == "normal"]
+    if idx:
+        idx = sorted(idx, key=lambda i: lat.rows[i].axis)
+        S[np.ix_(idx, idx)] = s2_normal_block(lat, model)
+    return S
 
 
 # --------------------------------------------------------------------------
@@ -188,27 +219,29 @@ def force_hermite(lat, n, force):
     return hermite_from_raw(lat, M, max_order=2)
 
 
-def aux_hermite(lat, model, s, u, force, extra=None):
-    """Hermite moments of the auxiliary distribution G.
+def aux_hermite(lat, model, S, u, force, extra=None):
+    """Hermite moments of the auxiliary distribution G; S is the relaxation
+    matrix on the rows of order <= 3.
 
-    NSE: M2G = (I - S2/2)(uF + Fu) (Hermite-diagonal S2), zero otherwise.
+    NSE: M2G = (I - S2/2)(uF + Fu) (eqs. M2G-1, M2Ga-1), zero otherwise.
     NCDE: M1G = (I - S1/2) B with B = d_t(phi u) + div(phi uu) supplied in
     ``extra``.
     """
     n = u.shape[1]
     d = lat.d
+    G = np.eye(len(lat.rows)) - 0.5 * S
     if model.eq == NCDE:
         if extra is None:
             return np.zeros((len(lat.rows), n))
         M = [np.zeros(n), extra, None, None]
-        return (1 - 0.5 * s)[:, None] * hermite_from_raw(lat, M, max_order=1)
+        return G @ hermite_from_raw(lat, M, max_order=1)
     if force is None:
         return np.zeros((len(lat.rows), n))
     T = np.einsum("an,bn->abn", u, force) + np.einsum("an,bn->abn", force, u)
     M = [np.zeros(n), np.zeros((d, n)), T, None]
     mg = hermite_from_raw(lat, M, max_order=2)
     mg[[r.order != 2 for r in lat.rows]] = 0.0
-    return (1 - 0.5 * s)[:, None] * mg
+    return G @ mg
 
 
 def populations_from_hermite(lat: Lattice, m: np.ndarray) -> np.ndarray:
@@ -251,7 +284,7 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None):
     ``ncde_b`` is the NCDE field B^n (d, n) of the auxiliary first moment;
     for the CDE ``force`` is the velocity field (d, n)."""
     n = f.shape[1]
-    s = rates(lat, model)
+    S = relaxation_matrix(lat, model)
     R0, u, rho_m = macroscopic(lat, model, f, force)
     m = lat.H() @ f
     meq = equilibrium_hermite(lat, model, R0, u, rho_m)
@@ -260,11 +293,11 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None):
         mF = np.zeros_like(m)
         mG = np.zeros_like(m)
         mG[[r.order == 0 for r in lat.rows]] = (1 - 0.5 * model.s0) * cde_source(lat, model, f, force)
-        mstar = m - s[:, None] * (m - meq) + mG
+        mstar = m - S @ (m - meq) + mG
         return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
     mF = force_hermite(lat, n, force) if model.eq != NCDE else np.zeros_like(m)
-    mG = aux_hermite(lat, model, s, u, force, extra=ncde_b)
-    mstar = m - s[:, None] * (m - meq) + mG + (1 - 0.5 * s)[:, None] * mF
+    mG = aux_hermite(lat, model, S, u, force, extra=ncde_b)
+    mstar = m - S @ (m - meq) + mG + (np.eye(len(lat.rows)) - 0.5 * S) @ mF
     return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
 
 

@@ -29,12 +29,14 @@ class NaiveStepper:
         self.lat, self.mdl = lat, mdl
         rows = complete_rows(lat, lat.rows)
         self.Hf = full_H(lat, rows)
-        s_low = M.rates(lat, mdl)
-        s = np.concatenate([s_low, np.full(lat.b - len(lat.rows), mdl.s_h)])
+        S_low = M.relaxation_matrix(lat, mdl)
+        nlow = len(lat.rows)
+        S = np.diag(np.full(lat.b, mdl.s_h))
+        S[:nlow, :nlow] = S_low
         self.Hinv = np.linalg.inv(self.Hf)
-        self.Lam = self.Hinv @ np.diag(s) @ self.Hf
-        self.nlow = len(lat.rows)
-        self.s_low = s_low
+        self.Lam = self.Hinv @ S @ self.Hf
+        self.nlow = nlow
+        self.S_low = S_low
 
     def _velocity_space(self, m_low):
         full = np.zeros(self.lat.b)
@@ -76,11 +78,11 @@ class NaiveStepper:
             feq = self._velocity_space(M.equilibrium_hermite(lat, mdl, R0, uv, rm)[:, 0])
             if mdl.eq == M.NCDE:
                 Bx = np.array([Bfield[(a,) + x] for a in range(d)])[:, None]
-                G = self._velocity_space(M.aux_hermite(lat, mdl, self.s_low, uv, None, extra=Bx)[:, 0])
+                G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, None, extra=Bx)[:, 0])
                 Fv = np.zeros(b)
             else:
                 Fa = None if F is None else F[:, None]
-                G = self._velocity_space(M.aux_hermite(lat, mdl, self.s_low, uv, Fa)[:, 0])
+                G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, Fa)[:, 0])
                 Fv = np.zeros(b) if F is None else self._velocity_space(M.force_hermite(lat, 1, Fa)[:, 0])
             out = f - self.Lam @ (f - feq) + G + (np.eye(b) - 0.5 * self.Lam) @ Fv
             for j in range(b):

@@ -20,7 +20,9 @@ from oracle import model as M
 from oracle import naive as N
 from paper_2512_16230_amd import workloads as W
 
-CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT, W.Q45_RECT] + W.Q17_CASES
+CARDS = [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT, W.Q45_RECT, W.Q9_RECT,
+         W.Q27_RECT] + W.Q17_CASES
+MULTISPEED = [c for c in CARDS if c.kind not in L.STANDARD]
 
 
 def card_lattice(card):
@@ -60,7 +62,7 @@ def _delta_u(d, v):
 # equilibrium
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("card", CARDS, ids=lambda c: c.kind)
+@pytest.mark.parametrize("card", MULTISPEED, ids=lambda c: c.kind)
 @pytest.mark.parametrize("eq", [M.NSE_INC, M.NSE_COMP])
 def test_equilibrium_moments_nse(card, eq):
     """sum f_eq {1, c, cc, ccc} = M0..M3 of eqs. (M-NSEs-6a), (M-NSEs-6) /
