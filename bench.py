@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+STANDARD = ("D2Q9", "D3Q27")      # k = 1 model: M30 = 0
 STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2, "i16_dev": 2}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_dev": "f32", "fp16_dev": "f32 (fp16 storage)",
          "bf16_dev": "f32 (bf16 storage)", "i16_dev": "f32 (int16 fixed-point storage)"}
@@ -123,13 +124,13 @@ def bench_tgv3d(torch, H, W, stream, args):
     """rD3Q53 (1 : 1.25 : 1.5) compressible isothermal 3D Taylor-Green, 256^3."""
     n = args.size if args.size != 4096 else 256
     shape = (n, n, n)
-    card3 = {"rD3Q53": W.Q53_RECT, "rD3Q45": W.Q45_RECT, "rD3Q33": W.Q33_CUBIC}[args.lattice3d]
+    card3 = {"rD3Q53": W.Q53_RECT, "rD3Q45": W.Q45_RECT, "rD3Q33": W.Q33_CUBIC, "D3Q27": W.Q27_RECT}[args.lattice3d]
     wl = W.tgv3d(shape=shape, steps=args.steps, card=card3)
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
     md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                      **_bounds(W, args.storage, wl))
+                      m30=card.kind not in STANDARD, **_bounds(W, args.storage, wl))
     s = H.Solve(ctx, lat, md, shape, args.storage)
     s.init_fields(wl.rho_or_phi, wl.u)
     del wl
@@ -140,7 +141,7 @@ def bench_tgv3d(torch, H, W, stream, args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nodes = n ** 3
-    bq = {"rD3Q53": 53, "rD3Q45": 45, "rD3Q33": 33}[card.kind]
+    bq = {"rD3Q53": 53, "rD3Q45": 45, "rD3Q33": 33, "D3Q27": 27}[card.kind]
     launch_bytes = 2 * bq * STORE_BYTES[args.storage] * nodes
     out = _line("%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline" % card.kind,
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
@@ -265,9 +266,10 @@ def main():
                          "ncde-batch: 256 rD2Q13 NCDE solves advanced by one batched launch per step")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--requests", type=int, default=300, help="serve: requests in the measured window")
-    ap.add_argument("--lattice2d", default="rD2Q25", choices=["rD2Q25", "rD2Q21", "D2Q21K"],
-                    help="lattice of the tgv2d workload (rD2Q21: rD2Q25 subgroup; D2Q21K: knight-move D2Q21)")
-    ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33"],
+    ap.add_argument("--lattice2d", default="rD2Q25", choices=["rD2Q25", "rD2Q21", "D2Q21K", "D2Q9"],
+                    help="lattice of the tgv2d workload (rD2Q21: rD2Q25 subgroup; D2Q21K: knight-move D2Q21; "
+                         "D2Q9: standard lattice, k = 1 model)")
+    ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33", "D3Q27"],
                     help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of 2 x 1.68 GB instead (HBM reference and counter calibration)")
@@ -297,13 +299,13 @@ def main():
     if args.workload == "serve":
         return bench_serve(stream, args)
     shape = (args.size, args.size)
-    card2 = {"rD2Q25": W.Q25_RECT, "rD2Q21": W.Q21_RECT, "D2Q21K": W.Q21K_RECT}[args.lattice2d]
+    card2 = {"rD2Q25": W.Q25_RECT, "rD2Q21": W.Q21_RECT, "D2Q21K": W.Q21K_RECT, "D2Q9": W.Q9_RECT}[args.lattice2d]
     wl = W.tgv_large(0, shape=shape, steps=args.steps, card=card2)
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
     md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                      **_bounds(W, args.storage, wl))
+                      m30=card.kind not in STANDARD, **_bounds(W, args.storage, wl))
     s = H.Solve(ctx, lat, md, shape, args.storage)
     s.init_fields(wl.rho_or_phi, wl.u)
     del wl
@@ -315,7 +317,7 @@ def main():
     wall = time.perf_counter() - t0
     mass, _ = s.conserved()
     nodes = shape[0] * shape[1]
-    b = {"rD2Q25": 25, "rD2Q21": 21, "D2Q21K": 21}[card.kind]
+    b = {"rD2Q25": 25, "rD2Q21": 21, "D2Q21K": 21, "D2Q9": 9}[card.kind]
     launch_bytes = 2 * b * STORE_BYTES[args.storage] * nodes
     per_launch_s = kernel_ms / 1e3 / args.steps
     achieved = launch_bytes / per_launch_s / 1e9

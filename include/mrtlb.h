@@ -103,6 +103,16 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  *                 w21} of eq. (WeightQ25); with the given c and cs2 the weights
  *                 of the case's dropped velocity groups must vanish (|w| <=
  *                 1e-12, else EINVAL).
+ *   MRTLB_D2Q9, MRTLB_D3Q27  standard single-layer lattices (the first layer
+ *                 of eq. (3-1) / of the App. D velocity matrix) for the
+ *                 k = 1 model of the standard-lattice case (Sec. IV-B):
+ *                 weights prod_a (1 - d_a at rest, d_a / 2 at +-1),
+ *                 d_a = cs^2 / c_a^2 (the moment conditions of Sec. V a
+ *                 single layer can meet); no free w.  These lattices have no
+ *                 pure third-order rows, and their normal second-order rows
+ *                 relax with the non-diagonal S2 block of eqs. (4-27),
+ *                 (4-27-1) (see mrtlb_model_desc).  Use m30 = 0 (M30 = 0
+ *                 there).
  * c[0..d-1] = c_a = dx_a/dt; cs2 = sound speed squared (direction
  * independent, Remark 2).  The Hermite rows of orders 0..3 are
  * H0 = 1, H1 = c, H2 = cc - cs^2 I, H3 = c_a(c_b^2 - cs^2), c_x c_y c_z and
@@ -113,7 +123,7 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  * ------------------------------------------------------------------------- */
 typedef enum { MRTLB_RD2Q25 = 0, MRTLB_RD2Q13 = 1, MRTLB_RD3Q53 = 2, MRTLB_RD3Q33 = 3, MRTLB_RD2Q21 = 4,
                MRTLB_D2Q21K = 5, MRTLB_RD3Q45 = 6, MRTLB_RD2Q17_1 = 7, MRTLB_RD2Q17_2 = 8, MRTLB_RD2Q17_3 = 9,
-               MRTLB_RD2Q17_4 = 10, MRTLB_RD2Q17_5 = 11 } mrtlb_lattice_kind;
+               MRTLB_RD2Q17_4 = 10, MRTLB_RD2Q17_5 = 11, MRTLB_D2Q9 = 12, MRTLB_D3Q27 = 13 } mrtlb_lattice_kind;
 
 typedef struct {
   int kind;          /* mrtlb_lattice_kind */
@@ -126,7 +136,8 @@ typedef struct {
 mrtlb_status mrtlb_lattice_create(const mrtlb_lattice_desc* desc, mrtlb_lattice** out);
 void mrtlb_lattice_destroy(mrtlb_lattice* lat);
 /* Query: b, d, e (b*d ints, integer multiples, row j = velocity j), w (b),
- * nlow (number of Hermite rows of order <= 3: 10 in 2D, 20 in 3D),
+ * nlow (number of Hermite rows of order <= 3: 10 in 2D, 20 in 3D; 8 and 17
+ * on the standard lattices, which have no pure rows),
  * H (nlow*b, row-major, component rows 1, x, y, [z], xx, yy, [zz], xy, [xz, yz],
  * then x yy, [x zz], y xx, [y zz], [z xx, z yy], [xyz], xxx, yyy, [zzz] with the
  * pure rows corrected) and norms (nlow) = H_r W H_r^T.  Any output pointer
@@ -140,6 +151,12 @@ mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* lat, int* b, int* d, int* 
  *   order-2 rows), s_bulk (trace of order 2), s3 (order 3), s_high (every
  *   row above order 3).  Shear viscosity nu = cs^2 (1/s_shear - 1/2) dt,
  *   bulk nu_b = (2/d) cs^2 (1/s_bulk - 1/2) dt (eq. 4-29, k = 0).
+ *   On the standard lattices (k = 1) the same nu and nu_b fix the normal
+ *   block S2 = (diag(1/s_sa) + a b^T / d)^-1 of eqs. (4-27), (4-27-1):
+ *   1/s_sa = 1/2 + 2 nu / (c_a^2 - cs^2), 1/s_ba = 1/2 + d nu_b / (c_a^2 - cs^2),
+ *   a_a = (1/s_ba - 1/s_sa)(c_a^2 - cs^2), b_b = 1 / (c_b^2 - cs^2) (eq. 4-29
+ *   with k = 1); the off-diagonal rows keep s_shear.  The auxiliary
+ *   second moment uses the same (I - S2/2).
  * MRTLB_NSE_INC   M0 = rho_bar, M1 = rho0 u, M2 = rho0 uu + cs^2 rho_bar I,
  *                 M3 = rho0 cs^2 Delta.u + M30 (Sec. III, multispeed case);
  *                 rho_bar carries the pressure p = cs^2 rho_bar.

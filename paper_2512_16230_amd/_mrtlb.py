@@ -23,12 +23,13 @@ LIB_PATH = os.environ.get("MRTLB_LIB", os.path.join(_HERE, "libmrtlb.so"))
 MRTLB_OK, MRTLB_EINVAL, MRTLB_ENOMEM, MRTLB_EDEVICE, MRTLB_ENUMERIC = 0, -1, -2, -3, -4
 MRTLB_RD2Q25, MRTLB_RD2Q13, MRTLB_RD3Q53, MRTLB_RD3Q33, MRTLB_RD2Q21, MRTLB_D2Q21K, MRTLB_RD3Q45 = range(7)
 MRTLB_RD2Q17 = {k: 6 + k for k in range(1, 6)}     # D2Q17 cases 1-5
+MRTLB_D2Q9, MRTLB_D3Q27 = 12, 13                     # standard lattices, k = 1 model
 MRTLB_NSE_INC, MRTLB_NSE_COMP, MRTLB_NCDE, MRTLB_CDE = 0, 1, 2, 3
 MRTLB_FP64, MRTLB_FP32, MRTLB_FP32_DEV, MRTLB_FP16_DEV, MRTLB_BF16_DEV, MRTLB_I16_DEV = 0, 1, 2, 3, 4, 5
 
 KINDS = {"rD2Q25": MRTLB_RD2Q25, "rD2Q13": MRTLB_RD2Q13, "rD3Q53": MRTLB_RD3Q53, "rD3Q33": MRTLB_RD3Q33,
          "rD2Q21": MRTLB_RD2Q21, "D2Q21K": MRTLB_D2Q21K, "rD3Q45": MRTLB_RD3Q45,
-         **{"rD2Q17-%d" % k: v for k, v in MRTLB_RD2Q17.items()}}
+         "D2Q9": MRTLB_D2Q9, "D3Q27": MRTLB_D3Q27, **{"rD2Q17-%d" % k: v for k, v in MRTLB_RD2Q17.items()}}
 MODELS = {"NSE_INC": MRTLB_NSE_INC, "NSE_COMP": MRTLB_NSE_COMP, "NCDE": MRTLB_NCDE, "CDE": MRTLB_CDE}
 STORAGES = {"fp64": MRTLB_FP64, "fp32": MRTLB_FP32, "fp32_dev": MRTLB_FP32_DEV, "fp16_dev": MRTLB_FP16_DEV,
             "bf16_dev": MRTLB_BF16_DEV, "i16_dev": MRTLB_I16_DEV}

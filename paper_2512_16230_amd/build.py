@@ -10,13 +10,15 @@ import os
 import subprocess
 import sys
 import tempfile
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrtlb.so")
-SOURCES = ["abi.hip", "host_lattice.cpp", "inst_common.hip", "inst_rd2q25.hip", "inst_rd2q13.hip",
-           "inst_rd3q53.hip", "inst_rd3q33.hip", "inst_rd2q21.hip", "inst_d2q21k.hip",
-           "inst_rd3q45.hip"] + ["inst_rd2q17_%d.hip" % k for k in range(1, 6)]
+# the 3D lattices compile longest and start first
+SOURCES = ["inst_rd3q53.hip", "inst_rd3q45.hip", "inst_rd3q33.hip", "inst_d3q27.hip", "abi.hip",
+           "host_lattice.cpp", "inst_common.hip", "inst_rd2q25.hip", "inst_rd2q13.hip", "inst_rd2q21.hip",
+           "inst_d2q21k.hip", "inst_d2q9.hip"] + ["inst_rd2q17_%d.hip" % k for k in range(1, 6)]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -49,8 +51,8 @@ def build(verbose: bool = False, jobs: int = 8, out: str = LIB) -> str:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
         objs.append(obj)
-        if len([p for p in procs if p.poll() is None]) >= jobs:
-            procs[0].wait()
+        while len([p for p in procs if p.poll() is None]) >= jobs:
+            time.sleep(0.2)
     failed = [src for src, p in zip(SOURCES, procs) if p.wait() != 0]
     if failed:
         raise RuntimeError("hipcc failed on " + ", ".join(failed))

@@ -106,6 +106,7 @@ static size_t elem_bytes(int storage) {
   }
 }
 static int lattice_maxe(int kind) {
+  if (kind == kD2Q9 || kind == kD3Q27) return 1;
   return kind == kRD2Q25 || kind == kRD2Q21 || kind == kD2Q21K || (kind >= kRD2Q17_1 && kind <= kRD2Q17_4) ? 3 : 2;
 }
 
@@ -133,15 +134,69 @@ static int pick_vec(int storage, int kind, int model, int nx) {
   // pressure), for rows under 512 nodes and for the NCDE; otherwise 2 nodes
   // (FP32/FP64) or 4 nodes (16-bit storage, 8-byte accesses per lane).
   const bool small = storage != kFP64 && storage != kFP32 && storage != kFP32Dev;
-  int v = (kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || nx < 512 || model == MRTLB_NCDE ||
+  int v = (kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || kind == kD3Q27 || nx < 512 || model == MRTLB_NCDE ||
            model == MRTLB_CDE) ? 1
                                                                                             : (small ? 4 : 2);
   if (const char* e = std::getenv("MRTLB_STEP_VEC")) {
     const int o = std::atoi(e);
     if (o == 1 || o == 2 || o == 4) v = o;
   }
+  // only the 2D NSE step kernels are built with several nodes per thread
+  const bool is3d = kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || kind == kD3Q27;
+  if (is3d || model == MRTLB_NCDE || model == MRTLB_CDE) v = 1;
   while (v > 1 && (nx % v != 0 || nx < 4 * v)) v >>= 1;
   return v;
+}
+
+// S2 on the normal second-order component rows (FP64).  Standard lattices
+// (k = 1), eqs. (4-27), (4-27-1): S2 = (diag(1/s_sa) + a b^T / d)^-1 with
+// 1/s_sa = 1/2 + 2 nu / g_a, 1/s_ba = 1/2 + d nu_b / g_a, g_a = c_a^2 - cs^2,
+// a_a = (1/s_ba - 1/s_sa) g_a, b_b = 1 / g_b, where nu = cs^2 (1/s_shear - 1/2)
+// and nu_b = (2/d) cs^2 (1/s_bulk - 1/2) (eq. 4-29 with k = 1).  Multispeed
+// lattices: s_bulk on the trace, s_shear on the deviator.  Returns false if
+// the block is singular or not finite.
+static bool s2_normal_block(const HostLattice& L, const mrtlb_model_desc& m, double S2[3][3]) {
+  const int D = L.D;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) S2[a][b] = 0;
+  if (!L.standard) {
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) S2[a][b] = m.s_bulk / D + m.s_shear * ((a == b) - 1.0 / D);
+    return true;
+  }
+  const double nu = L.cs2 * (1.0 / m.s_shear - 0.5);
+  const double nu_b = (2.0 / D) * L.cs2 * (1.0 / m.s_bulk - 0.5);
+  double A[3][6];
+  for (int a = 0; a < D; ++a) {
+    const double g = L.c[a] * L.c[a] - L.cs2;
+    const double iss = 0.5 + 2 * nu / g, isb = 0.5 + D * nu_b / g;
+    for (int b = 0; b < D; ++b) {
+      const double gb = L.c[b] * L.c[b] - L.cs2;
+      A[a][b] = (a == b ? iss : 0.0) + (isb - iss) * g / (gb * D);
+      A[a][D + b] = a == b;
+    }
+  }
+  // Gauss-Jordan with partial pivoting on [A | I]
+  for (int col = 0; col < D; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < D; ++r)
+      if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+    if (!(std::fabs(A[piv][col]) > 1e-300)) return false;
+    for (int k = 0; k < 2 * D; ++k) std::swap(A[col][k], A[piv][k]);
+    const double inv = 1.0 / A[col][col];
+    for (int k = 0; k < 2 * D; ++k) A[col][k] *= inv;
+    for (int r = 0; r < D; ++r) {
+      if (r == col) continue;
+      const double f = A[r][col];
+      for (int k = 0; k < 2 * D; ++k) A[r][k] -= f * A[col][k];
+    }
+  }
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      S2[a][b] = A[a][D + b];
+      if (!std::isfinite(S2[a][b])) return false;
+    }
+  return true;
 }
 
 template <class Real>
@@ -215,7 +270,7 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   for (int a = 0; a < D; ++a) {
     P.in1[a] = (Real)(1.0 / L.norms[row_j(D, a)]);
     P.in2n[a] = (Real)(1.0 / L.norms[row_nn(D, a)]);
-    P.in3p[a] = (Real)(1.0 / L.norms[row_aaa(D, a)]);
+    P.in3p[a] = L.standard ? (Real)0 : (Real)(1.0 / L.norms[row_aaa(D, a)]);
     for (int b = 0; b < D; ++b) {
       if (b != a) P.in3m[a][b] = (Real)(1.0 / L.norms[row_abb(D, a, b)]);
       if (b > a) P.in2o[off_index(a, b)] = (Real)(1.0 / L.norms[row_off(D, a, b)]);
@@ -224,6 +279,13 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   if (D == 3) P.inxyz = (Real)(1.0 / L.norms[row_xyz()]);
   const mrtlb_model_desc& m = s.model;
   P.s1 = (Real)m.s1; P.ss = (Real)m.s_shear; P.sb = (Real)m.s_bulk; P.s3 = (Real)m.s3; P.sh = (Real)m.s_high;
+  double S2[3][3];
+  s2_normal_block(L, m, S2);
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      P.k2[a][b] = (Real)((a == b) - S2[a][b]);
+      P.g2[a][b] = (Real)((a == b) - 0.5 * S2[a][b]);
+    }
   const bool dev = s.storage != kFP64 && s.storage != kFP32;
   P.rho_ref = (Real)(dev && m.model != MRTLB_NCDE && m.model != MRTLB_CDE ? m.rho0 : 0.0);
   P.rho0 = (Real)m.rho0;
@@ -267,6 +329,8 @@ static hipError_t dispatch(int kind, const LaunchReq& r) {
     case kRD2Q17_3: return launch_rd2q17_3(r);
     case kRD2Q17_4: return launch_rd2q17_4(r);
     case kRD2Q17_5: return launch_rd2q17_5(r);
+    case kD2Q9: return launch_d2q9(r);
+    case kD3Q27: return launch_d3q27(r);
   }
   return hipErrorInvalidValue;
 }
@@ -403,7 +467,8 @@ mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* l, int* b, int* d, int* e,
   return MRTLB_OK;
 }
 
-static mrtlb_status check_model(const mrtlb_model_desc& m, int D, int kind) {
+static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L) {
+  const int D = L.D;
   if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP && m.model != MRTLB_NCDE && m.model != MRTLB_CDE)
     return fail(MRTLB_EINVAL, "unknown model");
   const double r[6] = {m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high};
@@ -414,7 +479,12 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, int D, int kind) {
   if (m.model == MRTLB_CDE && D != 2) return fail(MRTLB_EINVAL, "the CDE model is built for 2D lattices");
   if (!(m.u_bound >= 0 && m.u_bound < 1e3) || !(m.dev_bound >= 0 && m.dev_bound < 1e3))
     return fail(MRTLB_EINVAL, "u_bound and dev_bound must be finite and >= 0");
-  (void)kind;
+  if (L.standard) {
+    if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
+      return fail(MRTLB_EINVAL, "the standard lattices carry the k = 1 NSE models only");
+    double S2[3][3];
+    if (!s2_normal_block(L, m, S2)) return fail(MRTLB_EINVAL, "singular S2 block for these rates and this lattice");
+  }
   return MRTLB_OK;
 }
 
@@ -462,7 +532,7 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   if (!ctx || !lat || !model || !n || !out) return fail(MRTLB_EINVAL, "NULL argument");
   *out = nullptr;
   const int D = lat->L.D;
-  mrtlb_status st = check_model(*model, D, lat->L.kind);
+  mrtlb_status st = check_model(*model, lat->L);
   if (st != MRTLB_OK) return st;
   if (has_force && (model->model == MRTLB_NCDE || model->model == MRTLB_CDE))
     return fail(MRTLB_EINVAL, "the NCDE and CDE models take no force field");

@@ -412,7 +412,7 @@ __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Rea
           S0 += s;
           S2 += Real(k * k) * s;
           D1 += Real(sk) * d;
-          D3 += Real(sk * k * k) * d;
+          if constexpr (!is_standard<L>()) D3 += Real(sk * k * k) * d;
         }
       });
       R0 += S0;
@@ -420,20 +420,22 @@ __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Rea
         constexpr int a = decltype(aa)::value;
         constexpr int ba = ray_dir<L>(lead, a);
         if constexpr (ba != 0) {
+          // single layer (k = 1 on every ray): D3 = D1, and no pure rows
+          const Real Dodd = is_standard<L>() ? D1 : D3;
           R1[a] += Real(ba) * D1;
           R2n[a] += Real(ba * ba) * S2;
-          R3p[a] += Real(ba * ba * ba) * D3;
+          if constexpr (!is_standard<L>()) R3p[a] += Real(ba * ba * ba) * D3;
           static_for<0, D>([&](auto bb) {
             constexpr int b = decltype(bb)::value;
             constexpr int bv = ray_dir<L>(lead, b);
-            if constexpr (b != a && bv != 0) R3m[a][b] += Real(ba * bv * bv) * D3;
+            if constexpr (b != a && bv != 0) R3m[a][b] += Real(ba * bv * bv) * Dodd;
             if constexpr (b > a && bv != 0) R2o[off_index(a, b)] += Real(ba * bv) * S2;
           });
         }
       });
       if constexpr (D == 3) {
         constexpr int bxyz = ray_dir<L>(lead, 0) * ray_dir<L>(lead, 1) * ray_dir<L>(lead, 2);
-        if constexpr (bxyz != 0) Rxyz += Real(bxyz) * D3;
+        if constexpr (bxyz != 0) Rxyz += Real(bxyz) * (is_standard<L>() ? D1 : D3);
       }
     }
   });
@@ -456,7 +458,7 @@ __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Rea
       M.m3m[a][b] = P.cabb[a][b] * R3m[a][b] - P.cs2 * M.m1[a];
       pure -= P.corr[a][b] * M.m3m[a][b];
     }
-    M.m3p[a] = pure;
+    M.m3p[a] = is_standard<L>() ? Real(0) : pure;
   }
   if constexpr (D == 3) M.mxyz = P.cxyz * Rxyz;
 }
@@ -480,16 +482,17 @@ __device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P
   for (int a = 0; a < D; ++a) b0 -= P.cs2 * d2n[a];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    Real t = d1[a] + P.k3[a] * d3p[a];
+    constexpr bool pure3 = !is_standard<L>();
+    Real t = pure3 ? d1[a] + P.k3[a] * d3p[a] : d1[a];
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       if (b == a) continue;
       t -= P.cs2 * d3m[a][b];
-      b3m[a][b] = P.cabb[a][b] * (d3m[a][b] - P.corr[a][b] * d3p[a]);
+      b3m[a][b] = pure3 ? P.cabb[a][b] * (d3m[a][b] - P.corr[a][b] * d3p[a]) : P.cabb[a][b] * d3m[a][b];
     }
     b1[a] = P.c1[a] * t;
     b2n[a] = P.c2[a] * d2n[a];
-    b3p[a] = P.c3[a] * d3p[a];
+    b3p[a] = pure3 ? P.c3[a] * d3p[a] : Real(0);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a)
@@ -508,7 +511,7 @@ __device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P
         if constexpr (ba != 0) {
           E2 += Real(ba * ba) * b2n[a];
           O1 += Real(ba) * b1[a];
-          O3 += Real(ba * ba * ba) * b3p[a];
+          if constexpr (!is_standard<L>()) O3 += Real(ba * ba * ba) * b3p[a];
           static_for<0, D>([&](auto bb) {
             constexpr int b = decltype(bb)::value;
             constexpr int bv = ray_dir<L>(lead, b);
@@ -595,7 +598,7 @@ struct Equilibrium {
           e3m[a][b] = e2n[b] * u[a];  // rho u_a u_b^2
           pure -= P.corr[a][b] * e3m[a][b];
         }
-        e3p[a] = g30 * pure;
+        e3p[a] = is_standard<L>() ? Real(0) : g30 * pure;
 #pragma unroll
         for (int b = 0; b < D; ++b) e3m[a][b] *= g30;
       }
@@ -740,10 +743,24 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
     tT *= Real(1.0 / D);
     const Real kb = Real(1) - P.sb, ks = Real(1) - P.ss;
     const Real gb = Real(1) - Real(0.5) * P.sb, gs = Real(1) - Real(0.5) * P.ss;
+    if constexpr (is_standard<L>()) {
+      // k = 1: the full normal block, m* = m_eq + (I - S2) neq + (I - S2/2) T
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const Real ms = E.e2n[a] + kb * tn + ks * (neq[a] - tn) + gb * tT + gs * (T2n[a] - tT);
-      d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
+      for (int a = 0; a < D; ++a) {
+        Real ms = E.e2n[a];
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          ms += P.k2[a][b] * neq[b];
+          if constexpr (FORCE) ms += P.g2[a][b] * T2n[b];
+        }
+        d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const Real ms = E.e2n[a] + kb * tn + ks * (neq[a] - tn) + gb * tT + gs * (T2n[a] - tT);
+        d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
+      }
     }
 #pragma unroll
     for (int a = 0; a < D; ++a)
@@ -758,7 +775,7 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
     const Real k3 = Real(1) - P.s3;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      d3p[a] = (E.e3p[a] + k3 * (M.m3p[a] - E.e3p[a]) - kx * M.m3p[a]) * P.in3p[a];
+      d3p[a] = is_standard<L>() ? Real(0) : (E.e3p[a] + k3 * (M.m3p[a] - E.e3p[a]) - kx * M.m3p[a]) * P.in3p[a];
 #pragma unroll
       for (int b = 0; b < D; ++b) {
         if (b == a) continue;
@@ -1096,23 +1113,33 @@ hipError_t launch_lattice(const LaunchReq& r) {
     if ((ncde || cde) && L::D != 2) return;
     switch (r.op) {
       case kOpStep: {
+        // Several nodes per thread are built only where the host picks them:
+        // the NSE models on the 2D lattices.  Any other request is refused.
+        bool launched = false;
         auto step = [&](auto vc) {
           constexpr int V = decltype(vc)::value;
           if (ncde) {
-            if constexpr (L::D == 2)
+            if constexpr (L::D == 2 && V == 1) {
               hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              launched = true;
+            }
           } else if (cde) {
-            if constexpr (L::D == 2)
+            if constexpr (L::D == 2 && V == 1) {
               hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
-          } else if (r.force) {
-            hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
-          } else {
-            hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              launched = true;
+            }
+          } else if constexpr (L::D == 2 || V == 1) {
+            if (r.force)
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+            else
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+            launched = true;
           }
         };
         if (r.vec == 4) step(std::integral_constant<int, 4>{});
         else if (r.vec == 2) step(std::integral_constant<int, 2>{});
         else step(std::integral_constant<int, 1>{});
+        if (!launched) return;
         break;
       }
       case kOpInit:

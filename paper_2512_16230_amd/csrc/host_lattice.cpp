@@ -78,6 +78,18 @@ void weights_d2q21k(const double* c, double cs2, double w9, HostLattice* out) {
 }
 
 // rD2Q13 closed-form weights printed with Sec. V eq. (Q13lattice).
+// Standard single-layer lattices: one D1Q3 weight per axis, 1 - d_a at
+// rest and d_a / 2 at +-1 (d_a = cs^2 / c_a^2), multiplied over the axes:
+// unit mass, Delta2 = cs^2 I and Delta4_aabb = cs^4 (a != b).
+void weights_standard(const double* c, double cs2, HostLattice* out) {
+  out->w.assign(out->B, 1.0);
+  for (int j = 0; j < out->B; ++j)
+    for (int a = 0; a < out->D; ++a) {
+      const double d = cs2 / (c[a] * c[a]);
+      out->w[j] *= out->e[j * out->D + a] != 0 ? 0.5 * d : 1.0 - d;
+    }
+}
+
 void weights_rd2q13(const double* c, double cs2, HostLattice* out) {
   const double d1 = cs2 / (c[0] * c[0]), d2 = cs2 / (c[1] * c[1]);
   const double w9 = d1 * (3 * d1 - 1) / 24, w10 = d2 * (3 * d2 - 1) / 24;
@@ -171,6 +183,8 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
     case kRD2Q17_3: copy_velocities<LatRD2Q17_3>(&L); break;
     case kRD2Q17_4: copy_velocities<LatRD2Q17_4>(&L); break;
     case kRD2Q17_5: copy_velocities<LatRD2Q17_5>(&L); break;
+    case kD2Q9: copy_velocities<LatD2Q9>(&L); break;
+    case kD3Q27: copy_velocities<LatD3Q27>(&L); break;
     default:
       snprintf(buf, sizeof buf, "unknown lattice kind %d", desc.kind);
       *err = buf;
@@ -239,6 +253,7 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
       weights_3d(L.c, L.cs2, fr, true, &L);
       break;
     }
+    case kD2Q9: case kD3Q27: weights_standard(L.c, L.cs2, &L); break;
   }
   for (int j = 0; j < B; ++j) {
     if (!(L.w[j] > 0)) {
@@ -255,8 +270,13 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
   auto cc = [&](int j, int a) { return cv[j * D + a]; };
   const double cs2 = L.cs2;
 
-  L.nlow = D == 2 ? 10 : 20;
-  std::vector<std::vector<double>> rows(L.nlow, std::vector<double>(B, 0.0));
+  // Standard lattices: c_a^3 = c_a^2 c_a on one layer, so the pure rows
+  // would repeat the first-order rows; they are left out (rows are built
+  // in the full order and the first nlow kept).
+  L.standard = desc.kind == kD2Q9 || desc.kind == kD3Q27;
+  const int nfull = D == 2 ? 10 : 20;
+  L.nlow = L.standard ? nfull - D : nfull;
+  std::vector<std::vector<double>> rows(nfull, std::vector<double>(B, 0.0));
   for (int j = 0; j < B; ++j) {
     rows[0][j] = 1.0;
     for (int a = 0; a < D; ++a) {
@@ -272,7 +292,7 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
   // Correction: remove from each pure row its W-projection on the span of
   // the mixed rows c_a (c_b^2 - cs^2), b != a.  The Gram system is at most
   // 2 x 2 and solved directly.
-  for (int a = 0; a < D; ++a) {
+  for (int a = 0; a < D && !L.standard; ++a) {
     int bs[2], nb = 0;
     for (int b = 0; b < D; ++b)
       if (b != a) bs[nb++] = b;

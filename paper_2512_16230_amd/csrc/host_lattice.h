@@ -12,8 +12,10 @@ namespace mrtlb {
 // 2D: 1, x, y, xx, yy, xy, xyy, yxx, xxx, yyy
 // 3D: 1, x, y, z, xx, yy, zz, xy, xz, yz, xyy, xzz, yxx, yzz, zxx, zyy, xyz,
 //     xxx, yyy, zzz
+// Standard lattices (D2Q9, D3Q27) stop before the pure rows (nlow 8 / 17).
 struct HostLattice {
   int kind = 0, D = 0, B = 0, nlow = 0;
+  bool standard = false;
   double c[3] = {1, 1, 1};
   double cs2 = 0;
   std::vector<int> e;          // B x D

@@ -53,6 +53,9 @@ struct KParams {
   Real k3[3];               // -3 cs^2 + cs^2 sum_b corr[a][b]
   Real in0, in1[3], in2n[3], in2o[3], in3m[3][3], in3p[3], inxyz;  // 1 / norms
   Real s1, ss, sb, s3, sh;  // rates (s0 never acts: order-0 moment is conserved)
+  // Standard lattices: the normal second-order block, I - S2 and I - S2/2
+  // on the component rows c_a^2 - cs^2 (eq. 4-27); unused elsewhere.
+  Real k2[3][3], g2[3][3];
   Real rho_ref;             // deviation reference: stored = f_bar - w rho_ref
   Real rho0;
   Real phi_coef, D2;        // NCDE: Phi = phi_coef (phi + D2 phi^3 / 3)

@@ -16,7 +16,7 @@ namespace mrtlb {
 
 enum LatticeKind {
   kRD2Q25 = 0, kRD2Q13 = 1, kRD3Q53 = 2, kRD3Q33 = 3, kRD2Q21 = 4, kD2Q21K = 5, kRD3Q45 = 6,
-  kRD2Q17_1 = 7, kRD2Q17_2 = 8, kRD2Q17_3 = 9, kRD2Q17_4 = 10, kRD2Q17_5 = 11
+  kRD2Q17_1 = 7, kRD2Q17_2 = 8, kRD2Q17_3 = 9, kRD2Q17_4 = 10, kRD2Q17_5 = 11, kD2Q9 = 12, kD3Q27 = 13
 };
 
 struct LatRD2Q25 {
@@ -82,6 +82,15 @@ struct LatRD2Q17_5 {
   static constexpr int EZ[B] = {};
 };
 
+// Standard single-layer D2Q9 (the first layer of eq. 3-1): k = 1 model,
+// no pure third-order rows, non-diagonal S2 block (eq. 4-27).
+struct LatD2Q9 {
+  static constexpr int kind = kD2Q9, D = 2, B = 9, MAXE = 1;
+  static constexpr int EX[B] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int EY[B] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static constexpr int EZ[B] = {};
+};
+
 #define MRTLB_D3Q27_X 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1
 #define MRTLB_D3Q27_Y 0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, 1, -1, -1, 1, 1, -1
 #define MRTLB_D3Q27_Z 0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1, 1, -1
@@ -100,6 +109,14 @@ struct LatRD3Q45 {
   static constexpr int EZ[B] = {MRTLB_D3Q27_Z, 0, 0, 0, 0, 2, -2, 0, 0, 0, 0, 2, -2, 2, -2, 2, -2, 2, -2};
 };
 
+// Standard D3Q27: the first 27 columns of the rD3Q53 velocity matrix.
+struct LatD3Q27 {
+  static constexpr int kind = kD3Q27, D = 3, B = 27, MAXE = 1;
+  static constexpr int EX[B] = {MRTLB_D3Q27_X};
+  static constexpr int EY[B] = {MRTLB_D3Q27_Y};
+  static constexpr int EZ[B] = {MRTLB_D3Q27_Z};
+};
+
 struct LatRD3Q33 {
   static constexpr int kind = kRD3Q33, D = 3, B = 33, MAXE = 2;
   static constexpr int EX[B] = {MRTLB_D3Q27_X, 2, -2, 0, 0, 0, 0};
@@ -111,15 +128,10 @@ struct LatRD3Q33 {
 #undef MRTLB_D3Q27_Y
 #undef MRTLB_D3Q27_Z
 
-// Index of the population with velocity -e_j.
+// Standard lattices: single layer, k = 1 model.
 template <class L>
-constexpr int opposite(int j) {
-  for (int k = 0; k < L::B; ++k) {
-    bool same = L::EX[k] == -L::EX[j] && L::EY[k] == -L::EY[j];
-    if (L::D == 3) same = same && L::EZ[k] == -L::EZ[j];
-    if (same) return k;
-  }
-  return -1;
+constexpr bool is_standard() {
+  return L::kind == kD2Q9 || L::kind == kD3Q27;
 }
 
 template <class L>
@@ -128,66 +140,93 @@ constexpr int ez(int j) {
   return 0;
 }
 
-// Pair list: the p-th pair is (pair_first<L>(p), opposite of it), taken in
-// increasing order of the first index with first < opposite.
+constexpr int iabs(int v) { return v < 0 ? -v : v; }
+constexpr int igcd(int a, int b) { return b == 0 ? a : igcd(b, a % b); }
+
+// Per-lattice index tables, evaluated once per lattice at compile time (the
+// kernels query them inside nested compile-time loops):
+//  * opp[j]: the population with velocity -e_j;
+//  * pairs: the p-th pair is (first[p], opp[first[p]]), taken in increasing
+//    order of the first index with first < opposite;
+//  * rays: pairs whose velocities are multiples of one direction (e, 2e, 3e
+//    on the multispeed lattices) form a ray.  Pair p's first velocity is
+//    sign[p] * scale[p] * base, base = dir[leader[p]] being the primitive
+//    direction of the ray's first pair (its leader).
 template <class L>
-constexpr int pair_first(int p) {
-  int count = 0;
-  for (int j = 1; j < L::B; ++j) {
-    if (j < opposite<L>(j)) {
-      if (count == p) return j;
-      ++count;
+struct LatticeTables {
+  static constexpr int NP = (L::B - 1) / 2;
+  int opp[L::B] = {};
+  int first[NP > 0 ? NP : 1] = {};
+  int scale[NP > 0 ? NP : 1] = {};
+  int leader[NP > 0 ? NP : 1] = {};
+  int sign[NP > 0 ? NP : 1] = {};
+  int dir[NP > 0 ? NP : 1][3] = {};
+};
+
+template <class L>
+constexpr LatticeTables<L> make_tables() {
+  LatticeTables<L> t;
+  for (int j = 0; j < L::B; ++j) {
+    t.opp[j] = -1;
+    for (int k = 0; k < L::B && t.opp[j] < 0; ++k) {
+      bool same = L::EX[k] == -L::EX[j] && L::EY[k] == -L::EY[j];
+      if (L::D == 3) same = same && ez<L>(k) == -ez<L>(j);
+      if (same) t.opp[j] = k;
     }
   }
-  return -1;
+  int count = 0;
+  for (int j = 1; j < L::B; ++j)
+    if (j < t.opp[j]) t.first[count++] = j;
+  for (int p = 0; p < LatticeTables<L>::NP; ++p) {
+    const int j = t.first[p];
+    const int v[3] = {L::EX[j], L::EY[j], ez<L>(j)};
+    t.scale[p] = igcd(igcd(iabs(v[0]), iabs(v[1])), iabs(v[2]));
+    for (int a = 0; a < 3; ++a) t.dir[p][a] = a < L::D ? v[a] / t.scale[p] : 0;
+  }
+  for (int p = 0; p < LatticeTables<L>::NP; ++p) {
+    t.leader[p] = p;
+    t.sign[p] = 1;
+    for (int q = 0; q <= p; ++q) {
+      bool same = true, opp = true;
+      for (int a = 0; a < L::D; ++a) {
+        same = same && t.dir[q][a] == t.dir[p][a];
+        opp = opp && t.dir[q][a] == -t.dir[p][a];
+      }
+      if (same || opp) {
+        t.leader[p] = q;
+        t.sign[p] = same ? 1 : -1;
+        break;
+      }
+    }
+  }
+  return t;
 }
+
+template <class L>
+inline constexpr LatticeTables<L> kTables = make_tables<L>();
+
+// Index of the population with velocity -e_j.
+template <class L>
+constexpr int opposite(int j) { return kTables<L>.opp[j]; }
+
+template <class L>
+constexpr int pair_first(int p) { return kTables<L>.first[p]; }
 
 template <class L>
 constexpr int n_pairs() { return (L::B - 1) / 2; }
 
-// Rays: pairs whose velocities are multiples of one direction (e, 2e, 3e on
-// the multispeed lattices) form a ray.  Pair p's first velocity is
-// sign * scale * base, base being the ray's direction as given by its first
-// pair (the leader).
-constexpr int iabs(int v) { return v < 0 ? -v : v; }
-constexpr int igcd(int a, int b) { return b == 0 ? a : igcd(b, a % b); }
+template <class L>
+constexpr int ray_scale(int p) { return kTables<L>.scale[p]; }
 
 template <class L>
-constexpr int ray_scale(int p) {
-  const int j = pair_first<L>(p);
-  return igcd(igcd(iabs(L::EX[j]), iabs(L::EY[j])), iabs(ez<L>(j)));
-}
+constexpr int ray_leader(int p) { return kTables<L>.leader[p]; }
 
+// +1 / -1: pair p's direction equals / opposes its ray leader's
 template <class L>
-constexpr int prim(int p, int a) {
-  const int j = pair_first<L>(p);
-  const int v = a == 0 ? L::EX[j] : (a == 1 ? L::EY[j] : ez<L>(j));
-  return v / ray_scale<L>(p);
-}
-
-// +1 / -1 if pair q's direction equals / opposes pair p's, 0 otherwise
-template <class L>
-constexpr int ray_relation(int p, int q) {
-  bool same = true, opp = true;
-  for (int a = 0; a < L::D; ++a) {
-    same = same && prim<L>(p, a) == prim<L>(q, a);
-    opp = opp && prim<L>(p, a) == -prim<L>(q, a);
-  }
-  return same ? 1 : (opp ? -1 : 0);
-}
-
-template <class L>
-constexpr int ray_leader(int p) {
-  for (int q = 0; q <= p; ++q)
-    if (ray_relation<L>(q, p) != 0) return q;
-  return p;
-}
-
-template <class L>
-constexpr int ray_sign(int p) { return ray_relation<L>(ray_leader<L>(p), p); }
+constexpr int ray_sign(int p) { return kTables<L>.sign[p]; }
 
 // component a of the ray direction (the leader's primitive velocity)
 template <class L>
-constexpr int ray_dir(int leader, int a) { return a < L::D ? prim<L>(leader, a) : 0; }
+constexpr int ray_dir(int leader, int a) { return kTables<L>.dir[leader][a]; }
 
 }  // namespace mrtlb

@@ -40,6 +40,8 @@ hipError_t launch_rd2q17_2(const LaunchReq& r);
 hipError_t launch_rd2q17_3(const LaunchReq& r);
 hipError_t launch_rd2q17_4(const LaunchReq& r);
 hipError_t launch_rd2q17_5(const LaunchReq& r);
+hipError_t launch_d2q9(const LaunchReq& r);
+hipError_t launch_d3q27(const LaunchReq& r);
 
 // FP64 sums of every population plane (and force plane) in chunks.
 hipError_t launch_plane_sums(int storage, const void* base, uint32_t N, int npop, const void* force, int nforce,

@@ -37,7 +37,7 @@ def test_version():
 
 
 @pytest.mark.parametrize("card", [W.Q25_RECT, W.Q13_SQUARE, W.Q53_RECT, W.Q33_CUBIC, W.Q21_RECT, W.Q21K_RECT,
-                                  W.Q45_RECT] + W.Q17_CASES,
+                                  W.Q45_RECT, W.Q9_RECT, W.Q27_RECT] + W.Q17_CASES,
                          ids=lambda c: c.kind)
 def test_host_lattice_matches_oracle(card):
     q = H.Lattice(card.kind, card.c, card.cs2, card.free).query()
@@ -61,6 +61,10 @@ def test_host_lattice_matches_oracle(card):
             idx[3] = list(range(1 + lat.d + n2, Hm.shape[0]))
         Bm = Hm[idx[order]]
         assert np.linalg.matrix_rank(np.vstack([A, Bm]), tol=1e-9) == rank_A == Bm.shape[0]
+    if card.kind in OL.STANDARD:
+        # no pure third-order rows on a single layer
+        assert q["H"].shape[0] == len(lat.rows) == (8 if lat.d == 2 else 17)
+        return
     # corrected pure third-order rows are identical (same definition)
     pure_o = Ho[[r.name in ("xxx", "yyy", "zzz") for r in lat.rows]]
     pure_h = Hm[-lat.d:]

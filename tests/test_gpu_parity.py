@@ -162,6 +162,33 @@ def test_d2q17_cases(ctx, card):
         assert max_rel(v, u_o) < tu
 
 
+@pytest.mark.parametrize("card,shape", [(W.Q9_RECT, (7, 300)), (W.Q9_RECT, (37, 66)), (W.Q27_RECT, (6, 10, 70))],
+                         ids=["D2Q9-7x300", "D2Q9-37x66", "D3Q27"])
+@pytest.mark.parametrize("eq", ["NSE_INC", "NSE_COMP"])
+@pytest.mark.parametrize("forced", [False, True], ids=["free", "force"])
+def test_standard_lattices(ctx, card, shape, eq, forced):
+    """Standard D2Q9 / D3Q27 with the k = 1 model: non-diagonal S2 block
+    (eq. 4-27) on the normal second-order rows, the same block in
+    (I - S2/2)(uF + Fu), M30 = 0; against the oracle on ragged tiles."""
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    rho, u = _random_fields(card, shape, 25)
+    F = W.sinusoidal_force(card, shape, 1e-3, seed=5) if forced else None
+    steps = 12
+    r_o, u_o, _ = _oracle_run(card, eq, rates, rho, u, steps, force=F, m30=False)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4), ("fp32_dev", 1e-6, 2e-5),
+                            ("i16_dev", 1e-4, 1e-2)):
+        print("case: %s %s %s force=%s %s" % (card.kind, eq, shape, forced, storage), flush=True)
+        r, v, _ = _gpu_run(ctx, card, eq, rates, shape, storage, rho, u, steps, force=F, m30=False)
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+
+
+def test_standard_lattice_refuses_the_ncde(ctx):
+    with pytest.raises(H.MrtlbError) as e:
+        H.Solve(ctx, hip_lattice(W.Q9_RECT), hip_model("NCDE", W.Rates(), D0=0.1), (16, 16), "fp32")
+    assert e.value.status == H.MRTLB_EINVAL
+
+
 @pytest.mark.parametrize("card", [W.Q21_RECT, W.Q21K_RECT], ids=lambda c: c.kind)
 def test_rd2q21_lattices_ncde(ctx, card):
     wl = W.ncde_hill((40, 72), adv_u=(0.03, -0.02), D0=0.1, D2=1.0, card=card)
