@@ -72,6 +72,11 @@ class Model:
     D0: float = 0.0          # NCDE: D(phi) = D0 (1 + D2 phi^2)
     D2: float = 0.0
     adv_u: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    # general NCDE (eq. M-NCDE-6): A1 dt(B_bar) = gn_bt * dt(phi) per axis
+    # (B_bar = phi b_bar, gn_bt = A1 b_bar) and A2 div(D_bar) = gn_dd * grad(phi)
+    # per axis (D_bar = phi I, gn_dd = diag A2)
+    gn_bt: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    gn_dd: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
 
     def rate(self, group: str) -> float:
         return {"rho": self.s0, "j": self.s1, "bulk": self.s_bulk, "shear": self.s_shear,
@@ -219,22 +224,25 @@ def force_hermite(lat, n, force):
     return hermite_from_raw(lat, M, max_order=2)
 
 
-def aux_hermite(lat, model, S, u, force, extra=None):
+def aux_hermite(lat, model, S, u, force, extra=None, cross=None):
     """Hermite moments of the auxiliary distribution G; S is the relaxation
     matrix on the rows of order <= 3.
 
     NSE: M2G = (I - S2/2)(uF + Fu) (eqs. M2G-1, M2Ga-1), zero otherwise.
-    NCDE: M1G = (I - S1/2) B with B = d_t(phi u) + div(phi uu) supplied in
-    ``extra``.
+    NCDE (eq. M-NCDE-6): M1G = (I - S1/2) B - S1 X with
+    B = d_t(phi u) + div(phi uu) supplied in ``extra`` and
+    X = A1 d_t(B_bar) + A2 div(D_bar) in ``cross`` (general NCDE; None = 0).
     """
     n = u.shape[1]
     d = lat.d
     G = np.eye(len(lat.rows)) - 0.5 * S
     if model.eq == NCDE:
-        if extra is None:
-            return np.zeros((len(lat.rows), n))
-        M = [np.zeros(n), extra, None, None]
-        return G @ hermite_from_raw(lat, M, max_order=1)
+        out = np.zeros((len(lat.rows), n))
+        if extra is not None:
+            out += G @ hermite_from_raw(lat, [np.zeros(n), extra, None, None], max_order=1)
+        if cross is not None:
+            out -= S @ hermite_from_raw(lat, [np.zeros(n), cross, None, None], max_order=1)
+        return out
     if force is None:
         return np.zeros((len(lat.rows), n))
     T = np.einsum("an,bn->abn", u, force) + np.einsum("an,bn->abn", force, u)
@@ -254,6 +262,26 @@ def populations_from_hermite(lat: Lattice, m: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 # NCDE helper: B^n = u [ (phi^n - phi^{n-1}) / dt + u . grad_h phi^{n-1} ]
 # --------------------------------------------------------------------------
+
+def ncde_cross(lat: Lattice, model: Model, phi_grid: np.ndarray, phi_prev_grid: np.ndarray):
+    """X^n = A1 d_t(B_bar) + A2 div(D_bar) of the general NCDE (eq. M-NCDE-6)
+    with B_bar = phi b_bar and D_bar = phi I: per axis a,
+    X_a = gn_bt_a (phi^n - phi^{n-1}) / dt + gn_dd_a d_a phi^{n-1}, the same
+    backward time difference and central space difference of the previous
+    step's phi as B^n; None when both coefficient vectors vanish."""
+    d = lat.d
+    bt = np.asarray(model.gn_bt[:d], dtype=np.float64)
+    dd = np.asarray(model.gn_dd[:d], dtype=np.float64)
+    if not (bt.any() or dd.any()):
+        return None
+    nd = phi_grid.ndim
+    X = np.zeros((d,) + phi_grid.shape)
+    for a in range(d):
+        axis = nd - 1 - a
+        grad = (np.roll(phi_prev_grid, -1, axis=axis) - np.roll(phi_prev_grid, 1, axis=axis)) / (2 * lat.c[a])
+        X[a] = bt[a] * (phi_grid - phi_prev_grid) + dd[a] * grad
+    return X.reshape(d, -1)
+
 
 def ncde_B(lat: Lattice, model: Model, phi_grid: np.ndarray, phi_prev_grid: np.ndarray):
     d = lat.d
@@ -278,11 +306,11 @@ class State:
     phi_prev: np.ndarray = None   # NCDE only: phi of the previous step
 
 
-def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None):
+def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, ncde_x=None):
     """Post-collision populations f* (b, n) from pre-collision f_bar (b, n).
 
-    ``ncde_b`` is the NCDE field B^n (d, n) of the auxiliary first moment;
-    for the CDE ``force`` is the velocity field (d, n)."""
+    ``ncde_b`` and ``ncde_x`` are the NCDE fields B^n and X^n (d, n) of the
+    auxiliary first moment; for the CDE ``force`` is the velocity field (d, n)."""
     n = f.shape[1]
     S = relaxation_matrix(lat, model)
     R0, u, rho_m = macroscopic(lat, model, f, force)
@@ -296,7 +324,7 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None):
         mstar = m - S @ (m - meq) + mG
         return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
     mF = force_hermite(lat, n, force) if model.eq != NCDE else np.zeros_like(m)
-    mG = aux_hermite(lat, model, S, u, force, extra=ncde_b)
+    mG = aux_hermite(lat, model, S, u, force, extra=ncde_b, cross=ncde_x)
     mstar = m - S @ (m - meq) + mG + (np.eye(len(lat.rows)) - 0.5 * S) @ mF
     return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
 
@@ -314,13 +342,14 @@ def stream(lat: Lattice, fstar_grid: np.ndarray) -> np.ndarray:
 def step(lat: Lattice, model: Model, st: State, force=None) -> State:
     grid = st.f.shape[1:]
     f = st.f.reshape(lat.b, -1)
-    extra = None
+    extra = cross = None
     phi = None
     if model.eq == NCDE:
         phi = f.sum(axis=0).reshape(grid)
         extra = ncde_B(lat, model, phi, st.phi_prev)
+        cross = ncde_cross(lat, model, phi, st.phi_prev)
     F = None if force is None else force.reshape(lat.d, -1)
-    fstar = collide(lat, model, f, F, extra)
+    fstar = collide(lat, model, f, F, extra, cross)
     return State(stream(lat, fstar.reshape(st.f.shape)), phi)
 
 

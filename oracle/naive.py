@@ -56,6 +56,9 @@ class NaiveStepper:
             for x in itertools.product(*[range(n) for n in grid]):
                 phi_grid[x] = sum(st.f[(j,) + x] for j in range(b))
             Bfield = M.ncde_B(lat, mdl, phi_grid, st.phi_prev).reshape((d,) + grid)
+            Xfield = M.ncde_cross(lat, mdl, phi_grid, st.phi_prev)
+            if Xfield is not None:
+                Xfield = Xfield.reshape((d,) + grid)
         for x in itertools.product(*[range(n) for n in grid]):
             f = np.array([st.f[(j,) + x] for j in range(b)])
             F = None if force is None else np.array([force[(a,) + x] for a in range(d)])
@@ -78,7 +81,8 @@ class NaiveStepper:
             feq = self._velocity_space(M.equilibrium_hermite(lat, mdl, R0, uv, rm)[:, 0])
             if mdl.eq == M.NCDE:
                 Bx = np.array([Bfield[(a,) + x] for a in range(d)])[:, None]
-                G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, None, extra=Bx)[:, 0])
+                Xx = None if Xfield is None else np.array([Xfield[(a,) + x] for a in range(d)])[:, None]
+                G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, None, extra=Bx, cross=Xx)[:, 0])
                 Fv = np.zeros(b)
             else:
                 Fa = None if F is None else F[:, None]

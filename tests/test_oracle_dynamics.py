@@ -7,7 +7,11 @@
     kinetic-energy decay -2 nu |k|^2 E, second-order convergence;
   * rD2Q13 NCDE: advected Gaussian hill closed form for linear D,
     variance growth 2 D0 per axis, and for D(phi) = D0 (1 + phi^2) the
-    identity d/dt int |x|^2 phi = 2 d int G(phi), G' = D (eq. GNCDE).
+    identity d/dt int |x|^2 phi = 2 d int G(phi), G' = D (eq. GNCDE);
+  * general NCDE (eqs. M-NCDE-6, GNCDE) with B_bar = phi b_bar and
+    D_bar = phi I: the complex rate of a Fourier mode equals the dispersion
+    relation of d_t phi + u . grad phi = D0 lap phi + dt (A1 b_bar . grad) d_t phi
+    + dt sum_a A2_aa d_a^2 phi, i.e. K1 = dt A1 and K2 = dt A2.
 """
 
 import numpy as np
@@ -212,3 +216,42 @@ def test_cde_shear_field_converges_at_second_order():
     assert 3.0 < e1 / e2 < 5.5
     for N, phi, m0 in out:
         assert abs(phi.sum() - m0) / m0 < 1e-3
+
+
+def _gncde_mode_rate(bt, dd, u, s1=1.5, D0=0.05, n=64, steps=400):
+    """Fitted complex rate (per step) of the mode exp(i k.x), k = (1, 2) x the
+    box wavenumbers, and the two candidate dispersion relations."""
+    card = W.Q13_SQUARE
+    lat = L.make_lattice(card.kind, card.c, card.cs2, card.free)
+    mdl = M.Model(eq=M.NCDE, s0=1.2, s1=s1, s_shear=1.3, s_bulk=1.1, s3=1.2, s_h=1.2, D0=D0, D2=0.0,
+                  adv_u=tuple(u) + (0.0,), gn_bt=tuple(bt) + (0.0,), gn_dd=tuple(dd) + (0.0,))
+    shape = (n, n)
+    k = np.array([2 * np.pi / (n * card.c[0]), 4 * np.pi / (n * card.c[1])])
+    ph = sum(k[a] * W.axis_coords(card, shape, a) for a in range(2)) * np.ones(shape)
+    st = M.init_state(lat, mdl, 1 + 1e-3 * np.cos(ph))
+    amp = []
+    for _ in range(steps):
+        amp.append((st.f.sum(0) * np.exp(-1j * ph)).mean())
+        st = M.step(lat, mdl, st)
+    t = np.arange(100, steps)
+    amp = np.array(amp[100:])
+    rate = complex(np.polyfit(t, np.log(np.abs(amp)), 1)[0], np.polyfit(t, np.unwrap(np.angle(amp)), 1)[0])
+    uk, bk, k2 = float(np.dot(u, k)), float(np.dot(bt, k)), float(np.dot(k, k))
+    ddk = float(np.dot(dd, k * k))
+    derived = (-1j * uk - D0 * k2 - ddk) / (1 - 1j * bk)                 # K1 = dt A1, K2 = dt A2
+    printed = (-1j * uk - D0 * k2 - s1 * ddk) / (1 - 1j * s1 * bk)       # K1 = dt S1 A1, K2 = dt S1 A2
+    return rate, derived, printed
+
+
+@pytest.mark.parametrize("bt,dd,u", [((0.2, 0.1), (0.0, 0.0), (0.02, -0.01)),
+                                     ((0.0, 0.0), (0.02, 0.01), (0.02, -0.01)),
+                                     ((0.3, -0.1), (0.02, 0.01), (0.015, 0.01))],
+                         ids=["mixed", "cross", "both+advection"])
+def test_general_ncde_fourier_mode(bt, dd, u):
+    rate, derived, printed = _gncde_mode_rate(bt, dd, u)
+    assert abs(rate.real / derived.real - 1) < 0.01
+    assert abs(rate.imag - derived.imag) < 0.02 * abs(derived.imag) + 1e-7
+    # the printed K1 = dt S1 A1, K2 = dt S1 A2 (eq. GNCDE-0) misses one of
+    # the two parts by 5% or more
+    off = max(abs(rate.real / printed.real - 1), abs(rate.imag - printed.imag) / (abs(printed.imag) + 1e-12))
+    assert off > 0.05
