@@ -194,6 +194,15 @@ typedef struct {
    * dev_bound >= max |rho - rho0| / rho0 (NSE) or max |phi| (NCDE).
    * Both 0 (the default) selects the uniform range |f_bar - w rho_ref| <= 2 w. */
   double u_bound, dev_bound;
+  /* General NCDE (eq. M-NCDE-6): the auxiliary first moment gains
+   * -S1 (A1 d_t B_bar + A2 div D_bar) with B_bar = phi b_bar and
+   * D_bar = phi I, here gn_bt = A1 b_bar and gn_dd = diag(A2) per axis,
+   * lagged like the rest of M1G (phi^n - phi^{n-1}; central difference of
+   * phi^{n-1}).  Recovers phi_t + div(phi u) = div(D grad phi)
+   * + dt sum_a gn_bt_a d_a d_t phi + dt sum_a gn_dd_a d_a^2 phi
+   * (K1 = dt A1, K2 = dt A2).  NCDE only; zero otherwise.  The explicit
+   * lagged d_t term limits |gn_bt| (order 1 is unstable). */
+  double gn_bt[3], gn_dd[3];
 } mrtlb_model_desc;
 
 /* Population storage in HBM (compute is FP64 for MRTLB_FP64, FP32 otherwise):

@@ -294,7 +294,12 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
     P.phi_coef = (Real)(m.D0 / K);
     P.D2 = (Real)m.D2;
   }
-  for (int a = 0; a < 3; ++a) P.adv[a] = (Real)(a < D ? m.adv_u[a] : 0.0);
+  for (int a = 0; a < 3; ++a) {
+    P.adv[a] = (Real)(a < D ? m.adv_u[a] : 0.0);
+    const bool gn = m.model == MRTLB_NCDE && a < D;
+    P.gbt[a] = (Real)(gn ? m.gn_bt[a] : 0.0);
+    P.gdd[a] = (Real)(gn ? m.gn_dd[a] : 0.0);
+  }
 }
 
 template <class Real>
@@ -479,6 +484,9 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
   if (m.model == MRTLB_CDE && D != 2) return fail(MRTLB_EINVAL, "the CDE model is built for 2D lattices");
   if (!(m.u_bound >= 0 && m.u_bound < 1e3) || !(m.dev_bound >= 0 && m.dev_bound < 1e3))
     return fail(MRTLB_EINVAL, "u_bound and dev_bound must be finite and >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(m.gn_bt[a]) || !std::isfinite(m.gn_dd[a]))
+      return fail(MRTLB_EINVAL, "gn_bt and gn_dd must be finite");
   if (L.standard) {
     if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
       return fail(MRTLB_EINVAL, "the standard lattices carry the k = 1 NSE models only");

@@ -668,7 +668,7 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   for (int a = 0; a < D; ++a) M.m1[a] += P.dm1[a];
 
   // a2: conserved variables, a5: sources
-  Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
+  Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
   Real u[3] = {0, 0, 0}, jm[3] = {0, 0, 0};
   const Real R = M.R0 + P.rho_ref;
   Real sg = 0;   // CDE: S_G = -u . grad(phi), grad(phi) = -s1 sum_j c_j f_j / cs^2
@@ -681,18 +681,24 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
     sg = P.s1 * dot / P.cs2;
   } else if constexpr (MODEL == kNcde) {
     const Real phi_prev = gload<Real>(J.phi_prev, self * (uint32_t)sizeof(Real));
-    Real adv = 0;
+    Real adv = 0, grad[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       u[a] = P.adv[a];
-      const Real grad = (gload<Real>(J.phi_prev, g.shifted(ix, a, 1) * (uint32_t)sizeof(Real)) -
-                         gload<Real>(J.phi_prev, g.shifted(ix, a, -1) * (uint32_t)sizeof(Real))) /
-                        (2 * P.c1[a]);
-      adv += u[a] * grad;
+      grad[a] = (gload<Real>(J.phi_prev, g.shifted(ix, a, 1) * (uint32_t)sizeof(Real)) -
+                 gload<Real>(J.phi_prev, g.shifted(ix, a, -1) * (uint32_t)sizeof(Real))) /
+                (2 * P.c1[a]);
+      adv += u[a] * grad[a];
     }
-    const Real scal = (R - phi_prev) + adv;
+    const Real dphi = R - phi_prev;
+    const Real scal = dphi + adv;
+    // M1G = (1 - s1/2) u scal - s1 X with X = A1 d_t(B_bar) + A2 div(D_bar)
+    // of the general NCDE (gbt = gdd = 0: the plain NCDE)
 #pragma unroll
-    for (int a = 0; a < D; ++a) src1[a] = u[a] * scal;
+    for (int a = 0; a < D; ++a) {
+      src1[a] = u[a] * scal;
+      x1[a] = P.gbt[a] * dphi + P.gdd[a] * grad[a];
+    }
     gstore<Real>(J.phi_out, self * (uint32_t)sizeof(Real), R);
   } else {
     if constexpr (FORCE) {
@@ -728,7 +734,8 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   Real d1[3], d2n[3], d2o[3], d3m[3][3], d3p[3], dxyz = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const Real ms = M.m1[a] - P.s1 * (M.m1[a] - E.e1[a]) + (Real(1) - Real(0.5) * P.s1) * src1[a];
+    Real ms = M.m1[a] - P.s1 * (M.m1[a] - E.e1[a]) + (Real(1) - Real(0.5) * P.s1) * src1[a];
+    if constexpr (MODEL == kNcde) ms -= P.s1 * x1[a];
     d1[a] = (ms - kx * M.m1[a]) * P.in1[a];
   }
   {

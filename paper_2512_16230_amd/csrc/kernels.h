@@ -60,6 +60,7 @@ struct KParams {
   Real rho0;
   Real phi_coef, D2;        // NCDE: Phi = phi_coef (phi + D2 phi^3 / 3)
   Real adv[3];              // NCDE advection velocity
+  Real gbt[3], gdd[3];      // general NCDE: A1 b_bar, diag(A2)
   // Drift correction: added to every node's zeroth and first Hermite moments
   // before the collision of one step (zero otherwise); the collision keeps
   // them, so the step moves the totals by N * dm0 and N * dm1.

@@ -243,6 +243,26 @@ def test_rd2q13_ncde(ctx, shape):
         assert max_rel(phi, phi_o) < tol
 
 
+@pytest.mark.parametrize("card,shape", [(W.Q13_SQUARE, (48, 136)), (W.Q13_SQUARE, (9, 70)), (W.Q25_RECT, (40, 72))],
+                         ids=["rD2Q13-48x136", "rD2Q13-9x70", "rD2Q25-40x72"])
+def test_general_ncde(ctx, card, shape):
+    """General NCDE: M1G gains -S1 (A1 d_t B_bar + A2 div D_bar) with
+    B_bar = phi b_bar, D_bar = phi I (eq. M-NCDE-6), nonlinear D."""
+    wl = W.ncde_hill(shape, adv_u=(0.03, -0.02), D0=0.1, D2=1.0, card=card)
+    steps = 25
+    kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u, gn_bt=(0.25, -0.15, 0.0), gn_dd=(0.03, 0.01, 0.0))
+    phi_o, _, _ = _oracle_run(card, "NCDE", wl.rates, wl.rho_or_phi, None, steps, **kw)
+    plain, _, _ = _oracle_run(card, "NCDE", wl.rates, wl.rho_or_phi, None, steps, D0=wl.D0, D2=wl.D2,
+                              adv=wl.adv_u)
+    assert max_rel(plain, phi_o) > 1e-4          # the terms matter at this size
+    for storage, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        print("case: general NCDE %s %s %s" % (card.kind, shape, storage), flush=True)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, **kw), shape, storage)
+        s.init_fields(wl.rho_or_phi)
+        s.step(steps)
+        assert max_rel(s.read_moments(with_u=False), phi_o) < tol
+
+
 @pytest.mark.parametrize("card,shape", [(W.Q53_RECT, (6, 10, 70)), (W.Q33_CUBIC, (5, 9, 66)),
                                         (W.Q45_RECT, (7, 6, 40))], ids=["rD3Q53", "rD3Q33", "rD3Q45"])
 def test_3d_comp(ctx, card, shape):
