@@ -77,6 +77,14 @@ class Model:
     # per axis (D_bar = phi I, gn_dd = diag A2)
     gn_bt: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
     gn_dd: tuple = field(default_factory=lambda: (0.0, 0.0, 0.0))
+    # NCDE source S = S_F = src_q + src_k phi (F_j with M0F = S_F, M1F = 0,
+    # eqs. M-NCDE-4, M-NCDE-5) and the scheme of eq. (2-1): False = full
+    # correction (theta = gamma = 1, shifted f_bar, eq. 2-3 with eq. 2-4-1),
+    # True = explicit three-level scheme (theta = 1, gamma = 0: unshifted f,
+    # d_t F_j by the backward difference F_j(t) - F_j(t - dt))
+    src_q: float = 0.0
+    src_k: float = 0.0
+    three_level: bool = False
 
     def rate(self, group: str) -> float:
         return {"rho": self.s0, "j": self.s1, "bulk": self.s_bulk, "shear": self.s_shear,
@@ -182,6 +190,9 @@ def macroscopic(lat: Lattice, model: Model, f: np.ndarray, force=None):
         return R0 + 0.5 * cde_source(lat, model, f, force), force, None
     if model.eq == NCDE:
         u = np.repeat(np.asarray(model.adv_u[: lat.d], dtype=np.float64)[:, None], f.shape[1], axis=1)
+        if not model.three_level:
+            # eq. 2-4-1 with S_G = 0: phi = sum f_bar + S_F / 2, S_F = q + k phi
+            R0 = (R0 + 0.5 * model.src_q) / (1 - 0.5 * model.src_k)
         return R0, u, None
     j = lat.E.T @ f
     if force is not None:
@@ -306,11 +317,21 @@ class State:
     phi_prev: np.ndarray = None   # NCDE only: phi of the previous step
 
 
-def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, ncde_x=None):
+def ncde_source_hermite(lat: Lattice, model: Model, phi):
+    """Hermite moments of the NCDE source distribution: M0F = S_F = q + k phi,
+    M1F = 0 (eq. M-NCDE-5), nothing above."""
+    mF = np.zeros((len(lat.rows), np.size(phi)))
+    mF[[r.order == 0 for r in lat.rows]] = model.src_q + model.src_k * np.ravel(phi)
+    return mF
+
+
+def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, ncde_x=None, phi_prev=None):
     """Post-collision populations f* (b, n) from pre-collision f_bar (b, n).
 
     ``ncde_b`` and ``ncde_x`` are the NCDE fields B^n and X^n (d, n) of the
-    auxiliary first moment; for the CDE ``force`` is the velocity field (d, n)."""
+    auxiliary first moment and ``phi_prev`` the previous step's phi (the
+    three-level scheme's F(t - dt)); for the CDE ``force`` is the velocity
+    field (d, n)."""
     n = f.shape[1]
     S = relaxation_matrix(lat, model)
     R0, u, rho_m = macroscopic(lat, model, f, force)
@@ -323,9 +344,14 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, 
         mG[[r.order == 0 for r in lat.rows]] = (1 - 0.5 * model.s0) * cde_source(lat, model, f, force)
         mstar = m - S @ (m - meq) + mG
         return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
-    mF = force_hermite(lat, n, force) if model.eq != NCDE else np.zeros_like(m)
+    mF = force_hermite(lat, n, force) if model.eq != NCDE else ncde_source_hermite(lat, model, R0)
     mG = aux_hermite(lat, model, S, u, force, extra=ncde_b, cross=ncde_x)
-    mstar = m - S @ (m - meq) + mG + (np.eye(len(lat.rows)) - 0.5 * S) @ mF
+    if model.eq == NCDE and model.three_level:
+        # eq. 2-1 with theta = 1, gamma = 0: f - Lambda f_ne + G + F + (F(t) - F(t - dt)) / 2
+        mFp = ncde_source_hermite(lat, model, R0 if phi_prev is None else phi_prev)
+        mstar = m - S @ (m - meq) + mG + mF + 0.5 * (mF - mFp)
+    else:
+        mstar = m - S @ (m - meq) + mG + (np.eye(len(lat.rows)) - 0.5 * S) @ mF
     return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
 
 
@@ -342,14 +368,15 @@ def stream(lat: Lattice, fstar_grid: np.ndarray) -> np.ndarray:
 def step(lat: Lattice, model: Model, st: State, force=None) -> State:
     grid = st.f.shape[1:]
     f = st.f.reshape(lat.b, -1)
-    extra = cross = None
+    extra = cross = prev = None
     phi = None
     if model.eq == NCDE:
-        phi = f.sum(axis=0).reshape(grid)
+        phi = macroscopic(lat, model, f)[0].reshape(grid)
         extra = ncde_B(lat, model, phi, st.phi_prev)
         cross = ncde_cross(lat, model, phi, st.phi_prev)
+        prev = st.phi_prev.reshape(-1)
     F = None if force is None else force.reshape(lat.d, -1)
-    fstar = collide(lat, model, f, F, extra, cross)
+    fstar = collide(lat, model, f, F, extra, cross, prev)
     return State(stream(lat, fstar.reshape(st.f.shape)), phi)
 
 
@@ -376,6 +403,9 @@ def init_state(lat: Lattice, model: Model, rho_or_phi: np.ndarray, u=None, force
         uu = np.repeat(np.asarray(model.adv_u[: lat.d], dtype=np.float64)[:, None], n, axis=1)
         meq = equilibrium_hermite(lat, model, R0, uu, None)
         f = populations_from_hermite(lat, meq)
+        if not model.three_level:
+            # f_bar = f_eq - dt F / 2 with the source distribution F
+            f = f - 0.5 * populations_from_hermite(lat, ncde_source_hermite(lat, model, R0))
         return State(f.reshape((lat.b,) + grid), rho_or_phi.astype(np.float64).copy())
     uv = u.reshape(lat.d, -1).astype(np.float64)
     rho_m = np.full(n, model.rho0) if model.eq == NSE_INC else R0

@@ -51,10 +51,14 @@ class NaiveStepper:
         fstar = np.empty_like(st.f)
         phi_grid = None
         Bfield = None
+        two_level_src = mdl.eq == M.NCDE and not mdl.three_level
         if mdl.eq == M.NCDE:
             phi_grid = np.zeros(grid)
             for x in itertools.product(*[range(n) for n in grid]):
                 phi_grid[x] = sum(st.f[(j,) + x] for j in range(b))
+                if two_level_src:
+                    # phi = sum f_bar + (q + k phi) / 2 solved for phi
+                    phi_grid[x] = (phi_grid[x] + 0.5 * mdl.src_q) / (1 - 0.5 * mdl.src_k)
             Bfield = M.ncde_B(lat, mdl, phi_grid, st.phi_prev).reshape((d,) + grid)
             Xfield = M.ncde_cross(lat, mdl, phi_grid, st.phi_prev)
             if Xfield is not None:
@@ -70,6 +74,7 @@ class NaiveStepper:
             if mdl.eq == M.NCDE:
                 u = np.asarray(mdl.adv_u[:d], dtype=np.float64)
                 rho_m = None
+                rho = phi_grid[x]
             else:
                 if F is not None:
                     mom = mom + 0.5 * F
@@ -83,7 +88,14 @@ class NaiveStepper:
                 Bx = np.array([Bfield[(a,) + x] for a in range(d)])[:, None]
                 Xx = None if Xfield is None else np.array([Xfield[(a,) + x] for a in range(d)])[:, None]
                 G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, None, extra=Bx, cross=Xx)[:, 0])
-                Fv = np.zeros(b)
+                Fv = self._velocity_space(M.ncde_source_hermite(lat, mdl, R0)[:, 0])
+                if mdl.three_level:
+                    Fp = self._velocity_space(M.ncde_source_hermite(lat, mdl, st.phi_prev[x])[:, 0])
+                    # eq. 2-1, theta = 1, gamma = 0: F + (F(t) - F(t - dt)) / 2, no (I - Lambda/2)
+                    out = f - self.Lam @ (f - feq) + G + Fv + 0.5 * (Fv - Fp)
+                    for j in range(b):
+                        fstar[(j,) + x] = out[j]
+                    continue
             else:
                 Fa = None if F is None else F[:, None]
                 G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, Fa)[:, 0])

@@ -313,3 +313,26 @@ def test_general_ncde_step_equals_brute_force():
     for _ in range(3):
         c = M.step(lat, plain, c)
     assert np.abs(a.f - c.f).max() > 1e-6
+
+
+@pytest.mark.parametrize("three_level", [False, True], ids=["full-correction", "three-level"])
+def test_ncde_source_step_equals_brute_force(three_level):
+    """NCDE with the source S = q + k phi under both schemes of eq. (2-1)
+    through the explicit b x b collision."""
+    lat = card_lattice(W.Q13_SQUARE)
+    rng = np.random.default_rng(15)
+    shape = (4, 5)
+    mdl = M.Model(eq=M.NCDE, s0=1.1, s1=1.3, s_shear=1.6, s_bulk=1.05, s3=1.4, s_h=0.9, D0=0.1, D2=1.0,
+                  adv_u=(0.03, -0.02, 0.0), gn_bt=(0.1, 0.0, 0.0), src_q=0.02, src_k=-0.05,
+                  three_level=three_level)
+    phi = 1 + 0.05 * rng.normal(size=shape)
+    st = M.init_state(lat, mdl, phi)
+    st.f = st.f + 1e-3 * rng.normal(size=st.f.shape) * lat.w[:, None, None]
+    st.phi_prev = st.phi_prev + 0.01 * rng.normal(size=shape)
+    nv = N.NaiveStepper(lat, mdl)
+    a = st
+    b = M.State(st.f.copy(), st.phi_prev.copy())
+    for _ in range(3):
+        a = M.step(lat, mdl, a)
+        b = nv.step(b)
+    assert np.abs(a.f - b.f).max() < 1e-13

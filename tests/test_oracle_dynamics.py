@@ -11,7 +11,12 @@
   * general NCDE (eqs. M-NCDE-6, GNCDE) with B_bar = phi b_bar and
     D_bar = phi I: the complex rate of a Fourier mode equals the dispersion
     relation of d_t phi + u . grad phi = D0 lap phi + dt (A1 b_bar . grad) d_t phi
-    + dt sum_a A2_aa d_a^2 phi, i.e. K1 = dt A1 and K2 = dt A2.
+    + dt sum_a A2_aa d_a^2 phi, i.e. K1 = dt A1 and K2 = dt A2;
+  * NCDE source S = q + k phi under the two schemes of eq. (2-1): on a
+    uniform field the full-correction scheme is exactly the trapezoidal rule
+    (closed form) and the explicit three-level scheme is a different
+    second-order scheme (Adams-Bashforth 2 after an Euler start: error of
+    opposite sign and larger); a Fourier mode gains the rate k.
 """
 
 import numpy as np
@@ -255,3 +260,58 @@ def test_general_ncde_fourier_mode(bt, dd, u):
     # the two parts by 5% or more
     off = max(abs(rate.real / printed.real - 1), abs(rate.imag - printed.imag) / (abs(printed.imag) + 1e-12))
     assert off > 0.05
+
+
+def _uniform_source_run(q, k, steps, three_level, phi0=1.0):
+    card = W.Q13_SQUARE
+    lat = L.make_lattice(card.kind, card.c, card.cs2, card.free)
+    mdl = M.Model(eq=M.NCDE, s0=1.2, s1=1.4, s_shear=1.3, s_bulk=1.1, s3=1.2, s_h=1.2, D0=0.05, D2=0.5,
+                  adv_u=(0.02, -0.01, 0.0), src_q=q, src_k=k, three_level=three_level)
+    st = M.init_state(lat, mdl, np.full((3, 4), phi0))
+    st = M.run(lat, mdl, st, steps)
+    phi, _ = M.moments(lat, mdl, st)
+    assert np.ptp(phi) < 1e-13
+    return float(phi.mean())
+
+
+def test_source_full_correction_is_the_trapezoidal_rule():
+    q, k, n = 0.01, -0.03, 150
+    r = (1 + k / 2) / (1 - k / 2)
+    closed = (1.0 + q / k) * r ** n - q / k
+    assert abs(_uniform_source_run(q, k, n, False) - closed) < 1e-13
+
+
+def test_source_three_level_scheme_is_second_order():
+    def errors(q, k, n):
+        exact = (1.0 + q / k) * np.exp(k * n) - q / k
+        return _uniform_source_run(q, k, n, True) - exact, _uniform_source_run(q, k, n, False) - exact
+
+    e3a, e2a = errors(0.02, -0.04, 50)
+    e3b, e2b = errors(0.01, -0.02, 100)       # same k t, half the step
+    assert 3.6 < e3a / e3b < 4.4 and 3.6 < e2a / e2b < 4.4
+    # a different second-order scheme: opposite sign, larger constant
+    assert e3b / e2b < -1.5
+
+
+@pytest.mark.parametrize("three_level", [False, True], ids=["full-correction", "three-level"])
+def test_source_adds_its_rate_to_a_fourier_mode(three_level):
+    card = W.Q13_SQUARE
+    lat = L.make_lattice(card.kind, card.c, card.cs2, card.free)
+    n, steps, kap = 48, 300, -0.004
+    shape = (n, n)
+    kv = 2 * np.pi / (n * card.c[0])
+    ph = kv * W.axis_coords(card, shape, 0) * np.ones(shape)
+
+    def rate(k):
+        mdl = M.Model(eq=M.NCDE, s0=1.2, s1=1.4, s_shear=1.3, s_bulk=1.1, s3=1.2, s_h=1.2, D0=0.05,
+                      adv_u=(0.02, -0.01, 0.0), src_k=k, three_level=three_level)
+        st = M.init_state(lat, mdl, 1e-3 * np.cos(ph))
+        amp = []
+        for _ in range(steps):
+            amp.append(abs((M.moments(lat, mdl, st)[0] * np.exp(-1j * ph)).mean()))
+            st = M.step(lat, mdl, st)
+        return np.polyfit(np.arange(100, steps), np.log(amp[100:]), 1)[0]
+
+    plain = rate(0.0)
+    assert abs(plain / (-0.05 * kv * kv) - 1) < 0.01
+    assert abs(rate(kap) - plain - kap) < 0.01 * abs(kap)
