@@ -203,6 +203,18 @@ typedef struct {
    * (K1 = dt A1, K2 = dt A2).  NCDE only; zero otherwise.  The explicit
    * lagged d_t term limits |gn_bt| (order 1 is unstable). */
   double gn_bt[3], gn_dd[3];
+  /* NCDE source S = src_q + src_k phi (F_j with M0F = S, M1F = 0, eqs.
+   * M-NCDE-4, M-NCDE-5; |src_k| < 1) and the scheme of eq. (2-1):
+   * three_level = 0: full correction (theta = gamma = 1, shifted f_bar,
+   *   phi = sum f_bar + S/2 (eq. 2-4-1), solved for phi; the initial state
+   *   is f_eq - w S/2);
+   * three_level = 1: explicit three-level scheme (theta = 1, gamma = 0,
+   *   unshifted f, phi = sum f, F + (F(t) - F(t - dt))/2 with F(t - dt)
+   *   from the stored phi^{n-1}; initial state f_eq).
+   * read_moments and conserved report phi of the chosen scheme.  Other
+   * models: all zero. */
+  double src_q, src_k;
+  int three_level;
 } mrtlb_model_desc;
 
 /* Population storage in HBM (compute is FP64 for MRTLB_FP64, FP32 otherwise):
@@ -280,12 +292,14 @@ mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every);
 mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* nsteps);
 
 /* rho_or_phi (N) and u (d*N, may be NULL) at the current time, eq. (2-4-2)
- * / (2-4-1): rho_bar = sum f_bar, u = (sum c f_bar + F/2)/rho_m.
+ * / (2-4-1): rho_bar = sum f_bar, u = (sum c f_bar + F/2)/rho_m; NCDE
+ * phi = sum f_bar + S/2 (full correction) or sum f (three-level scheme).
  * Synchronous. */
 mrtlb_status mrtlb_read_moments(mrtlb_solve* s, double* rho_or_phi, double* u);
 
 /* Domain totals in FP64 with a fixed reduction order: mass = sum rho_bar
- * (or phi), momentum[d] = sum (sum c f_bar + F/2).  Returns ENUMERIC if a
+ * (or sum phi, phi as read_moments gives it), momentum[d] =
+ * sum (sum c f_bar + F/2).  Returns ENUMERIC if a
  * stored value is not finite.  Synchronous. */
 mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum);
 

@@ -294,6 +294,18 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
     P.phi_coef = (Real)(m.D0 / K);
     P.D2 = (Real)m.D2;
   }
+  if (m.model == MRTLB_NCDE) {
+    const bool three = m.three_level != 0;
+    P.sq = (Real)m.src_q;
+    P.sk = (Real)m.src_k;
+    P.sqh = (Real)(three ? 0.0 : 0.5 * m.src_q);
+    P.sci = (Real)(three ? 1.0 : 1.0 / (1.0 - 0.5 * m.src_k));
+    P.sa = (Real)(three ? 1.5 : 1.0);
+    P.sp = (Real)(three ? -0.5 : 0.0);
+    P.sinit = (Real)(three ? 0.0 : 0.5);
+  } else {
+    P.sci = (Real)1;
+  }
   for (int a = 0; a < 3; ++a) {
     P.adv[a] = (Real)(a < D ? m.adv_u[a] : 0.0);
     const bool gn = m.model == MRTLB_NCDE && a < D;
@@ -487,6 +499,10 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(m.gn_bt[a]) || !std::isfinite(m.gn_dd[a]))
       return fail(MRTLB_EINVAL, "gn_bt and gn_dd must be finite");
+  if (!std::isfinite(m.src_q) || !std::isfinite(m.src_k) || !(std::fabs(m.src_k) < 1.0))
+    return fail(MRTLB_EINVAL, "src_q must be finite and |src_k| < 1");
+  if ((m.src_q != 0 || m.src_k != 0 || m.three_level != 0) && m.model != MRTLB_NCDE)
+    return fail(MRTLB_EINVAL, "the source and the three-level scheme belong to the NCDE model");
   if (L.standard) {
     if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
       return fail(MRTLB_EINVAL, "the standard lattices carry the k = 1 NSE models only");
@@ -666,6 +682,8 @@ static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
     for (int a = 0; a < D; ++a) mom[a] += s->L.c[a] * s->L.e[j * D + a] * plane[j];
   }
   m += ref * (double)s->N;
+  if (s->model.model == MRTLB_NCDE && s->model.three_level == 0 && (s->model.src_q != 0 || s->model.src_k != 0))
+    m = (m + 0.5 * s->model.src_q * (double)s->N) / (1.0 - 0.5 * s->model.src_k);   // phi = sum f_bar + S/2
   for (int a = 0; a < nf; ++a) mom[a] += 0.5 * plane[B + a];
   bool finite = std::isfinite(m);
   for (int a = 0; a < D; ++a) finite = finite && std::isfinite(mom[a]);
@@ -730,6 +748,8 @@ mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every) {
   if (every < 0) return fail(MRTLB_EINVAL, "every must be >= 0");
   if (every > 0 && s->model.model == MRTLB_CDE)
     return fail(MRTLB_EINVAL, "the CDE does not conserve its total (S_G = -u . grad phi)");
+  if (every > 0 && s->model.model == MRTLB_NCDE && (s->model.src_q != 0 || s->model.src_k != 0))
+    return fail(MRTLB_EINVAL, "an NCDE with a source does not conserve its total");
   HIP_TRY(hipSetDevice(s->ctx->device));
   s->drift_every = every;
   return record_reference(s);

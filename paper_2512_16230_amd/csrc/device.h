@@ -670,7 +670,9 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   // a2: conserved variables, a5: sources
   Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
   Real u[3] = {0, 0, 0}, jm[3] = {0, 0, 0};
-  const Real R = M.R0 + P.rho_ref;
+  // NCDE: phi from the sum and the source correction (eq. 2-4-1)
+  const Real R = MODEL == kNcde ? (M.R0 + P.sqh) * P.sci : M.R0 + P.rho_ref;
+  Real src0 = 0;   // NCDE source increment of the zeroth moment
   Real sg = 0;   // CDE: S_G = -u . grad(phi), grad(phi) = -s1 sum_j c_j f_j / cs^2
   if constexpr (MODEL == kCde) {
     const char* vel = static_cast<const char*>(static_cast<const void*>(J.force));
@@ -692,6 +694,7 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
     }
     const Real dphi = R - phi_prev;
     const Real scal = dphi + adv;
+    src0 = P.sa * (P.sq + P.sk * R) + P.sp * (P.sq + P.sk * phi_prev);
     // M1G = (1 - s1/2) u scal - s1 X with X = A1 d_t(B_bar) + A2 div(D_bar)
     // of the general NCDE (gbt = gdd = 0: the plain NCDE)
 #pragma unroll
@@ -793,7 +796,7 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   }
   // order 0 is conserved, m*_0 = m_0, except for the CDE source:
   // m*_0 = m_0 + M0G + s0 S_G / 2 = m_0 + S_G (M0G = (1 - s0/2) S_G)
-  const Real d0 = (P.sh * M.R0 + sg) * P.in0;
+  const Real d0 = (P.sh * M.R0 + sg + src0) * P.in0;
 
   // a7: back to populations (output numbers of the storage)
   backward<L>(x, P, kx * P.kin, P.wo, d0, d1, d2n, d2o, d3m, d3p, dxyz);
@@ -957,7 +960,9 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   if constexpr (D == 3) dxyz = E.exyz * P.inxyz;
   double x[B];
   for (int j = 0; j < B; ++j) x[j] = 0;
-  const double d0 = R * P.in0 - P.rho_ref;
+  // NCDE, full correction: f_bar = f_eq - w S(phi0) / 2
+  const double r0 = MODEL == kNcde ? R - P.sinit * (P.sq + P.sk * R) : R;
+  const double d0 = r0 * P.in0 - P.rho_ref;
   backward<L>(x, P, 0.0, P.w, d0, d1, d2n, d2o, d3m, d3p, dxyz);
   const KParams<Real>& PR = J.P;
   static_for<0, B>([&](auto jj) {
@@ -1009,7 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const Job<typename StoreT<ST>
         for (int a = 0; a < D; ++a) out1[(size_t)a * N + self] = (double)J.force[(size_t)a * N + self];
       return;
     }
-    out0[self] = R;
+    out0[self] = MODEL == kNcde ? (R + P.sqh) * P.sci : R;
     if (out1) {
       if constexpr (MODEL == kNcde) {
         for (int a = 0; a < D; ++a) out1[(size_t)a * N + self] = P.adv[a];

@@ -61,6 +61,12 @@ struct KParams {
   Real phi_coef, D2;        // NCDE: Phi = phi_coef (phi + D2 phi^3 / 3)
   Real adv[3];              // NCDE advection velocity
   Real gbt[3], gdd[3];      // general NCDE: A1 b_bar, diag(A2)
+  // NCDE source S = sq + sk phi.  phi = (sum f + sqh) * sci; the zeroth
+  // moment gains sa S(phi^n) + sp S(phi^{n-1}); the initial f_bar is
+  // f_eq - sinit w S(phi0).  Full correction: sqh = sq/2, sci = 1/(1 - sk/2),
+  // (sa, sp) = (1, 0), sinit = 1/2; three-level: sqh = 0, sci = 1,
+  // (sa, sp) = (3/2, -1/2), sinit = 0.  No source: all terms vanish.
+  Real sq, sk, sqh, sci, sa, sp, sinit;
   // Drift correction: added to every node's zeroth and first Hermite moments
   // before the collision of one step (zero otherwise); the collision keeps
   // them, so the step moves the totals by N * dm0 and N * dm1.

@@ -263,6 +263,38 @@ def test_general_ncde(ctx, card, shape):
         assert max_rel(s.read_moments(with_u=False), phi_o) < tol
 
 
+@pytest.mark.parametrize("three_level", [False, True], ids=["full-correction", "three-level"])
+@pytest.mark.parametrize("shape", [(48, 136), (9, 70)])
+def test_ncde_source(ctx, three_level, shape):
+    """NCDE with the source S = q + k phi under the full-correction and the
+    explicit three-level schemes of eq. (2-1), with the general-NCDE terms."""
+    card = W.Q13_SQUARE
+    wl = W.ncde_hill(shape, adv_u=(0.03, -0.02), D0=0.1, D2=1.0)
+    steps = 25
+    kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u, gn_bt=(0.1, 0.05, 0.0), src_q=0.002, src_k=-0.01,
+              three_level=three_level)
+    lat, mdl = oracle_for(card, "NCDE", wl.rates, **kw)
+    st = OM.run(lat, mdl, OM.init_state(lat, mdl, wl.rho_or_phi), steps)
+    phi_o = OM.moments(lat, mdl, st)[0]
+    for storage, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        print("case: NCDE source three_level=%s %s %s" % (three_level, shape, storage), flush=True)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, **kw), shape, storage)
+        s.init_fields(wl.rho_or_phi)
+        s.step(steps)
+        phi = s.read_moments(with_u=False)
+        assert max_rel(phi, phi_o) < tol
+        mass, _ = s.conserved()
+        assert abs(mass - phi_o.sum()) < 1e-9 * abs(phi_o.sum())
+        with pytest.raises(H.MrtlbError):
+            s.set_drift_correction(10)
+
+
+def test_source_belongs_to_the_ncde(ctx):
+    with pytest.raises(H.MrtlbError) as e:
+        H.Solve(ctx, hip_lattice(W.Q25_RECT), hip_model("NSE_COMP", W.Rates(), src_q=0.01), (16, 16), "fp32")
+    assert e.value.status == H.MRTLB_EINVAL
+
+
 @pytest.mark.parametrize("card,shape", [(W.Q53_RECT, (6, 10, 70)), (W.Q33_CUBIC, (5, 9, 66)),
                                         (W.Q45_RECT, (7, 6, 40))], ids=["rD3Q53", "rD3Q33", "rD3Q45"])
 def test_3d_comp(ctx, card, shape):
