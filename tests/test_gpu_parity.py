@@ -284,7 +284,7 @@ def test_ncde_source(ctx, three_level, shape):
         phi = s.read_moments(with_u=False)
         assert max_rel(phi, phi_o) < tol
         mass, _ = s.conserved()
-        assert abs(mass - phi_o.sum()) < 1e-9 * abs(phi_o.sum())
+        assert abs(mass - phi_o.sum()) < tol * abs(phi_o.sum())
         with pytest.raises(H.MrtlbError):
             s.set_drift_correction(10)
 
