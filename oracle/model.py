@@ -85,6 +85,8 @@ class Model:
     src_q: float = 0.0
     src_k: float = 0.0
     three_level: bool = False
+    # NSE_COMP uniform mass source S (M0F = S, eq. M-NSEs-5 with S_G = 0)
+    mass_src: float = 0.0
 
     def rate(self, group: str) -> float:
         return {"rho": self.s0, "j": self.s1, "bulk": self.s_bulk, "shear": self.s_shear,
@@ -197,6 +199,9 @@ def macroscopic(lat: Lattice, model: Model, f: np.ndarray, force=None):
     j = lat.E.T @ f
     if force is not None:
         j = j + 0.5 * force
+    if model.mass_src:
+        # eq. 2-4-2 with S_G = 0: rho = sum f_bar + S_F / 2
+        R0 = R0 + 0.5 * model.mass_src
     rho_m = np.full_like(R0, model.rho0) if model.eq == NSE_INC else R0
     return R0, j / rho_m, rho_m
 
@@ -226,12 +231,14 @@ def equilibrium_hermite(lat, model, R0, u, rho_m):
     return hermite_from_raw(lat, M, max_order=2 if model.eq == NCDE else 3)
 
 
-def force_hermite(lat, n, force):
-    """Hermite moments of the force distribution F_j: M0F = 0, M1F = F, M2F = 0."""
+def force_hermite(lat, n, force, mass_src=0.0):
+    """Hermite moments of the source distribution F_j: M0F = S (mass
+    source), M1F = F, M2F = 0 (raw moments, eq. M-NSEs-5)."""
     d = lat.d
-    if force is None:
+    if force is None and not mass_src:
         return np.zeros((len(lat.rows), n))
-    M = [np.zeros(n), force, np.zeros((d, d, n)), None]
+    F = np.zeros((d, n)) if force is None else force
+    M = [np.full(n, float(mass_src)), F, np.zeros((d, d, n)), None]
     return hermite_from_raw(lat, M, max_order=2)
 
 
@@ -254,9 +261,15 @@ def aux_hermite(lat, model, S, u, force, extra=None, cross=None):
         if cross is not None:
             out -= S @ hermite_from_raw(lat, [np.zeros(n), cross, None, None], max_order=1)
         return out
-    if force is None:
+    if force is None and not model.mass_src:
         return np.zeros((len(lat.rows), n))
-    T = np.einsum("an,bn->abn", u, force) + np.einsum("an,bn->abn", force, u)
+    T = np.zeros((d, d, n))
+    if force is not None:
+        T = np.einsum("an,bn->abn", u, force) + np.einsum("an,bn->abn", force, u)
+    if model.mass_src:
+        # (cs^2 I - uu) S: eq. M2G-1 with S_bar = S, where the isothermal
+        # d_t p I + div(p u I) = cs^2 (d_t rho + div(rho u)) I = cs^2 S I
+        T = T + model.mass_src * (lat.cs2 * np.eye(d)[:, :, None] - np.einsum("an,bn->abn", u, u))
     M = [np.zeros(n), np.zeros((d, n)), T, None]
     mg = hermite_from_raw(lat, M, max_order=2)
     mg[[r.order != 2 for r in lat.rows]] = 0.0
@@ -344,7 +357,7 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, 
         mG[[r.order == 0 for r in lat.rows]] = (1 - 0.5 * model.s0) * cde_source(lat, model, f, force)
         mstar = m - S @ (m - meq) + mG
         return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
-    mF = force_hermite(lat, n, force) if model.eq != NCDE else ncde_source_hermite(lat, model, R0)
+    mF = force_hermite(lat, n, force, model.mass_src) if model.eq != NCDE else ncde_source_hermite(lat, model, R0)
     mG = aux_hermite(lat, model, S, u, force, extra=ncde_b, cross=ncde_x)
     if model.eq == NCDE and model.three_level:
         # eq. 2-1 with theta = 1, gamma = 0: f - Lambda f_ne + G + F + (F(t) - F(t - dt)) / 2
@@ -411,8 +424,9 @@ def init_state(lat: Lattice, model: Model, rho_or_phi: np.ndarray, u=None, force
     rho_m = np.full(n, model.rho0) if model.eq == NSE_INC else R0
     meq = equilibrium_hermite(lat, model, R0, uv, rho_m)
     f = populations_from_hermite(lat, meq)
-    if force is not None:
-        f = f - 0.5 * populations_from_hermite(lat, force_hermite(lat, n, force.reshape(lat.d, -1)))
+    if force is not None or model.mass_src:
+        F = None if force is None else force.reshape(lat.d, -1)
+        f = f - 0.5 * populations_from_hermite(lat, force_hermite(lat, n, F, model.mass_src))
     return State(f.reshape((lat.b,) + grid), None)
 
 
@@ -427,7 +441,7 @@ def moments(lat: Lattice, model: Model, st: State, force=None):
 
 def conserved(lat: Lattice, model: Model, st: State, force=None):
     f = st.f.reshape(lat.b, -1)
-    mass = f.sum()
+    mass = f.sum() + 0.5 * model.mass_src * f.shape[1]
     mom = lat.E.T @ f.sum(axis=1)
     if force is not None:
         mom = mom + 0.5 * force.reshape(lat.d, -1).sum(axis=1)

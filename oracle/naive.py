@@ -78,6 +78,7 @@ class NaiveStepper:
             else:
                 if F is not None:
                     mom = mom + 0.5 * F
+                rho = rho + 0.5 * mdl.mass_src      # rho = sum f_bar + S / 2
                 rho_m = mdl.rho0 if mdl.eq == M.NSE_INC else rho
                 u = mom / rho_m
             R0 = np.array([rho])
@@ -99,7 +100,8 @@ class NaiveStepper:
             else:
                 Fa = None if F is None else F[:, None]
                 G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, Fa)[:, 0])
-                Fv = np.zeros(b) if F is None else self._velocity_space(M.force_hermite(lat, 1, Fa)[:, 0])
+                Fv = (np.zeros(b) if F is None and not mdl.mass_src
+                      else self._velocity_space(M.force_hermite(lat, 1, Fa, mdl.mass_src)[:, 0]))
             out = f - self.Lam @ (f - feq) + G + (np.eye(b) - 0.5 * self.Lam) @ Fv
             for j in range(b):
                 fstar[(j,) + x] = out[j]

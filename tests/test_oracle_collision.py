@@ -336,3 +336,89 @@ def test_ncde_source_step_equals_brute_force(three_level):
         a = M.step(lat, mdl, a)
         b = nv.step(b)
     assert np.abs(a.f - b.f).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# NSE mass source (compressible): M0F = S, rho = sum f_bar + S/2,
+# M2G = (I - S2/2)[uF + Fu + (cs^2 I - uu) S]
+# --------------------------------------------------------------------------
+
+def _uniform_mass_source(card, S, steps, u0=(0.05, -0.03, 0.02)):
+    lat = card_lattice(card)
+    d = lat.d
+    mdl = M.Model(eq=M.NSE_COMP, s_shear=1.4, s_bulk=1.1, s3=1.3, s_h=1.2, mass_src=S,
+                  m30=card.kind not in L.STANDARD)
+    shape = (3,) * d
+    rho0 = 1.05
+    u = np.stack([np.full(shape, u0[a]) for a in range(d)])
+    st = M.init_state(lat, mdl, np.full(shape, rho0), u)
+    for _ in range(steps):
+        st = M.step(lat, mdl, st)
+    rho, uu = M.moments(lat, mdl, st)
+    return lat, mdl, st, rho0, np.asarray(u0[:d]), rho, uu
+
+
+def _stress_residual(lat, st, rho, u, S):
+    """M2_ne + X/2 at one node, X = (cs^2 I - uu) S.  The recovered stress
+    (I - S2/2) M2_ne + M2G/2 with M2G = (I - S2/2) X (eqs. 4-5 ff., M2G-1)
+    vanishes in a uniform state exactly when this residual does."""
+    d = lat.d
+    f = st.f.reshape(lat.b, -1)[:, 0]
+    r = float(rho.reshape(-1)[0])
+    v = u.reshape(d, -1)[:, 0]
+    M2 = np.einsum("j,ja,jb->ab", f, lat.E, lat.E)        # raw; M2F = 0, so f and f_bar agree
+    M2eq = r * np.outer(v, v) + lat.cs2 * r * np.eye(d)
+    X = (lat.cs2 * np.eye(d) - np.outer(v, v)) * S
+    return np.abs(M2 - M2eq + 0.5 * X).max()
+
+
+@pytest.mark.parametrize("card", [W.Q25_RECT, W.Q53_RECT, W.Q9_RECT], ids=lambda c: c.kind)
+def test_mass_source_uniform_state(card):
+    """rho grows by S per step and rho u stays constant (the injected mass
+    carries no momentum), exactly; once the start-up transient has relaxed,
+    the recovered viscous stress of the uniform state is zero (to rounding)."""
+    S, n = 2e-4, 60
+    lat, mdl, st, rho0, u0, rho, u = _uniform_mass_source(card, S, n)
+    assert np.abs(rho - (rho0 + S * n)).max() < 1e-13
+    assert np.abs(rho * u - (rho0 * u0).reshape((-1,) + (1,) * lat.d)).max() < 1e-13
+    assert _stress_residual(lat, st, rho, u, S) < 1e-12
+
+
+def test_mass_source_planted_m2g_mistake_leaves_a_stress(monkeypatch):
+    """Without the (cs^2 I - uu) S part of M2G the uniform state keeps an
+    O(S) viscous stress."""
+    S, n = 2e-4, 60
+    orig = M.aux_hermite
+
+    def no_mass_term(lat, model, Sm, u, force, extra=None, cross=None):
+        plain = M.Model(**{**model.__dict__, "mass_src": 0.0})
+        return orig(lat, plain, Sm, u, force, extra, cross)
+
+    monkeypatch.setattr(M, "aux_hermite", no_mass_term)
+    lat, mdl, st, rho0, u0, rho, u = _uniform_mass_source(W.Q25_RECT, S, n)
+    assert _stress_residual(lat, st, rho, u, S) > 0.1 * S
+
+
+@pytest.mark.parametrize("card,shape", [(W.Q25_RECT, (4, 3)), (W.Q53_RECT, (2, 3, 2)), (W.Q9_RECT, (3, 5))],
+                         ids=lambda v: getattr(v, "kind", str(v)))
+def test_mass_source_step_equals_brute_force(card, shape):
+    lat = card_lattice(card)
+    rng = np.random.default_rng(16)
+    d = lat.d
+    mdl = M.Model(eq=M.NSE_COMP, s0=1.1, s1=1.15, s_shear=1.6, s_bulk=1.05, s3=1.4, s_h=0.9,
+                  m30=card.kind not in L.STANDARD, mass_src=3e-4)
+    rho = 1 + 0.05 * rng.normal(size=shape)
+    u = 0.05 * rng.normal(size=(d,) + shape)
+    F = 1e-3 * rng.normal(size=(d,) + shape)
+    st = M.init_state(lat, mdl, rho, u, F)
+    st.f = st.f + 1e-3 * rng.normal(size=st.f.shape) * lat.w.reshape((-1,) + (1,) * len(shape))
+    nv = N.NaiveStepper(lat, mdl)
+    a = st
+    b = M.State(st.f.copy())
+    m_a = M.conserved(lat, mdl, a, F)[0]
+    for _ in range(3):
+        a = M.step(lat, mdl, a, F)
+        b = nv.step(b, F)
+    assert np.abs(a.f - b.f).max() < 1e-13
+    # the total grows by N S per step
+    assert abs(M.conserved(lat, mdl, a, F)[0] - m_a - 3 * 3e-4 * np.prod(shape)) < 1e-12
