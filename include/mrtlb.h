@@ -215,6 +215,13 @@ typedef struct {
    * models: all zero. */
   double src_q, src_k;
   int three_level;
+  /* MRTLB_NSE_COMP uniform mass source S (M0F = S, M1F = F, M2F = 0,
+   * eq. M-NSEs-5 with S_G = 0): rho = sum f_bar + S/2 (eq. 2-4-2) and
+   * M2G = (I - S2/2)[uF + Fu + (cs^2 I - uu) S] (eq. M2G-1 with S_bar = S;
+   * for isothermal p, d_t p I + div(p u I) = cs^2 S I).  The initial state
+   * is f_eq - F/2.  Runs in the forced kernel: the solve needs has_force
+   * (a zero force field is fine); EINVAL otherwise and for other models. */
+  double mass_src;
 } mrtlb_model_desc;
 
 /* Population storage in HBM (compute is FP64 for MRTLB_FP64, FP32 otherwise):

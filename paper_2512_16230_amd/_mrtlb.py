@@ -51,7 +51,7 @@ class mrtlb_model_desc(ctypes.Structure):
                 ("s_bulk", c_double), ("s3", c_double), ("s_high", c_double), ("m30", c_int), ("D0", c_double),
                 ("D2", c_double), ("adv_u", c_double * 3), ("u_bound", c_double), ("dev_bound", c_double),
                 ("gn_bt", c_double * 3), ("gn_dd", c_double * 3), ("src_q", c_double), ("src_k", c_double),
-                ("three_level", c_int)]
+                ("three_level", c_int), ("mass_src", c_double)]
 
 
 _lib = None
@@ -216,12 +216,13 @@ class Lattice:
 
 def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s_high=1.2, m30=True, D0=0.0,
                D2=0.0, adv_u=(0.0, 0.0, 0.0), u_bound=0.0, dev_bound=0.0, gn_bt=(0.0, 0.0, 0.0),
-               gn_dd=(0.0, 0.0, 0.0), src_q=0.0, src_k=0.0, three_level=False):
+               gn_dd=(0.0, 0.0, 0.0), src_q=0.0, src_k=0.0, three_level=False, mass_src=0.0):
     """Model parameters; u_bound / dev_bound size the int16 storage's ranges
     (max |u| and max |rho - rho0| / rho0, or max |phi| for the NCDE);
     gn_bt / gn_dd are the general-NCDE coefficients A1 b_bar and diag(A2);
     src_q + src_k phi is the NCDE source, three_level selects the explicit
-    three-level scheme instead of full correction."""
+    three-level scheme instead of full correction; mass_src is the
+    compressible NSE's uniform mass source (the solve needs has_force)."""
     m = mrtlb_model_desc()
     m.model = MODELS[eq] if isinstance(eq, str) else int(eq)
     m.rho0, m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high = rho0, s0, s1, s_shear, s_bulk, s3, s_high
@@ -235,6 +236,7 @@ def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s
         m.gn_dd[a] = float(gn_dd[a]) if a < len(gn_dd) else 0.0
     m.src_q, m.src_k = float(src_q), float(src_k)
     m.three_level = 1 if three_level else 0
+    m.mass_src = float(mass_src)
     return m
 
 

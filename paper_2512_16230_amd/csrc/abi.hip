@@ -306,6 +306,8 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   } else {
     P.sci = (Real)1;
   }
+  P.msrc = (Real)(m.model == MRTLB_NSE_COMP ? m.mass_src : 0.0);
+  P.msh = (Real)(m.model == MRTLB_NSE_COMP ? 0.5 * m.mass_src : 0.0);
   for (int a = 0; a < 3; ++a) {
     P.adv[a] = (Real)(a < D ? m.adv_u[a] : 0.0);
     const bool gn = m.model == MRTLB_NCDE && a < D;
@@ -503,6 +505,9 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
     return fail(MRTLB_EINVAL, "src_q must be finite and |src_k| < 1");
   if ((m.src_q != 0 || m.src_k != 0 || m.three_level != 0) && m.model != MRTLB_NCDE)
     return fail(MRTLB_EINVAL, "the source and the three-level scheme belong to the NCDE model");
+  if (!std::isfinite(m.mass_src)) return fail(MRTLB_EINVAL, "mass_src must be finite");
+  if (m.mass_src != 0 && m.model != MRTLB_NSE_COMP)
+    return fail(MRTLB_EINVAL, "the mass source belongs to the compressible NSE model");
   if (L.standard) {
     if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
       return fail(MRTLB_EINVAL, "the standard lattices carry the k = 1 NSE models only");
@@ -560,6 +565,9 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   if (st != MRTLB_OK) return st;
   if (has_force && (model->model == MRTLB_NCDE || model->model == MRTLB_CDE))
     return fail(MRTLB_EINVAL, "the NCDE and CDE models take no force field");
+  if (model->mass_src != 0 && !has_force)
+    return fail(MRTLB_EINVAL, "a mass source runs in the forced kernel: create the solve with has_force "
+                              "(a zero force field is fine)");
   size_t bytes = 0;
   st = mrtlb_solve_footprint(lat, n, storage, model->model, has_force, &bytes);
   if (st != MRTLB_OK) return st;
@@ -684,6 +692,7 @@ static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
   m += ref * (double)s->N;
   if (s->model.model == MRTLB_NCDE && s->model.three_level == 0 && (s->model.src_q != 0 || s->model.src_k != 0))
     m = (m + 0.5 * s->model.src_q * (double)s->N) / (1.0 - 0.5 * s->model.src_k);   // phi = sum f_bar + S/2
+  if (s->model.model == MRTLB_NSE_COMP) m += 0.5 * s->model.mass_src * (double)s->N;  // rho = sum f_bar + S/2
   for (int a = 0; a < nf; ++a) mom[a] += 0.5 * plane[B + a];
   bool finite = std::isfinite(m);
   for (int a = 0; a < D; ++a) finite = finite && std::isfinite(mom[a]);
@@ -750,6 +759,7 @@ mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every) {
     return fail(MRTLB_EINVAL, "the CDE does not conserve its total (S_G = -u . grad phi)");
   if (every > 0 && s->model.model == MRTLB_NCDE && (s->model.src_q != 0 || s->model.src_k != 0))
     return fail(MRTLB_EINVAL, "an NCDE with a source does not conserve its total");
+  if (every > 0 && s->model.mass_src != 0) return fail(MRTLB_EINVAL, "a mass source does not conserve the mass");
   HIP_TRY(hipSetDevice(s->ctx->device));
   s->drift_every = every;
   return record_reference(s);

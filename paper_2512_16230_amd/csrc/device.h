@@ -671,8 +671,8 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
   Real u[3] = {0, 0, 0}, jm[3] = {0, 0, 0};
   // NCDE: phi from the sum and the source correction (eq. 2-4-1)
-  const Real R = MODEL == kNcde ? (M.R0 + P.sqh) * P.sci : M.R0 + P.rho_ref;
-  Real src0 = 0;   // NCDE source increment of the zeroth moment
+  const Real R = MODEL == kNcde ? (M.R0 + P.sqh) * P.sci : (FORCE ? M.R0 + P.rho_ref + P.msh : M.R0 + P.rho_ref);
+  Real src0 = 0;   // source increment of the zeroth moment (NCDE source, NSE mass source)
   Real sg = 0;   // CDE: S_G = -u . grad(phi), grad(phi) = -s1 sum_j c_j f_j / cs^2
   if constexpr (MODEL == kCde) {
     const char* vel = static_cast<const char*>(static_cast<const void*>(J.force));
@@ -719,12 +719,15 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
       src1[a] = F[a];
     }
     if constexpr (FORCE) {
+      // uF + Fu, and for a mass source (cs^2 I - uu) S of M2G together with
+      // the -cs^2 S I Hermite part of the source distribution (M0F = S): -uu S
 #pragma unroll
-      for (int a = 0; a < D; ++a) T2n[a] = 2 * u[a] * F[a];
+      for (int a = 0; a < D; ++a) T2n[a] = 2 * u[a] * F[a] - P.msrc * u[a] * u[a];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = a + 1; b < D; ++b) T2o[off_index(a, b)] = u[a] * F[b] + u[b] * F[a];
+        for (int b = a + 1; b < D; ++b) T2o[off_index(a, b)] = u[a] * F[b] + u[b] * F[a] - P.msrc * u[a] * u[b];
+      src0 = P.msrc;
     }
   }
 
@@ -961,7 +964,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   double x[B];
   for (int j = 0; j < B; ++j) x[j] = 0;
   // NCDE, full correction: f_bar = f_eq - w S(phi0) / 2
-  const double r0 = MODEL == kNcde ? R - P.sinit * (P.sq + P.sk * R) : R;
+  // NSE mass source: f_bar = f_eq - F/2 with M0F = S (Hermite second order -cs^2 S)
+  const double r0 = MODEL == kNcde ? R - P.sinit * (P.sq + P.sk * R) : R - P.msh;
+  if constexpr (MODEL != kNcde && MODEL != kCde)
+    for (int a = 0; a < D; ++a) d2n[a] += P.msh * P.cs2 * P.in2n[a];
   const double d0 = r0 * P.in0 - P.rho_ref;
   backward<L>(x, P, 0.0, P.w, d0, d1, d2n, d2o, d3m, d3p, dxyz);
   const KParams<Real>& PR = J.P;
@@ -1014,6 +1020,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const Job<typename StoreT<ST>
         for (int a = 0; a < D; ++a) out1[(size_t)a * N + self] = (double)J.force[(size_t)a * N + self];
       return;
     }
+    if constexpr (MODEL != kNcde) R += P.msh;
     out0[self] = MODEL == kNcde ? (R + P.sqh) * P.sci : R;
     if (out1) {
       if constexpr (MODEL == kNcde) {

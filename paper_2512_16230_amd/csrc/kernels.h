@@ -67,6 +67,9 @@ struct KParams {
   // (sa, sp) = (1, 0), sinit = 1/2; three-level: sqh = 0, sci = 1,
   // (sa, sp) = (3/2, -1/2), sinit = 0.  No source: all terms vanish.
   Real sq, sk, sqh, sci, sa, sp, sinit;
+  // NSE_COMP mass source S (forced kernel only): rho = sum f_bar + msh with
+  // msh = S/2, the zeroth moment gains S, the second-order source gains -uu S
+  Real msrc, msh;
   // Drift correction: added to every node's zeroth and first Hermite moments
   // before the collision of one step (zero otherwise); the collision keeps
   // them, so the step moves the totals by N * dm0 and N * dm1.

@@ -289,6 +289,32 @@ def test_ncde_source(ctx, three_level, shape):
             s.set_drift_correction(10)
 
 
+@pytest.mark.parametrize("card,shape", [(W.Q25_RECT, (12, 70)), (W.Q53_RECT, (6, 10, 40)), (W.Q9_RECT, (37, 66))],
+                         ids=["rD2Q25", "rD3Q53", "D2Q9"])
+@pytest.mark.parametrize("forced", [False, True], ids=["zero-force", "force"])
+def test_mass_source(ctx, card, shape, forced):
+    """Compressible NSE with a uniform mass source: rho = sum f_bar + S/2,
+    M2G = (I - S2/2)[uF + Fu + (cs^2 I - uu) S]; the total grows by N S per step."""
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    rho, u = _random_fields(card, shape, 27)
+    F = W.sinusoidal_force(card, shape, 1e-3, seed=6) if forced else np.zeros((card.d,) + tuple(shape))
+    steps, S = 12, 2e-4
+    kw = dict(m30=card.kind not in ("D2Q9", "D3Q27"), mass_src=S)
+    r_o, u_o, _ = _oracle_run(card, "NSE_COMP", rates, rho, u, steps, force=F, **kw)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4)):
+        print("case: mass source %s %s force=%s %s" % (card.kind, shape, forced, storage), flush=True)
+        r, v, s = _gpu_run(ctx, card, "NSE_COMP", rates, shape, storage, rho, u, steps, force=F, **kw)
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+        m1, _ = s.conserved()
+        s.step(3)
+        m2, _ = s.conserved()
+        n = int(np.prod(shape))
+        assert abs(m2 - m1 - 3 * S * n) < (1e-10 if storage == "fp64" else 1e-5) * m1
+    with pytest.raises(H.MrtlbError):         # needs the forced kernel
+        H.Solve(ctx, hip_lattice(card), hip_model("NSE_COMP", rates, mass_src=S), shape, "fp32")
+
+
 def test_source_belongs_to_the_ncde(ctx):
     with pytest.raises(H.MrtlbError) as e:
         H.Solve(ctx, hip_lattice(W.Q25_RECT), hip_model("NSE_COMP", W.Rates(), src_q=0.01), (16, 16), "fp32")
