@@ -99,3 +99,38 @@ def test_footprint():
     b16 = H.footprint(lat, (4096, 4096), "fp16_dev", "NSE_INC")
     assert b32 >= 2 * 25 * 4 * 4096 * 4096
     assert b16 < 0.51 * b32
+
+
+def _header_struct_fields(name):
+    """(field, C type, array length) of the typedef'd struct ``name`` in
+    include/mrtlb.h, in declaration order (comments stripped)."""
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "include", "mrtlb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    m = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for item in names.split(","):
+            item = item.strip()
+            arr = re.match(r"(\w+)\[(\d+)\]", item)
+            fields.append((arr.group(1), ctype, int(arr.group(2))) if arr else (item, ctype, 1))
+    return fields
+
+
+@pytest.mark.parametrize("name", ["mrtlb_lattice_desc", "mrtlb_model_desc"])
+def test_binding_structs_match_the_header(name):
+    """The ctypes mirrors of the descriptor structs have the header's
+    fields, types and order, so the library reads what the binding writes."""
+    cls = getattr(H, name)
+    ctype_of = {"int": ctypes.c_int, "double": ctypes.c_double}
+    want = _header_struct_fields(name)
+    got = cls._fields_
+    assert [f for f, _, _ in want] == [f for f, _ in got]
+    for (f, ct, n), (_, t) in zip(want, got):
+        assert t == (ctype_of[ct] * n if n > 1 else ctype_of[ct]), f
