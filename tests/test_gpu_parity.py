@@ -451,6 +451,39 @@ def test_batch_equals_single(ctx):
             assert np.array_equal(a.read_populations(), b.read_populations())
 
 
+def test_batch_equals_single_new_models(ctx):
+    """Batched launches of solves that differ in their per-solve model
+    parameters (general NCDE, source, three-level scheme; standard D2Q9 with
+    a mass source and a force) give each solve its solo result bit for bit."""
+    ncde = []
+    for i, N in enumerate([48, 80, 66]):
+        wl = W.ncde_hill((N, N), adv_u=(0.02, -0.01 * i), D0=0.1, D2=1.0)
+        kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u, gn_bt=(0.1 * i, 0.0, 0.0), gn_dd=(0.0, 0.02, 0.0),
+                  src_q=0.001 * i, src_k=-0.01, three_level=i == 1)
+        ncde.append((W.Q13_SQUARE, "NCDE", wl.rates, (N, N), wl.rho_or_phi, None, None, kw))
+    nse = []
+    for i, shape in enumerate([(40, 70), (33, 130)]):
+        rho, u = _random_fields(W.Q9_RECT, shape, 31 + i)
+        F = W.sinusoidal_force(W.Q9_RECT, shape, 1e-3, seed=7 + i)
+        nse.append((W.Q9_RECT, "NSE_COMP", W.rates_tau(0.8), shape, rho, u, F, dict(m30=False, mass_src=1e-4 * i)))
+    for storage in ("fp32", "i16_dev"):
+        for group in (ncde, nse):
+            solo, batch = [], []
+            for card, eq, rates, shape, r, u, F, kw in group:
+                for lst in (solo, batch):
+                    s = H.Solve(ctx, hip_lattice(card), hip_model(eq, rates, **kw), shape, storage,
+                                has_force=F is not None)
+                    s.init_fields(r, u, F)
+                    lst.append(s)
+            counts = [9, 4, 6][: len(group)]
+            for s, k in zip(solo, counts):
+                s.step(k)
+            print("case: batch %s %s" % (group[0][1], storage), flush=True)
+            H.batch_step(batch, counts)
+            for a, b in zip(solo, batch):
+                assert np.array_equal(a.read_populations(), b.read_populations())
+
+
 def test_zero_steps_and_errors(ctx):
     card = W.Q25_RECT
     rates = W.rates_tau(0.8)
