@@ -257,6 +257,28 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
 /* Device bytes mrtlb_solve_create would allocate. */
 mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3], int storage, int model,
                                    int has_force, size_t* bytes);
+/* Bytes of one population buffer of a solve on this grid and storage.  The
+ * buffer is row-blocked: for each grid row (y fastest, then z) its b
+ * population rows back to back, each of pitch elements (nx rounded up to a
+ * multiple of 32), x fastest; elements of the storage's type (8, 4 or 2
+ * bytes, values as in mrtlb_storage).  f_bar_j of node (x, y, z) is the
+ * element ((z' * ny + y') * b + j) * pitch + x' with (x', y', z') =
+ * (x, y, z) - e_j modulo (nx, ny, nz): where the next step's pull gather
+ * reads it. */
+mrtlb_status mrtlb_population_bytes(const mrtlb_lattice* lat, const int64_t n[3], int storage, size_t* bytes);
+/* As mrtlb_solve_create, but the two population buffers are the caller's:
+ * f0 and f1 are device pointers on the context's device (for example two
+ * torch tensors' data), each at least mrtlb_population_bytes long and
+ * 16-byte aligned.  The solve reads and writes them in the layout above
+ * (which of the two holds the current state alternates with the step
+ * parity) and never frees them; the caller keeps them alive and unused by
+ * other work until mrtlb_solve_destroy.  The remaining device memory
+ * (parameters, force and history fields) is the library's and counts
+ * against the budget.  Errors: as mrtlb_solve_create, and EINVAL for NULL,
+ * equal or misaligned buffers. */
+mrtlb_status mrtlb_solve_create_external(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
+                                         const int64_t n[3], int storage, int has_force, void* f0, void* f1,
+                                         mrtlb_solve** out);
 /* Destroy every solve before its context. */
 void mrtlb_solve_destroy(mrtlb_solve* s);
 

@@ -80,6 +80,9 @@ def lib():
         "mrtlb_solve_create": (c_int, [c_void_p, c_void_p, POINTER(mrtlb_model_desc), POINTER(c_int64), c_int, c_int,
                                        POINTER(c_void_p)]),
         "mrtlb_solve_footprint": (c_int, [c_void_p, POINTER(c_int64), c_int, c_int, c_int, POINTER(c_size_t)]),
+        "mrtlb_population_bytes": (c_int, [c_void_p, POINTER(c_int64), c_int, POINTER(c_size_t)]),
+        "mrtlb_solve_create_external": (c_int, [c_void_p, c_void_p, POINTER(mrtlb_model_desc), POINTER(c_int64),
+                                                c_int, c_int, c_void_p, c_void_p, POINTER(c_void_p)]),
         "mrtlb_solve_destroy": (None, [c_void_p]),
         "mrtlb_init_fields": (c_int, [c_void_p, _DP, _DP, _DP]),
         "mrtlb_step": (c_int, [c_void_p, c_int64]),
@@ -107,7 +110,7 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_solve_create", "mrtlb_solve_footprint", "mrtlb_solve_destroy", "mrtlb_init_fields",
             "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
-            "mrtlb_host_alloc", "mrtlb_host_free"]
+            "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external"]
 
 
 def _check(status):
@@ -280,10 +283,21 @@ def _nxyz(shape):
     return int(shape[2]), int(shape[1]), int(shape[0])
 
 
+def population_bytes(lattice, shape, storage="fp32"):
+    """Bytes of one population buffer of a solve on this grid and storage."""
+    n = (c_int64 * 3)(*_nxyz(shape))
+    out = c_size_t()
+    st = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    _check(lib().mrtlb_population_bytes(lattice.h, n, st, byref(out)))
+    return out.value
+
+
 class Solve:
     """mrtlb_solve on a periodic grid of array shape (Ny, Nx) or (Nz, Ny, Nx)."""
 
-    def __init__(self, ctx, lattice, model, shape, storage="fp32", has_force=False):
+    def __init__(self, ctx, lattice, model, shape, storage="fp32", has_force=False, external=None):
+        """``external`` = (f0, f1): two caller-owned device pointers (ints) of
+        at least ``population_bytes(lattice, shape, storage)`` each."""
         self.h = None
         self.ctx, self.shape, self.d = ctx, tuple(shape), len(shape)
         self.N = int(np.prod(shape))
@@ -292,7 +306,11 @@ class Solve:
         n = (c_int64 * 3)(*_nxyz(shape))
         h = c_void_p()
         st = STORAGES[storage] if isinstance(storage, str) else int(storage)
-        _check(lib().mrtlb_solve_create(ctx.h, lattice.h, byref(model), n, st, 1 if has_force else 0, byref(h)))
+        if external is None:
+            _check(lib().mrtlb_solve_create(ctx.h, lattice.h, byref(model), n, st, 1 if has_force else 0, byref(h)))
+        else:
+            _check(lib().mrtlb_solve_create_external(ctx.h, lattice.h, byref(model), n, st, 1 if has_force else 0,
+                                                     c_void_p(external[0]), c_void_p(external[1]), byref(h)))
         self.h = h
         self.storage = storage
         ctx._solves.add(self)

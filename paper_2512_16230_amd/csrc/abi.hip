@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <cstdint>
 #include <vector>
 
 #include "../../include/mrtlb.h"
@@ -93,6 +94,7 @@ struct mrtlb_solve {
   double dm0 = 0, dm1[3] = {0, 0, 0};
   void* part = nullptr;         // FP64 partial sums of the plane-sum kernel
   size_t part_bytes = 0;
+  bool external = false;        // f[0], f[1] belong to the caller
 };
 
 namespace mrtlb {
@@ -539,7 +541,10 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
 static void release(mrtlb_solve* s) {
   if (!s) return;
   (void)hipSetDevice(s->ctx->device);
-  for (void* p : {s->f[0], s->f[1], s->force, s->phi[0], s->phi[1], s->jobs, s->pd, s->part})
+  if (!s->external)
+    for (void* p : {s->f[0], s->f[1]})
+      if (p) (void)hipFree(p);
+  for (void* p : {s->force, s->phi[0], s->phi[1], s->jobs, s->pd, s->part})
     if (p) (void)hipFree(p);
 }
 
@@ -556,9 +561,11 @@ static mrtlb_status upload_jobs(mrtlb_solve* s) {
   return MRTLB_OK;
 }
 
-mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
-                                const int64_t n[3], int storage, int has_force, mrtlb_solve** out) {
+static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
+                                 const int64_t n[3], int storage, int has_force, void* ext0, void* ext1,
+                                 mrtlb_solve** out) {
   if (!ctx || !lat || !model || !n || !out) return fail(MRTLB_EINVAL, "NULL argument");
+  const bool external = ext0 != nullptr;
   *out = nullptr;
   const int D = lat->L.D;
   mrtlb_status st = check_model(*model, lat->L);
@@ -572,6 +579,8 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   st = mrtlb_solve_footprint(lat, n, storage, model->model, has_force, &bytes);
   if (st != MRTLB_OK) return st;
   const int64_t nz = D == 3 ? n[2] : 1;
+  if (external)   // the population buffers are the caller's
+    bytes -= 2 * (size_t)lat->L.B * (size_t)(n[1] * nz * row_pitch(n[0], storage)) * elem_bytes(storage);
   const int maxe = lattice_maxe(lat->L.kind);
   if (n[0] < maxe || n[1] < maxe || (D == 3 && nz < maxe))
     return fail(MRTLB_EINVAL, "every grid size must be at least the largest lattice offset");
@@ -604,7 +613,12 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   const size_t pop = (size_t)s->L.B * (size_t)s->ny * s->nz * s->nxp * elem_bytes(storage);
   const size_t real = is_double(storage) ? 8 : 4;
   auto alloc = [&](void** p, size_t sz) { return hipMalloc(p, sz) == hipSuccess; };
-  bool ok = alloc(&s->f[0], pop) && alloc(&s->f[1], pop) &&
+  s->external = external;
+  if (external) {
+    s->f[0] = ext0;
+    s->f[1] = ext1;
+  }
+  bool ok = (external || (alloc(&s->f[0], pop) && alloc(&s->f[1], pop))) &&
             alloc(&s->jobs, 3 * std::max(sizeof(Job<double>), sizeof(Job<float>))) &&
             alloc(&s->pd, sizeof(KParams<double>));
   if (ok && has_force) ok = alloc(&s->force, (size_t)D * s->N * real);
@@ -627,6 +641,35 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
   ctx->used += bytes;
   *out = s;
   return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
+                                const int64_t n[3], int storage, int has_force, mrtlb_solve** out) {
+  return create_solve(ctx, lat, model, n, storage, has_force, nullptr, nullptr, out);
+}
+
+mrtlb_status mrtlb_population_bytes(const mrtlb_lattice* lat, const int64_t n[3], int storage, size_t* bytes) {
+  if (!lat || !n || !bytes) return fail(MRTLB_EINVAL, "NULL argument");
+  if (storage < kFP64 || storage > kI16Dev) return fail(MRTLB_EINVAL, "unknown storage");
+  const int64_t nz = lat->L.D == 3 ? n[2] : 1;
+  if (n[0] < 1 || n[1] < 1 || nz < 1) return fail(MRTLB_EINVAL, "grid sizes must be >= 1");
+  *bytes = (size_t)lat->L.B * (size_t)(n[1] * nz * row_pitch(n[0], storage)) * elem_bytes(storage);
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_solve_create_external(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
+                                         const int64_t n[3], int storage, int has_force, void* f0, void* f1,
+                                         mrtlb_solve** out) {
+  if (!f0 || !f1) return fail(MRTLB_EINVAL, "external population buffers must not be NULL");
+  if (f0 == f1) return fail(MRTLB_EINVAL, "the two population buffers must differ");
+  if (((uintptr_t)f0 | (uintptr_t)f1) % 16 != 0)
+    return fail(MRTLB_EINVAL, "external population buffers must be 16-byte aligned");
+  size_t pop = 0;
+  const mrtlb_status st = mrtlb_population_bytes(lat, n, storage, &pop);
+  if (st != MRTLB_OK) return st;
+  const uintptr_t a = (uintptr_t)f0, b = (uintptr_t)f1;
+  if ((a < b ? b - a : a - b) < pop) return fail(MRTLB_EINVAL, "the two population buffers overlap");
+  return create_solve(ctx, lat, model, n, storage, has_force, f0, f1, out);
 }
 
 void mrtlb_solve_destroy(mrtlb_solve* s) {

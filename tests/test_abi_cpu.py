@@ -134,3 +134,12 @@ def test_binding_structs_match_the_header(name):
     assert [f for f, _, _ in want] == [f for f, _ in got]
     for (f, ct, n), (_, t) in zip(want, got):
         assert t == (ctype_of[ct] * n if n > 1 else ctype_of[ct]), f
+
+
+def test_population_bytes_follow_the_documented_layout():
+    """ny*nz grid rows of b population rows, each nx rounded up to 32 elements."""
+    q25 = H.Lattice(W.Q25_RECT.kind, W.Q25_RECT.c, W.Q25_RECT.cs2, W.Q25_RECT.free)
+    assert H.population_bytes(q25, (70, 50), "fp32") == 25 * 70 * 64 * 4
+    assert H.population_bytes(q25, (7, 300), "i16_dev") == 25 * 7 * 320 * 2
+    q53 = H.Lattice(W.Q53_RECT.kind, W.Q53_RECT.c, W.Q53_RECT.cs2, W.Q53_RECT.free)
+    assert H.population_bytes(q53, (6, 10, 70), "fp64") == 53 * 60 * 96 * 8
