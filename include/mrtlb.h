@@ -123,7 +123,8 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  * ------------------------------------------------------------------------- */
 typedef enum { MRTLB_RD2Q25 = 0, MRTLB_RD2Q13 = 1, MRTLB_RD3Q53 = 2, MRTLB_RD3Q33 = 3, MRTLB_RD2Q21 = 4,
                MRTLB_D2Q21K = 5, MRTLB_RD3Q45 = 6, MRTLB_RD2Q17_1 = 7, MRTLB_RD2Q17_2 = 8, MRTLB_RD2Q17_3 = 9,
-               MRTLB_RD2Q17_4 = 10, MRTLB_RD2Q17_5 = 11, MRTLB_D2Q9 = 12, MRTLB_D3Q27 = 13 } mrtlb_lattice_kind;
+               MRTLB_RD2Q17_4 = 10, MRTLB_RD2Q17_5 = 11, MRTLB_D2Q9 = 12, MRTLB_D3Q27 = 13,
+               MRTLB_CUSTOM = 14 } mrtlb_lattice_kind;
 
 typedef struct {
   int kind;          /* mrtlb_lattice_kind */
@@ -131,6 +132,17 @@ typedef struct {
   double cs2;
   double free_w[4];  /* free weights, see above */
   int n_free;        /* 4 for RD2Q25 and RD3Q53, 0 otherwise */
+  /* MRTLB_CUSTOM only (ignored otherwise): dimension d (2 or 3), b
+   * velocities (b <= 53) given as integer multiples e (b*d ints, |e| <= 8,
+   * row j = velocity j) and their weights w (b doubles, positive, summing
+   * to 1); both arrays are copied.  The Hermite rows are built as for the
+   * multispeed lattices (corrected pure third-order rows) and must come out
+   * W-orthogonal with nonzero norms, else ENUMERIC.  Solves on a custom
+   * lattice run run-time-generic kernels (one node per thread, every
+   * population read twice per step) and take the NSE models only. */
+  int d, b;
+  const int* e;
+  const double* w;
 } mrtlb_lattice_desc;
 
 mrtlb_status mrtlb_lattice_create(const mrtlb_lattice_desc* desc, mrtlb_lattice** out);

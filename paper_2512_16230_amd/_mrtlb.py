@@ -24,12 +24,13 @@ MRTLB_OK, MRTLB_EINVAL, MRTLB_ENOMEM, MRTLB_EDEVICE, MRTLB_ENUMERIC = 0, -1, -2,
 MRTLB_RD2Q25, MRTLB_RD2Q13, MRTLB_RD3Q53, MRTLB_RD3Q33, MRTLB_RD2Q21, MRTLB_D2Q21K, MRTLB_RD3Q45 = range(7)
 MRTLB_RD2Q17 = {k: 6 + k for k in range(1, 6)}     # D2Q17 cases 1-5
 MRTLB_D2Q9, MRTLB_D3Q27 = 12, 13                     # standard lattices, k = 1 model
+MRTLB_CUSTOM = 14                                    # user-supplied velocity set
 MRTLB_NSE_INC, MRTLB_NSE_COMP, MRTLB_NCDE, MRTLB_CDE = 0, 1, 2, 3
 MRTLB_FP64, MRTLB_FP32, MRTLB_FP32_DEV, MRTLB_FP16_DEV, MRTLB_BF16_DEV, MRTLB_I16_DEV = 0, 1, 2, 3, 4, 5
 
 KINDS = {"rD2Q25": MRTLB_RD2Q25, "rD2Q13": MRTLB_RD2Q13, "rD3Q53": MRTLB_RD3Q53, "rD3Q33": MRTLB_RD3Q33,
          "rD2Q21": MRTLB_RD2Q21, "D2Q21K": MRTLB_D2Q21K, "rD3Q45": MRTLB_RD3Q45,
-         "D2Q9": MRTLB_D2Q9, "D3Q27": MRTLB_D3Q27, **{"rD2Q17-%d" % k: v for k, v in MRTLB_RD2Q17.items()}}
+         "D2Q9": MRTLB_D2Q9, "D3Q27": MRTLB_D3Q27, "custom": MRTLB_CUSTOM, **{"rD2Q17-%d" % k: v for k, v in MRTLB_RD2Q17.items()}}
 MODELS = {"NSE_INC": MRTLB_NSE_INC, "NSE_COMP": MRTLB_NSE_COMP, "NCDE": MRTLB_NCDE, "CDE": MRTLB_CDE}
 STORAGES = {"fp64": MRTLB_FP64, "fp32": MRTLB_FP32, "fp32_dev": MRTLB_FP32_DEV, "fp16_dev": MRTLB_FP16_DEV,
             "bf16_dev": MRTLB_BF16_DEV, "i16_dev": MRTLB_I16_DEV}
@@ -43,7 +44,7 @@ class MrtlbError(RuntimeError):
 
 class mrtlb_lattice_desc(ctypes.Structure):
     _fields_ = [("kind", c_int), ("c", c_double * 3), ("cs2", c_double), ("free_w", c_double * 4),
-                ("n_free", c_int)]
+                ("n_free", c_int), ("d", c_int), ("b", c_int), ("e", POINTER(c_int)), ("w", POINTER(c_double))]
 
 
 class mrtlb_model_desc(ctypes.Structure):
@@ -177,9 +178,10 @@ class Context:
 
 
 class Lattice:
-    """mrtlb_lattice built from (kind, c, cs2, free weights)."""
+    """mrtlb_lattice built from (kind, c, cs2, free weights); kind "custom"
+    takes the velocity set ``e`` (b x d integer multiples) and weights ``w``."""
 
-    def __init__(self, kind, c, cs2, free=()):
+    def __init__(self, kind, c, cs2, free=(), e=None, w=None):
         d = mrtlb_lattice_desc()
         d.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
         for a, v in enumerate(c):
@@ -188,6 +190,12 @@ class Lattice:
         for i, v in enumerate(free):
             d.free_w[i] = float(v)
         d.n_free = len(free)
+        if e is not None:
+            ea = np.ascontiguousarray(np.asarray(e, dtype=np.int32))
+            wa = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+            d.b, d.d = ea.shape
+            d.e = ea.ctypes.data_as(POINTER(c_int))
+            d.w = _ptr(wa)
         h = c_void_p()
         _check(lib().mrtlb_lattice_create(byref(d), byref(h)))
         self.h = h

@@ -107,9 +107,11 @@ static size_t elem_bytes(int storage) {
     default: return 2;
   }
 }
-static int lattice_maxe(int kind) {
-  if (kind == kD2Q9 || kind == kD3Q27) return 1;
-  return kind == kRD2Q25 || kind == kRD2Q21 || kind == kD2Q21K || (kind >= kRD2Q17_1 && kind <= kRD2Q17_4) ? 3 : 2;
+// Largest |e_a| of the velocity set.
+static int lattice_maxe(const HostLattice& L) {
+  int m = 0;
+  for (int v : L.e) m = std::max(m, v < 0 ? -v : v);
+  return m;
 }
 
 // Population row pitch: nx rounded up to 32 nodes.  Rows start on a 32-element
@@ -145,7 +147,7 @@ static int pick_vec(int storage, int kind, int model, int nx) {
   }
   // only the 2D NSE step kernels are built with several nodes per thread
   const bool is3d = kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || kind == kD3Q27;
-  if (is3d || model == MRTLB_NCDE || model == MRTLB_CDE) v = 1;
+  if (is3d || kind == kCustom || model == MRTLB_NCDE || model == MRTLB_CDE) v = 1;
   while (v > 1 && (nx % v != 0 || nx < 4 * v)) v >>= 1;
   return v;
 }
@@ -308,6 +310,9 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   } else {
     P.sci = (Real)1;
   }
+  P.cb = L.B;
+  for (int j = 0; j < L.B; ++j)
+    for (int a = 0; a < 3; ++a) P.ce[j][a] = (int8_t)(a < D ? L.e[j * D + a] : 0);
   P.msrc = (Real)(m.model == MRTLB_NSE_COMP ? m.mass_src : 0.0);
   P.msh = (Real)(m.model == MRTLB_NSE_COMP ? 0.5 * m.mass_src : 0.0);
   for (int a = 0; a < 3; ++a) {
@@ -352,6 +357,7 @@ static hipError_t dispatch(int kind, const LaunchReq& r) {
     case kRD2Q17_5: return launch_rd2q17_5(r);
     case kD2Q9: return launch_d2q9(r);
     case kD3Q27: return launch_d3q27(r);
+    case kCustom: return launch_custom(r);
   }
   return hipErrorInvalidValue;
 }
@@ -363,6 +369,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.model = s.model.model;
   r.force = s.has_force != 0;
   r.vec = s.vec;
+  r.dim = s.L.D;
   r.jobs = jobs;
   r.njobs = 1;
   r.blocks = op == kOpStep ? s.nblocks : s.nblocks_node;
@@ -510,6 +517,8 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
   if (!std::isfinite(m.mass_src)) return fail(MRTLB_EINVAL, "mass_src must be finite");
   if (m.mass_src != 0 && m.model != MRTLB_NSE_COMP)
     return fail(MRTLB_EINVAL, "the mass source belongs to the compressible NSE model");
+  if (L.kind == kCustom && m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
+    return fail(MRTLB_EINVAL, "custom lattices carry the NSE models only");
   if (L.standard) {
     if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
       return fail(MRTLB_EINVAL, "the standard lattices carry the k = 1 NSE models only");
@@ -581,7 +590,7 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   const int64_t nz = D == 3 ? n[2] : 1;
   if (external)   // the population buffers are the caller's
     bytes -= 2 * (size_t)lat->L.B * (size_t)(n[1] * nz * row_pitch(n[0], storage)) * elem_bytes(storage);
-  const int maxe = lattice_maxe(lat->L.kind);
+  const int maxe = lattice_maxe(lat->L);
   if (n[0] < maxe || n[1] < maxe || (D == 3 && nz < maxe))
     return fail(MRTLB_EINVAL, "every grid size must be at least the largest lattice offset");
   if (n[0] * n[1] * nz >= ((int64_t)1 << 31)) return fail(MRTLB_EINVAL, "node count must be below 2^31");

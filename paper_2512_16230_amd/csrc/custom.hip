@@ -1,0 +1,267 @@
+// Kernels for a user-supplied velocity set (kind MRTLB_CUSTOM).  The
+// structured kernels are compiled per velocity set; here the set is read at
+// run time from KParams (b velocities, integer multiples e_j), so every
+// population is addressed and summed in a run-time loop.  The moment-space
+// part of the step (conserved variables, sources, equilibrium, relaxation)
+// is the same code as for the compiled lattices; the NSE models only.
+//
+// Each population is read twice per step (once for the monomial sums, once
+// for the update, the second read mostly from L2), so this path trades
+// speed for generality.
+#include "device.h"
+
+namespace mrtlb {
+
+namespace {
+
+// Element of f_bar_j at node (ix, iy, iz): the pull source x - e_j in the
+// row-blocked layout (per grid row its b population rows of pitch nxp).
+template <class Real>
+__device__ __forceinline__ uint32_t csrc(const KParams<Real>& P, int j, int ix, int iy, int iz) {
+  const uint32_t xs = (uint32_t)wrap(ix - (int)P.ce[j][0], P.nx);
+  const uint32_t ys = (uint32_t)wrap(iy - (int)P.ce[j][1], P.ny);
+  const uint32_t zs = (uint32_t)wrap(iz - (int)P.ce[j][2], P.nz);
+  return ((zs * (uint32_t)P.ny + ys) * (uint32_t)P.cb + (uint32_t)j) * (uint32_t)P.nxp + xs;
+}
+
+// sum_r H_r delta_r / n_r at velocity e (lattice units), from the monomial
+// coefficients of back_coeffs.
+template <int D, class Real>
+__device__ __forceinline__ Real poly_at(const BackCoeffs<Real>& C, const int (&e)[3]) {
+  Real v = C.b0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const Real ea = (Real)e[a];
+    v += ea * C.b1[a] + ea * ea * C.b2n[a] + ea * ea * ea * C.b3p[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == a) continue;
+      const Real eb = (Real)e[b];
+      v += ea * eb * eb * C.b3m[a][b];
+      if (b > a) v += ea * eb * C.b2o[off_index(a, b)];
+    }
+  }
+  if constexpr (D == 3) v += (Real)(e[0] * e[1] * e[2]) * C.bxyz;
+  return v;
+}
+
+template <class Real>
+__device__ __forceinline__ void velocity(const KParams<Real>& P, int j, int (&e)[3]) {
+  e[0] = P.ce[j][0];
+  e[1] = P.ce[j][1];
+  e[2] = P.ce[j][2];
+}
+
+}  // namespace
+
+// One fused step, one node per thread over the padded rows.
+template <int DIM, int ST, bool FORCE>
+__global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                       int njobs, uint32_t total_blocks) {
+  using Real = typename StoreT<ST>::Real;
+  using L = LatCustom<DIM>;
+  const uint32_t lin = xcd_remap(blockIdx.x, total_blocks);
+  const int jb = njobs > 1 ? find_job(jobs, njobs, lin) : 0;
+  const Job<Real>& J = jobs[jb];
+  const KParams<Real>& P = J.P;
+  int ix, iy, iz;
+  if (!tile_node<1>(J, lin - J.block_begin, ix, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
+  const int b = P.cb;
+
+  // a1 + a3: monomial sums of the gathered populations (physical deviations)
+  const Real z = Real(-0.0);
+  Real R0 = z, R1[3] = {z, z, z}, R2n[3] = {z, z, z}, R2o[3] = {z, z, z}, R3p[3] = {z, z, z};
+  Real R3m[3][3] = {{z, z, z}, {z, z, z}, {z, z, z}};
+  Real Rxyz = z;
+  for (int j = 0; j < b; ++j) {
+    const Real v = load_pop<ST>(J.fin, csrc(P, j, ix, iy, iz), P, j);
+    int e[3];
+    velocity(P, j, e);
+    R0 += v;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const Real ea = (Real)e[a];
+      R1[a] += ea * v;
+      R2n[a] += ea * ea * v;
+      R3p[a] += ea * ea * ea * v;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        if (c == a) continue;
+        R3m[a][c] += ea * (Real)(e[c] * e[c]) * v;
+        if (c > a) R2o[off_index(a, c)] += ea * (Real)e[c] * v;
+      }
+    }
+    if constexpr (DIM == 3) Rxyz += (Real)(e[0] * e[1] * e[2]) * v;
+  }
+  Moments<Real> M;
+  finish_moments<DIM, false>(P, R0, R1, R2n, R2o, R3p, R3m, Rxyz, M);
+
+  // a2, a4-a6
+  Targets<Real> T;
+  relax_node<L, ST, kNseComp, FORCE>(M, J, g, ix, T);
+
+  // a7 + a8: f* = kx f + w (sum_r H_r delta_r / n_r), stored at the own node
+  BackCoeffs<Real> C;
+  back_coeffs<DIM, false>(P, T.d0, T.d1, T.d2n, T.d2o, T.d3m, T.d3p, T.dxyz, C);
+  const uint32_t own = ((uint32_t)iz * (uint32_t)P.ny + (uint32_t)iy) * (uint32_t)b * (uint32_t)P.nxp + (uint32_t)ix;
+  for (int j = 0; j < b; ++j) {
+    const Real v = load_pop<ST>(J.fin, csrc(P, j, ix, iy, iz), P, j);
+    int e[3];
+    velocity(P, j, e);
+    const Real out = T.kx * v + P.w[j] * poly_at<DIM>(C, e);
+    store_pop<ST>(J.fout, own + (uint32_t)j * (uint32_t)P.nxp, out, P, j);
+  }
+}
+
+// f_bar(x, 0) = f_eq - F/2 in FP64, written at the pull source x - e_j.
+template <int DIM, int ST>
+__global__ __launch_bounds__(kBlock) void k_init_custom(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                       const KParams<double>* __restrict__ PD,
+                                                       const double* __restrict__ rho, const double* __restrict__ uin,
+                                                       const double* __restrict__ fin) {
+  using Real = typename StoreT<ST>::Real;
+  using L = LatCustom<DIM>;
+  const Job<Real>& J = jobs[0];
+  const KParams<double>& P = *PD;
+  int ix, iy, iz;
+  if (!node_of_thread<L>(P, ix, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
+  const uint32_t self = g.node(ix);
+  const uint32_t N = P.N;
+  const double R = rho[self];
+  double u[3] = {0, 0, 0}, jm[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+  const double rho_m = P.inc ? P.rho0 : R;
+  for (int a = 0; a < DIM; ++a) {
+    u[a] = uin[(size_t)a * N + self];
+    jm[a] = rho_m * u[a];
+    if (fin) F[a] = fin[(size_t)a * N + self];
+  }
+  Equilibrium<L, double, kNseComp> E;
+  E.build(P, R, jm, u);
+  double d1[3] = {0, 0, 0}, d2n[3] = {0, 0, 0}, d2o[3] = {0, 0, 0}, d3m[3][3] = {}, d3p[3] = {0, 0, 0}, dxyz = 0;
+  for (int a = 0; a < DIM; ++a) {
+    d1[a] = (E.e1[a] - 0.5 * F[a]) * P.in1[a];
+    // mass source: -F/2 has the Hermite second-order part +cs^2 S / 2
+    d2n[a] = (E.e2n[a] + P.msh * P.cs2) * P.in2n[a];
+    d3p[a] = E.e3p[a] * P.in3p[a];
+    for (int c = 0; c < DIM; ++c)
+      if (c != a) d3m[a][c] = E.e3m[a][c] * P.in3m[a][c];
+    for (int c = a + 1; c < DIM; ++c) d2o[off_index(a, c)] = E.e2o[off_index(a, c)] * P.in2o[off_index(a, c)];
+  }
+  if constexpr (DIM == 3) dxyz = E.exyz * P.inxyz;
+  const double d0 = (R - P.msh) * P.in0 - P.rho_ref;
+  BackCoeffs<double> C;
+  back_coeffs<DIM, false>(P, d0, d1, d2n, d2o, d3m, d3p, dxyz, C);
+  const KParams<Real>& PR = J.P;
+  for (int j = 0; j < P.cb; ++j) {
+    int e[3];
+    velocity(P, j, e);
+    const double x = P.w[j] * poly_at<DIM>(C, e);
+    store_pop<ST>(J.fout, csrc(P, j, ix, iy, iz), (Real)x, PR, j);
+  }
+}
+
+// Read-out: moments (WHAT 0) or populations (WHAT 1) in FP64.
+template <int DIM, int ST, int WHAT>
+__global__ __launch_bounds__(kBlock) void k_gather_custom(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                         const KParams<double>* __restrict__ PD,
+                                                         double* __restrict__ out0, double* __restrict__ out1) {
+  using L = LatCustom<DIM>;
+  const auto& J = jobs[0];
+  const KParams<double>& P = *PD;
+  int ix, iy, iz;
+  if (!node_of_thread<L>(P, ix, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
+  const uint32_t self = g.node(ix);
+  const uint32_t N = P.N;
+  double R = 0, m1[3] = {0, 0, 0};
+  for (int j = 0; j < P.cb; ++j) {
+    const double v = (double)load_pop<ST>(J.fin, csrc(P, j, ix, iy, iz), J.P, j);
+    if constexpr (WHAT == 1) {
+      out0[(size_t)j * N + self] = v + P.w[j] * P.rho_ref;
+    } else {
+      R += v;
+      for (int a = 0; a < DIM; ++a) m1[a] += (double)P.ce[j][a] * v;
+    }
+  }
+  if constexpr (WHAT == 0) {
+    R += P.rho_ref + P.msh;
+    out0[self] = R;
+    if (out1) {
+      const double rho_m = P.inc ? P.rho0 : R;
+      for (int a = 0; a < DIM; ++a) {
+        double jmom = P.c1[a] * m1[a];
+        if (J.force) jmom += 0.5 * (double)J.force[(size_t)a * N + self];
+        out1[(size_t)a * N + self] = jmom / rho_m;
+      }
+    }
+  }
+}
+
+// Restore populations (b x N, FP64, node order) into the pull layout.
+template <int DIM, int ST>
+__global__ __launch_bounds__(kBlock) void k_scatter_custom(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                          const KParams<double>* __restrict__ PD,
+                                                          const double* __restrict__ in) {
+  using Real = typename StoreT<ST>::Real;
+  using L = LatCustom<DIM>;
+  const Job<Real>& J = jobs[0];
+  const KParams<double>& P = *PD;
+  int ix, iy, iz;
+  if (!node_of_thread<L>(P, ix, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
+  const uint32_t self = g.node(ix);
+  for (int j = 0; j < P.cb; ++j) {
+    const double v = in[(size_t)j * P.N + self] - P.w[j] * P.rho_ref;
+    store_pop<ST>(J.fout, csrc(P, j, ix, iy, iz), (Real)v, J.P, j);
+  }
+}
+
+template <int DIM>
+static hipError_t launch_custom_dim(const LaunchReq& r) {
+  hipError_t err = hipErrorInvalidValue;
+  const dim3 grid(r.blocks), block(kBlock);
+  if (r.model == kNcde || r.model == kCde) return err;   // the NSE models only
+  with_storage(r.storage, [&](auto stc) {
+    constexpr int ST = decltype(stc)::value;
+    using Real = typename StoreT<ST>::Real;
+    const auto* J = static_cast<const Job<Real>*>(r.jobs);
+    const auto* PD = static_cast<const KParams<double>*>(r.pd);
+    switch (r.op) {
+      case kOpStep:
+        if (r.vec != 1) return;
+        if (r.force)
+          hipLaunchKernelGGL((k_step_custom<DIM, ST, true>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+        else
+          hipLaunchKernelGGL((k_step_custom<DIM, ST, false>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+        break;
+      case kOpInit:
+        hipLaunchKernelGGL((k_init_custom<DIM, ST>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2);
+        break;
+      case kOpMoments:
+        hipLaunchKernelGGL((k_gather_custom<DIM, ST, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        break;
+      case kOpPopulations:
+        hipLaunchKernelGGL((k_gather_custom<DIM, ST, 1>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        break;
+      case kOpScatter:
+        hipLaunchKernelGGL((k_scatter_custom<DIM, ST>), grid, block, 0, r.stream, J, PD, r.in0);
+        break;
+      default:
+        return;
+    }
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+hipError_t launch_custom(const LaunchReq& r) {
+  return r.dim == 3 ? launch_custom_dim<3>(r) : launch_custom_dim<2>(r);
+}
+
+}  // namespace mrtlb

@@ -376,6 +376,38 @@ struct Moments {
   Real m1[3], m2n[3], m2o[3], m3m[3][3], m3p[3], mxyz;
 };
 
+// Component Hermite moments from the monomial sums of the populations in
+// lattice units: R0 = sum f, R1_a = sum e_a f, R2n_a = sum e_a^2 f,
+// R2o_ab = sum e_a e_b f, R3p_a = sum e_a^3 f, R3m_ab = sum e_a e_b^2 f,
+// Rxyz = sum e_x e_y e_z f (PURE3 = false: no pure third-order rows).
+template <int D, bool STANDARD, class Real>
+__device__ __forceinline__ void finish_moments(const KParams<Real>& P, Real R0, const Real (&R1)[3],
+                                               const Real (&R2n)[3], const Real (&R2o)[3], const Real (&R3p)[3],
+                                               const Real (&R3m)[3][3], Real Rxyz, Moments<Real>& M) {
+  M.R0 = R0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    M.m1[a] = P.c1[a] * R1[a];
+    M.m2n[a] = P.c2[a] * R2n[a] - P.cs2 * R0;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a + 1; b < D; ++b) M.m2o[off_index(a, b)] = P.cab[off_index(a, b)] * R2o[off_index(a, b)];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    Real pure = P.c3[a] * R3p[a] - 3 * P.cs2 * M.m1[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == a) continue;
+      M.m3m[a][b] = P.cabb[a][b] * R3m[a][b] - P.cs2 * M.m1[a];
+      pure -= P.corr[a][b] * M.m3m[a][b];
+    }
+    M.m3p[a] = STANDARD ? Real(0) : pure;
+  }
+  if constexpr (D == 3) M.mxyz = P.cxyz * Rxyz;
+}
+
 // Hermite moments (component rows, physical units) of x[0..B-1].  SCALED:
 // x holds read numbers, population j is x_j * wsc[j] (one scale per pair).
 // The monomial sums run over rays: the pairs of a ray have velocities
@@ -439,28 +471,7 @@ __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Rea
       }
     }
   });
-  M.R0 = R0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    M.m1[a] = P.c1[a] * R1[a];
-    M.m2n[a] = P.c2[a] * R2n[a] - P.cs2 * R0;
-  }
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = a + 1; b < D; ++b) M.m2o[off_index(a, b)] = P.cab[off_index(a, b)] * R2o[off_index(a, b)];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    Real pure = P.c3[a] * R3p[a] - 3 * P.cs2 * M.m1[a];
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      if (b == a) continue;
-      M.m3m[a][b] = P.cabb[a][b] * R3m[a][b] - P.cs2 * M.m1[a];
-      pure -= P.corr[a][b] * M.m3m[a][b];
-    }
-    M.m3p[a] = is_standard<L>() ? Real(0) : pure;
-  }
-  if constexpr (D == 3) M.mxyz = P.cxyz * Rxyz;
+  finish_moments<D, is_standard<L>()>(P, R0, R1, R2n, R2o, R3p, R3m, Rxyz, M);
 }
 
 // Per-row coefficients delta_r = (target_r) / n_r turned into monomial
@@ -470,36 +481,58 @@ __device__ __forceinline__ void forward(const Real (&x)[L::B], const KParams<Rea
 // storages, whose output numbers it writes directly).  Per ray the even and
 // odd parts are b0 + k^2 E2 and sign (k O1 + k^3 O3), with E2, O1, O3 the
 // degree-2, -1 and -3 polynomials at the ray direction.
+// Monomial coefficients (lattice units) of sum_r H_r delta_r for the
+// targets delta_r = d*: f_j gains wo_j times
+//   b0 + sum_a b1_a e_a + sum_a b2n_a e_a^2 + sum_{a<b} b2o_ab e_a e_b
+//      + sum_a b3p_a e_a^3 + sum_{a!=b} b3m_ab e_a e_b^2 + bxyz e_x e_y e_z.
+template <class Real>
+struct BackCoeffs {
+  Real b0, b1[3], b2n[3], b2o[3], b3m[3][3], b3p[3], bxyz;
+};
+
+template <int D, bool STANDARD, class Real>
+__device__ __forceinline__ void back_coeffs(const KParams<Real>& P, Real d0, const Real* d1, const Real* d2n,
+                                            const Real* d2o, const Real (*d3m)[3], const Real* d3p, Real dxyz,
+                                            BackCoeffs<Real>& C) {
+  C.b0 = d0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) C.b0 -= P.cs2 * d2n[a];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    constexpr bool pure3 = !STANDARD;
+    Real t = pure3 ? d1[a] + P.k3[a] * d3p[a] : d1[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (b == a) continue;
+      t -= P.cs2 * d3m[a][b];
+      C.b3m[a][b] = pure3 ? P.cabb[a][b] * (d3m[a][b] - P.corr[a][b] * d3p[a]) : P.cabb[a][b] * d3m[a][b];
+    }
+    C.b1[a] = P.c1[a] * t;
+    C.b2n[a] = P.c2[a] * d2n[a];
+    C.b3p[a] = pure3 ? P.c3[a] * d3p[a] : Real(0);
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a + 1; b < D; ++b) C.b2o[off_index(a, b)] = P.cab[off_index(a, b)] * d2o[off_index(a, b)];
+  C.bxyz = 0;
+  if constexpr (D == 3) C.bxyz = P.cxyz * dxyz;
+}
+
 template <class L, class Real>
 __device__ __forceinline__ void backward(Real (&x)[L::B], const KParams<Real>& P, Real kx, const Real* wo, Real d0,
                                          const Real* d1, const Real* d2n, const Real* d2o, const Real (*d3m)[3],
                                          const Real* d3p, Real dxyz) {
   constexpr int D = L::D;
   const Real z = Real(-0.0);
-  Real b0 = d0;
-  Real b1[3], b2n[3], b2o[3], b3m[3][3], b3p[3];
-#pragma unroll
-  for (int a = 0; a < D; ++a) b0 -= P.cs2 * d2n[a];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    constexpr bool pure3 = !is_standard<L>();
-    Real t = pure3 ? d1[a] + P.k3[a] * d3p[a] : d1[a];
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-      if (b == a) continue;
-      t -= P.cs2 * d3m[a][b];
-      b3m[a][b] = pure3 ? P.cabb[a][b] * (d3m[a][b] - P.corr[a][b] * d3p[a]) : P.cabb[a][b] * d3m[a][b];
-    }
-    b1[a] = P.c1[a] * t;
-    b2n[a] = P.c2[a] * d2n[a];
-    b3p[a] = pure3 ? P.c3[a] * d3p[a] : Real(0);
-  }
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = a + 1; b < D; ++b) b2o[off_index(a, b)] = P.cab[off_index(a, b)] * d2o[off_index(a, b)];
-  Real bxyz = 0;
-  if constexpr (D == 3) bxyz = P.cxyz * dxyz;
+  BackCoeffs<Real> C;
+  back_coeffs<D, is_standard<L>()>(P, d0, d1, d2n, d2o, d3m, d3p, dxyz, C);
+  const Real b0 = C.b0, bxyz = C.bxyz;
+  const auto& b1 = C.b1;
+  const auto& b2n = C.b2n;
+  const auto& b2o = C.b2o;
+  const auto& b3m = C.b3m;
+  const auto& b3p = C.b3p;
   x[0] = kx * x[0] + wo[0] * b0;
   static_for<0, n_pairs<L>()>([&](auto ll) {
     constexpr int lead = decltype(ll)::value;
@@ -648,20 +681,24 @@ __device__ __forceinline__ bool tile_node(const Job<Real>& J, uint32_t local, in
   return ix0 < J.P.nx && r < ny * (uint32_t)J.P.nz;
 }
 
-// One node of the method after the gather: a2-a7 in registers.
-// x[] holds the pre-collision populations on entry, post-collision on exit.
+// Relaxation targets of one node: f* = kx f + W sum_r H_r delta_r / n_r
+// with the delta_r (scaled by 1/n_r) below.
+template <class Real>
+struct Targets {
+  Real kx, d0, d1[3], d2n[3], d2o[3], d3m[3][3], d3p[3], dxyz;
+};
+
+// a2 and a4-a6 of one node in moment space: conserved variables, sources,
+// equilibrium, relaxation.  M holds the node's Hermite moments on entry.
 template <class L, int ST, int MODEL, bool FORCE>
-__device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B],
-                                             const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix) {
+__device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M,
+                                           const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix,
+                                           Targets<typename StoreT<ST>::Real>& T) {
   using Real = typename StoreT<ST>::Real;
   constexpr int D = L::D;
   const KParams<Real>& P = J.P;
   const uint32_t self = g.node(ix);
   const uint32_t N = P.N;
-
-  // a3: forward Hermite moments
-  Moments<Real> M;
-  forward<L, scaled_storage<ST>()>(x, P, M);
   // a8 drift correction (zero except on the step after an FP64 check)
   M.R0 += P.dm0;
 #pragma unroll
@@ -800,9 +837,36 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   // order 0 is conserved, m*_0 = m_0, except for the CDE source:
   // m*_0 = m_0 + M0G + s0 S_G / 2 = m_0 + S_G (M0G = (1 - s0/2) S_G)
   const Real d0 = (P.sh * M.R0 + sg + src0) * P.in0;
+  T.kx = kx;
+  T.d0 = d0;
+  T.dxyz = dxyz;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    T.d1[a] = d1[a];
+    T.d2n[a] = d2n[a];
+    T.d3p[a] = d3p[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+      if (b != a) T.d3m[a][b] = d3m[a][b];
+  }
+#pragma unroll
+  for (int o = 0; o < D * (D - 1) / 2; ++o) T.d2o[o] = d2o[o];
+}
 
+// One node of the method after the gather: a2-a7 in registers.
+// x[] holds the pre-collision populations on entry, post-collision on exit.
+template <class L, int ST, int MODEL, bool FORCE>
+__device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B],
+                                             const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix) {
+  using Real = typename StoreT<ST>::Real;
+  const KParams<Real>& P = J.P;
+  // a3: forward Hermite moments
+  Moments<Real> M;
+  forward<L, scaled_storage<ST>()>(x, P, M);
+  Targets<Real> T;
+  relax_node<L, ST, MODEL, FORCE>(M, J, g, ix, T);
   // a7: back to populations (output numbers of the storage)
-  backward<L>(x, P, kx * P.kin, P.wo, d0, d1, d2n, d2o, d3m, d3p, dxyz);
+  backward<L>(x, P, T.kx * P.kin, P.wo, T.d0, T.d1, T.d2n, T.d2o, T.d3m, T.d3p, T.dxyz);
 }
 
 // ---------------------------------------------------------------------------

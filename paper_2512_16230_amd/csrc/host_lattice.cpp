@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "kernels.h"
 #include "lattices.h"
 
 namespace mrtlb {
@@ -185,6 +186,29 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
     case kRD2Q17_5: copy_velocities<LatRD2Q17_5>(&L); break;
     case kD2Q9: copy_velocities<LatD2Q9>(&L); break;
     case kD3Q27: copy_velocities<LatD3Q27>(&L); break;
+    case kCustom: {
+      if (!(desc.d == 2 || desc.d == 3) || desc.b < 2 || desc.b > kMaxB || !desc.e || !desc.w) {
+        snprintf(buf, sizeof buf, "a custom lattice needs d in {2, 3}, 2 <= b <= %d and both arrays", kMaxB);
+        *err = buf;
+        return MRTLB_EINVAL;
+      }
+      L.D = desc.d;
+      L.B = desc.b;
+      L.e.assign(desc.e, desc.e + (size_t)desc.b * desc.d);
+      for (int v : L.e)
+        if (v < -8 || v > 8) {
+          *err = "custom velocities must be integer multiples with |e| <= 8";
+          return MRTLB_EINVAL;
+        }
+      L.w.assign(desc.w, desc.w + desc.b);
+      double sum = 0;
+      for (double v : L.w) sum += v;
+      if (!(std::fabs(sum - 1.0) <= 1e-12)) {
+        *err = "custom weights must sum to 1";
+        return MRTLB_EINVAL;
+      }
+      break;
+    }
     default:
       snprintf(buf, sizeof buf, "unknown lattice kind %d", desc.kind);
       *err = buf;
@@ -254,6 +278,7 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
       break;
     }
     case kD2Q9: case kD3Q27: weights_standard(L.c, L.cs2, &L); break;
+    case kCustom: break;   // given
   }
   for (int j = 0; j < B; ++j) {
     if (!(L.w[j] > 0)) {
@@ -325,6 +350,18 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
     L.norms[r] = wdot(L, rows[r], rows[r]);
     if (!(L.norms[r] > 0)) { *err = "zero Hermite norm"; return MRTLB_ENUMERIC; }
   }
+  // The reduced collision needs W-orthogonal rows of order <= 3 (the
+  // paper's lattices meet this by construction; a custom set must).
+  for (int r = 0; r < L.nlow; ++r)
+    for (int q = r + 1; q < L.nlow; ++q) {
+      const double g = wdot(L, rows[r], rows[q]);
+      if (!(std::fabs(g) <= 1e-10 * std::sqrt(L.norms[r] * L.norms[q]))) {
+        snprintf(buf, sizeof buf, "Hermite rows %d and %d are not W-orthogonal (relative inner product %.3g)", r, q,
+                 g / std::sqrt(L.norms[r] * L.norms[q]));
+        *err = buf;
+        return MRTLB_ENUMERIC;
+      }
+    }
   *out = std::move(L);
   return MRTLB_OK;
 }

@@ -70,6 +70,9 @@ struct KParams {
   // NSE_COMP mass source S (forced kernel only): rho = sum f_bar + msh with
   // msh = S/2, the zeroth moment gains S, the second-order source gains -uu S
   Real msrc, msh;
+  // velocity set at run time (read by the user-supplied-lattice kernels)
+  int cb;                    // b
+  int8_t ce[kMaxB][3];       // integer velocity multiples e_j
   // Drift correction: added to every node's zeroth and first Hermite moments
   // before the collision of one step (zero otherwise); the collision keeps
   // them, so the step moves the totals by N * dm0 and N * dm1.

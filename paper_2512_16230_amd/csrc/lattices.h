@@ -16,7 +16,8 @@ namespace mrtlb {
 
 enum LatticeKind {
   kRD2Q25 = 0, kRD2Q13 = 1, kRD3Q53 = 2, kRD3Q33 = 3, kRD2Q21 = 4, kD2Q21K = 5, kRD3Q45 = 6,
-  kRD2Q17_1 = 7, kRD2Q17_2 = 8, kRD2Q17_3 = 9, kRD2Q17_4 = 10, kRD2Q17_5 = 11, kD2Q9 = 12, kD3Q27 = 13
+  kRD2Q17_1 = 7, kRD2Q17_2 = 8, kRD2Q17_3 = 9, kRD2Q17_4 = 10, kRD2Q17_5 = 11, kD2Q9 = 12, kD3Q27 = 13,
+  kCustom = 14
 };
 
 struct LatRD2Q25 {
@@ -127,6 +128,16 @@ struct LatRD3Q33 {
 #undef MRTLB_D3Q27_X
 #undef MRTLB_D3Q27_Y
 #undef MRTLB_D3Q27_Z
+
+// User-supplied velocity set: the velocities live in KParams at run time;
+// this type only carries the dimension for the moment-space code.
+template <int DIM>
+struct LatCustom {
+  static constexpr int kind = kCustom, D = DIM, B = 1, MAXE = 1;
+  static constexpr int EX[1] = {0};
+  static constexpr int EY[1] = {0};
+  static constexpr int EZ[1] = {0};
+};
 
 // Standard lattices: single layer, k = 1 model.
 template <class L>

@@ -16,6 +16,7 @@ struct LaunchReq {
   int model = 0;             // ModelKind
   bool force = false;        // NSE with a body-force field
   int vec = 1;               // step kernel: nodes per thread along x (1, 2, 4)
+  int dim = 2;               // lattice dimension (user-supplied lattices)
   const void* jobs = nullptr;
   int njobs = 1;
   uint32_t blocks = 0;
@@ -42,6 +43,7 @@ hipError_t launch_rd2q17_4(const LaunchReq& r);
 hipError_t launch_rd2q17_5(const LaunchReq& r);
 hipError_t launch_d2q9(const LaunchReq& r);
 hipError_t launch_d3q27(const LaunchReq& r);
+hipError_t launch_custom(const LaunchReq& r);
 
 // FP64 sums of every population plane (and force plane) in chunks.
 hipError_t launch_plane_sums(int storage, const void* base, uint32_t N, int npop, const void* force, int nforce,

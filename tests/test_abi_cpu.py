@@ -115,9 +115,13 @@ def _header_struct_fields(name):
         decl = decl.strip()
         if not decl:
             continue
-        ctype, names = decl.split(None, 1)
+        decl = decl.replace("const ", "")
+        ctype, names = decl.split(None, 1)     # "int* e" -> ("int*", "e")
         for item in names.split(","):
             item = item.strip()
+            if item.startswith("*"):
+                fields.append((item[1:], ctype + "*", 1))
+                continue
             arr = re.match(r"(\w+)\[(\d+)\]", item)
             fields.append((arr.group(1), ctype, int(arr.group(2))) if arr else (item, ctype, 1))
     return fields
@@ -128,7 +132,8 @@ def test_binding_structs_match_the_header(name):
     """The ctypes mirrors of the descriptor structs have the header's
     fields, types and order, so the library reads what the binding writes."""
     cls = getattr(H, name)
-    ctype_of = {"int": ctypes.c_int, "double": ctypes.c_double}
+    ctype_of = {"int": ctypes.c_int, "double": ctypes.c_double, "int*": ctypes.POINTER(ctypes.c_int),
+                "double*": ctypes.POINTER(ctypes.c_double)}
     want = _header_struct_fields(name)
     got = cls._fields_
     assert [f for f, _, _ in want] == [f for f, _ in got]
@@ -143,3 +148,40 @@ def test_population_bytes_follow_the_documented_layout():
     assert H.population_bytes(q25, (7, 300), "i16_dev") == 25 * 7 * 320 * 2
     q53 = H.Lattice(W.Q53_RECT.kind, W.Q53_RECT.c, W.Q53_RECT.cs2, W.Q53_RECT.free)
     assert H.population_bytes(q53, (6, 10, 70), "fp64") == 53 * 60 * 96 * 8
+
+
+def _shuffled(card, seed=0):
+    lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
+    perm = np.random.default_rng(seed).permutation(lat.b)
+    return lat.e[perm], lat.w[perm]
+
+
+@pytest.mark.parametrize("card", [W.Q25_RECT, W.Q33_CUBIC, W.Q21K_RECT], ids=lambda c: c.kind)
+def test_custom_lattice_matches_oracle(card):
+    """A user-supplied velocity set (a known lattice in shuffled order):
+    the library keeps e and w and builds W-orthogonal rows spanning the
+    oracle's, with the same corrected pure rows."""
+    e, w = _shuffled(card, 5)
+    q = H.Lattice("custom", card.c, card.cs2, e=e, w=w).query()
+    lat = OL.custom_lattice("custom", card.c, card.cs2, e, w)
+    assert np.array_equal(q["e"], e) and np.array_equal(q["w"], w)
+    Hm = q["H"]
+    G = (Hm * w) @ Hm.T
+    assert np.abs(G - np.diag(np.diag(G))).max() < 1e-12 * np.abs(np.diag(G)).max()
+    pure_o = lat.H()[[r.name in ("xxx", "yyy", "zzz") for r in lat.rows]]
+    assert np.allclose(pure_o, Hm[-lat.d:], atol=1e-12)
+
+
+def test_custom_lattice_errors():
+    e, w = _shuffled(W.Q25_RECT)
+    for kw, status in [(dict(e=e, w=w * 1.01), H.MRTLB_EINVAL),                  # weights do not sum to 1
+                       (dict(e=e * 3, w=w), H.MRTLB_EINVAL),                      # |e| > 8
+                       (dict(e=e[:, :1].repeat(2, 1), w=w), H.MRTLB_ENUMERIC)]:   # rows not orthogonal
+        with pytest.raises(H.MrtlbError) as err:
+            H.Lattice("custom", W.Q25_RECT.c, W.Q25_RECT.cs2, **kw)
+        assert err.value.status == status
+    # the single-layer D2Q9 has no independent pure third-order rows
+    q9 = OL.make_lattice("D2Q9", (1.0, 1.0), 1 / 3)
+    with pytest.raises(H.MrtlbError) as err:
+        H.Lattice("custom", (1.0, 1.0), 1 / 3, e=q9.e, w=q9.w)
+    assert err.value.status == H.MRTLB_ENUMERIC

@@ -484,6 +484,57 @@ def test_batch_equals_single_new_models(ctx):
                 assert np.array_equal(a.read_populations(), b.read_populations())
 
 
+def _shuffled_set(card, seed):
+    from oracle import lattice as OL
+    lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
+    perm = np.random.default_rng(seed).permutation(lat.b)
+    return OL.custom_lattice("custom", card.c, card.cs2, lat.e[perm], lat.w[perm])
+
+
+@pytest.mark.parametrize("card,shape", [(W.Q25_RECT, (7, 300)), (W.Q25_RECT, (37, 66)), (W.Q21K_RECT, (20, 40)),
+                                        (W.Q33_CUBIC, (5, 9, 66))],
+                         ids=["rD2Q25-7x300", "rD2Q25-37x66", "D2Q21K", "rD3Q33"])
+@pytest.mark.parametrize("eq", ["NSE_INC", "NSE_COMP"])
+@pytest.mark.parametrize("forced", [False, True], ids=["free", "force"])
+def test_custom_lattice(ctx, card, shape, eq, forced):
+    """A user-supplied velocity set (a known lattice, velocities shuffled)
+    through the run-time-generic kernels, against the oracle built from the
+    same set and weights."""
+    olat = _shuffled_set(card, 9)
+    rates = W.Rates(1.1, 1.3, 1.6, 1.05, 1.4, 0.9)
+    rho, u = _random_fields(card, shape, 43)
+    F = W.sinusoidal_force(card, shape, 1e-3, seed=8) if forced else None
+    steps = 12
+    mdl = OM.Model(eq=eq, rho0=1.0, s0=rates.s0, s1=rates.s1, s_shear=rates.s_shear, s_bulk=rates.s_bulk,
+                   s3=rates.s3, s_h=rates.s_h)
+    st = OM.run(olat, mdl, OM.init_state(olat, mdl, rho, u, F), steps, F)
+    r_o, u_o = OM.moments(olat, mdl, st, F)
+    hl = H.Lattice("custom", card.c, card.cs2, e=olat.e, w=olat.w)
+    for storage, tr, tu in (("fp64", 1e-13, 1e-11), ("fp32", 1e-6, 2e-4), ("fp32_dev", 1e-6, 2e-5),
+                            ("i16_dev", 1e-4, 1e-2)):
+        print("case: custom %s %s %s force=%s %s" % (card.kind, eq, shape, forced, storage), flush=True)
+        s = H.Solve(ctx, hl, hip_model(eq, rates), shape, storage, has_force=F is not None)
+        s.init_fields(rho, u, F)
+        s.step(steps)
+        r, v = s.read_moments()
+        assert max_rel(r, r_o) < tr
+        assert max_rel(v, u_o) < tu
+        if storage == "fp64":
+            f = s.read_populations()
+            assert np.abs(f - st.f).max() / np.abs(st.f).max() < 1e-12
+            s.write_populations(f)             # restore through the custom scatter
+            assert np.array_equal(s.read_populations(), f)
+        s.close()
+
+
+def test_custom_lattice_refuses_the_ncde(ctx):
+    olat = _shuffled_set(W.Q13_SQUARE, 2)
+    hl = H.Lattice("custom", W.Q13_SQUARE.c, W.Q13_SQUARE.cs2, e=olat.e, w=olat.w)
+    with pytest.raises(H.MrtlbError) as e:
+        H.Solve(ctx, hl, hip_model("NCDE", W.Rates(), D0=0.1), (16, 16), "fp32")
+    assert e.value.status == H.MRTLB_EINVAL
+
+
 def test_external_population_buffers(ctx):
     """mrtlb_solve_create_external: caller-owned device buffers (allocated
     here with the HIP runtime directly) hold the populations in the
