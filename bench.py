@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--lattice2d", default="rD2Q25", choices=["rD2Q25", "rD2Q21", "D2Q21K", "D2Q9"],
                     help="lattice of the tgv2d workload (rD2Q21: rD2Q25 subgroup; D2Q21K: knight-move D2Q21; "
                          "D2Q9: standard lattice, k = 1 model)")
+    ap.add_argument("--custom", action="store_true",
+                    help="tgv2d: run the lattice's velocity set as a user-supplied (run-time) lattice")
     ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33", "D3Q27"],
                     help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -304,6 +306,10 @@ def main():
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
+    if args.custom:
+        # the same velocity set and weights as a user-supplied (run-time) lattice
+        q = lat.query()
+        lat = H.Lattice("custom", card.c, card.cs2, e=q["e"], w=q["w"])
     md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
                       m30=card.kind not in STANDARD, **_bounds(W, args.storage, wl))
     s = H.Solve(ctx, lat, md, shape, args.storage)
@@ -323,7 +329,8 @@ def main():
     achieved = launch_bytes / per_launch_s / 1e9
     value = nodes * args.steps / wall / 1e6
     out = {
-        "metric": "%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline" % card.kind,
+        "metric": "%s%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline"
+                  % (card.kind, " as a user-supplied lattice" if args.custom else ""),
         "value": round(value, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -335,12 +342,14 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic",
-        "config": {"workload": "tgv-%s-%dx%d" % (card.kind, shape[1], shape[0]), "lattice": card.kind,
+        "config": {"workload": "tgv-%s-%dx%d" % (card.kind, shape[1], shape[0]),
+                   "lattice": card.kind + (" (user-supplied)" if args.custom else ""),
                    "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes,
                    "tau_shear": 0.6, "mass_check": mass},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.storage, launch_bytes) if card.kind == "rD2Q25" else None,
+                     "traffic": (measured_traffic(args.storage, launch_bytes)
+                                 if card.kind == "rD2Q25" and not args.custom else None),
                      "kernel_ms_per_launch": round(per_launch_s * 1e3, 5),
                      "algorithmic_bytes_per_launch": launch_bytes},
     }
