@@ -654,6 +654,38 @@ def test_full_size_sampled(ctx):
     assert abs(m_after - wl.rho_or_phi.sum()) < 1e-6 * wl.rho_or_phi.sum()
 
 
+def _crop3(a, iz, iy, ix, r):
+    nz, ny, nx = a.shape[-3:]
+    zs = (np.arange(iz - r, iz + r + 1)) % nz
+    ys = (np.arange(iy - r, iy + r + 1)) % ny
+    xs = (np.arange(ix - r, ix + r + 1)) % nx
+    return a[..., zs[:, None, None], ys[None, :, None], xs[None, None, :]]
+
+
+def test_full_size_sampled_3d(ctx):
+    """The rD3Q53 256^3 compressible Taylor-Green benchmark workload, FP32, in
+    the launch configuration the benchmark times: sampled nodes against the
+    oracle on crops wide enough for the nodes' dependency cones."""
+    wl = W.tgv3d(shape=(256, 256, 256), steps=3)
+    steps = 3
+    print("case: tgv3d-rD3Q53-256^3 fp32 sampled", flush=True)
+    s = H.Solve(ctx, hip_lattice(wl.card), hip_model(wl.eq, wl.rates), wl.shape, "fp32")
+    s.init_fields(wl.rho_or_phi, wl.u)
+    s.step(steps)
+    r, v = s.read_moments()
+    s.close()
+    rng = np.random.default_rng(1)
+    R = 2 * steps + 1                                  # largest offset 2
+    lat, mdl = oracle_for(wl.card, wl.eq, wl.rates)
+    pts = [(0, 0, 0), (255, 255, 255), (128, 3, 250)] + [tuple(rng.integers(0, 256, 3)) for _ in range(3)]
+    for iz, iy, ix in pts:
+        st = OM.run(lat, mdl, OM.init_state(lat, mdl, _crop3(wl.rho_or_phi, iz, iy, ix, R),
+                                            _crop3(wl.u, iz, iy, ix, R)), steps)
+        ro, uo = OM.moments(lat, mdl, st)
+        assert abs(r[iz, iy, ix] - ro[R, R, R]) < 1e-6 * abs(ro[R, R, R])
+        assert np.abs(v[:, iz, iy, ix] - uo[:, R, R, R]).max() < 1e-6 * 0.1 * np.sqrt(wl.card.cs2)
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16_dev", "i16_dev", "fp64"])
 def test_launch_shape_invariance(ctx, storage, monkeypatch):
     """1, 2 or 4 nodes per thread change only the memory access pattern of
