@@ -686,6 +686,39 @@ def test_full_size_sampled_3d(ctx):
         assert np.abs(v[:, iz, iy, ix] - uo[:, R, R, R]).max() < 1e-6 * 0.1 * np.sqrt(wl.card.cs2)
 
 
+def test_full_size_sampled_ncde_batch(ctx):
+    """The 256-solve rD2Q13 NCDE batch benchmark workload (sides 128-1024),
+    FP32, advanced by batched launches: sampled nodes of several solves
+    against the oracle on crops covering the nodes' dependency cones (two
+    lattice offsets plus the one-node stencil of the lagged gradient per step)."""
+    wls = W.ncde_batch(256, steps=3)
+    steps = 3
+    print("case: ncde-batch-rD2Q13-256 fp32 sampled", flush=True)
+    card = wls[0].card
+    lat_h = hip_lattice(card)
+    solves = []
+    for wl in wls:
+        s = H.Solve(ctx, lat_h, hip_model("NCDE", wl.rates, D0=wl.D0, D2=wl.D2, adv=wl.adv_u), wl.shape, "fp32")
+        s.init_fields(wl.rho_or_phi)
+        solves.append(s)
+    H.batch_step(solves, steps)
+    sizes = [w.shape[0] for w in wls]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 200})
+    rng = np.random.default_rng(2)
+    R = 3 * steps + 2
+    for k in picks:
+        wl = wls[k]
+        phi = solves[k].read_moments(with_u=False)
+        lat, mdl = oracle_for(card, "NCDE", wl.rates, D0=wl.D0, D2=wl.D2, adv=wl.adv_u)
+        n = wl.shape[0]
+        for iy, ix in [(0, 0), (n - 1, n // 2)] + [tuple(rng.integers(0, n, 2)) for _ in range(2)]:
+            st = OM.run(lat, mdl, OM.init_state(lat, mdl, _crop(wl.rho_or_phi, iy, ix, R)), steps)
+            po, _ = OM.moments(lat, mdl, st)
+            assert abs(phi[iy, ix] - po[R, R]) < 1e-6 * max(abs(po[R, R]), 1e-3 * np.abs(wl.rho_or_phi).max())
+    for s in solves:
+        s.close()
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16_dev", "i16_dev", "fp64"])
 def test_launch_shape_invariance(ctx, storage, monkeypatch):
     """1, 2 or 4 nodes per thread change only the memory access pattern of
