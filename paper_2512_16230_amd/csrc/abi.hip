@@ -1029,7 +1029,9 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
     const mrtlb_solve* a = solves[i];
     for (int k = i; k < n; ++k) {
       const mrtlb_solve* b = solves[k];
-      if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->storage == a->storage &&
+      // one launch serves one kernel: same lattice kind and dimension (user-
+      // supplied lattices share a kind), storage, model, force and VEC
+      if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->L.D == a->L.D && b->storage == a->storage &&
           b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec) {
         grp.emplace_back(solves[k], nsteps[k]);
         done[k] = 1;

@@ -527,6 +527,28 @@ def test_custom_lattice(ctx, card, shape, eq, forced):
         s.close()
 
 
+def test_custom_lattice_batch(ctx):
+    """User-supplied lattices of different sizes and dimensions in one
+    batch_step call: each solve ends where its solo run does, bit for bit."""
+    cases = [(W.Q25_RECT, (20, 40), 3), (W.Q21K_RECT, (30, 33), 4), (W.Q33_CUBIC, (6, 7, 9), 5),
+             (W.Q25_RECT, (9, 70), 6)]
+    solo, batch = [], []
+    for card, shape, seed in cases:
+        olat = _shuffled_set(card, seed)
+        hl = H.Lattice("custom", card.c, card.cs2, e=olat.e, w=olat.w)
+        rho, u = _random_fields(card, shape, seed)
+        for lst in (solo, batch):
+            s = H.Solve(ctx, hl, hip_model("NSE_COMP", W.rates_tau(0.8)), shape, "fp32")
+            s.init_fields(rho, u)
+            lst.append(s)
+    counts = [5, 3, 4, 0]
+    for s, k in zip(solo, counts):
+        s.step(k)
+    H.batch_step(batch, counts)
+    for a, b in zip(solo, batch):
+        assert np.array_equal(a.read_populations(), b.read_populations())
+
+
 def test_custom_lattice_refuses_the_ncde(ctx):
     olat = _shuffled_set(W.Q13_SQUARE, 2)
     hl = H.Lattice("custom", W.Q13_SQUARE.c, W.Q13_SQUARE.cs2, e=olat.e, w=olat.w)
