@@ -287,7 +287,8 @@ mrtlb_status mrtlb_population_bytes(const mrtlb_lattice* lat, const int64_t n[3]
  * other work until mrtlb_solve_destroy.  The remaining device memory
  * (parameters, force and history fields) is the library's and counts
  * against the budget.  Errors: as mrtlb_solve_create, and EINVAL for NULL,
- * equal or misaligned buffers. */
+ * equal, overlapping or misaligned buffers and for pointers that are not
+ * device memory on the context's device. */
 mrtlb_status mrtlb_solve_create_external(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
                                          const int64_t n[3], int storage, int has_force, void* f0, void* f1,
                                          mrtlb_solve** out);

@@ -678,6 +678,15 @@ mrtlb_status mrtlb_solve_create_external(mrtlb_ctx* ctx, const mrtlb_lattice* la
   if (st != MRTLB_OK) return st;
   const uintptr_t a = (uintptr_t)f0, b = (uintptr_t)f1;
   if ((a < b ? b - a : a - b) < pop) return fail(MRTLB_EINVAL, "the two population buffers overlap");
+  if (!ctx) return fail(MRTLB_EINVAL, "NULL argument");
+  for (void* p : {f0, f1}) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != ctx->device) {
+      (void)hipGetLastError();
+      return fail(MRTLB_EINVAL, "external population buffers must be device memory on the context's device");
+    }
+  }
   return create_solve(ctx, lat, model, n, storage, has_force, f0, f1, out);
 }
 

@@ -591,7 +591,9 @@ def test_external_population_buffers(ctx):
         assert np.array_equal(own.read_populations(), ext.read_populations())
         own.close()
         ext.close()
-        for bad in ((bufs[0] + 4, bufs[1]), (bufs[0], bufs[0] + 16), (bufs[0], bufs[0])):
+        hostbuf = np.zeros(2 * nbytes // 8 + 64)
+        hp = (hostbuf.ctypes.data + 15) // 16 * 16
+        for bad in ((bufs[0] + 4, bufs[1]), (bufs[0], bufs[0] + 16), (bufs[0], bufs[0]), (hp, bufs[1])):
             with pytest.raises(H.MrtlbError) as e:
                 H.Solve(ctx, lat, model, shape, storage, external=bad)
             assert e.value.status == H.MRTLB_EINVAL
