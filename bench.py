@@ -130,9 +130,10 @@ def bench_tgv3d(torch, H, W, stream, args):
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
     md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                      m30=card.kind not in STANDARD, **_bounds(W, args.storage, wl))
-    s = H.Solve(ctx, lat, md, shape, args.storage)
-    s.init_fields(wl.rho_or_phi, wl.u)
+                      m30=card.kind not in STANDARD, mass_src=args.mass_src, **_bounds(W, args.storage, wl))
+    forced = args.mass_src != 0          # the mass source runs in the forced kernel (zero force field)
+    s = H.Solve(ctx, lat, md, shape, args.storage, has_force=forced)
+    s.init_fields(wl.rho_or_phi, wl.u, np.zeros((3,) + shape) if forced else None)
     del wl
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -142,8 +143,9 @@ def bench_tgv3d(torch, H, W, stream, args):
     wall = time.perf_counter() - t0
     nodes = n ** 3
     bq = {"rD3Q53": 53, "rD3Q45": 45, "rD3Q33": 33, "D3Q27": 27}[card.kind]
-    launch_bytes = 2 * bq * STORE_BYTES[args.storage] * nodes
-    out = _line("%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline" % card.kind,
+    launch_bytes = (2 * bq * STORE_BYTES[args.storage] + (3 * 4 if forced else 0)) * nodes
+    out = _line("%s MRT-LB MLUPS (fused collide-and-stream%s), %% of HBM roofline"
+                % (card.kind, ", mass source" if forced else ""),
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
                 {"workload": "tgv3d-%s-%dx%dx%d" % (card.kind, n, n, n), "lattice": card.kind,
                                       "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes},
@@ -195,8 +197,10 @@ def bench_ncde_batch(torch, H, W, stream, args):
     solves = []
     for wl in wls:
         r = wl.rates
+        extra = (dict(gn_bt=(0.1, -0.05, 0.0), gn_dd=(0.01, 0.02, 0.0), src_q=1e-4, src_k=-1e-3, three_level=True)
+                 if args.gncde else {})
         md = H.model_desc("NCDE", s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                          D0=wl.D0, D2=wl.D2, adv_u=wl.adv_u, **_bounds(W, args.storage, wl))
+                          D0=wl.D0, D2=wl.D2, adv_u=wl.adv_u, **extra, **_bounds(W, args.storage, wl))
         s = H.Solve(ctx, lat, md, wl.shape, args.storage)
         s.init_fields(wl.rho_or_phi)
         solves.append(s)
@@ -210,7 +214,8 @@ def bench_ncde_batch(torch, H, W, stream, args):
     wall = time.perf_counter() - t0
     real = 8 if args.storage == "fp64" else 4
     launch_bytes = (2 * 13 * STORE_BYTES[args.storage] + 2 * real) * nodes
-    out = _line("rD2Q13 NCDE batch MLUPS (256 solves, one launch per step), % of HBM roofline",
+    out = _line("rD2Q13 NCDE batch MLUPS (256 solves, one launch per step%s), %% of HBM roofline"
+                % (", general terms, source, three-level scheme" if args.gncde else ""),
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
                 {"workload": "ncde-batch-rD2Q13-256-solves", "lattice": "rD2Q13", "storage": args.storage,
                  "nodes": nodes, "solves": len(solves)}, args.storage, launch_bytes, wall / args.steps)
@@ -269,6 +274,10 @@ def main():
     ap.add_argument("--lattice2d", default="rD2Q25", choices=["rD2Q25", "rD2Q21", "D2Q21K", "D2Q9"],
                     help="lattice of the tgv2d workload (rD2Q21: rD2Q25 subgroup; D2Q21K: knight-move D2Q21; "
                          "D2Q9: standard lattice, k = 1 model)")
+    ap.add_argument("--gncde", action="store_true",
+                    help="ncde-batch: general NCDE terms (gn_bt, gn_dd), a source and the three-level scheme")
+    ap.add_argument("--mass-src", type=float, default=0.0,
+                    help="tgv3d: compressible NSE with this uniform mass source (forced kernel)")
     ap.add_argument("--custom", action="store_true",
                     help="tgv2d: run the lattice's velocity set as a user-supplied (run-time) lattice")
     ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33", "D3Q27"],
