@@ -112,7 +112,7 @@ mrtlb_status mrtlb_ctx_synchronize(mrtlb_ctx* ctx);
  *                 pure third-order rows, and their normal second-order rows
  *                 relax with the non-diagonal S2 block of eqs. (4-27),
  *                 (4-27-1) (see mrtlb_model_desc).  Use m30 = 0 (M30 = 0
- *                 there).
+ *                 there).  The NCDE and CDE models run on D2Q9 too.
  * c[0..d-1] = c_a = dx_a/dt; cs2 = sound speed squared (direction
  * independent, Remark 2).  The Hermite rows of orders 0..3 are
  * H0 = 1, H1 = c, H2 = cc - cs^2 I, H3 = c_a(c_b^2 - cs^2), c_x c_y c_z and

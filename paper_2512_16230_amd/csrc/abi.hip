@@ -520,8 +520,6 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
   if (L.kind == kCustom && m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
     return fail(MRTLB_EINVAL, "custom lattices carry the NSE models only");
   if (L.standard) {
-    if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
-      return fail(MRTLB_EINVAL, "the standard lattices carry the k = 1 NSE models only");
     double S2[3][3];
     if (!s2_normal_block(L, m, S2)) return fail(MRTLB_EINVAL, "singular S2 block for these rates and this lattice");
   }

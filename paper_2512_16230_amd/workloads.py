@@ -58,6 +58,7 @@ Q45_RECT = Card("rD3Q45", (1.0, 1.25, 1.5), 0.86, (4.3e-3, 4.8e-4, 4.3e-4))
 # standard single-layer lattices (k = 1 model, non-diagonal S2 block) on
 # the same aspect ratios; every weight is positive for cs^2 < min c_a^2
 Q9_RECT = Card("D2Q9", (1.5, 1.0), 0.5)
+Q9_SQUARE = Card("D2Q9", (1.0, 1.0), 1 / 3)
 Q27_RECT = Card("D3Q27", (1.0, 1.25, 1.5), 0.6)
 
 

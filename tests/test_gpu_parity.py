@@ -183,9 +183,30 @@ def test_standard_lattices(ctx, card, shape, eq, forced):
         assert max_rel(v, u_o) < tu
 
 
-def test_standard_lattice_refuses_the_ncde(ctx):
-    with pytest.raises(H.MrtlbError) as e:
-        H.Solve(ctx, hip_lattice(W.Q9_RECT), hip_model("NCDE", W.Rates(), D0=0.1), (16, 16), "fp32")
+@pytest.mark.parametrize("card", [W.Q9_RECT, W.Q9_SQUARE], ids=["D2Q9-rect", "D2Q9-square"])
+def test_standard_lattice_ncde_and_cde(ctx, card):
+    """NCDE (nonlinear D, general terms, source) and CDE (shear velocity field)
+    on the standard D2Q9 against the oracle, ragged tiles."""
+    shape = (37, 70)
+    wl = W.ncde_hill(shape, adv_u=(0.03, -0.02), D0=0.1, D2=1.0, card=card)
+    kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u, gn_bt=(0.1, 0.0, 0.0), src_k=-0.01)
+    phi_o, _, _ = _oracle_run(card, "NCDE", wl.rates, wl.rho_or_phi, None, 20, **kw)
+    cw = W.cde_hill(shape, 20, u=W.shear_field(card, shape, 0.04), D0=0.1, card=card)
+    lat, mdl = oracle_for(card, "CDE", cw.rates)
+    st = OM.run(lat, mdl, OM.init_state(lat, mdl, cw.rho_or_phi), 20, force=cw.u)
+    cphi_o, _ = OM.moments(lat, mdl, st, force=cw.u)
+    for storage, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        print("case: %s NCDE/CDE %s" % (card.kind, storage), flush=True)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, **kw), shape, storage)
+        s.init_fields(wl.rho_or_phi)
+        s.step(20)
+        assert max_rel(s.read_moments(with_u=False), phi_o) < tol
+        c = H.Solve(ctx, hip_lattice(card), hip_model("CDE", cw.rates), shape, storage)
+        c.init_fields(cw.rho_or_phi, cw.u)
+        c.step(20)
+        assert max_rel(c.read_moments(with_u=False), cphi_o) < tol
+    with pytest.raises(H.MrtlbError) as e:       # the NCDE is built for 2D lattices
+        H.Solve(ctx, hip_lattice(W.Q27_RECT), hip_model("NCDE", W.Rates(), D0=0.1), (8, 8, 8), "fp32")
     assert e.value.status == H.MRTLB_EINVAL
 
 

@@ -90,8 +90,8 @@ def test_taylor_green_3d_energy_decay(card):
     assert 3.0 < abs(coarse - 1) / abs(fine - 1) < 5.5
 
 
-def _hill_error(N, steps, adv=(0.03, -0.02), D0=0.1):
-    wl = W.ncde_hill((N, N), adv_u=adv, D0=D0, D2=0.0)
+def _hill_error(N, steps, adv=(0.03, -0.02), D0=0.1, card=W.Q13_SQUARE):
+    wl = W.ncde_hill((N, N), adv_u=adv, D0=D0, D2=0.0, card=card)
     lat, mdl = setup(wl)
     st = M.init_state(lat, mdl, wl.rho_or_phi)
     mass0 = st.f.sum()
@@ -157,8 +157,8 @@ def test_nonlinear_diffusion_second_moment_identity():
 # CDE special case (3): diffusion-type equilibrium, S_G = -u . grad(phi)
 # --------------------------------------------------------------------------
 
-def _cde_hill_error(N, steps, adv=(0.03, -0.02), D0=0.1):
-    wl = W.cde_hill((N, N), steps, u=adv, D0=D0)
+def _cde_hill_error(N, steps, adv=(0.03, -0.02), D0=0.1, card=W.Q13_SQUARE):
+    wl = W.cde_hill((N, N), steps, u=adv, D0=D0, card=card)
     lat, mdl = setup(wl)
     st = M.init_state(lat, mdl, wl.rho_or_phi)
     st = M.run(lat, mdl, st, steps, force=wl.u)
@@ -315,3 +315,15 @@ def test_source_adds_its_rate_to_a_fourier_mode(three_level):
     plain = rate(0.0)
     assert abs(plain / (-0.05 * kv * kv) - 1) < 0.01
     assert abs(rate(kap) - plain - kap) < 0.01 * abs(kap)
+
+
+def test_ncde_and_cde_on_the_standard_d2q9():
+    """The NCDE (linear D) and the CDE on the standard D2Q9: the same
+    closed-form advected Gaussian hill and second-order convergence (the
+    convection-diffusion models need only the isotropic second moment)."""
+    e64, dm = _hill_error(64, 100, card=W.Q9_SQUARE)
+    e32, _ = _hill_error(32, 25, card=W.Q9_SQUARE)
+    assert abs(dm) < 1e-13 and e64 < 1.5e-2 and 3.0 < e32 / e64 < 5.0
+    c64 = _cde_hill_error(64, 100, card=W.Q9_SQUARE)
+    c32 = _cde_hill_error(32, 25, card=W.Q9_SQUARE)
+    assert c64 < 2e-2 and 3.0 < c32 / c64 < 5.5
