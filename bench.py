@@ -286,7 +286,7 @@ def main():
                     help="time a plain device copy of 2 x 1.68 GB instead (HBM reference and counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the multi-GPU (slab-decomposed) path is not part of this build",
+        print("bench.py runs on one GPU only: the library has no multi-GPU (slab-decomposed) path",
               file=sys.stderr)
         sys.exit(2)
 
