@@ -107,3 +107,66 @@ def test_wrong_cde_gradient_is_caught(monkeypatch):
     orig = M.cde_source
     monkeypatch.setattr(M, "cde_source", lambda *a: 0.5 * orig(*a))
     _pin_fails(TD.test_cde_gaussian_hill_closed_form)
+
+
+# --------------------------------------------------------------------------
+# standard lattices, general NCDE, source schemes
+# --------------------------------------------------------------------------
+
+import test_oracle_standard as TS  # noqa: E402
+
+
+def test_wrong_standard_weights_are_caught(monkeypatch):
+    orig = L.weights_standard
+    monkeypatch.setattr(L, "weights_standard", lambda e, c, cs2: orig(e, c, cs2 * 1.02))
+    _pin_fails(TS.test_rectangular_weights_meet_the_moment_conditions, W.Q9_RECT)
+
+
+def test_wrong_sign_in_the_s2_block_is_caught(monkeypatch):
+    """a_a = (1/s_ba - 1/s_sa)(c_a^2 - cs^2) with the sign flipped."""
+    def flipped(lat, model):
+        d, cs2 = lat.d, lat.cs2
+        nu = cs2 * (1.0 / model.s_shear - 0.5)
+        nu_b = (2.0 / d) * cs2 * (1.0 / model.s_bulk - 0.5)
+        g = np.array([lat.c[a] ** 2 - cs2 for a in range(d)])
+        inv_ss, inv_sb = 0.5 + 2 * nu / g, 0.5 + d * nu_b / g
+        return np.linalg.inv(np.diag(inv_ss) + np.outer((inv_ss - inv_sb) * g, 1.0 / g) / d)
+    monkeypatch.setattr(M, "s2_normal_block", flipped)
+    _pin_fails(TS.test_sound_damping_on_rectangular_lattices, W.Q9_RECT, 0)
+
+
+def test_wrong_sign_of_the_ncde_cross_terms_is_caught(monkeypatch):
+    orig = M.ncde_cross
+
+    def neg(*a):
+        x = orig(*a)
+        return None if x is None else -x
+    monkeypatch.setattr(M, "ncde_cross", neg)
+    _pin_fails(TD.test_general_ncde_fourier_mode, (0.2, 0.1), (0.0, 0.0), (0.02, -0.01))
+
+
+def test_missing_source_correction_is_caught(monkeypatch):
+    """phi = sum f_bar without the S/2 of eq. 2-4-1 under full correction."""
+    orig = M.macroscopic
+
+    def uncorrected(lat, model, f, force=None):
+        R0, u, rho_m = orig(lat, model, f, force)
+        if model.eq == M.NCDE and not model.three_level:
+            R0 = f.sum(axis=0)
+        return R0, u, rho_m
+    monkeypatch.setattr(M, "macroscopic", uncorrected)
+    _pin_fails(TD.test_source_full_correction_is_the_trapezoidal_rule)
+
+
+def test_first_order_source_scheme_is_caught(monkeypatch):
+    """Dropping the (F(t) - F(t - dt))/2 term of the three-level scheme
+    leaves a first-order (explicit Euler) source."""
+    orig_collide = M.collide
+
+    def euler(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None):
+        if model.eq == M.NCDE and model.three_level:
+            R0 = M.macroscopic(lat, model, f)[0]
+            phi_prev = R0              # F(t - dt) = F(t): the correction term vanishes
+        return orig_collide(lat, model, f, force, ncde_b, ncde_x, phi_prev)
+    monkeypatch.setattr(M, "collide", euler)
+    _pin_fails(TD.test_source_three_level_scheme_is_second_order)
