@@ -170,3 +170,19 @@ def test_first_order_source_scheme_is_caught(monkeypatch):
         return orig_collide(lat, model, f, force, ncde_b, ncde_x, phi_prev)
     monkeypatch.setattr(M, "collide", euler)
     _pin_fails(TD.test_source_three_level_scheme_is_second_order)
+
+
+# --------------------------------------------------------------------------
+# bulk viscosity on the multispeed lattices
+# --------------------------------------------------------------------------
+
+import test_oracle_sound as TSO  # noqa: E402
+
+
+@pytest.mark.parametrize("card,axis", [(W.Q25_RECT, 1), (W.Q53_RECT, 2)], ids=["rD2Q25-y", "rD3Q53-z"])
+def test_trace_row_at_the_shear_rate_is_caught(card, axis, monkeypatch):
+    """The trace of the normal second-order rows relaxing at s_shear instead
+    of s_bulk (a wrong bulk viscosity) misses the acoustic damping."""
+    orig = M.Model.rate
+    monkeypatch.setattr(M.Model, "rate", lambda self, g: orig(self, "shear" if g == "bulk" else g))
+    _pin_fails(TSO.test_sound_damping_sets_the_bulk_viscosity, card, axis)
