@@ -55,31 +55,37 @@ def measured_traffic(storage, launch_bytes):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(sample_shape=(512, 512), steps=200):
-    """The FP64 oracle on a bounded sample of the same workload."""
+def cpu_baseline(sample_shape=(512, 512), steps=100):
+    """The FP64 oracle on a bounded sample of the same workload, timed with
+    the host's BLAS threads and again with one thread."""
     from oracle import lattice as OL
     from oracle import model as OM
     from paper_2512_16230_amd import workloads as W
+    from threadpoolctl import threadpool_info, threadpool_limits
 
-    threads = None
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max((p.get("num_threads") or 1) for p in threadpool_info()) if threadpool_info() else 1
-    except Exception:
-        threads = os.cpu_count()
+    info = threadpool_info()
+    threads = max((p.get("num_threads") or 1) for p in info) if info else 1
     wl = W.tgv_large(0, shape=sample_shape, steps=steps)
     card, r = wl.card, wl.rates
     lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
     mdl = OM.Model(eq=wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_h=r.s_h)
     st = OM.init_state(lat, mdl, wl.rho_or_phi, wl.u)
     st = OM.step(lat, mdl, st)               # warm-up
-    t0 = time.perf_counter()
-    OM.run(lat, mdl, st, steps)
-    dt = time.perf_counter() - t0
     n = sample_shape[0] * sample_shape[1]
+
+    def timed():
+        t0 = time.perf_counter()
+        OM.run(lat, mdl, st, steps)
+        return time.perf_counter() - t0
+
+    dt = timed()
+    with threadpool_limits(limits=1):
+        dt1 = timed()
     return {"value": round(n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%dx%d rD2Q25 TGV, %d FP64 steps, %.1f s (elementwise NumPy single-threaded, "
-                      "BLAS matmuls on %s threads)" % (sample_shape[1], sample_shape[0], steps, dt, threads)}
+            "value_1_thread": round(n * steps / dt1 / 1e6, 4),
+            "sample": "%dx%d rD2Q25 TGV (the benchmark physics on a smaller box), %d FP64 steps: %.1f s with "
+                      "BLAS on %d threads (elementwise NumPy single-threaded), %.1f s with one thread"
+                      % (sample_shape[1], sample_shape[0], steps, dt, threads, dt1)}
 
 
 def copy_probe(torch, dev, steps, warmup):
@@ -104,7 +110,8 @@ def _bounds(W, storage, wl):
     """Flow bounds that size the int16 storage's ranges (only that storage uses them)."""
     if storage != "i16_dev":
         return {}
-    ub, db = W.flow_bounds(wl.eq, wl.rho_or_phi, wl.u, wl.force, wl.steps, wl.rho0, wl.adv_u)
+    ub, db = W.flow_bounds(wl.eq, wl.rho_or_phi, wl.u, wl.force, wl.steps, wl.rho0, wl.adv_u, cs2=wl.card.cs2,
+                           mass_src=getattr(wl, "mass_src", 0.0))
     return {"u_bound": ub, "dev_bound": db}
 
 
@@ -152,7 +159,7 @@ def bench_tgv3d(torch, H, W, stream, args):
                 args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
     s.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_cde(torch, H, W, stream, args):
@@ -185,7 +192,7 @@ def bench_cde(torch, H, W, stream, args):
                  "nodes": nodes}, args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
     s.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_ncde_batch(torch, H, W, stream, args):
@@ -222,7 +229,7 @@ def bench_ncde_batch(torch, H, W, stream, args):
     for s in solves:
         s.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_serve(stream, args):
@@ -255,7 +262,7 @@ def bench_serve(stream, args):
            "offered_load_vs_measured_capacity": round(work / busy_rate / window, 3) if window > 0 else None,
            "max_resident": s["max_resident"], "failed": s["failed"],
            "host_split_s": {k: round(s[k], 3) for k in ("t_create_s", "t_step_s", "t_read_s", "t_wait_s")}}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -263,9 +270,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="fp32", choices=sorted(STORE_BYTES))
+    ap.add_argument("--storage", default="fp32_dev", choices=sorted(STORE_BYTES))
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload: time only the rD2Q25 FP32 line (no int16, rD3Q53 and serving legs)")
+    ap.add_argument("--serve-rate-low", type=float, default=50.0,
+                    help="legs: arrival rate of the served stream near 0.8 of capacity (requests/s)")
+    ap.add_argument("--serve-requests", type=int, default=300, help="legs: requests per served window")
     ap.add_argument("--workload", default="tgv2d", choices=["tgv2d", "tgv3d", "ncde-batch", "cde", "serve"],
                     help="tgv2d: rD2Q25 4096^2 (default); tgv3d: rD3Q53 256^3 compressible; "
                          "ncde-batch: 256 rD2Q13 NCDE solves advanced by one batched launch per step")
@@ -302,13 +314,63 @@ def main():
         return
     stream = torch.cuda.current_stream(dev)
     if args.workload == "tgv3d":
-        return bench_tgv3d(torch, H, W, stream, args)
+        return emit(bench_tgv3d(torch, H, W, stream, args))
     if args.workload == "ncde-batch":
-        return bench_ncde_batch(torch, H, W, stream, args)
+        return emit(bench_ncde_batch(torch, H, W, stream, args))
     if args.workload == "cde":
-        return bench_cde(torch, H, W, stream, args)
+        return emit(bench_cde(torch, H, W, stream, args))
     if args.workload == "serve":
-        return bench_serve(stream, args)
+        return emit(bench_serve(stream, args))
+    out = bench_tgv2d(torch, H, W, stream, args)
+    if not args.no_legs and not args.custom and args.lattice2d == "rD2Q25" and args.size == 4096:
+        out["legs"] = other_legs(torch, H, W, stream, args)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    emit(out)
+
+
+def emit(out):
+    print(json.dumps(out), flush=True)
+
+
+def _leg_summary(line):
+    """The figures of one leg (its own full-step timed region)."""
+    keep = ("metric", "value", "unit", "ms_per_step", "dtype", "config", "roofline")
+    return {k: line[k] for k in keep if k in line}
+
+
+def other_legs(torch, H, W, stream, args):
+    """The rest of the headline metric, each leg timed like the main one:
+    rD2Q25 with the int16 deviation storage (the mixed-precision form),
+    rD3Q53 256^3 compressible Taylor-Green in FP32 and int16, and the served
+    request stream at about 0.8 of capacity and at the stated 200 requests/s.
+    Progress goes to stderr."""
+    import copy
+
+    legs = {}
+    a = copy.copy(args)
+    a.storage = "i16_dev"
+    print("leg: rD2Q25 4096^2 i16_dev", file=sys.stderr, flush=True)
+    legs["rD2Q25-4096x4096-i16_dev"] = _leg_summary(bench_tgv2d(torch, H, W, stream, a))
+    for st in ("fp32", "i16_dev"):
+        a = copy.copy(args)
+        a.storage, a.lattice3d, a.size, a.mass_src = st, "rD3Q53", 256, 0.0
+        print("leg: rD3Q53 256^3 %s" % st, file=sys.stderr, flush=True)
+        legs["rD3Q53-256x256x256-%s" % st] = _leg_summary(bench_tgv3d(torch, H, W, stream, a))
+    for rate, n in ((args.serve_rate_low, args.serve_requests), (200.0, args.serve_requests)):
+        a = copy.copy(args)
+        a.storage, a.rate, a.requests = "i16_dev", rate, n
+        print("leg: served stream %.0f requests/s, %d requests" % (rate, n), file=sys.stderr, flush=True)
+        line = bench_serve(stream, a)
+        legs["serve-%g-per-s" % rate] = {k: v for k, v in line.items()
+                                         if k not in ("n_gpus", "steps", "warmup", "scaling", "vs_baseline",
+                                                      "data", "higher_is_better")}
+    return legs
+
+
+def bench_tgv2d(torch, H, W, stream, args):
+    """rD2Q25 (or another 2D card) incompressible Taylor-Green at Ma = 0.1 on
+    a periodic square box, one launch per step."""
     shape = (args.size, args.size)
     card2 = {"rD2Q25": W.Q25_RECT, "rD2Q21": W.Q21_RECT, "D2Q21K": W.Q21K_RECT, "D2Q9": W.Q9_RECT}[args.lattice2d]
     wl = W.tgv_large(0, shape=shape, steps=args.steps, card=card2)
@@ -364,9 +426,7 @@ def main():
     }
     s.close()
     ctx.close()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

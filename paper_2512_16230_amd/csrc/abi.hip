@@ -74,7 +74,8 @@ struct mrtlb_solve {
   void* f[2] = {nullptr, nullptr};
   void* force = nullptr;        // Real, d x N
   void* phi[2] = {nullptr, nullptr};
-  void* jobs = nullptr;         // two Job<Real> (parity 0, 1)
+  void* jobs = nullptr;         // three Job<Real> slots (parity 0, 1, drift-corrected step), then the
+                                // int16 saturation flag (an int) at jobs + kFlagOffset
   void* pd = nullptr;           // KParams<double>
   int cur = 0;
   int64_t steps = 0;
@@ -100,6 +101,9 @@ struct mrtlb_solve {
 namespace mrtlb {
 
 static bool is_double(int storage) { return storage == kFP64; }
+// The job slots of a solve and, after them, its saturation flag.
+constexpr size_t kFlagOffset = 3 * (sizeof(Job<double>) > sizeof(Job<float>) ? sizeof(Job<double>) : sizeof(Job<float>));
+constexpr size_t kJobsBytes = kFlagOffset + 256;
 static size_t elem_bytes(int storage) {
   switch (storage) {
     case kFP64: return 8;
@@ -242,6 +246,15 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
         const double t = std::sqrt(cn) * md.u_bound / L.cs2;
         const double r = md.dev_bound;
         A = 2.0 * (r + (1.0 + r) * (std::expm1(t) + md.u_bound * md.u_bound / (2.0 * L.cs2)));
+        if (md.model == MRTLB_NCDE) {
+          // the diffusion term of the NCDE equilibrium: cs^2 (Phi - phi) I in
+          // M2 adds (Phi - phi)(|c_j|^2 - d cs^2) / (2 cs^2) to f_eq,j / w_j,
+          // with |Phi(phi) - phi| <= r max(|k - 1|, |k (1 + D2 r^2 / 3) - 1|)
+          // for |phi| <= r, k = D0 / K, Phi = k (phi + D2 phi^3 / 3)
+          const double k = md.D0 / (L.cs2 * (1.0 / md.s1 - 0.5));
+          const double dphi = r * std::max(std::fabs(k - 1.0), std::fabs(k * (1.0 + md.D2 * r * r / 3.0) - 1.0));
+          A += 2.0 * dphi * std::fabs(cn - D * L.cs2) / (2.0 * L.cs2);
+        }
       }
       unit[j] = A * L.w[j] / 32767.0;
       inv[j] = 1.0 / (A * L.w[j]);
@@ -333,6 +346,7 @@ static Job<Real> make_job(const mrtlb_solve& s, int parity, const KParams<Real>&
   J.force = static_cast<const Real*>(s.force);
   J.phi_prev = static_cast<const Real*>(s.phi[parity]);
   J.phi_out = static_cast<Real*>(s.phi[parity ^ 1]);
+  J.sat = reinterpret_cast<int*>(static_cast<char*>(s.jobs) + kFlagOffset);
   J.block_begin = 0;
   J.nblocks = s.nblocks;
   J.vec = s.vec;
@@ -540,7 +554,7 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
   if (has_force) b += (size_t)D * (size_t)N * real;
   if (model == MRTLB_NCDE) b += 2 * (size_t)N * real;
   if (model == MRTLB_CDE) b += (size_t)D * (size_t)N * real;   // velocity field
-  b += 3 * sizeof(Job<double>) + sizeof(KParams<double>);
+  b += kJobsBytes + sizeof(KParams<double>);
   *bytes = b;
   return MRTLB_OK;
 }
@@ -626,7 +640,7 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
     s->f[1] = ext1;
   }
   bool ok = (external || (alloc(&s->f[0], pop) && alloc(&s->f[1], pop))) &&
-            alloc(&s->jobs, 3 * std::max(sizeof(Job<double>), sizeof(Job<float>))) &&
+            alloc(&s->jobs, kJobsBytes) &&
             alloc(&s->pd, sizeof(KParams<double>));
   if (ok && has_force) ok = alloc(&s->force, (size_t)D * s->N * real);
   if (ok && model->model == MRTLB_NCDE) ok = alloc(&s->phi[0], s->N * real) && alloc(&s->phi[1], s->N * real);
@@ -711,34 +725,70 @@ struct DevBuf {
   ~DevBuf() { if (p) (void)hipFreeAsync(p, st); }
 };
 
+// int16 saturation flag: cleared when the state is (re)written from the
+// host, raised by the kernels, read after the synchronous calls.
+static mrtlb_status clear_saturation(mrtlb_solve* s) {
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(static_cast<char*>(s->jobs) + kFlagOffset, &zero, sizeof zero, hipMemcpyHostToDevice,
+                         s->ctx->stream));
+  return MRTLB_OK;
+}
+
+// Call with the context stream synchronized.
+static mrtlb_status check_saturation(mrtlb_solve* s) {
+  if (s->storage != kI16Dev) return MRTLB_OK;
+  int flag = 0;
+  HIP_TRY(hipMemcpy(&flag, static_cast<char*>(s->jobs) + kFlagOffset, sizeof flag, hipMemcpyDeviceToHost));
+  if (flag)
+    return fail(MRTLB_ENUMERIC, "int16 storage saturated: a population left the fixed-point range set by "
+                                "u_bound and dev_bound (raise them); the state is clamped");
+  return MRTLB_OK;
+}
+
 // FP64 mass and momentum of the solve's current state: per-plane partial
 // sums on the device (fixed order), then a fixed-order sum on the host.
-static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
-  const int B = s->L.B, D = s->L.D;
-  const int nf = s->force && s->model.model != MRTLB_CDE ? D : 0;
-  const int planes = B + nf;
+// Planes of the FP64 sums of a solve's state (populations, then the force
+// components) and the chunks each is summed in.
+static void sum_layout(const mrtlb_solve* s, int* planes, uint32_t* nchunks) {
+  const int nf = s->force && s->model.model != MRTLB_CDE ? s->L.D : 0;
   const uint32_t chunk = kBlock * kChunkIters;
-  const uint32_t nchunks = (s->N + chunk - 1) / chunk;
-  const size_t need = (size_t)planes * nchunks * 8;
-  if (need > s->part_bytes) {
-    if (s->part) HIP_TRY(hipFree(s->part));
-    s->part = nullptr;
-    s->part_bytes = 0;
-    HIP_TRY(hipMalloc(&s->part, need));
-    s->part_bytes = need;
-  }
+  *planes = s->L.B + nf;
+  *nchunks = (s->N + chunk - 1) / chunk;
+}
+
+// Device doubles plane_totals needs in its work buffer.
+static size_t sum_work_doubles(const mrtlb_solve* s) {
+  int planes;
+  uint32_t nchunks;
+  sum_layout(s, &planes, &nchunks);
+  return (size_t)planes * nchunks + (size_t)planes;
+}
+
+// FP64 total of every plane into plane[] (host, kMaxB + 3 entries): partial
+// sums per chunk, then per plane in chunk order, both on the device, in
+// `work` (sum_work_doubles entries of device memory); synchronizes.
+static mrtlb_status plane_totals(mrtlb_solve* s, double* work, double* plane) {
+  int planes;
+  uint32_t nchunks;
+  sum_layout(s, &planes, &nchunks);
   hipStream_t st = s->ctx->stream;
   // KParams is the first member of the job in device memory
   const void* params = job_ptr(*s, s->cur);
-  hipError_t err = launch_plane_sums(s->storage, s->f[s->cur], s->N, B, s->force, nf, params, (double*)s->part,
+  hipError_t err = launch_plane_sums(s->storage, s->f[s->cur], s->N, s->L.B, s->force, planes - s->L.B, params, work,
                                      nchunks, st);
   if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("sum launch: ") + hipGetErrorString(err));
-  std::vector<double> h((size_t)planes * nchunks);
-  HIP_TRY(hipMemcpyAsync(h.data(), s->part, h.size() * 8, hipMemcpyDeviceToHost, st));
+  double* totals = work + (size_t)planes * nchunks;
+  err = launch_plane_totals(work, nchunks, planes, totals, st);
+  if (err != hipSuccess) return fail(MRTLB_EDEVICE, std::string("total launch: ") + hipGetErrorString(err));
+  HIP_TRY(hipMemcpyAsync(plane, totals, (size_t)planes * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  std::vector<double> plane(planes, 0.0);
-  for (int p = 0; p < planes; ++p)
-    for (uint32_t c = 0; c < nchunks; ++c) plane[p] += h[(size_t)p * nchunks + c];
+  return MRTLB_OK;
+}
+
+// Mass and momentum from the plane totals (fixed order), then the state checks.
+static mrtlb_status totals_from_planes(mrtlb_solve* s, const double* plane, double* mass, double* momentum) {
+  const int B = s->L.B, D = s->L.D;
+  const int nf = s->force && s->model.model != MRTLB_CDE ? D : 0;
   double m = 0, mom[3] = {0, 0, 0};
   const double ref = s->storage != kFP64 && s->storage != kFP32 && s->model.model != MRTLB_NCDE &&
                              s->model.model != MRTLB_CDE
@@ -759,7 +809,24 @@ static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
   if (momentum)
     for (int a = 0; a < 3; ++a) momentum[a] = a < D ? mom[a] : 0.0;
   if (!finite) return fail(MRTLB_ENUMERIC, "non-finite value in the solve's state");
-  return MRTLB_OK;
+  return check_saturation(s);
+}
+
+// FP64 mass and momentum of the solve's current state, with the solve's own
+// work buffer (grown on demand).
+static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
+  const size_t need = sum_work_doubles(s) * sizeof(double);
+  if (need > s->part_bytes) {
+    if (s->part) HIP_TRY(hipFree(s->part));
+    s->part = nullptr;
+    s->part_bytes = 0;
+    HIP_TRY(hipMalloc(&s->part, need));
+    s->part_bytes = need;
+  }
+  double plane[kMaxB + 3];
+  mrtlb_status st = plane_totals(s, static_cast<double*>(s->part), plane);
+  if (st != MRTLB_OK) return st;
+  return totals_from_planes(s, plane, mass, momentum);
 }
 
 mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum) {
@@ -873,6 +940,8 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
   // the init kernel writes f into buffer cur^1 and phi into both history
   // slots; run it with the parity-1 job so that fout = f[0]
   mrtlb_status rs = upload_jobs(s);
+  if (rs != MRTLB_OK) return rs;
+  rs = clear_saturation(s);
   if (rs != MRTLB_OK) return rs;
   LaunchReq r = base_req(*s, kOpInit, job_ptr(*s, 1));
   r.in0 = (const double*)dr.p;
@@ -1071,7 +1140,7 @@ mrtlb_status mrtlb_read_moments(mrtlb_solve* s, double* rho, double* u) {
   HIP_TRY(hipMemcpyAsync(rho, dr.p, (size_t)s->N * 8, hipMemcpyDeviceToHost, s->ctx->stream));
   if (u) HIP_TRY(hipMemcpyAsync(u, du.p, (size_t)D * s->N * 8, hipMemcpyDeviceToHost, s->ctx->stream));
   HIP_TRY(hipStreamSynchronize(s->ctx->stream));
-  return MRTLB_OK;
+  return check_saturation(s);
 }
 
 mrtlb_status mrtlb_read_populations(mrtlb_solve* s, double* f) {
@@ -1084,7 +1153,7 @@ mrtlb_status mrtlb_read_populations(mrtlb_solve* s, double* f) {
   if (st != MRTLB_OK) return st;
   HIP_TRY(hipMemcpyAsync(f, d.p, n * 8, hipMemcpyDeviceToHost, s->ctx->stream));
   HIP_TRY(hipStreamSynchronize(s->ctx->stream));
-  return MRTLB_OK;
+  return check_saturation(s);
 }
 
 mrtlb_status mrtlb_write_populations(mrtlb_solve* s, const double* f) {
@@ -1097,6 +1166,8 @@ mrtlb_status mrtlb_write_populations(mrtlb_solve* s, const double* f) {
   DevBuf d;
   HIP_TRY(d.alloc(n * 8, s->ctx->stream));
   HIP_TRY(hipMemcpyAsync(d.p, f, n * 8, hipMemcpyHostToDevice, st));
+  mrtlb_status cs = clear_saturation(s);
+  if (cs != MRTLB_OK) return cs;
   // write into the current buffer: the parity-(cur^1) job has fout = f[cur]
   LaunchReq r = base_req(*s, kOpScatter, job_ptr(*s, s->cur ^ 1));
   r.in0 = (const double*)d.p;

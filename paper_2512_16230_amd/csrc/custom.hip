@@ -106,13 +106,16 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
   BackCoeffs<Real> C;
   back_coeffs<DIM, false>(P, T.d0, T.d1, T.d2n, T.d2o, T.d3m, T.d3p, T.dxyz, C);
   const uint32_t own = ((uint32_t)iz * (uint32_t)P.ny + (uint32_t)iy) * (uint32_t)b * (uint32_t)P.nxp + (uint32_t)ix;
+  float smax = 0.0f;
   for (int j = 0; j < b; ++j) {
     const Real v = load_pop<ST>(J.fin, csrc(P, j, ix, iy, iz), P, j);
     int e[3];
     velocity(P, j, e);
     const Real out = T.kx * v + P.w[j] * poly_at<DIM>(C, e);
+    smax = fmaxf(smax, sat_of<ST>(out, P, j));
     store_pop<ST>(J.fout, own + (uint32_t)j * (uint32_t)P.nxp, out, P, j);
   }
+  raise_saturation<ST>(J, smax);
 }
 
 // f_bar(x, 0) = f_eq - F/2 in FP64, written at the pull source x - e_j.
@@ -156,12 +159,15 @@ __global__ __launch_bounds__(kBlock) void k_init_custom(const Job<typename Store
   BackCoeffs<double> C;
   back_coeffs<DIM, false>(P, d0, d1, d2n, d2o, d3m, d3p, dxyz, C);
   const KParams<Real>& PR = J.P;
+  float smax = 0.0f;
   for (int j = 0; j < P.cb; ++j) {
     int e[3];
     velocity(P, j, e);
     const double x = P.w[j] * poly_at<DIM>(C, e);
+    smax = fmaxf(smax, sat_of<ST>((Real)x, PR, j));
     store_pop<ST>(J.fout, csrc(P, j, ix, iy, iz), (Real)x, PR, j);
   }
+  raise_saturation<ST>(J, smax);
 }
 
 // Read-out: moments (WHAT 0) or populations (WHAT 1) in FP64.
@@ -216,10 +222,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter_custom(const Job<typename St
   RowGeom<L> g;
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t self = g.node(ix);
+  float smax = 0.0f;
   for (int j = 0; j < P.cb; ++j) {
     const double v = in[(size_t)j * P.N + self] - P.w[j] * P.rho_ref;
+    smax = fmaxf(smax, sat_of<ST>((Real)v, J.P, j));
     store_pop<ST>(J.fout, csrc(P, j, ix, iy, iz), (Real)v, J.P, j);
   }
+  raise_saturation<ST>(J, smax);
 }
 
 template <int DIM>

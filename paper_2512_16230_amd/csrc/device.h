@@ -316,6 +316,7 @@ __device__ __forceinline__ void snorm16x2(float a, float b, int16_t& qa, int16_t
   qa = r[0];
   qb = r[1];
 }
+__device__ __forceinline__ mrtlb_short2 snorm16x2(float a, float b) { return __builtin_amdgcn_cvt_pknorm_i16(a, b); }
 
 // Output number -> stored element.  FP16/BF16 round the FP32 value to
 // nearest even; int16 as snorm16x2.
@@ -353,6 +354,50 @@ __device__ __forceinline__ typename StoreT<ST>::T encode(Real v, const KParams<R
     return (T)v;
   }
 }
+
+// int16 storage: an output number beyond [-1, 1] saturates in the
+// conversion.  Kernels that write int16 populations keep the largest
+// |output number| and raise the solve's flag (a plain vector store of 1)
+// when it exceeds 1; the host reports it at the next synchronous read.
+template <int ST, class Real>
+__device__ __forceinline__ float sat_of(Real v, const KParams<Real>& P, int j) {
+  if constexpr (ST == kI16Dev) return fabsf((float)v * (float)P.iwsc[j]);
+  else return 0.0f;
+}
+
+template <int ST, class Real>
+__device__ __forceinline__ void raise_saturation(const Job<Real>& J, float smax) {
+  if constexpr (ST == kI16Dev) {
+    if (smax > 1.0f) *J.sat = 1;
+  }
+}
+
+// int16 saturation: an output number beyond [-1, 1] is clamped by the
+// conversion (to +-32767).  The step kernel tracks each converted pair and
+// flags the solve if any value was clamped: with one node per thread by
+// the largest |output number| (one three-way max per pair), with several by
+// a packed max and min of the converted pairs (fewer live registers there).
+template <bool PACKED>
+struct SatTrack;
+template <>
+struct SatTrack<false> {
+  float m = 0.0f;
+  __device__ __forceinline__ void add(float a, float b, mrtlb_short2) {
+    m = __builtin_fmaxf(m, __builtin_fmaxf(fabsf(a), fabsf(b)));
+  }
+  __device__ __forceinline__ bool any() const { return m > 1.0f; }
+};
+template <>
+struct SatTrack<true> {
+  mrtlb_short2 hi = {-32768, -32768}, lo = {32767, 32767};
+  __device__ __forceinline__ void add(float, float, mrtlb_short2 v) {
+    hi = __builtin_elementwise_max(hi, v);
+    lo = __builtin_elementwise_min(lo, v);
+  }
+  __device__ __forceinline__ bool any() const {
+    return (hi[0] == 32767) | (hi[1] == 32767) | (lo[0] == -32767) | (lo[1] == -32767);
+  }
+};
 
 template <int ST, class Real>
 __device__ __forceinline__ Real load_pop(const void* buf, uint32_t i, const KParams<Real>& P, int j) {
@@ -699,7 +744,11 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
   const KParams<Real>& P = J.P;
   const uint32_t self = g.node(ix);
   const uint32_t N = P.N;
-  // a8 drift correction (zero except on the step after an FP64 check)
+  // a8 drift correction (zero except on the step after an FP64 check): the
+  // conserved moments enter the collision shifted by dm0, dm1, and the
+  // targets below add (1 - s_h) dm to rows 0 and 1, whose (1 - s_h) f term
+  // acts on the unshifted populations, so the step moves each node's totals
+  // by exactly dm0 and dm1
   M.R0 += P.dm0;
 #pragma unroll
   for (int a = 0; a < D; ++a) M.m1[a] += P.dm1[a];
@@ -779,7 +828,7 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
   for (int a = 0; a < D; ++a) {
     Real ms = M.m1[a] - P.s1 * (M.m1[a] - E.e1[a]) + (Real(1) - Real(0.5) * P.s1) * src1[a];
     if constexpr (MODEL == kNcde) ms -= P.s1 * x1[a];
-    d1[a] = (ms - kx * M.m1[a]) * P.in1[a];
+    d1[a] = (ms - kx * (M.m1[a] - P.dm1[a])) * P.in1[a];
   }
   {
     Real neq[3], tn = 0, tT = 0;
@@ -836,7 +885,7 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
   }
   // order 0 is conserved, m*_0 = m_0, except for the CDE source:
   // m*_0 = m_0 + M0G + s0 S_G / 2 = m_0 + S_G (M0G = (1 - s0/2) S_G)
-  const Real d0 = (P.sh * M.R0 + sg + src0) * P.in0;
+  const Real d0 = (P.sh * M.R0 + kx * P.dm0 + sg + src0) * P.in0;
   T.kx = kx;
   T.d0 = d0;
   T.dxyz = dxyz;
@@ -933,6 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   // int16 format converts two nodes per instruction: an even node's output
   // waits in keep[] for the odd one.
   Real keep[ST == kI16Dev && VEC > 1 ? B : 1];
+  SatTrack<(VEC > 1)> sat;
   static_for<0, VEC>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
     Real x[B];
@@ -944,17 +994,34 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
     static_for<0, B>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
       if constexpr (ST == kI16Dev && VEC == 1) {
-        int16_t unused;
-        snorm16x2(x[j], 0.0f, raw[j][0], unused);
+        // one node: populations j - 1 and j share a conversion
+        if constexpr (j % 2 == 1) {
+          const mrtlb_short2 r = snorm16x2(x[j - 1], x[j]);
+          sat.add(x[j - 1], x[j], r);
+          raw[j - 1][0] = r[0];
+          raw[j][0] = r[1];
+        } else if constexpr (j == B - 1) {
+          const mrtlb_short2 r = snorm16x2(x[j], 0.0f);
+          sat.add(x[j], 0.0f, r);
+          raw[j][0] = r[0];
+        }
       } else if constexpr (ST == kI16Dev && k % 2 == 0) {
         keep[j] = x[j];
       } else if constexpr (ST == kI16Dev) {
-        snorm16x2(keep[j], x[j], raw[j][k - 1], raw[j][k]);
+        const mrtlb_short2 r = snorm16x2(keep[j], x[j]);
+        sat.add(keep[j], x[j], r);
+        raw[j][k - 1] = r[0];
+        raw[j][k] = r[1];
       } else {
         raw[j][k] = to_stored<ST>(x[j]);
       }
     });
   });
+
+  // int16: a conversion clamped at +-1 gives +-32767; flag the solve
+  if constexpr (ST == kI16Dev) {
+    if (sat.any()) *J.sat = 1;
+  }
 
   // a8: store at the own nodes
   const auto rout = make_rsrc(J.fout, P.pop_bytes);
@@ -1035,11 +1102,14 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   const double d0 = r0 * P.in0 - P.rho_ref;
   backward<L>(x, P, 0.0, P.w, d0, d1, d2n, d2o, d3m, d3p, dxyz);
   const KParams<Real>& PR = J.P;
+  float smax = 0.0f;
   static_for<0, B>([&](auto jj) {
     constexpr int j = decltype(jj)::value;
     // buf_j(x - e_j) = f_bar_j(x): the source index of the pull gather
+    smax = fmaxf(smax, sat_of<ST>((Real)x[j], PR, j));
     store_pop<ST>(J.fout, g.template src<j>(ix), (Real)x[j], PR, j);
   });
+  raise_saturation<ST>(J, smax);
 }
 
 // read-out: gather f_bar(x, t) and compute moments (WHAT 0) or copy the
@@ -1115,11 +1185,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const Job<typename StoreT<ST
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t self = g.node(ix);
   const uint32_t N = P.N;
+  float smax = 0.0f;
   static_for<0, B>([&](auto jj) {
     constexpr int j = decltype(jj)::value;
     const double v = in[(size_t)j * N + self] - P.w[j] * P.rho_ref;
+    smax = fmaxf(smax, sat_of<ST>((Real)v, J.P, j));
     store_pop<ST>(J.fout, g.template src<j>(ix), (Real)v, J.P, j);
   });
+  raise_saturation<ST>(J, smax);
 }
 
 // ---------------------------------------------------------------------------

@@ -88,6 +88,7 @@ struct Job {
   const Real* force;        // d x N, or nullptr (CDE: the velocity field)
   const Real* phi_prev;     // NCDE: phi^{n-1}
   Real* phi_out;            // NCDE: phi^n
+  int* sat;                 // int16 storage: set to 1 when a value saturates
   uint32_t block_begin;     // first linear workgroup of this job
   uint32_t nblocks;
   int vec;                  // nodes per thread along x

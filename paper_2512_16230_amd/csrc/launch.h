@@ -48,5 +48,8 @@ hipError_t launch_custom(const LaunchReq& r);
 // FP64 sums of every population plane (and force plane) in chunks.
 hipError_t launch_plane_sums(int storage, const void* base, uint32_t N, int npop, const void* force, int nforce,
                              const void* params, double* partial, uint32_t nchunks, hipStream_t stream);
+// totals[p] = sum over c of partial[p * nchunks + c], in chunk order.
+hipError_t launch_plane_totals(const double* partial, uint32_t nchunks, int planes, double* totals,
+                               hipStream_t stream);
 
 }  // namespace mrtlb

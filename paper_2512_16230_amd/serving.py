@@ -173,7 +173,8 @@ class GpuExecutor:
         bounds, and page-locked copies of its fields."""
         p = make_payload(req)
         if req.storage == "i16_dev":
-            p["bounds"] = W.flow_bounds(req.eq, p["rho_or_phi"], p["u"], p["force"], req.steps, adv_u=req.adv_u)
+            p["bounds"] = W.flow_bounds(req.eq, p["rho_or_phi"], p["u"], p["force"], req.steps, adv_u=req.adv_u,
+                                          cs2=req.card.cs2)
         if self.pool is not None:
             p["_pinned"] = []
             for key in ("rho_or_phi", "u", "force"):
@@ -210,7 +211,7 @@ class GpuExecutor:
         ub = db = 0.0
         if req.storage == "i16_dev":
             ub, db = p.get("bounds") or W.flow_bounds(req.eq, p["rho_or_phi"], p["u"], p["force"], req.steps,
-                                                       adv_u=req.adv_u)
+                                                       adv_u=req.adv_u, cs2=req.card.cs2)
         md = H.model_desc(req.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
                           D0=req.D0, D2=req.D2, adv_u=req.adv_u, u_bound=ub, dev_bound=db)
         s = H.Solve(self.ctx, self._lattice(req.card), md, req.shape, req.storage, has_force=req.with_force)

@@ -172,13 +172,16 @@ def sinusoidal_force(card: Card, shape, F0, seed, modes=3):
     return F
 
 
-def flow_bounds(eq, rho_or_phi, u=None, force=None, steps=0, rho0=1.0, adv_u=(0.0, 0.0, 0.0), margin=1.5):
+def flow_bounds(eq, rho_or_phi, u=None, force=None, steps=0, rho0=1.0, adv_u=(0.0, 0.0, 0.0), margin=1.5,
+                cs2=None, mass_src=0.0):
     """Run-long bounds (u_bound, dev_bound) on max |u| and on max |rho - rho0|
     / rho0 (NSE) or max |phi| (NCDE, CDE), from the initial fields: ``margin``
     times the initial maxima, which bound an unforced run (decaying kinetic
     energy; maximum principle of the convection-diffusion equation), plus for
     a body force the velocity it can add in ``steps`` steps, max |F| steps /
-    min rho."""
+    min rho, and (given cs2) the pressure deviation u_bound^2 / cs2 of that
+    flow; a mass source S adds |S| steps / rho0 to the density bound.  (The
+    library adds the NCDE equilibrium's diffusion term itself.)"""
     if eq == "NCDE":
         return margin * float(np.linalg.norm(adv_u)), margin * float(np.abs(rho_or_phi).max())
     if eq == "CDE":
@@ -186,9 +189,13 @@ def flow_bounds(eq, rho_or_phi, u=None, force=None, steps=0, rho0=1.0, adv_u=(0.
         return margin * umax, margin * float(np.abs(rho_or_phi).max())
     rho = np.asarray(rho_or_phi)
     umax = float(np.sqrt((np.asarray(u) ** 2).sum(0)).max()) if u is not None else 0.0
+    dev = float(np.abs(rho - rho0).max()) / rho0
     if force is not None:
         umax += float(np.sqrt((np.asarray(force) ** 2).sum(0)).max()) * steps / float(rho.min())
-    return margin * umax, margin * float(np.abs(rho - rho0).max()) / rho0
+        if cs2:
+            dev += (margin * umax) ** 2 / cs2
+    dev += abs(mass_src) * steps / rho0
+    return margin * umax, margin * dev
 
 
 # ---------------------------------------------------------------------------

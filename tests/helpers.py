@@ -1,6 +1,8 @@
 """Shared helpers of the parity tests: build the oracle and the HIP solve
 from the same workload parameters and compare them."""
 
+import os
+
 import numpy as np
 
 from oracle import lattice as OL
@@ -43,3 +45,13 @@ def max_rel(a, b):
 def max_rel_dev(a, b, ref):
     """max |a - b| / max |b - ref| for fields close to a constant ref."""
     return float(np.abs(a - b).max() / np.abs(b - ref).max())
+
+
+def check_errs(storage, r, r_o, v, u_o, tr, tu):
+    """Assert max_rel of rho (or phi) and u against their tolerances, after
+    printing both errors with the test's id (the measured floors behind the
+    FP32 tolerances come from these lines)."""
+    er, eu = max_rel(r, r_o), max_rel(v, u_o)
+    test = os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
+    print("errs %s %s rho %.3e u %.3e (tol %.1e %.1e)" % (test, storage, er, eu, tr, tu), flush=True)
+    assert er < tr and eu < tu, (storage, er, eu)

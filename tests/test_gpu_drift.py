@@ -92,3 +92,31 @@ def test_accuracy_kept(ctx):
     e_rho, e_u = max_rel(rho, refs["rho_noise"]), max_rel(u, refs["u_noise"])
     print("i16_dev with drift correction: rho %.2e u %.2e" % (e_rho, e_u), flush=True)
     assert e_rho < 1e-3 and e_u < 1e-3
+
+
+@pytest.mark.parametrize("s_high", [0.9, 1.5])
+def test_one_corrected_step_restores_the_totals(ctx, s_high):
+    """After the FP64 check at step K the next step moves the totals back to
+    the reference by the whole difference: the rate s_h of the rows above
+    third order (which act on the uncorrected populations) must not scale
+    it.  FP32 storage drifts systematically; the step after the correction
+    keeps at most its own one-step drift."""
+    wl = W.tgv_large(0, shape=(256, 256), steps=201)
+    r = wl.rates
+    wl.rates = W.Rates(r.s0, r.s1, r.s_shear, r.s_bulk, r.s3, s_high)
+    K = 200
+    print("case: tgv-rD2Q25-256x256 fp32 s_high %.2f, check after %d steps, one corrected step" % (s_high, K),
+          flush=True)
+    s = _solve(ctx, wl, "fp32", every=K)
+    m_ref, p_ref = s.conserved()
+    s.step(K)                 # the check at step K finds the drift; the correction is pending
+    m_k, p_k = s.conserved()
+    s.step(1)
+    m_1, p_1 = s.conserved()
+    s.close()
+    dm, dp = abs(m_k - m_ref), np.abs(p_k - p_ref).max()
+    rm, rp = abs(m_1 - m_ref), np.abs(p_1 - p_ref).max()
+    print("drift before %.3e / %.3e, after the corrected step %.3e / %.3e" % (dm, dp, rm, rp), flush=True)
+    assert dm > 1e-8 * m_ref                  # there is a drift to correct
+    assert rm < 0.05 * dm
+    assert rp < max(0.05 * dp, 1e-9 * m_ref)
