@@ -345,6 +345,19 @@ mrtlb_status mrtlb_read_moments(mrtlb_solve* s, double* rho_or_phi, double* u);
  * stored value is not finite.  Synchronous. */
 mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * totals as mrtlb_conserved, bit for bit, computed without any device or
+ * host allocation.  The FP64 partial sums live in a scratch array of the
+ * library, 4 MiB per GPU, held from the first context on that GPU until the
+ * process ends and shared by every call on that GPU: calls that overlap on
+ * one GPU (several threads, or contexts on different streams) race, and
+ * each call overwrites what the previous one left.  The solve's sums need
+ * (b + force components) * (ceil(N / 4096) + 1) doubles, e.g. 1.7 MB for
+ * rD3Q53 at 256^3; larger solves get EINVAL (use mrtlb_conserved).  Errors
+ * otherwise as mrtlb_conserved.  Synchronous. */
+mrtlb_status mrtlb_conserved_noalloc(mrtlb_solve* s, double* mass, double* momentum);
+
 /* Checkpoint / restore of f_bar at the current time (b*N values). */
 mrtlb_status mrtlb_read_populations(mrtlb_solve* s, double* f);
 mrtlb_status mrtlb_write_populations(mrtlb_solve* s, const double* f);

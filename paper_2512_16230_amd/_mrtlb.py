@@ -91,6 +91,7 @@ def lib():
         "mrtlb_batch_step": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int64)]),
         "mrtlb_read_moments": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
+        "mrtlb_conserved_noalloc": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_set_drift_correction": (c_int, [c_void_p, c_int64]),
         "mrtlb_host_alloc": (c_int, [c_size_t, POINTER(c_void_p)]),
         "mrtlb_host_free": (None, [c_void_p]),
@@ -111,7 +112,8 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_solve_create", "mrtlb_solve_footprint", "mrtlb_solve_destroy", "mrtlb_init_fields",
             "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
-            "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external"]
+            "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external",
+            "mrtlb_conserved_noalloc"]
 
 
 def _check(status):
@@ -362,6 +364,13 @@ class Solve:
         m = c_double()
         mom = np.zeros(3)
         _check(lib().mrtlb_conserved(self.h, byref(m), _ptr(mom)))
+        return m.value, mom[: self.d].copy()
+
+    def conserved_noalloc(self):
+        """As conserved(), through the allocation-free entry point."""
+        m = c_double()
+        mom = np.zeros(3)
+        _check(lib().mrtlb_conserved_noalloc(self.h, byref(m), _ptr(mom)))
         return m.value, mom[: self.d].copy()
 
     def read_populations(self):

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <cstdint>
@@ -55,6 +56,8 @@ struct mrtlb_ctx {
   void* job_dev = nullptr;
   void* job_host = nullptr;
   size_t job_cap = 0;
+  // device address of this GPU's scratch array (mrtlb_conserved_noalloc)
+  void* scratch = nullptr;
 };
 
 struct mrtlb_lattice {
@@ -397,6 +400,41 @@ static const void* job_ptr(const mrtlb_solve& s, int parity) {
   return static_cast<const char*>(s.jobs) + jsz * parity;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (mrtlb_conserved_noalloc): a
+// file-scope device array of kScratchBytes, one copy on every GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is a stand-in, not a
+// device address): the device address comes from hipGetSymbolAddress, once
+// per device with that device current, at context creation, and is kept per
+// device.  Every call on a GPU shares its array; calls that overlap on one
+// GPU (two threads, or contexts with different streams) race.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr size_t kScratchDoubles = kScratchBytes / sizeof(double);
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on `device` (which must be current).
+static mrtlb_status scratch_setup(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return fail(MRTLB_EINVAL, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return fail(MRTLB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return MRTLB_OK;
+}
+
 }  // namespace mrtlb
 
 // ===========================================================================
@@ -437,6 +475,13 @@ mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx
   if (!c) return fail(MRTLB_ENOMEM, "host allocation failed");
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  {
+    const mrtlb_status sst = scratch_setup(device, &c->scratch);
+    if (sst != MRTLB_OK) {
+      delete c;
+      return sst;
+    }
+  }
   c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
   // keep the stream-ordered allocator's freed staging memory for reuse
   hipMemPool_t pool;
@@ -834,6 +879,26 @@ mrtlb_status mrtlb_conserved(mrtlb_solve* s, double* mass, double* momentum) {
   HIP_TRY(hipSetDevice(s->ctx->device));
   double m = 0, mom[3] = {0, 0, 0};
   mrtlb_status st = state_sums(s, &m, mom);
+  *mass = m;
+  if (momentum)
+    for (int a = 0; a < s->L.D; ++a) momentum[a] = mom[a];
+  return st;
+}
+
+mrtlb_status mrtlb_conserved_noalloc(mrtlb_solve* s, double* mass, double* momentum) {
+  if (!s || !mass) return fail(MRTLB_EINVAL, "NULL argument");
+  const size_t need = sum_work_doubles(s);
+  if (need > kScratchDoubles)
+    return fail(MRTLB_EINVAL, "the solve's sums need " + std::to_string(need * sizeof(double)) +
+                                  " B of scratch, more than the " + std::to_string(kScratchBytes) +
+                                  " B of the allocation-free path; use mrtlb_conserved");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  if (!s->ctx->scratch) return fail(MRTLB_EDEVICE, "no scratch address for this device");
+  double plane[kMaxB + 3];
+  mrtlb_status st = plane_totals(s, static_cast<double*>(s->ctx->scratch), plane);
+  if (st != MRTLB_OK) return st;
+  double m = 0, mom[3] = {0, 0, 0};
+  st = totals_from_planes(s, plane, &m, mom);
   *mass = m;
   if (momentum)
     for (int a = 0; a < s->L.D; ++a) momentum[a] = mom[a];
