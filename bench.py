@@ -36,7 +36,7 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "fp32_dev": "f32", "fp16_dev": "f32 (fp16
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("device.h", "kernels.h", "lattices.h", "launch.h", "abi.hip"):
+    for name in ("device.h", "kernels.h", "lattices.h", "launch.h", "launchers.h", "mfma.h", "mfma_layout.h", "abi.hip"):
         with open(os.path.join(ROOT, "paper_2512_16230_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -140,6 +140,8 @@ def bench_tgv3d(torch, H, W, stream, args):
                       m30=card.kind not in STANDARD, mass_src=args.mass_src, **_bounds(W, args.storage, wl))
     forced = args.mass_src != 0          # the mass source runs in the forced kernel (zero force field)
     s = H.Solve(ctx, lat, md, shape, args.storage, has_force=forced)
+    if args.transform != "valu":
+        s.set_transform(args.transform)
     s.init_fields(wl.rho_or_phi, wl.u, np.zeros((3,) + shape) if forced else None)
     del wl
     s.step(args.warmup)
@@ -151,11 +153,13 @@ def bench_tgv3d(torch, H, W, stream, args):
     nodes = n ** 3
     bq = {"rD3Q53": 53, "rD3Q45": 45, "rD3Q33": 33, "D3Q27": 27}[card.kind]
     launch_bytes = (2 * bq * STORE_BYTES[args.storage] + (3 * 4 if forced else 0)) * nodes
-    out = _line("%s MRT-LB MLUPS (fused collide-and-stream%s), %% of HBM roofline"
-                % (card.kind, ", mass source" if forced else ""),
+    out = _line("%s MRT-LB MLUPS (fused collide-and-stream%s%s), %% of HBM roofline"
+                % (card.kind, ", mass source" if forced else "",
+                   ", Hermite transforms on MFMA" if args.transform == "mfma" else ""),
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
                 {"workload": "tgv3d-%s-%dx%dx%d" % (card.kind, n, n, n), "lattice": card.kind,
-                                      "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes},
+                 "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes,
+                 "transform": args.transform},
                 args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
     s.close()
     ctx.close()
@@ -294,6 +298,8 @@ def main():
                     help="tgv2d: run the lattice's velocity set as a user-supplied (run-time) lattice")
     ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33", "D3Q27"],
                     help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
+    ap.add_argument("--transform", default="valu", choices=["valu", "mfma"],
+                    help="tgv3d: Hermite transforms on the vector ALUs or on the matrix cores (int16 storage)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of 2 x 1.68 GB instead (HBM reference and counter calibration)")
     args = ap.parse_args()
@@ -352,11 +358,12 @@ def other_legs(torch, H, W, stream, args):
     a.storage = "i16_dev"
     print("leg: rD2Q25 4096^2 i16_dev", file=sys.stderr, flush=True)
     legs["rD2Q25-4096x4096-i16_dev"] = _leg_summary(bench_tgv2d(torch, H, W, stream, a))
-    for st in ("fp32", "i16_dev"):
+    for st, tr in (("fp32", "valu"), ("i16_dev", "valu"), ("i16_dev", "mfma")):
         a = copy.copy(args)
-        a.storage, a.lattice3d, a.size, a.mass_src = st, "rD3Q53", 256, 0.0
-        print("leg: rD3Q53 256^3 %s" % st, file=sys.stderr, flush=True)
-        legs["rD3Q53-256x256x256-%s" % st] = _leg_summary(bench_tgv3d(torch, H, W, stream, a))
+        a.storage, a.lattice3d, a.size, a.mass_src, a.transform = st, "rD3Q53", 256, 0.0, tr
+        print("leg: rD3Q53 256^3 %s %s" % (st, tr), file=sys.stderr, flush=True)
+        legs["rD3Q53-256x256x256-%s%s" % (st, "-mfma" if tr == "mfma" else "")] = \
+            _leg_summary(bench_tgv3d(torch, H, W, stream, a))
     for rate, n in ((args.serve_rate_low, args.serve_requests), (200.0, args.serve_requests)):
         a = copy.copy(args)
         a.storage, a.rate, a.requests = "i16_dev", rate, n

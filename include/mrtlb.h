@@ -303,6 +303,27 @@ void mrtlb_solve_destroy(mrtlb_solve* s);
  * Resets the step counter.  Synchronous. */
 mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho_or_phi, const double* u, const double* force);
 
+/* How the step kernel evaluates the Hermite transforms (a solve setting):
+ *   MRTLB_TRANSFORM_VALU  (default) structured monomial sums on the vector
+ *                         ALUs, every lattice, storage and model;
+ *   MRTLB_TRANSFORM_MFMA  dense products on the matrix cores: the forward
+ *                         transform as the monomial matrix of order <= 3
+ *                         (times each population's storage scale, f16 hi + lo)
+ *                         against the stored int16 numbers (two exact f16
+ *                         chunks each), the back-transform as its transpose
+ *                         (times the output weights, bf16 hi + lo) against the
+ *                         monomial coefficients (bf16 hi + lo), FP32
+ *                         accumulation; the relaxation in between is the same
+ *                         FP32 code.  3D lattices (|e| <= 2), MRTLB_I16_DEV
+ *                         storage, NSE models without a force field, a row
+ *                         pitch (nx rounded up to 32) that is a multiple of 64.
+ * The stored format is the same for both, so a solve may switch at any step;
+ * results agree to the int16 storage's precision, not bit for bit.
+ * Errors: EINVAL (unknown transform, or MFMA outside the cases above),
+ * ENOMEM (16 KB of tables beyond the budget), EDEVICE. */
+typedef enum { MRTLB_TRANSFORM_VALU = 0, MRTLB_TRANSFORM_MFMA = 1 } mrtlb_transform;
+mrtlb_status mrtlb_solve_set_transform(mrtlb_solve* s, int transform);
+
 /* Enqueue nsteps >= 0 collide-and-stream steps (asynchronous). */
 mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);
 

@@ -27,6 +27,7 @@ MRTLB_D2Q9, MRTLB_D3Q27 = 12, 13                     # standard lattices, k = 1 
 MRTLB_CUSTOM = 14                                    # user-supplied velocity set
 MRTLB_NSE_INC, MRTLB_NSE_COMP, MRTLB_NCDE, MRTLB_CDE = 0, 1, 2, 3
 MRTLB_FP64, MRTLB_FP32, MRTLB_FP32_DEV, MRTLB_FP16_DEV, MRTLB_BF16_DEV, MRTLB_I16_DEV = 0, 1, 2, 3, 4, 5
+TRANSFORMS = {"valu": 0, "mfma": 1}
 
 KINDS = {"rD2Q25": MRTLB_RD2Q25, "rD2Q13": MRTLB_RD2Q13, "rD3Q53": MRTLB_RD3Q53, "rD3Q33": MRTLB_RD3Q33,
          "rD2Q21": MRTLB_RD2Q21, "D2Q21K": MRTLB_D2Q21K, "rD3Q45": MRTLB_RD3Q45,
@@ -92,6 +93,7 @@ def lib():
         "mrtlb_read_moments": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved_noalloc": (c_int, [c_void_p, _DP, _DP]),
+        "mrtlb_solve_set_transform": (c_int, [c_void_p, c_int]),
         "mrtlb_set_drift_correction": (c_int, [c_void_p, c_int64]),
         "mrtlb_host_alloc": (c_int, [c_size_t, POINTER(c_void_p)]),
         "mrtlb_host_free": (None, [c_void_p]),
@@ -113,7 +115,7 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
             "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external",
-            "mrtlb_conserved_noalloc"]
+            "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform"]
 
 
 def _check(status):
@@ -328,6 +330,11 @@ class Solve:
     def init_fields(self, rho_or_phi, u=None, force=None):
         r, uu, ff = _f64(rho_or_phi), _f64(u), _f64(force)
         _check(lib().mrtlb_init_fields(self.h, _ptr(r), _ptr(uu), _ptr(ff)))
+
+    def set_transform(self, transform):
+        """Hermite transforms of the step kernel: "valu" (default) or "mfma"."""
+        t = TRANSFORMS[transform] if isinstance(transform, str) else int(transform)
+        _check(lib().mrtlb_solve_set_transform(self.h, t))
 
     def step(self, n=1):
         _check(lib().mrtlb_step(self.h, int(n)))

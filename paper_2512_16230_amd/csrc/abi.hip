@@ -20,6 +20,7 @@
 #include "kernels.h"
 #include "lattices.h"
 #include "launch.h"
+#include "mfma_layout.h"
 
 namespace mrtlb {
 
@@ -99,6 +100,8 @@ struct mrtlb_solve {
   void* part = nullptr;         // FP64 partial sums of the plane-sum kernel
   size_t part_bytes = 0;
   bool external = false;        // f[0], f[1] belong to the caller
+  int transform = 0;            // Hermite transforms of the step: 0 VALU, 1 MFMA
+  void* mtab = nullptr;         // MFMA operand tables (kMfmaTabBytes)
 };
 
 namespace mrtlb {
@@ -350,6 +353,7 @@ static Job<Real> make_job(const mrtlb_solve& s, int parity, const KParams<Real>&
   J.phi_prev = static_cast<const Real*>(s.phi[parity]);
   J.phi_out = static_cast<Real*>(s.phi[parity ^ 1]);
   J.sat = reinterpret_cast<int*>(static_cast<char*>(s.jobs) + kFlagOffset);
+  J.mtab = s.mtab;
   J.block_begin = 0;
   J.nblocks = s.nblocks;
   J.vec = s.vec;
@@ -386,6 +390,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.model = s.model.model;
   r.force = s.has_force != 0;
   r.vec = s.vec;
+  r.transform = s.transform;
   r.dim = s.L.D;
   r.jobs = jobs;
   r.njobs = 1;
@@ -610,7 +615,7 @@ static void release(mrtlb_solve* s) {
   if (!s->external)
     for (void* p : {s->f[0], s->f[1]})
       if (p) (void)hipFree(p);
-  for (void* p : {s->force, s->phi[0], s->phi[1], s->jobs, s->pd, s->part})
+  for (void* p : {s->force, s->phi[0], s->phi[1], s->jobs, s->pd, s->part, s->mtab})
     if (p) (void)hipFree(p);
 }
 
@@ -956,6 +961,117 @@ mrtlb_status mrtlb_set_drift_correction(mrtlb_solve* s, int64_t every) {
   return record_reference(s);
 }
 
+// --- MFMA transform ---------------------------------------------------------
+
+static uint16_t host_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float host_bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+static uint16_t host_f16_bits(_Float16 v) {
+  uint16_t b;
+  std::memcpy(&b, &v, 2);
+  return b;
+}
+
+// Operand tables of the MFMA transform (layout in mfma_layout.h) from the
+// solve's storage scales wsc_j and output weights wo_j: forward
+// E[P][j] = e_j^P wsc_j / sigma as f16 hi + lo with |E| <= 16384, the
+// per-row constant 99328 sum_j E[P][j] that the shifted chunks of the int16
+// numbers add (q = f_lo + 2 f_hi - 99328), and backward e_j^P wo_j as bf16
+// hi + lo.
+static void build_mfma_tables(mrtlb_solve& s, std::vector<uint32_t>& words) {
+  const HostLattice& L = s.L;
+  const int B = L.B;
+  KParams<float>& P = s.Pf;
+  double wmax = 0;
+  for (int j = 0; j < B; ++j) wmax = std::max(wmax, (double)P.wsc[j]);
+  const double sigma = wmax * 8.0 / 16384.0;
+  std::vector<_Float16> eh(kMono * 64, (_Float16)0.0f), el(kMono * 64, (_Float16)0.0f);
+  for (int p = 0; p < kMono; ++p) {
+    double bias = 0;
+    for (int j = 0; j < B; ++j) {
+      const int* e = &L.e[j * 3];
+      const double v = mono(p, e[0], e[1], e[2]) * (double)P.wsc[j] / sigma;
+      const _Float16 hi = (_Float16)v;
+      const _Float16 lo = (_Float16)(v - (double)hi);
+      eh[p * 64 + j] = hi;
+      el[p * 64 + j] = lo;
+      bias += (double)hi + (double)lo;
+    }
+    P.mbias[p] = (float)(99328.0 * bias);
+  }
+  P.msig = (float)sigma;
+  words.assign((size_t)kMfmaTabVec * 4, 0u);
+  for (int part = 0; part < 2; ++part)
+    for (int k = 0; k < 4; ++k)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int t = 0; t < 8; ++t) {
+          const int row = lane % 32, K = 16 * k + 8 * (lane / 32) + t;
+          uint16_t bits = 0;
+          if (row < kMono && K < B) bits = host_f16_bits(part == 0 ? eh[row * 64 + K] : el[row * 64 + K]);
+          words[((size_t)((part * 4 + k) * 64 + lane)) * 4 + t / 2] |= (uint32_t)bits << (16 * (t % 2));
+        }
+  for (int part = 0; part < 2; ++part)
+    for (int m = 0; m < 2; ++m)
+      for (int k = 0; k < 2; ++k)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int t = 0; t < 8; ++t) {
+            const int j = 32 * m + lane % 32, K = 16 * k + 8 * (lane / 32) + t;
+            uint16_t bits = 0;
+            if (j < B && K < kMono) {
+              const int* e = &L.e[j * 3];
+              const float v = (float)(mono(K, e[0], e[1], e[2]) * (double)P.wo[j]);
+              const uint16_t hi = host_bf16_rne(v);
+              bits = part == 0 ? hi : host_bf16_rne(v - host_bf16_value(hi));
+            }
+            words[((size_t)kMfmaFwdVec + (size_t)(((part * 2 + m) * 2 + k) * 64 + lane)) * 4 + t / 2] |=
+                (uint32_t)bits << (16 * (t % 2));
+          }
+}
+
+mrtlb_status mrtlb_solve_set_transform(mrtlb_solve* s, int transform) {
+  if (!s) return fail(MRTLB_EINVAL, "solve is NULL");
+  if (transform != MRTLB_TRANSFORM_VALU && transform != MRTLB_TRANSFORM_MFMA)
+    return fail(MRTLB_EINVAL, "unknown transform");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  if (transform == MRTLB_TRANSFORM_MFMA) {
+    int maxe = 0;
+    for (int v : s->L.e) maxe = std::max(maxe, v < 0 ? -v : v);
+    if (s->L.D != 3 || s->L.kind == kCustom || maxe > 2 || s->L.B > 64)
+      return fail(MRTLB_EINVAL, "the MFMA transform is built for the 3D lattices (rD3Q53, rD3Q45, rD3Q33, D3Q27)");
+    if (s->storage != kI16Dev) return fail(MRTLB_EINVAL, "the MFMA transform runs with the int16 deviation storage");
+    if ((s->model.model != MRTLB_NSE_INC && s->model.model != MRTLB_NSE_COMP) || s->has_force)
+      return fail(MRTLB_EINVAL, "the MFMA transform runs the NSE models without a force field");
+    if (s->nxp % 64 != 0)
+      return fail(MRTLB_EINVAL, "the MFMA transform needs a row pitch (nx rounded up to 32) that is a multiple of 64");
+    if (!s->mtab) {
+      if (s->ctx->used + (size_t)kMfmaTabBytes > s->ctx->budget)
+        return fail(MRTLB_ENOMEM, "the MFMA tables exceed the remaining HBM budget");
+      if (hipMalloc(&s->mtab, kMfmaTabBytes) != hipSuccess) {
+        (void)hipGetLastError();
+        s->mtab = nullptr;
+        return fail(MRTLB_ENOMEM, "device allocation failed");
+      }
+      s->ctx->used += kMfmaTabBytes;
+      s->bytes += kMfmaTabBytes;
+    }
+    std::vector<uint32_t> words;
+    build_mfma_tables(*s, words);
+    HIP_TRY(hipMemcpyAsync(s->mtab, words.data(), kMfmaTabBytes, hipMemcpyHostToDevice, s->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+  }
+  s->transform = transform;
+  return upload_jobs(s);
+}
+
 mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* u, const double* force) {
   if (!s || !rho) return fail(MRTLB_EINVAL, "NULL argument");
   const int D = s->L.D;
@@ -1173,7 +1289,8 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
       // one launch serves one kernel: same lattice kind and dimension (user-
       // supplied lattices share a kind), storage, model, force and VEC
       if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->L.D == a->L.D && b->storage == a->storage &&
-          b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec) {
+          b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec &&
+          b->transform == a->transform) {
         grp.emplace_back(solves[k], nsteps[k]);
         done[k] = 1;
       }

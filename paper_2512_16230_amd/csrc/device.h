@@ -918,6 +918,49 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
   backward<L>(x, P, T.kx * P.kin, P.wo, T.d0, T.d1, T.d2n, T.d2o, T.d3m, T.d3p, T.dxyz);
 }
 
+// a1 of VEC consecutive nodes of a row: f_bar_j(x, t) read from the row of
+// x - e_j.  The rest population (e = 0) is read at the own node; population
+// j >= 1 at a wave-uniform base (soffset) plus a lane offset that depends on
+// the source row only (RowGeom); at the periodic x-edges the wrapped
+// elements are loaded one by one with one lane offset per distinct e_x.
+template <class L, int ST, int VEC>
+__device__ __forceinline__ void gather(const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix0,
+                                       typename StoreT<ST>::T (&raw)[L::B][VEC]) {
+  using T = typename StoreT<ST>::T;
+  constexpr int B = L::B;
+  constexpr int M = L::MAXE;
+  static_assert(L::EX[0] == 0 && L::EY[0] == 0, "population 0 is the rest velocity");
+  const auto& P = J.P;
+  const auto rin = make_rsrc(J.fin, P.pop_bytes);
+  // one node per lane: a wave-uniform choice, so no wave runs both paths
+  const bool inside = ix0 >= M && ix0 + VEC - 1 + M < P.nx;
+  const bool interior = VEC == 1 ? __all(inside) != 0 : inside;
+  if (interior) {
+    // whole VEC-runs inside the row: the lane part depends on the row only
+    const uint32_t lx = (uint32_t)(ix0 + M);
+    load_vec<ST, VEC>(rin, 0u, g.lown() + (uint32_t)ix0, raw[0]);
+    static_for<1, B>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      load_vec<ST, VEC>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx, raw[j]);
+    });
+  } else {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      uint32_t lx[2 * M + 1];
+#pragma unroll
+      for (int e = -M; e <= M; ++e) lx[e + M] = (uint32_t)(wrap(ix0 + k - e, P.nx) + e + M);
+      T one[1];
+      load_vec<ST, 1>(rin, 0u, g.lown() + (uint32_t)(ix0 + k), one);
+      raw[0][k] = one[0];
+      static_for<1, B>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        load_vec<ST, 1>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx[L::EX[j] + M], one);
+        raw[j][k] = one[0];
+      });
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the fused collide-and-stream step: every thread owns VEC consecutive nodes
 // along x.  a1: each population is gathered with one VEC-wide load from the
@@ -943,39 +986,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t N = P.N;
 
-  // a1: gather along -e_j.  The rest population (e = 0) is read at the
-  // own node; population j >= 1 at uniform base + lane offset (RowGeom).
-  static_assert(L::EX[0] == 0 && L::EY[0] == 0, "population 0 is the rest velocity");
-  const auto rin = make_rsrc(J.fin, P.pop_bytes);
+  // a1: gather along -e_j
   T raw[B][VEC];
-  // one node per lane: a wave-uniform choice, so no wave runs both paths
-  const bool inside = ix0 >= M && ix0 + VEC - 1 + M < P.nx;
-  const bool interior = VEC == 1 ? __all(inside) != 0 : inside;
-  if (interior) {
-    // whole VEC-runs inside the row: the lane part depends on the row only
-    const uint32_t lx = (uint32_t)(ix0 + M);
-    load_vec<ST, VEC>(rin, 0u, g.lown() + (uint32_t)ix0, raw[0]);
-    static_for<1, B>([&](auto jj) {
-      constexpr int j = decltype(jj)::value;
-      load_vec<ST, VEC>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx, raw[j]);
-    });
-  } else {
-    // per node: x_src = wrap(x - e_x); one lane offset per distinct e_x
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      uint32_t lx[2 * M + 1];
-#pragma unroll
-      for (int e = -M; e <= M; ++e) lx[e + M] = (uint32_t)(wrap(ix0 + k - e, P.nx) + e + M);
-      T one[1];
-      load_vec<ST, 1>(rin, 0u, g.lown() + (uint32_t)(ix0 + k), one);
-      raw[0][k] = one[0];
-      static_for<1, B>([&](auto jj) {
-        constexpr int j = decltype(jj)::value;
-        load_vec<ST, 1>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx[L::EX[j] + M], one);
-        raw[j][k] = one[0];
-      });
-    }
-  }
+  gather<L, ST, VEC>(J, g, ix0, raw);
 
   // a2-a7 in registers: x holds the numbers the storage reads as, the
   // back-transform leaves the numbers it writes (equal for FP32/FP64).  The
@@ -1252,82 +1265,6 @@ inline bool with_storage(int st, F&& f) {
     case kI16Dev: f(std::integral_constant<int, kI16Dev>{}); return true;
   }
   return false;
-}
-
-// The NCDE kernels are instantiated for the 2D lattices only.
-template <class L>
-hipError_t launch_lattice(const LaunchReq& r) {
-  hipError_t err = hipErrorInvalidValue;
-  const dim3 grid(r.blocks), block(kBlock);
-  with_storage(r.storage, [&](auto stc) {
-    constexpr int ST = decltype(stc)::value;
-    using Real = typename StoreT<ST>::Real;
-    const auto* J = static_cast<const Job<Real>*>(r.jobs);
-    const auto* PD = static_cast<const KParams<double>*>(r.pd);
-    const bool ncde = r.model == kNcde;
-    const bool cde = r.model == kCde;
-    if ((ncde || cde) && L::D != 2) return;
-    switch (r.op) {
-      case kOpStep: {
-        // Several nodes per thread are built only where the host picks them:
-        // the NSE models on the 2D lattices.  Any other request is refused.
-        bool launched = false;
-        auto step = [&](auto vc) {
-          constexpr int V = decltype(vc)::value;
-          if (ncde) {
-            if constexpr (L::D == 2 && V == 1) {
-              hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
-              launched = true;
-            }
-          } else if (cde) {
-            if constexpr (L::D == 2 && V == 1) {
-              hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
-              launched = true;
-            }
-          } else if constexpr (L::D == 2 || V == 1) {
-            if (r.force)
-              hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
-            else
-              hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
-            launched = true;
-          }
-        };
-        if (r.vec == 4) step(std::integral_constant<int, 4>{});
-        else if (r.vec == 2) step(std::integral_constant<int, 2>{});
-        else step(std::integral_constant<int, 1>{});
-        if (!launched) return;
-        break;
-      }
-      case kOpInit:
-        if (ncde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kNcde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
-        } else if (cde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kCde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
-        } else {
-          hipLaunchKernelGGL((k_init<L, ST, kNseComp>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
-        }
-        break;
-      case kOpMoments:
-        if (ncde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kNcde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
-        } else if (cde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kCde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
-        } else {
-          hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
-        }
-        break;
-      case kOpPopulations:
-        hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 1>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
-        break;
-      case kOpScatter:
-        hipLaunchKernelGGL((k_scatter<L, ST>), grid, block, 0, r.stream, J, PD, r.in0);
-        break;
-      default:
-        return;
-    }
-    err = hipGetLastError();
-  });
-  return err;
 }
 
 }  // namespace mrtlb

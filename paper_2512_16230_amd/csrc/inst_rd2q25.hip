@@ -1,5 +1,5 @@
 // Kernel instantiations for the rd2q25 lattice.
-#include "device.h"
+#include "launchers.h"
 
 namespace mrtlb {
 hipError_t launch_rd2q25(const LaunchReq& r) { return launch_lattice<LatRD2Q25>(r); }

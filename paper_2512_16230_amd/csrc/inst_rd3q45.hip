@@ -1,5 +1,5 @@
 // Kernel instantiations for the rd3q45 lattice.
-#include "device.h"
+#include "launchers.h"
 
 namespace mrtlb {
 hipError_t launch_rd3q45(const LaunchReq& r) { return launch_lattice<LatRD3Q45>(r); }

@@ -73,6 +73,10 @@ struct KParams {
   // velocity set at run time (read by the user-supplied-lattice kernels)
   int cb;                    // b
   int8_t ce[kMaxB][3];       // integer velocity multiples e_j
+  // MFMA transform (3D lattices, int16 storage): the forward product gives
+  // the raw monomial sums as msig * (acc - mbias[P]) (see mfma.h)
+  Real mbias[20];
+  Real msig;
   // Drift correction: added to every node's zeroth and first Hermite moments
   // before the collision of one step (zero otherwise); the collision keeps
   // them, so the step moves the totals by N * dm0 and N * dm1.
@@ -89,6 +93,7 @@ struct Job {
   const Real* phi_prev;     // NCDE: phi^{n-1}
   Real* phi_out;            // NCDE: phi^n
   int* sat;                 // int16 storage: set to 1 when a value saturates
+  const void* mtab;         // MFMA transform: operand tables (16 KB), or nullptr
   uint32_t block_begin;     // first linear workgroup of this job
   uint32_t nblocks;
   int vec;                  // nodes per thread along x

@@ -16,6 +16,7 @@ struct LaunchReq {
   int model = 0;             // ModelKind
   bool force = false;        // NSE with a body-force field
   int vec = 1;               // step kernel: nodes per thread along x (1, 2, 4)
+  int transform = 0;         // step kernel: Hermite transforms on VALU (0) or MFMA (1)
   int dim = 2;               // lattice dimension (user-supplied lattices)
   const void* jobs = nullptr;
   int njobs = 1;

@@ -1,0 +1,98 @@
+// Host launchers of one lattice's kernels (step, initialisation, read-out,
+// restore), included by the per-lattice translation units inst_*.hip.
+#pragma once
+
+#include "device.h"
+#include "mfma.h"
+
+namespace mrtlb {
+
+// The NCDE kernels are instantiated for the 2D lattices only.
+template <class L>
+hipError_t launch_lattice(const LaunchReq& r) {
+  hipError_t err = hipErrorInvalidValue;
+  const dim3 grid(r.blocks), block(kBlock);
+  with_storage(r.storage, [&](auto stc) {
+    constexpr int ST = decltype(stc)::value;
+    using Real = typename StoreT<ST>::Real;
+    const auto* J = static_cast<const Job<Real>*>(r.jobs);
+    const auto* PD = static_cast<const KParams<double>*>(r.pd);
+    const bool ncde = r.model == kNcde;
+    const bool cde = r.model == kCde;
+    if ((ncde || cde) && L::D != 2) return;
+    switch (r.op) {
+      case kOpStep: {
+        // Several nodes per thread are built only where the host picks them:
+        // the NSE models on the 2D lattices.  Any other request is refused.
+        bool launched = false;
+        auto step = [&](auto vc) {
+          constexpr int V = decltype(vc)::value;
+          if (ncde) {
+            if constexpr (L::D == 2 && V == 1) {
+              hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              launched = true;
+            }
+          } else if (cde) {
+            if constexpr (L::D == 2 && V == 1) {
+              hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              launched = true;
+            }
+          } else if constexpr (L::D == 2 || V == 1) {
+            if (r.force)
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+            else
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+            launched = true;
+          }
+        };
+        if (r.transform == 1) {
+          // MFMA transforms: 3D lattices, int16 storage, the NSE models without a force field
+          if constexpr (L::D == 3 && ST == kI16Dev) {
+            if (!ncde && !cde && !r.force) {
+              hipLaunchKernelGGL((k_step_mfma<L, kNseComp>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              launched = true;
+            }
+          }
+        } else if (r.vec == 4) {
+          step(std::integral_constant<int, 4>{});
+        } else if (r.vec == 2) {
+          step(std::integral_constant<int, 2>{});
+        } else {
+          step(std::integral_constant<int, 1>{});
+        }
+        if (!launched) return;
+        break;
+      }
+      case kOpInit:
+        if (ncde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kNcde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+        } else if (cde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kCde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+        } else {
+          hipLaunchKernelGGL((k_init<L, ST, kNseComp>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+        }
+        break;
+      case kOpMoments:
+        if (ncde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kNcde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        } else if (cde) {
+          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kCde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        } else {
+          hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        }
+        break;
+      case kOpPopulations:
+        hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 1>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+        break;
+      case kOpScatter:
+        hipLaunchKernelGGL((k_scatter<L, ST>), grid, block, 0, r.stream, J, PD, r.in0);
+        break;
+      default:
+        return;
+    }
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+}  // namespace mrtlb
