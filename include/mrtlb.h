@@ -190,7 +190,10 @@ mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* lat, int* b, int* d, int* 
  *                 M2 = cs^2 phi I, M3 = 0; source S_G = -u . grad phi with
  *                 grad phi = -s1 sum_j c_j f_j / cs^2 and
  *                 phi = sum_j f_j + S_G / 2 (eq. M-NCDE-3-00),
- *                 M0G = (1 - s0/2) S_G; K = cs^2 (1/s1 - 1/2).  2D lattices.
+ *                 M0G = (1 - s0/2) S_G; K = cs^2 (1/s1 - 1/2).  The velocity field
+ *                 may change between steps (mrtlb_set_velocity_field).
+ *   The NCDE and CDE run on every compiled lattice, 2D and 3D (not on
+ *   user-supplied lattices).
  * ------------------------------------------------------------------------- */
 typedef enum { MRTLB_NSE_INC = 0, MRTLB_NSE_COMP = 1, MRTLB_NCDE = 2, MRTLB_CDE = 3 } mrtlb_model;
 
@@ -323,6 +326,13 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho_or_phi, const d
  * ENOMEM (16 KB of tables beyond the budget), EDEVICE. */
 typedef enum { MRTLB_TRANSFORM_VALU = 0, MRTLB_TRANSFORM_MFMA = 1 } mrtlb_transform;
 mrtlb_status mrtlb_solve_set_transform(mrtlb_solve* s, int transform);
+
+/* CDE only: replace the velocity field u(x) (d*N values, layout as in
+ * mrtlb_init_fields) from the next step on, for a velocity that changes in
+ * time, u(x, t): the steps use the field last set.  Waits for the work
+ * enqueued before it.  Errors: EINVAL (NULL, not a CDE solve), ENUMERIC
+ * (non-finite value), EDEVICE. */
+mrtlb_status mrtlb_set_velocity_field(mrtlb_solve* s, const double* u);
 
 /* Enqueue nsteps >= 0 collide-and-stream steps (asynchronous). */
 mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);

@@ -94,6 +94,7 @@ def lib():
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved_noalloc": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_solve_set_transform": (c_int, [c_void_p, c_int]),
+        "mrtlb_set_velocity_field": (c_int, [c_void_p, _DP]),
         "mrtlb_set_drift_correction": (c_int, [c_void_p, c_int64]),
         "mrtlb_host_alloc": (c_int, [c_size_t, POINTER(c_void_p)]),
         "mrtlb_host_free": (None, [c_void_p]),
@@ -115,7 +116,7 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
             "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external",
-            "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform"]
+            "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform", "mrtlb_set_velocity_field"]
 
 
 def _check(status):
@@ -335,6 +336,10 @@ class Solve:
         """Hermite transforms of the step kernel: "valu" (default) or "mfma"."""
         t = TRANSFORMS[transform] if isinstance(transform, str) else int(transform)
         _check(lib().mrtlb_solve_set_transform(self.h, t))
+
+    def set_velocity_field(self, u):
+        """CDE: the velocity field (d, *shape) used from the next step on."""
+        _check(lib().mrtlb_set_velocity_field(self.h, _ptr(_f64(u))))
 
     def step(self, n=1):
         _check(lib().mrtlb_step(self.h, int(n)))

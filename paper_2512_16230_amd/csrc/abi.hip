@@ -560,15 +560,12 @@ mrtlb_status mrtlb_lattice_query(const mrtlb_lattice* l, int* b, int* d, int* e,
 }
 
 static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L) {
-  const int D = L.D;
   if (m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP && m.model != MRTLB_NCDE && m.model != MRTLB_CDE)
     return fail(MRTLB_EINVAL, "unknown model");
   const double r[6] = {m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high};
   for (double v : r)
     if (!(v > 0 && v < 2)) return fail(MRTLB_EINVAL, "relaxation rates must lie in (0, 2)");
   if (m.model == MRTLB_NSE_INC && !(m.rho0 > 0)) return fail(MRTLB_EINVAL, "rho0 must be positive");
-  if (m.model == MRTLB_NCDE && D != 2) return fail(MRTLB_EINVAL, "the NCDE model is built for 2D lattices");
-  if (m.model == MRTLB_CDE && D != 2) return fail(MRTLB_EINVAL, "the CDE model is built for 2D lattices");
   if (!(m.u_bound >= 0 && m.u_bound < 1e3) || !(m.dev_bound >= 0 && m.dev_bound < 1e3))
     return fail(MRTLB_EINVAL, "u_bound and dev_bound must be finite and >= 0");
   for (int a = 0; a < 3; ++a)
@@ -1072,6 +1069,32 @@ mrtlb_status mrtlb_solve_set_transform(mrtlb_solve* s, int transform) {
   return upload_jobs(s);
 }
 
+// The CDE's velocity field (d x N, FP64 on the host) into the solve's
+// device field, in the compute precision; synchronous.
+static mrtlb_status upload_velocity(mrtlb_solve* s, const double* u) {
+  const int D = s->L.D;
+  for (size_t i = 0; i < (size_t)D * s->N; ++i)
+    if (!std::isfinite(u[i])) return fail(MRTLB_ENUMERIC, "non-finite velocity field");
+  hipStream_t st = s->ctx->stream;
+  if (is_double(s->storage)) {
+    HIP_TRY(hipMemcpyAsync(s->force, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  } else {
+    std::vector<float> tmp((size_t)D * s->N);
+    for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)u[i];
+    HIP_TRY(hipMemcpyAsync(s->force, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_set_velocity_field(mrtlb_solve* s, const double* u) {
+  if (!s || !u) return fail(MRTLB_EINVAL, "NULL argument");
+  if (s->model.model != MRTLB_CDE) return fail(MRTLB_EINVAL, "the velocity field belongs to the CDE model");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  return upload_velocity(s, u);
+}
+
 mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* u, const double* force) {
   if (!s || !rho) return fail(MRTLB_EINVAL, "NULL argument");
   const int D = s->L.D;
@@ -1087,18 +1110,8 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
   HIP_TRY(dr.alloc((size_t)s->N * 8, st));
   HIP_TRY(hipMemcpyAsync(dr.p, rho, (size_t)s->N * 8, hipMemcpyHostToDevice, st));
   if (cde) {
-    // the velocity field, in the compute precision
-    for (size_t i = 0; i < (size_t)D * s->N; ++i)
-      if (!std::isfinite(u[i])) return fail(MRTLB_ENUMERIC, "non-finite velocity field");
-    if (is_double(s->storage)) {
-      HIP_TRY(hipMemcpyAsync(s->force, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
-      HIP_TRY(hipStreamSynchronize(st));
-    } else {
-      std::vector<float> tmp((size_t)D * s->N);
-      for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)u[i];
-      HIP_TRY(hipMemcpyAsync(s->force, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, st));
-      HIP_TRY(hipStreamSynchronize(st));
-    }
+    const mrtlb_status vs = upload_velocity(s, u);
+    if (vs != MRTLB_OK) return vs;
   } else if (!ncde) {
     HIP_TRY(du.alloc((size_t)D * s->N * 8, st));
     HIP_TRY(hipMemcpyAsync(du.p, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));

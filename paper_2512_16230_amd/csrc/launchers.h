@@ -7,7 +7,6 @@
 
 namespace mrtlb {
 
-// The NCDE kernels are instantiated for the 2D lattices only.
 template <class L>
 hipError_t launch_lattice(const LaunchReq& r) {
   hipError_t err = hipErrorInvalidValue;
@@ -19,7 +18,6 @@ hipError_t launch_lattice(const LaunchReq& r) {
     const auto* PD = static_cast<const KParams<double>*>(r.pd);
     const bool ncde = r.model == kNcde;
     const bool cde = r.model == kCde;
-    if ((ncde || cde) && L::D != 2) return;
     switch (r.op) {
       case kOpStep: {
         // Several nodes per thread are built only where the host picks them:
@@ -28,12 +26,12 @@ hipError_t launch_lattice(const LaunchReq& r) {
         auto step = [&](auto vc) {
           constexpr int V = decltype(vc)::value;
           if (ncde) {
-            if constexpr (L::D == 2 && V == 1) {
+            if constexpr (V == 1) {
               hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
               launched = true;
             }
           } else if (cde) {
-            if constexpr (L::D == 2 && V == 1) {
+            if constexpr (V == 1) {
               hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
               launched = true;
             }
@@ -65,18 +63,18 @@ hipError_t launch_lattice(const LaunchReq& r) {
       }
       case kOpInit:
         if (ncde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kNcde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+          hipLaunchKernelGGL((k_init<L, ST, kNcde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
         } else if (cde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_init<L, ST, kCde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+          hipLaunchKernelGGL((k_init<L, ST, kCde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
         } else {
           hipLaunchKernelGGL((k_init<L, ST, kNseComp>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
         }
         break;
       case kOpMoments:
         if (ncde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kNcde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+          hipLaunchKernelGGL((k_gather<L, ST, kNcde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
         } else if (cde) {
-          if constexpr (L::D == 2) hipLaunchKernelGGL((k_gather<L, ST, kCde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
+          hipLaunchKernelGGL((k_gather<L, ST, kCde, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
         } else {
           hipLaunchKernelGGL((k_gather<L, ST, kNseComp, 0>), grid, block, 0, r.stream, J, PD, r.out0, r.out1);
         }

@@ -206,9 +206,6 @@ def test_standard_lattice_ncde_and_cde(ctx, card):
         c.init_fields(cw.rho_or_phi, cw.u)
         c.step(20)
         assert max_rel(c.read_moments(with_u=False), cphi_o) < tol
-    with pytest.raises(H.MrtlbError) as e:       # the NCDE is built for 2D lattices
-        H.Solve(ctx, hip_lattice(W.Q27_RECT), hip_model("NCDE", W.Rates(), D0=0.1), (8, 8, 8), "fp32")
-    assert e.value.status == H.MRTLB_EINVAL
 
 
 @pytest.mark.parametrize("card", [W.Q21_RECT, W.Q21K_RECT], ids=lambda c: c.kind)
@@ -888,3 +885,96 @@ def test_sound_wave(ctx, card, axis):
     print("damping / closed form %.4f, speed / cs %.4f" % (ratio, p[2] / (np.sqrt(card.cs2) * k)), flush=True)
     assert abs(ratio - 1) < 0.005
     s.close()
+
+
+# --------------------------------------------------------------------------
+# NCDE and CDE on the 3D lattices; a CDE velocity that changes in time
+# --------------------------------------------------------------------------
+
+def _field_3d(card, shape, U):
+    """Divergence-free u = (U sin(2 pi y / Ly), U sin(2 pi z / Lz), U sin(2 pi x / Lx))."""
+    x, y, z = (W.axis_coords(card, shape, a) for a in range(3))
+    Lx, Ly, Lz = (shape[2 - a] * card.c[a] for a in range(3))
+    return np.stack([np.broadcast_to(U * np.sin(2 * np.pi * y / Ly), shape),
+                     np.broadcast_to(U * np.sin(2 * np.pi * z / Lz), shape),
+                     np.broadcast_to(U * np.sin(2 * np.pi * x / Lx), shape)])
+
+
+@pytest.mark.parametrize("card", [W.Q53_RECT, W.Q33_CUBIC, W.Q27_RECT], ids=lambda c: c.kind)
+def test_ncde_and_cde_3d(ctx, card):
+    """NCDE (nonlinear D, advection, general terms, source) and CDE (3D
+    divergence-free velocity field) on a ragged 3D grid against the oracle."""
+    shape = (10, 12, 40)
+    steps = 20
+    wl = W.ncde_hill(shape, steps, adv_u=(0.02, -0.015, 0.01), D0=0.3 * card.cs2, D2=1.0, card=card)
+    wl.rho_or_phi = W.gaussian_hill(card, shape, sigma0=3.0)
+    kw = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u, gn_bt=(0.05, 0.0, -0.03), gn_dd=(0.01, 0.0, 0.02), src_k=-0.01)
+    phi_o, _, _ = _oracle_run(card, "NCDE", wl.rates, wl.rho_or_phi, None, steps, **kw)
+    vel = _field_3d(card, shape, 0.03)
+    cw = W.cde_hill(shape, steps, u=vel, D0=0.3 * card.cs2, card=card)
+    cw.rho_or_phi = wl.rho_or_phi
+    lat, mdl = oracle_for(card, "CDE", cw.rates)
+    st = OM.run(lat, mdl, OM.init_state(lat, mdl, cw.rho_or_phi), steps, force=vel)
+    cphi_o, _ = OM.moments(lat, mdl, st, force=vel)
+    for storage, tol in (("fp64", 5e-14), ("fp32", 1e-6), ("i16_dev", 1.5e-3)):
+        print("case: %s NCDE/CDE 3D %s" % (card.kind, storage), flush=True)
+        bk = {}
+        if storage == "i16_dev":
+            ub, db = W.flow_bounds("NCDE", wl.rho_or_phi, None, None, steps, adv_u=wl.adv_u)
+            bk = dict(u_bound=ub, dev_bound=db)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, **kw, **bk), shape, storage)
+        s.init_fields(wl.rho_or_phi)
+        s.step(steps)
+        e_n = max_rel(s.read_moments(with_u=False), phi_o)
+        s.close()
+        if storage == "i16_dev":
+            ub, db = W.flow_bounds("CDE", cw.rho_or_phi, vel)
+            bk = dict(u_bound=ub, dev_bound=db)
+        c = H.Solve(ctx, hip_lattice(card), hip_model("CDE", cw.rates, **bk), shape, storage)
+        c.init_fields(cw.rho_or_phi, vel)
+        c.step(steps)
+        e_c = max_rel(c.read_moments(with_u=False), cphi_o)
+        c.close()
+        print("errs %s 3D %s: NCDE phi %.3e, CDE phi %.3e" % (card.kind, storage, e_n, e_c), flush=True)
+        assert e_n < tol and e_c < tol
+
+
+@pytest.mark.parametrize("card,shape", [(W.Q13_SQUARE, (48, 64)), (W.Q33_CUBIC, (10, 12, 40))],
+                         ids=["rD2Q13", "rD3Q33"])
+def test_cde_velocity_changing_in_time(ctx, card, shape):
+    """A uniform velocity that turns in time, set before every step with
+    mrtlb_set_velocity_field: the same sequence as the oracle's."""
+    steps, U = 24, 0.04
+    w = 2 * np.pi / steps
+    d = card.d
+
+    def vel(n):
+        u = np.zeros(d)
+        u[0], u[1] = U * np.cos(w * n), U * np.sin(w * n)
+        return np.broadcast_to(u.reshape((d,) + (1,) * d), (d,) + tuple(shape)).copy()
+
+    wl = W.cde_hill(shape, steps, u=vel(0), D0=0.1, card=card)
+    lat, mdl = oracle_for(card, "CDE", wl.rates)
+    st = OM.init_state(lat, mdl, wl.rho_or_phi)
+    for n in range(steps):
+        st = OM.step(lat, mdl, st, force=vel(n))
+    phi_o, _ = OM.moments(lat, mdl, st, force=vel(steps))
+    for storage, tol in (("fp64", 6e-14), ("fp32", 1.4e-6)):
+        print("case: CDE turning velocity %s %s" % (card.kind, storage), flush=True)
+        s = H.Solve(ctx, hip_lattice(card), hip_model("CDE", wl.rates), shape, storage)
+        s.init_fields(wl.rho_or_phi, vel(0))
+        for n in range(steps):
+            s.set_velocity_field(vel(n))
+            s.step(1)
+        s.set_velocity_field(vel(steps))
+        phi, u = s.read_moments()
+        print("errs CDE turning %s %s phi %.3e" % (card.kind, storage, max_rel(phi, phi_o)), flush=True)
+        assert max_rel(phi, phi_o) < tol
+        assert np.abs(u - vel(steps)).max() < 1e-7
+        s.close()
+    with pytest.raises(H.MrtlbError):
+        n = H.Solve(ctx, hip_lattice(card), hip_model("NCDE", wl.rates, D0=0.1), shape, "fp32")
+        try:
+            n.set_velocity_field(vel(0))
+        finally:
+            n.close()
