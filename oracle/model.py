@@ -3,11 +3,13 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 The state is the shifted population f_bar of eq. (2-3) (theta = gamma = 1,
-full correction), stored as an array (b, [Nz,] Ny, Nx) with x fastest.  One
-step is, in the paper's order:
+full correction), or the unshifted f of the explicit three-level scheme
+(theta = 1, gamma = 0), stored as an array (b, [Nz,] Ny, Nx) with x fastest.
+One step is, in the paper's order:
 
-  1. macroscopic variables, eq. (2-4-2) / (2-4-1) with lambda = lambda1 =
-     lambda2 = 1 (eq. M-NSEs-6a);
+  1. macroscopic variables, eq. (2-4-2) / (2-4-1), or eq. (2-4-0) for the
+     three-level scheme; the NSE body force and mass source may be divided
+     between G (F_G, S_G, corrected with lambda2, lambda1) and F (F_F, S_F);
   2. Hermite moments m = H f_bar of the rows of order <= 3 (Sec. IV);
   3. equilibrium Hermite moments m_eq from the raw moments M0..M3 the model
      prescribes: M0 = rho_bar, M1 = rho u, M2 = rho uu + p I,
@@ -15,14 +17,19 @@ step is, in the paper's order:
      (eqs. M-NSEs-6a, M-NSEs-6 / M-NSEs-6-1, and the multispeed special cases
      of Sec. III), or for the NCDE M0 = phi, M1 = B = phi u,
      M2 = cs^2 D + M20 with D = Phi(phi) I and M20 = phi uu (eq. M-NCDE-6);
-  4. source moments: M1F = F, M2F = 0 (eq. M-NSEs-5); the auxiliary second
-     moment of G is (I - S2/2)(uF + Fu) (eq. M2G-1 with isothermal p, S = 0
-     and M30 = rho uuu); for the NCDE the auxiliary first moment of G is
-     (I - S1/2)(d_t M1 + div M20) (eq. M-NCDE-6, case (1));
+  4. source moments: M0F = S_F, M1F = F_F, M2F = 0 (eqs. M-NSEs-2,
+     M-NSEs-5); the auxiliary moments of G are M0G = (1 - s0 lambda1/2) S_G,
+     M1G = (I - lambda2 S1/2) F_G - lambda1 S10 S_G/2 and
+     M2G = M2G_bar - (lambda1 S20 S_G + lambda2 S21 F_G)/2 (eqs. M-NSEs-2,
+     M-NSEs-4-0) with M2G_bar = (I - S2/2)[uF + Fu + (cs^2 I - uu) S]
+     (eq. M2G-1 with isothermal p and M30 = rho uuu); for the NCDE the
+     auxiliary first moment of G is (I - S1/2)(d_t M1 + div M20)
+     (eq. M-NCDE-6, case (1));
   5. relaxation with S in Hermite space (diagonal, except the normal
      second-order block of the standard k = 1 lattices, eq. 4-27) and the update
      m* = m - S (m - m_eq) + m_G + (I - S/2) m_F (eq. 2-3 with
-     Lambda = H^-1 S H, eq. H-MRT-LB);
+     Lambda = H^-1 S H, eq. H-MRT-LB), or for the three-level scheme
+     m* = m - S (m - m_eq) + m_G + m_F + (m_F(t) - m_F(t - dt))/2 (eq. 2-1);
   6. back to populations with the reduced form of eq. (H-MRT-LB-1): every row
      above third order relaxes at the single rate s_h, so
      f* = (1 - s_h) f + W sum_{r<=3} H_r^T (m*_r - (1 - s_h) m_r) / n_r;
@@ -85,8 +92,17 @@ class Model:
     src_q: float = 0.0
     src_k: float = 0.0
     three_level: bool = False
-    # NSE_COMP uniform mass source S (M0F = S, eq. M-NSEs-5 with S_G = 0)
+    # NSE_COMP uniform mass source S
     mass_src: float = 0.0
+    # NSE: the share of the body force and of the mass source that the
+    # auxiliary distribution G carries, F_G = g_share F and S_G = g_share S
+    # (the rest, F_F and S_F, is carried by the source distribution F; eq.
+    # M-NSEs-2), and the partial-correction parameters of eqs. (2-4-0) and
+    # (2-4-2).  three_level also applies to the NSE: theta = 1, gamma = 0,
+    # unshifted f, F_j + (F_j(t) - F_j(t - dt)) / 2.
+    g_share: float = 0.0
+    lambda1: float = 1.0
+    lambda2: float = 1.0
 
     def rate(self, group: str) -> float:
         return {"rho": self.s0, "j": self.s1, "bulk": self.s_bulk, "shear": self.s_shear,
@@ -184,6 +200,29 @@ def cde_source(lat: Lattice, model: Model, f: np.ndarray, vel: np.ndarray):
     return -(vel * grad).sum(axis=0)
 
 
+def nse_split(model: Model, force, n: int):
+    """(F_G, F_F, S_G, S_F): the body force F (d, n) or None and the mass
+    source S divided between the auxiliary distribution G and the source
+    distribution F, F = F_G + F_F and S = S_G + S_F (eq. M-NSEs-2)."""
+    a = float(model.g_share)
+    S = np.full(n, float(model.mass_src))
+    if force is None:
+        return None, None, a * S, (1 - a) * S
+    return a * force, (1 - a) * force, a * S, (1 - a) * S
+
+
+def nse_corrections(model: Model, force, n: int):
+    """The source corrections of rho and rho u: (lambda1 S_G + h S_F) / 2 and
+    (lambda2 F_G + h F_F) / 2 with h = 1 for the shifted f_bar of the full
+    correction (eq. 2-4-2) and h = 0 for the unshifted f of the three-level
+    scheme (eq. 2-4-0); the momentum part is None without a force."""
+    FG, FF, SG, SF = nse_split(model, force, n)
+    h = 0.0 if model.three_level else 1.0
+    r = 0.5 * (model.lambda1 * SG + h * SF)
+    jc = None if force is None else 0.5 * (model.lambda2 * FG + h * FF)
+    return r, jc
+
+
 def macroscopic(lat: Lattice, model: Model, f: np.ndarray, force=None):
     """(rho_bar or phi, u, rho_m) from pre-collision f_bar of shape (b, n).
     For the CDE ``force`` carries the velocity field u (d, n)."""
@@ -196,12 +235,14 @@ def macroscopic(lat: Lattice, model: Model, f: np.ndarray, force=None):
             # eq. 2-4-1 with S_G = 0: phi = sum f_bar + S_F / 2, S_F = q + k phi
             R0 = (R0 + 0.5 * model.src_q) / (1 - 0.5 * model.src_k)
         return R0, u, None
+    # eq. 2-4-2: rho = sum f_bar + (lambda1 S_G + S_F) / 2,
+    # rho u = sum c f_bar + (lambda2 F_G + F_F) / 2 (eq. 2-4-0 for the
+    # three-level scheme's unshifted f: no S_F, F_F terms)
+    r, jc = nse_corrections(model, force, f.shape[1])
     j = lat.E.T @ f
-    if force is not None:
-        j = j + 0.5 * force
-    if model.mass_src:
-        # eq. 2-4-2 with S_G = 0: rho = sum f_bar + S_F / 2
-        R0 = R0 + 0.5 * model.mass_src
+    if jc is not None:
+        j = j + jc
+    R0 = R0 + r
     rho_m = np.full_like(R0, model.rho0) if model.eq == NSE_INC else R0
     return R0, j / rho_m, rho_m
 
@@ -232,14 +273,64 @@ def equilibrium_hermite(lat, model, R0, u, rho_m):
 
 
 def force_hermite(lat, n, force, mass_src=0.0):
-    """Hermite moments of the source distribution F_j: M0F = S (mass
-    source), M1F = F, M2F = 0 (raw moments, eq. M-NSEs-5)."""
+    """Hermite moments of the source distribution F_j: M0F = S_F (mass
+    source, a scalar or per node), M1F = F_F, M2F = 0 (raw moments, eqs.
+    M-NSEs-2, M-NSEs-5)."""
     d = lat.d
-    if force is None and not mass_src:
+    S = np.broadcast_to(np.asarray(mass_src, dtype=np.float64), (n,))
+    if force is None and not S.any():
         return np.zeros((len(lat.rows), n))
     F = np.zeros((d, n)) if force is None else force
-    M = [np.full(n, float(mass_src)), F, np.zeros((d, d, n)), None]
+    M = [np.array(S), F, np.zeros((d, d, n)), None]
     return hermite_from_raw(lat, M, max_order=2)
+
+
+def raw_blocks(lat: Lattice, model: Model):
+    """(s0, S10, S1, S20, S21): the blocks of the collision matrix on the raw
+    moments, sum_j Lambda_jk = s0, sum_j c_j Lambda_jk = S10 + S1 c_k and
+    sum_j c_j c_j Lambda_jk = S20 + S21 c_k + S2 c_k c_k (Sec. III), for
+    Lambda = H^-1 S H with S acting on the Hermite rows.  Summed against a
+    distribution g these read sum Lambda g = s0 M0, sum c Lambda g =
+    S10 M0 + S1 M1, sum cc Lambda g = S20 M0 + S21 M1 + S2 M2, so each block
+    is the raw response of the relaxation to a distribution with a single
+    unit raw moment: M0 = 1 gives s0, S10, S20; M1 = e_c gives column c of
+    S1 and S21."""
+    d = lat.d
+    S = relaxation_matrix(lat, model)
+    E = lat.E
+
+    def response(M0, M1):
+        m = hermite_from_raw(lat, [np.array([M0]), np.asarray(M1, dtype=np.float64).reshape(d, 1),
+                                   np.zeros((d, d, 1)), None], max_order=2)
+        g = populations_from_hermite(lat, S @ m)[:, 0]
+        return g.sum(), E.T @ g, np.einsum("ja,jb,j->ab", E, E, g)
+
+    s0, S10, S20 = response(1.0, np.zeros(d))
+    S1 = np.zeros((d, d))
+    S21 = np.zeros((d, d, d))
+    for c in range(d):
+        e = np.zeros(d)
+        e[c] = 1.0
+        _, S1[:, c], S21[:, :, c] = response(0.0, e)
+    return s0, S10, S1, S20, S21
+
+
+def g_route_hermite(lat: Lattice, model: Model, force, n: int):
+    """Hermite moments of the part of G that carries S_G and F_G: raw
+    M0G = (1 - s0 lambda1 / 2) S_G and M1G = (I - lambda2 S1 / 2) F_G
+    - lambda1 S10 S_G / 2 (eq. M-NSEs-2), and the second-moment share
+    -(lambda1 S20 S_G + lambda2 S21 F_G) / 2 by which M2G differs from the
+    prescribed M2G_bar of ``aux_hermite`` (eq. M-NSEs-4-0)."""
+    d = lat.d
+    FG, _, SG, _ = nse_split(model, force, n)
+    if FG is None:
+        FG = np.zeros((d, n))
+    s0, S10, S1, S20, S21 = raw_blocks(lat, model)
+    l1, l2 = model.lambda1, model.lambda2
+    M0 = (1 - 0.5 * s0 * l1) * SG
+    M1 = FG - 0.5 * l2 * (S1 @ FG) - 0.5 * l1 * np.outer(S10, SG)
+    M2 = -0.5 * (l1 * S20[:, :, None] * SG + l2 * np.einsum("abc,cn->abn", S21, FG))
+    return hermite_from_raw(lat, [M0, M1, M2, None], max_order=2)
 
 
 def aux_hermite(lat, model, S, u, force, extra=None, cross=None):
@@ -328,6 +419,7 @@ def ncde_B(lat: Lattice, model: Model, phi_grid: np.ndarray, phi_prev_grid: np.n
 class State:
     f: np.ndarray                 # (b, *grid) pre-collision f_bar
     phi_prev: np.ndarray = None   # NCDE only: phi of the previous step
+    force_prev: np.ndarray = None  # NSE three-level: the previous step's force (None: the current one)
 
 
 def ncde_source_hermite(lat: Lattice, model: Model, phi):
@@ -338,13 +430,15 @@ def ncde_source_hermite(lat: Lattice, model: Model, phi):
     return mF
 
 
-def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, ncde_x=None, phi_prev=None):
+def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, ncde_x=None, phi_prev=None,
+            force_prev=None):
     """Post-collision populations f* (b, n) from pre-collision f_bar (b, n).
 
     ``ncde_b`` and ``ncde_x`` are the NCDE fields B^n and X^n (d, n) of the
     auxiliary first moment and ``phi_prev`` the previous step's phi (the
-    three-level scheme's F(t - dt)); for the CDE ``force`` is the velocity
-    field (d, n)."""
+    three-level scheme's F(t - dt)); ``force_prev`` is the NSE three-level
+    scheme's force at t - dt (None: the current force); for the CDE
+    ``force`` is the velocity field (d, n)."""
     n = f.shape[1]
     S = relaxation_matrix(lat, model)
     R0, u, rho_m = macroscopic(lat, model, f, force)
@@ -357,11 +451,21 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, 
         mG[[r.order == 0 for r in lat.rows]] = (1 - 0.5 * model.s0) * cde_source(lat, model, f, force)
         mstar = m - S @ (m - meq) + mG
         return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
-    mF = force_hermite(lat, n, force, model.mass_src) if model.eq != NCDE else ncde_source_hermite(lat, model, R0)
     mG = aux_hermite(lat, model, S, u, force, extra=ncde_b, cross=ncde_x)
-    if model.eq == NCDE and model.three_level:
+    if model.eq == NCDE:
+        mF = ncde_source_hermite(lat, model, R0)
+    else:
+        _, FF, _, SF = nse_split(model, force, n)
+        mF = force_hermite(lat, n, FF, SF)
+        if model.g_share:
+            mG = mG + g_route_hermite(lat, model, force, n)
+    if model.three_level:
         # eq. 2-1 with theta = 1, gamma = 0: f - Lambda f_ne + G + F + (F(t) - F(t - dt)) / 2
-        mFp = ncde_source_hermite(lat, model, R0 if phi_prev is None else phi_prev)
+        if model.eq == NCDE:
+            mFp = ncde_source_hermite(lat, model, R0 if phi_prev is None else phi_prev)
+        else:
+            _, FFp, _, SFp = nse_split(model, force if force_prev is None else force_prev, n)
+            mFp = force_hermite(lat, n, FFp, SFp)
         mstar = m - S @ (m - meq) + mG + mF + 0.5 * (mF - mFp)
     else:
         mstar = m - S @ (m - meq) + mG + (np.eye(len(lat.rows)) - 0.5 * S) @ mF
@@ -389,8 +493,10 @@ def step(lat: Lattice, model: Model, st: State, force=None) -> State:
         cross = ncde_cross(lat, model, phi, st.phi_prev)
         prev = st.phi_prev.reshape(-1)
     F = None if force is None else force.reshape(lat.d, -1)
-    fstar = collide(lat, model, f, F, extra, cross, prev)
-    return State(stream(lat, fstar.reshape(st.f.shape)), phi)
+    Fp = None if st.force_prev is None else st.force_prev.reshape(lat.d, -1)
+    fstar = collide(lat, model, f, F, extra, cross, prev, force_prev=Fp)
+    keep = None if force is None or not model.three_level or model.eq == NCDE else np.array(force, dtype=np.float64)
+    return State(stream(lat, fstar.reshape(st.f.shape)), phi, keep)
 
 
 def run(lat, model, st: State, steps: int, force=None) -> State:
@@ -404,7 +510,12 @@ def run(lat, model, st: State, steps: int, force=None) -> State:
 # --------------------------------------------------------------------------
 
 def init_state(lat: Lattice, model: Model, rho_or_phi: np.ndarray, u=None, force=None) -> State:
-    """f_bar(x, 0) = f_eq(rho, u) - dt/2 F (NSE) or f_eq(phi) (NCDE, CDE)."""
+    """f_bar(x, 0) = f_eq(rho, u) - dt/2 F (NSE) or f_eq(phi) (NCDE, CDE).
+
+    For the NSE the subtracted distribution has the raw moments of the
+    corrections of eq. (2-4-2), [(lambda1 S_G + h S_F), (lambda2 F_G + h F_F),
+    0] / 2 (h = 0 for the three-level scheme), so that rho and u read back
+    as given; with F_G = S_G = 0 and h = 1 it is F_j / 2."""
     grid = rho_or_phi.shape
     R0 = rho_or_phi.reshape(-1).astype(np.float64)
     n = R0.size
@@ -424,9 +535,11 @@ def init_state(lat: Lattice, model: Model, rho_or_phi: np.ndarray, u=None, force
     rho_m = np.full(n, model.rho0) if model.eq == NSE_INC else R0
     meq = equilibrium_hermite(lat, model, R0, uv, rho_m)
     f = populations_from_hermite(lat, meq)
-    if force is not None or model.mass_src:
-        F = None if force is None else force.reshape(lat.d, -1)
-        f = f - 0.5 * populations_from_hermite(lat, force_hermite(lat, n, F, model.mass_src))
+    F = None if force is None else force.reshape(lat.d, -1).astype(np.float64)
+    r, jc = nse_corrections(model, F, n)
+    if jc is not None or r.any():
+        jc = np.zeros((lat.d, n)) if jc is None else jc
+        f = f - populations_from_hermite(lat, hermite_from_raw(lat, [r, jc, np.zeros((lat.d, lat.d, n)), None], 2))
     return State(f.reshape((lat.b,) + grid), None)
 
 
@@ -441,8 +554,12 @@ def moments(lat: Lattice, model: Model, st: State, force=None):
 
 def conserved(lat: Lattice, model: Model, st: State, force=None):
     f = st.f.reshape(lat.b, -1)
-    mass = f.sum() + 0.5 * model.mass_src * f.shape[1]
+    mass = f.sum()
     mom = lat.E.T @ f.sum(axis=1)
-    if force is not None:
-        mom = mom + 0.5 * force.reshape(lat.d, -1).sum(axis=1)
+    if model.eq in (NSE_INC, NSE_COMP):
+        F = None if force is None else force.reshape(lat.d, -1)
+        r, jc = nse_corrections(model, F, f.shape[1])
+        mass = mass + r.sum()
+        if jc is not None:
+            mom = mom + jc.sum(axis=1)
     return float(mass), mom

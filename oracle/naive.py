@@ -9,7 +9,12 @@ Differs from ``model`` on purpose, so that each pins the other:
   * equilibrium, source and auxiliary distributions are vectors in velocity
     space obtained as H^-1 applied to their Hermite moments (eqs. geq, feq);
   * the update is eq. (2-3) written literally:
-        f*_j = f_j - Lambda_jk (f_k - f_eq_k) + G_j + (delta_jk - Lambda_jk/2) F_k;
+        f*_j = f_j - Lambda_jk (f_k - f_eq_k) + G_j + (delta_jk - Lambda_jk/2) F_k,
+    or eq. (2-1) with theta = 1, gamma = 0 for the three-level scheme;
+  * the raw-moment blocks s0, S10, S1, S20, S21 that the NSE's partial
+    correction uses (eqs. M-NSEs-2, M-NSEs-4-0) are read off the columns of
+    Lambda by their defining sums: the rest velocity's column gives s0,
+    S10, S20, and the columns of +-c_a e_a give S1 and S21 by differences;
   * macroscopic sums and propagation are explicit loops over nodes and
     populations (eq. 2-2).
 """
@@ -37,6 +42,37 @@ class NaiveStepper:
         self.Lam = self.Hinv @ S @ self.Hf
         self.nlow = nlow
         self.S_low = S_low
+        self._read_blocks()
+
+    def _read_blocks(self):
+        """sum_j Lambda_jk = s0, sum_j c_j Lambda_jk = S10 + S1 c_k and
+        sum_j c_j c_j Lambda_jk = S20 + S21 c_k + S2 c_k c_k, evaluated on
+        the columns k of the rest velocity and of the unit steps +-e_a."""
+        lat, E, Lam = self.lat, self.lat.E, self.Lam
+        d = lat.d
+        col1 = E.T @ Lam                                   # (d, b): sum_j c_j Lambda_jk
+        col2 = np.einsum("ja,jb,jk->abk", E, E, Lam)       # (d, d, b)
+        rest = [k for k in range(lat.b) if not lat.e[k].any()][0]
+        self.s0 = float(Lam[:, rest].sum())
+        self.S10 = col1[:, rest].copy()
+        self.S20 = col2[:, :, rest].copy()
+        self.S1 = np.zeros((d, d))
+        self.S21 = np.zeros((d, d, d))
+        for a in range(d):
+            unit = np.zeros(d, dtype=int)
+            unit[a] = 1
+            kp = [k for k in range(lat.b) if (lat.e[k] == unit).all()][0]
+            km = [k for k in range(lat.b) if (lat.e[k] == -unit).all()][0]
+            span = 2 * lat.c[a]
+            self.S1[:, a] = (col1[:, kp] - col1[:, km]) / span
+            self.S21[:, :, a] = (col2[:, :, kp] - col2[:, :, km]) / span
+
+    def _raw_to_velocity(self, M0, M1, M2):
+        """The velocity-space distribution whose raw moments of order <= 2
+        are M0, M1, M2 and whose Hermite moments above order 2 vanish."""
+        Mr = [np.array([M0]), np.asarray(M1, dtype=np.float64).reshape(-1, 1),
+              np.asarray(M2, dtype=np.float64).reshape(self.lat.d, self.lat.d, 1), None]
+        return self._velocity_space(M.hermite_from_raw(self.lat, Mr, max_order=2)[:, 0])
 
     def _velocity_space(self, m_low):
         full = np.zeros(self.lat.b)
@@ -76,9 +112,14 @@ class NaiveStepper:
                 rho_m = None
                 rho = phi_grid[x]
             else:
-                if F is not None:
-                    mom = mom + 0.5 * F
-                rho = rho + 0.5 * mdl.mass_src      # rho = sum f_bar + S / 2
+                # F = F_G + F_F, S = S_G + S_F; rho and rho u by eq. 2-4-2
+                # (eq. 2-4-0 for the three-level scheme: no F_F, S_F terms)
+                share, h = mdl.g_share, (0.0 if mdl.three_level else 1.0)
+                Ftot = np.zeros(d) if F is None else F
+                FG, FF = share * Ftot, (1 - share) * Ftot
+                SG, SF = share * mdl.mass_src, (1 - share) * mdl.mass_src
+                mom = mom + 0.5 * (mdl.lambda2 * FG + h * FF)
+                rho = rho + 0.5 * (mdl.lambda1 * SG + h * SF)
                 rho_m = mdl.rho0 if mdl.eq == M.NSE_INC else rho
                 u = mom / rho_m
             R0 = np.array([rho])
@@ -100,8 +141,23 @@ class NaiveStepper:
             else:
                 Fa = None if F is None else F[:, None]
                 G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, Fa)[:, 0])
-                Fv = (np.zeros(b) if F is None and not mdl.mass_src
-                      else self._velocity_space(M.force_hermite(lat, 1, Fa, mdl.mass_src)[:, 0]))
+                if share:
+                    # the S_G, F_G part of G: M0G, M1G (eq. M-NSEs-2) and the
+                    # share of M2G beside M2G_bar (eq. M-NSEs-4-0)
+                    l1, l2 = mdl.lambda1, mdl.lambda2
+                    M0G = (1 - 0.5 * self.s0 * l1) * SG
+                    M1G = FG - 0.5 * l2 * (self.S1 @ FG) - 0.5 * l1 * self.S10 * SG
+                    M2G = -0.5 * (l1 * self.S20 * SG + l2 * np.einsum("abc,c->ab", self.S21, FG))
+                    G = G + self._raw_to_velocity(M0G, M1G, M2G)
+                Fv = self._raw_to_velocity(SF, FF, np.zeros((d, d)))
+                if mdl.three_level:
+                    Fp = Ftot if st.force_prev is None else np.array([st.force_prev[(a,) + x] for a in range(d)])
+                    Fvp = self._raw_to_velocity(SF, (1 - share) * Fp, np.zeros((d, d)))
+                    # eq. 2-1, theta = 1, gamma = 0
+                    out = f - self.Lam @ (f - feq) + G + Fv + 0.5 * (Fv - Fvp)
+                    for j in range(b):
+                        fstar[(j,) + x] = out[j]
+                    continue
             out = f - self.Lam @ (f - feq) + G + (np.eye(b) - 0.5 * self.Lam) @ Fv
             for j in range(b):
                 fstar[(j,) + x] = out[j]
@@ -116,4 +172,7 @@ class NaiveStepper:
                     ax = len(grid) - 1 - a
                     tgt[ax] = (x[ax] + int(lat.e[j, a])) % grid[ax]
                 new[(j,) + tuple(tgt)] = fstar[(j,) + x]
-        return M.State(new, phi_grid)
+        keep = None
+        if mdl.eq != M.NCDE and mdl.three_level and force is not None:
+            keep = np.array(force, dtype=np.float64)
+        return M.State(new, phi_grid, keep)

@@ -163,11 +163,11 @@ def test_first_order_source_scheme_is_caught(monkeypatch):
     leaves a first-order (explicit Euler) source."""
     orig_collide = M.collide
 
-    def euler(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None):
+    def euler(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None, force_prev=None):
         if model.eq == M.NCDE and model.three_level:
             R0 = M.macroscopic(lat, model, f)[0]
             phi_prev = R0              # F(t - dt) = F(t): the correction term vanishes
-        return orig_collide(lat, model, f, force, ncde_b, ncde_x, phi_prev)
+        return orig_collide(lat, model, f, force, ncde_b, ncde_x, phi_prev, force_prev)
     monkeypatch.setattr(M, "collide", euler)
     _pin_fails(TD.test_source_three_level_scheme_is_second_order)
 
@@ -186,3 +186,57 @@ def test_trace_row_at_the_shear_rate_is_caught(card, axis, monkeypatch):
     orig = M.Model.rate
     monkeypatch.setattr(M.Model, "rate", lambda self, g: orig(self, "shear" if g == "bulk" else g))
     _pin_fails(TSO.test_sound_damping_sets_the_bulk_viscosity, card, axis)
+
+
+# --------------------------------------------------------------------------
+# partial correction (force and mass source in G) and the three-level NSE
+# --------------------------------------------------------------------------
+
+import dataclasses  # noqa: E402
+
+import test_oracle_partial_correction as TP  # noqa: E402
+
+
+def test_lambda2_dropped_from_m1g_is_caught(monkeypatch):
+    """M1G = (I - S1/2) F_G instead of (I - lambda2 S1/2) F_G."""
+    orig = M.g_route_hermite
+    monkeypatch.setattr(M, "g_route_hermite",
+                        lambda lat, model, force, n: orig(lat, dataclasses.replace(model, lambda2=1.0), force, n))
+    _pin_fails(TP.test_uniform_force_closed_form, 1.0, 0.5, False)
+
+
+def test_lambda2_dropped_from_u_is_caught(monkeypatch):
+    """rho u = sum c f_bar + F_G / 2 whatever lambda2."""
+    orig = M.nse_corrections
+    monkeypatch.setattr(M, "nse_corrections",
+                        lambda model, force, n: orig(dataclasses.replace(model, lambda2=1.0), force, n))
+    _pin_fails(TP.test_uniform_force_closed_form, 1.0, 0.5, False)
+
+
+def test_lambda1_dropped_from_m0g_is_caught(monkeypatch):
+    """M0G = (1 - s0/2) S_G instead of (1 - s0 lambda1/2) S_G."""
+    orig = M.g_route_hermite
+    monkeypatch.setattr(M, "g_route_hermite",
+                        lambda lat, model, force, n: orig(lat, dataclasses.replace(model, lambda1=1.0), force, n))
+    _pin_fails(TP.test_uniform_mass_source_closed_form, 1.0, 0.5, False)
+
+
+def test_missing_s20_share_of_m2g_is_caught(monkeypatch):
+    """M2G = M2G_bar without the lambda1 S20 S_G / 2 term of eq. M-NSEs-4-0."""
+    orig = M.raw_blocks
+
+    def no_s20(lat, model):
+        s0, S10, S1, S20, S21 = orig(lat, model)
+        return s0, S10, S1, 0.0 * S20, S21
+    monkeypatch.setattr(M, "raw_blocks", no_s20)
+    _pin_fails(TP.test_force_in_g_with_unit_lambdas_is_the_force_in_f, W.Q25_RECT, (5, 6), M.NSE_COMP)
+
+
+def test_three_level_force_difference_dropped_is_caught(monkeypatch):
+    """The NSE three-level scheme without (F(t) - F(t - dt)) / 2."""
+    orig = M.collide
+
+    def no_history(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None, force_prev=None):
+        return orig(lat, model, f, force, ncde_b, ncde_x, phi_prev, None)
+    monkeypatch.setattr(M, "collide", no_history)
+    _pin_fails(TP.test_uniform_force_closed_form, 0.4, 1.0, True)
