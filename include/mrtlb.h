@@ -226,17 +226,42 @@ typedef struct {
    * three_level = 1: explicit three-level scheme (theta = 1, gamma = 0,
    *   unshifted f, phi = sum f, F + (F(t) - F(t - dt))/2 with F(t - dt)
    *   from the stored phi^{n-1}; initial state f_eq).
-   * read_moments and conserved report phi of the chosen scheme.  Other
-   * models: all zero. */
+   * read_moments and conserved report phi of the chosen scheme.  The NSE
+   * models take three_level too (see g_share below); src_q and src_k are
+   * zero for every model but the NCDE. */
   double src_q, src_k;
   int three_level;
-  /* MRTLB_NSE_COMP uniform mass source S (M0F = S, M1F = F, M2F = 0,
-   * eq. M-NSEs-5 with S_G = 0): rho = sum f_bar + S/2 (eq. 2-4-2) and
-   * M2G = (I - S2/2)[uF + Fu + (cs^2 I - uu) S] (eq. M2G-1 with S_bar = S;
-   * for isothermal p, d_t p I + div(p u I) = cs^2 S I).  The initial state
-   * is f_eq - F/2.  Runs in the forced kernel: the solve needs has_force
-   * (a zero force field is fine); EINVAL otherwise and for other models. */
+  /* MRTLB_NSE_COMP uniform mass source S (with g_share = 0: M0F = S,
+   * M1F = F, M2F = 0, eq. M-NSEs-5 with S_G = 0): rho = sum f_bar + S/2
+   * (eq. 2-4-2) and M2G = (I - S2/2)[uF + Fu + (cs^2 I - uu) S] (eq. M2G-1
+   * with S_bar = S; for isothermal p, d_t p I + div(p u I) = cs^2 S I).
+   * The initial state is f_eq - F/2.  Runs in the forced kernel: the solve
+   * needs has_force (a zero force field is fine); EINVAL otherwise and for
+   * other models. */
   double mass_src;
+  /* NSE partial correction (eqs. 2-4-0, 2-4-2, M-NSEs-2, M-NSEs-4-0): the
+   * share g_share in [0, 1] of the body force and of the mass source that
+   * the auxiliary distribution G carries, F_G = g F and S_G = g S (the rest,
+   * F_F and S_F, is carried by the source distribution F), with
+   *   rho = sum f + (lambda1 S_G + h S_F)/2,
+   *   rho u = sum c f + (lambda2 F_G + h F_F)/2,
+   *   M0G = (1 - s0 lambda1/2) S_G, M1G = (I - lambda2 S1/2) F_G,
+   *   M2G = M2G_bar - lambda1 S20 S_G/2, S20 = cs^2 (s0 I - S2 I)
+   * (the raw-moment block of the Hermite-space collision; S10 = S21 = 0),
+   * h = 1 for the full correction and h = 0 for three_level = 1, which for
+   * the NSE is the explicit three-level scheme of eq. (2-1) with theta = 1,
+   * gamma = 0: unshifted f, F + (F(t) - F(t - dt))/2 with F(t - dt) the
+   * force of the previous step (mrtlb_set_force_field), equal to the
+   * current force on the first step after mrtlb_init_fields.  g = 0,
+   * lambda1 = lambda2 = 1 is the full correction above; lambda1 = lambda2 = 1
+   * gives the same scheme for every g.  The scheme is second order when
+   * (1 - lambda1) S_G and (1 - lambda2) F_G do not vary in time and, for
+   * the three-level scheme, div F_F = 0 (eq. M-NSEs-5).  The initial state
+   * subtracts half a distribution of raw moments (lambda1 S_G + h S_F,
+   * lambda2 F_G + h F_F, 0), so rho and u read back as given.  With
+   * g_share = 0 (a zero-initialized descriptor) lambda1 and lambda2 act on
+   * nothing.  Other models: g_share = 0 (EINVAL otherwise), lambdas ignored. */
+  double g_share, lambda1, lambda2;
 } mrtlb_model_desc;
 
 /* Population storage in HBM (compute is FP64 for MRTLB_FP64, FP32 otherwise):
@@ -333,6 +358,17 @@ mrtlb_status mrtlb_solve_set_transform(mrtlb_solve* s, int transform);
  * enqueued before it.  Errors: EINVAL (NULL, not a CDE solve), ENUMERIC
  * (non-finite value), EDEVICE. */
 mrtlb_status mrtlb_set_velocity_field(mrtlb_solve* s, const double* u);
+
+/* NSE solves created with has_force: replace the body force F(x) (d*N
+ * values, layout as in mrtlb_init_fields) from the next step on, for a force
+ * that changes in time, F(x, t) (eq. 2-1 evaluates F at the step's time).
+ * For the three-level scheme with g_share < 1 the next step adds
+ * (1 - g_share)(F - F_prev)/2 to the first moment, F_prev being the force
+ * of the previous step; the first such call allocates d*N reals (8 or 4
+ * bytes, as the force field) for F_prev, kept until mrtlb_solve_destroy.
+ * Waits for the work enqueued before it.  Errors: EINVAL (NULL, not an NSE
+ * solve with a force field), ENUMERIC (non-finite value), ENOMEM, EDEVICE. */
+mrtlb_status mrtlb_set_force_field(mrtlb_solve* s, const double* force);
 
 /* Enqueue nsteps >= 0 collide-and-stream steps (asynchronous). */
 mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);

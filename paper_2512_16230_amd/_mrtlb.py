@@ -53,7 +53,8 @@ class mrtlb_model_desc(ctypes.Structure):
                 ("s_bulk", c_double), ("s3", c_double), ("s_high", c_double), ("m30", c_int), ("D0", c_double),
                 ("D2", c_double), ("adv_u", c_double * 3), ("u_bound", c_double), ("dev_bound", c_double),
                 ("gn_bt", c_double * 3), ("gn_dd", c_double * 3), ("src_q", c_double), ("src_k", c_double),
-                ("three_level", c_int), ("mass_src", c_double)]
+                ("three_level", c_int), ("mass_src", c_double), ("g_share", c_double), ("lambda1", c_double),
+                ("lambda2", c_double)]
 
 
 _lib = None
@@ -95,6 +96,7 @@ def lib():
         "mrtlb_conserved_noalloc": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_solve_set_transform": (c_int, [c_void_p, c_int]),
         "mrtlb_set_velocity_field": (c_int, [c_void_p, _DP]),
+        "mrtlb_set_force_field": (c_int, [c_void_p, _DP]),
         "mrtlb_set_drift_correction": (c_int, [c_void_p, c_int64]),
         "mrtlb_host_alloc": (c_int, [c_size_t, POINTER(c_void_p)]),
         "mrtlb_host_free": (None, [c_void_p]),
@@ -116,7 +118,8 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
             "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external",
-            "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform", "mrtlb_set_velocity_field"]
+            "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform", "mrtlb_set_velocity_field",
+            "mrtlb_set_force_field"]
 
 
 def _check(status):
@@ -232,13 +235,16 @@ class Lattice:
 
 def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s_high=1.2, m30=True, D0=0.0,
                D2=0.0, adv_u=(0.0, 0.0, 0.0), u_bound=0.0, dev_bound=0.0, gn_bt=(0.0, 0.0, 0.0),
-               gn_dd=(0.0, 0.0, 0.0), src_q=0.0, src_k=0.0, three_level=False, mass_src=0.0):
+               gn_dd=(0.0, 0.0, 0.0), src_q=0.0, src_k=0.0, three_level=False, mass_src=0.0, g_share=0.0,
+               lambda1=1.0, lambda2=1.0):
     """Model parameters; u_bound / dev_bound size the int16 storage's ranges
     (max |u| and max |rho - rho0| / rho0, or max |phi| for the NCDE);
     gn_bt / gn_dd are the general-NCDE coefficients A1 b_bar and diag(A2);
     src_q + src_k phi is the NCDE source, three_level selects the explicit
-    three-level scheme instead of full correction; mass_src is the
-    compressible NSE's uniform mass source (the solve needs has_force)."""
+    three-level scheme instead of full correction (NCDE and NSE); mass_src is
+    the compressible NSE's uniform mass source (the solve needs has_force);
+    g_share is the share of the NSE force and mass source carried by G,
+    corrected with lambda2 and lambda1."""
     m = mrtlb_model_desc()
     m.model = MODELS[eq] if isinstance(eq, str) else int(eq)
     m.rho0, m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high = rho0, s0, s1, s_shear, s_bulk, s3, s_high
@@ -253,6 +259,7 @@ def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s
     m.src_q, m.src_k = float(src_q), float(src_k)
     m.three_level = 1 if three_level else 0
     m.mass_src = float(mass_src)
+    m.g_share, m.lambda1, m.lambda2 = float(g_share), float(lambda1), float(lambda2)
     return m
 
 
@@ -340,6 +347,12 @@ class Solve:
     def set_velocity_field(self, u):
         """CDE: the velocity field (d, *shape) used from the next step on."""
         _check(lib().mrtlb_set_velocity_field(self.h, _ptr(_f64(u))))
+
+    def set_force_field(self, force):
+        """NSE with a force field: the body force (d, *shape) used from the next
+        step on (the three-level scheme's difference term uses the previous
+        step's force)."""
+        _check(lib().mrtlb_set_force_field(self.h, _ptr(_f64(force))))
 
     def step(self, n=1):
         _check(lib().mrtlb_step(self.h, int(n)))

@@ -77,6 +77,9 @@ struct mrtlb_solve {
   size_t bytes = 0;
   void* f[2] = {nullptr, nullptr};
   void* force = nullptr;        // Real, d x N
+  void* fprev = nullptr;        // Real, d x N: the NSE three-level scheme's F(t - dt) (allocated on the
+                                // first force change)
+  bool hist_pending = false;    // the next step adds the three-level difference term (fprev valid)
   void* phi[2] = {nullptr, nullptr};
   void* jobs = nullptr;         // three Job<Real> slots (parity 0, 1, drift-corrected step), then the
                                 // int16 saturation flag (an int) at jobs + kFlagOffset
@@ -332,8 +335,23 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   P.cb = L.B;
   for (int j = 0; j < L.B; ++j)
     for (int a = 0; a < 3; ++a) P.ce[j][a] = (int8_t)(a < D ? L.e[j * D + a] : 0);
-  P.msrc = (Real)(m.model == MRTLB_NSE_COMP ? m.mass_src : 0.0);
-  P.msh = (Real)(m.model == MRTLB_NSE_COMP ? 0.5 * m.mass_src : 0.0);
+  // NSE: force and mass source divided between G (share g) and F (eq.
+  // M-NSEs-2); h = 1 for the shifted f_bar, 0 for the three-level scheme
+  const bool nse = m.model == MRTLB_NSE_INC || m.model == MRTLB_NSE_COMP;
+  const double S = m.model == MRTLB_NSE_COMP ? m.mass_src : 0.0;
+  const double gsh = nse ? m.g_share : 0.0, h = nse && m.three_level ? 0.0 : 1.0;
+  const double msh = 0.5 * S * (gsh * m.lambda1 + (1 - gsh) * h);
+  const double fh = nse ? 0.5 * (gsh * m.lambda2 + (1 - gsh) * h) : 0.5;
+  P.msrc = (Real)S;
+  P.msh = (Real)msh;
+  P.fh = (Real)fh;
+  P.g1 = (Real)(1.0 - m.s1 * fh);
+  P.hf = (Real)(nse && m.three_level ? 0.5 * (1 - gsh) : 0.0);
+  for (int a = 0; a < 3; ++a) {
+    double s2i = 0;                   // (S2 I)_a: row sum of the normal block
+    for (int b = 0; b < D; ++b) s2i += S2[a][b];
+    P.x2n[a] = (Real)(a < D ? L.cs2 * s2i * (msh - 0.5 * S) : 0.0);
+  }
   for (int a = 0; a < 3; ++a) {
     P.adv[a] = (Real)(a < D ? m.adv_u[a] : 0.0);
     const bool gn = m.model == MRTLB_NCDE && a < D;
@@ -350,6 +368,7 @@ static Job<Real> make_job(const mrtlb_solve& s, int parity, const KParams<Real>&
   J.fin = s.f[parity];
   J.fout = s.f[parity ^ 1];
   J.force = static_cast<const Real*>(s.force);
+  J.fprev = nullptr;
   J.phi_prev = static_cast<const Real*>(s.phi[parity]);
   J.phi_out = static_cast<Real*>(s.phi[parity ^ 1]);
   J.sat = reinterpret_cast<int*>(static_cast<char*>(s.jobs) + kFlagOffset);
@@ -573,8 +592,14 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
       return fail(MRTLB_EINVAL, "gn_bt and gn_dd must be finite");
   if (!std::isfinite(m.src_q) || !std::isfinite(m.src_k) || !(std::fabs(m.src_k) < 1.0))
     return fail(MRTLB_EINVAL, "src_q must be finite and |src_k| < 1");
-  if ((m.src_q != 0 || m.src_k != 0 || m.three_level != 0) && m.model != MRTLB_NCDE)
-    return fail(MRTLB_EINVAL, "the source and the three-level scheme belong to the NCDE model");
+  const bool nse = m.model == MRTLB_NSE_INC || m.model == MRTLB_NSE_COMP;
+  if ((m.src_q != 0 || m.src_k != 0) && m.model != MRTLB_NCDE)
+    return fail(MRTLB_EINVAL, "the source q + k phi belongs to the NCDE model");
+  if (m.three_level != 0 && m.model != MRTLB_NCDE && !nse)
+    return fail(MRTLB_EINVAL, "the three-level scheme belongs to the NCDE and NSE models");
+  if (!(m.g_share >= 0 && m.g_share <= 1) || !std::isfinite(m.lambda1) || !std::isfinite(m.lambda2))
+    return fail(MRTLB_EINVAL, "g_share must lie in [0, 1] and lambda1, lambda2 must be finite");
+  if (!nse && m.g_share != 0) return fail(MRTLB_EINVAL, "g_share belongs to the NSE models (0 otherwise)");
   if (!std::isfinite(m.mass_src)) return fail(MRTLB_EINVAL, "mass_src must be finite");
   if (m.mass_src != 0 && m.model != MRTLB_NSE_COMP)
     return fail(MRTLB_EINVAL, "the mass source belongs to the compressible NSE model");
@@ -612,7 +637,7 @@ static void release(mrtlb_solve* s) {
   if (!s->external)
     for (void* p : {s->f[0], s->f[1]})
       if (p) (void)hipFree(p);
-  for (void* p : {s->force, s->phi[0], s->phi[1], s->jobs, s->pd, s->part, s->mtab})
+  for (void* p : {s->force, s->fprev, s->phi[0], s->phi[1], s->jobs, s->pd, s->part, s->mtab})
     if (p) (void)hipFree(p);
 }
 
@@ -848,8 +873,8 @@ static mrtlb_status totals_from_planes(mrtlb_solve* s, const double* plane, doub
   m += ref * (double)s->N;
   if (s->model.model == MRTLB_NCDE && s->model.three_level == 0 && (s->model.src_q != 0 || s->model.src_k != 0))
     m = (m + 0.5 * s->model.src_q * (double)s->N) / (1.0 - 0.5 * s->model.src_k);   // phi = sum f_bar + S/2
-  if (s->model.model == MRTLB_NSE_COMP) m += 0.5 * s->model.mass_src * (double)s->N;  // rho = sum f_bar + S/2
-  for (int a = 0; a < nf; ++a) mom[a] += 0.5 * plane[B + a];
+  if (s->model.model == MRTLB_NSE_COMP) m += s->Pd.msh * (double)s->N;  // rho = sum f + msh
+  for (int a = 0; a < nf; ++a) mom[a] += s->Pd.fh * plane[B + a];        // rho u = sum c f + fh F
   bool finite = std::isfinite(m);
   for (int a = 0; a < D; ++a) finite = finite && std::isfinite(mom[a]);
   *mass = m;
@@ -1071,20 +1096,48 @@ mrtlb_status mrtlb_solve_set_transform(mrtlb_solve* s, int transform) {
 
 // The CDE's velocity field (d x N, FP64 on the host) into the solve's
 // device field, in the compute precision; synchronous.
-static mrtlb_status upload_velocity(mrtlb_solve* s, const double* u) {
+// A d x N node field (the NSE force, the CDE velocity) into the solve's
+// field buffer, in the compute precision of the stepping kernels.
+static mrtlb_status upload_node_field(mrtlb_solve* s, const double* v, const char* what) {
   const int D = s->L.D;
   for (size_t i = 0; i < (size_t)D * s->N; ++i)
-    if (!std::isfinite(u[i])) return fail(MRTLB_ENUMERIC, "non-finite velocity field");
+    if (!std::isfinite(v[i])) return fail(MRTLB_ENUMERIC, std::string("non-finite ") + what);
   hipStream_t st = s->ctx->stream;
   if (is_double(s->storage)) {
-    HIP_TRY(hipMemcpyAsync(s->force, u, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->force, v, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
   } else {
     std::vector<float> tmp((size_t)D * s->N);
-    for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)u[i];
+    for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)v[i];
     HIP_TRY(hipMemcpyAsync(s->force, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
+  return MRTLB_OK;
+}
+
+static mrtlb_status upload_velocity(mrtlb_solve* s, const double* u) {
+  return upload_node_field(s, u, "velocity field");
+}
+
+mrtlb_status mrtlb_set_force_field(mrtlb_solve* s, const double* force) {
+  if (!s || !force) return fail(MRTLB_EINVAL, "NULL argument");
+  if ((s->model.model != MRTLB_NSE_INC && s->model.model != MRTLB_NSE_COMP) || !s->has_force)
+    return fail(MRTLB_EINVAL, "the force field belongs to an NSE solve created with has_force");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  // the three-level scheme's F(t - dt): the force of the last step, kept
+  // until the next step has used it
+  const bool history = s->model.three_level != 0 && s->model.g_share < 1.0 && s->steps > 0;
+  if (history && !s->hist_pending) {
+    const size_t bytes = (size_t)s->L.D * s->N * (is_double(s->storage) ? 8 : 4);
+    if (!s->fprev && hipMalloc(&s->fprev, bytes) != hipSuccess) {
+      s->fprev = nullptr;
+      return fail(MRTLB_ENOMEM, "out of device memory for the previous force field");
+    }
+    HIP_TRY(hipMemcpyAsync(s->fprev, s->force, bytes, hipMemcpyDeviceToDevice, s->ctx->stream));
+  }
+  const mrtlb_status st = upload_node_field(s, force, "force field");
+  if (st != MRTLB_OK) return st;
+  if (history) s->hist_pending = true;
   return MRTLB_OK;
 }
 
@@ -1120,17 +1173,12 @@ mrtlb_status mrtlb_init_fields(mrtlb_solve* s, const double* rho, const double* 
     HIP_TRY(df.alloc((size_t)D * s->N * 8, st));
     HIP_TRY(hipMemcpyAsync(df.p, force, (size_t)D * s->N * 8, hipMemcpyHostToDevice, st));
     // the stepping kernels read the force in the compute precision
-    if (is_double(s->storage)) {
-      HIP_TRY(hipMemcpyAsync(s->force, df.p, (size_t)D * s->N * 8, hipMemcpyDeviceToDevice, st));
-    } else {
-      std::vector<float> tmp((size_t)D * s->N);
-      for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)force[i];
-      HIP_TRY(hipMemcpyAsync(s->force, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, st));
-      HIP_TRY(hipStreamSynchronize(st));
-    }
+    const mrtlb_status fs = upload_node_field(s, force, "force field");
+    if (fs != MRTLB_OK) return fs;
   }
   s->cur = 0;
   s->steps = 0;
+  s->hist_pending = false;           // the force was constant before t = 0
   // the init kernel writes f into buffer cur^1 and phi into both history
   // slots; run it with the parity-1 job so that fout = f[0]
   mrtlb_status rs = upload_jobs(s);
@@ -1153,20 +1201,24 @@ mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps) {
   HIP_TRY(hipSetDevice(s->ctx->device));
   for (int64_t k = 0; k < nsteps; ++k) {
     const void* jp = job_ptr(*s, s->cur);
-    if (s->pending) {
-      // the corrected step runs from job slot 2
+    if (s->pending || s->hist_pending) {
+      // a drift-corrected step, or the three-level step after a force
+      // change, runs from job slot 2
       void* slot = static_cast<char*>(s->jobs) + 2 * (is_double(s->storage) ? sizeof(Job<double>) : sizeof(Job<float>));
       if (is_double(s->storage)) {
-        const Job<double> J = make_job(*s, s->cur, with_drift(*s, s->Pd));
+        Job<double> J = make_job(*s, s->cur, with_drift(*s, s->Pd));
+        if (s->hist_pending) J.fprev = static_cast<const double*>(s->fprev);
         HIP_TRY(hipMemcpyAsync(slot, &J, sizeof J, hipMemcpyHostToDevice, s->ctx->stream));
         HIP_TRY(hipStreamSynchronize(s->ctx->stream));
       } else {
-        const Job<float> J = make_job(*s, s->cur, with_drift(*s, s->Pf));
+        Job<float> J = make_job(*s, s->cur, with_drift(*s, s->Pf));
+        if (s->hist_pending) J.fprev = static_cast<const float*>(s->fprev);
         HIP_TRY(hipMemcpyAsync(slot, &J, sizeof J, hipMemcpyHostToDevice, s->ctx->stream));
         HIP_TRY(hipStreamSynchronize(s->ctx->stream));
       }
       jp = slot;
       s->pending = false;
+      s->hist_pending = false;
     }
     hipError_t e = dispatch(s->L.kind, base_req(*s, kOpStep, jp));
     if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -1241,6 +1293,7 @@ static mrtlb_status batch_group(std::vector<std::pair<mrtlb_solve*, int64_t>>& g
       const KParams<Real>& P = *reinterpret_cast<const KParams<Real>*>(is_double(s.storage) ? (const void*)&s.Pd
                                                                                             : (const void*)&s.Pf);
       Job<Real> J0 = make_job(s, s.cur, with_drift(s, P));
+      if (s.hist_pending) J0.fprev = static_cast<const Real*>(s.fprev);
       J0.block_begin = prefix[i];
       jobs[i] = J0;
       for (int par = 0; par < 2; ++par) {
@@ -1267,6 +1320,7 @@ static mrtlb_status batch_group(std::vector<std::pair<mrtlb_solve*, int64_t>>& g
       const int64_t adv = std::max<int64_t>(0, std::min(g[i].second, done + seg) - done);
       if (adv == 0) continue;
       s->pending = false;
+      s->hist_pending = false;
       s->cur ^= (int)(adv & 1);
       s->steps += adv;
       if (s->drift_every > 0 && (s->since_check += adv) >= s->drift_every) {

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_init_custom(const Job<typename Store
   E.build(P, R, jm, u);
   double d1[3] = {0, 0, 0}, d2n[3] = {0, 0, 0}, d2o[3] = {0, 0, 0}, d3m[3][3] = {}, d3p[3] = {0, 0, 0}, dxyz = 0;
   for (int a = 0; a < DIM; ++a) {
-    d1[a] = (E.e1[a] - 0.5 * F[a]) * P.in1[a];
+    d1[a] = (E.e1[a] - P.fh * F[a]) * P.in1[a];
     // mass source: -F/2 has the Hermite second-order part +cs^2 S / 2
     d2n[a] = (E.e2n[a] + P.msh * P.cs2) * P.in2n[a];
     d3p[a] = E.e3p[a] * P.in3p[a];
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_custom(const Job<typename Sto
       const double rho_m = P.inc ? P.rho0 : R;
       for (int a = 0; a < DIM; ++a) {
         double jmom = P.c1[a] * m1[a];
-        if (J.force) jmom += 0.5 * (double)J.force[(size_t)a * N + self];
+        if (J.force) jmom += P.fh * (double)J.force[(size_t)a * N + self];
         out1[(size_t)a * N + self] = jmom / rho_m;
       }
     }

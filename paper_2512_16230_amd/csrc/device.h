@@ -755,6 +755,7 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
 
   // a2: conserved variables, a5: sources
   Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
+  Real h1[3] = {0, 0, 0};   // NSE three-level: hf (F(t) - F(t - dt)) after a force change
   Real u[3] = {0, 0, 0}, jm[3] = {0, 0, 0};
   // NCDE: phi from the sum and the source correction (eq. 2-4-1)
   const Real R = MODEL == kNcde ? (M.R0 + P.sqh) * P.sci : (FORCE ? M.R0 + P.rho_ref + P.msh : M.R0 + P.rho_ref);
@@ -800,9 +801,18 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
     const Real inv = Real(1) / rho_m;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      jm[a] = M.m1[a] + Real(0.5) * F[a];
+      jm[a] = FORCE ? M.m1[a] + P.fh * F[a] : M.m1[a];
       u[a] = jm[a] * inv;
       src1[a] = F[a];
+    }
+    if constexpr (FORCE) {
+      if (J.fprev) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          h1[a] = P.hf * (F[a] - gload<Real>(static_cast<const char*>(static_cast<const void*>(J.fprev)) +
+                                                 (size_t)a * N * sizeof(Real),
+                                             self * (uint32_t)sizeof(Real)));
+      }
     }
     if constexpr (FORCE) {
       // uF + Fu, and for a mass source (cs^2 I - uu) S of M2G together with
@@ -826,7 +836,8 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
   Real d1[3], d2n[3], d2o[3], d3m[3][3], d3p[3], dxyz = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    Real ms = M.m1[a] - P.s1 * (M.m1[a] - E.e1[a]) + (Real(1) - Real(0.5) * P.s1) * src1[a];
+    Real ms = M.m1[a] - P.s1 * (M.m1[a] - E.e1[a]);
+    if constexpr (FORCE || MODEL == kNcde) ms += P.g1 * src1[a] + h1[a];
     if constexpr (MODEL == kNcde) ms -= P.s1 * x1[a];
     d1[a] = (ms - kx * (M.m1[a] - P.dm1[a])) * P.in1[a];
   }
@@ -852,12 +863,14 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
           ms += P.k2[a][b] * neq[b];
           if constexpr (FORCE) ms += P.g2[a][b] * T2n[b];
         }
+        if constexpr (FORCE) ms += P.x2n[a];
         d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
       }
     } else {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const Real ms = E.e2n[a] + kb * tn + ks * (neq[a] - tn) + gb * tT + gs * (T2n[a] - tT);
+        Real ms = E.e2n[a] + kb * tn + ks * (neq[a] - tn) + gb * tT + gs * (T2n[a] - tT);
+        if constexpr (FORCE) ms += P.x2n[a];
         d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
       }
     }
@@ -1097,7 +1110,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   E.build(P, R, jm, u);
   double d1[3], d2n[3], d2o[3], d3m[3][3], d3p[3], dxyz = 0;
   for (int a = 0; a < D; ++a) {
-    d1[a] = (E.e1[a] - 0.5 * F[a]) * P.in1[a];
+    d1[a] = (E.e1[a] - P.fh * F[a]) * P.in1[a];
     d2n[a] = E.e2n[a] * P.in2n[a];
     d3p[a] = E.e3p[a] * P.in3p[a];
     for (int b = 0; b < D; ++b)
@@ -1108,7 +1121,8 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   double x[B];
   for (int j = 0; j < B; ++j) x[j] = 0;
   // NCDE, full correction: f_bar = f_eq - w S(phi0) / 2
-  // NSE mass source: f_bar = f_eq - F/2 with M0F = S (Hermite second order -cs^2 S)
+  // NSE: f_bar = f_eq minus the distribution of raw moments (msh, fh F, 0)
+  // (Hermite second order -cs^2 msh); the F route: F/2 with M0F = S
   const double r0 = MODEL == kNcde ? R - P.sinit * (P.sq + P.sk * R) : R - P.msh;
   if constexpr (MODEL != kNcde && MODEL != kCde)
     for (int a = 0; a < D; ++a) d2n[a] += P.msh * P.cs2 * P.in2n[a];
@@ -1176,7 +1190,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(const Job<typename StoreT<ST>
         const double rho_m = P.inc ? P.rho0 : R;
         for (int a = 0; a < D; ++a) {
           double jmom = P.c1[a] * m1[a];
-          if (J.force) jmom += 0.5 * (double)J.force[(size_t)a * N + self];
+          if (J.force) jmom += P.fh * (double)J.force[(size_t)a * N + self];
           out1[(size_t)a * N + self] = jmom / rho_m;
         }
       }

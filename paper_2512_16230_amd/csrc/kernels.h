@@ -67,9 +67,20 @@ struct KParams {
   // (sa, sp) = (1, 0), sinit = 1/2; three-level: sqh = 0, sci = 1,
   // (sa, sp) = (3/2, -1/2), sinit = 0.  No source: all terms vanish.
   Real sq, sk, sqh, sci, sa, sp, sinit;
-  // NSE_COMP mass source S (forced kernel only): rho = sum f_bar + msh with
-  // msh = S/2, the zeroth moment gains S, the second-order source gains -uu S
+  // NSE_COMP mass source S (forced kernel only): the zeroth moment gains S,
+  // the second-order source gains -uu S.  NSE body force F and mass source
+  // divided between G (share g, corrected with lambda2 and lambda1) and F
+  // (eq. M-NSEs-2), h = 1 for the shifted f_bar and 0 for the three-level
+  // scheme's unshifted f: rho = sum f + msh, msh = S (g lambda1 + (1-g) h)/2,
+  // and rho u = sum c f + fh F, fh = (g lambda2 + (1-g) h)/2 (eqs. 2-4-0,
+  // 2-4-2); the first moment gains g1 F with g1 = 1 - s1 fh (NCDE: the
+  // factor 1 - s1/2 of M1G), plus hf (F - F_prev) on the step after a force
+  // change (three-level scheme, hf = (1-g)/2); the normal second-order rows
+  // gain x2n = cs^2 (S2 I)_a (msh - S/2), the S20 share of M2G (eq.
+  // M-NSEs-4-0) and of the source distribution's -cs^2 S_F I.
   Real msrc, msh;
+  Real fh, g1, hf;
+  Real x2n[3];
   // velocity set at run time (read by the user-supplied-lattice kernels)
   int cb;                    // b
   int8_t ce[kMaxB][3];       // integer velocity multiples e_j
@@ -90,6 +101,7 @@ struct Job {
   const void* fin;          // populations at t (post-collision, pre-propagation)
   void* fout;               // populations at t + 1
   const Real* force;        // d x N, or nullptr (CDE: the velocity field)
+  const Real* fprev;        // NSE three-level: the force before the last change, else nullptr
   const Real* phi_prev;     // NCDE: phi^{n-1}
   Real* phi_out;            // NCDE: phi^n
   int* sat;                 // int16 storage: set to 1 when a value saturates
