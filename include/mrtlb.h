@@ -264,10 +264,15 @@ typedef struct {
   double g_share, lambda1, lambda2;
 } mrtlb_model_desc;
 
-/* Population storage in HBM (compute is FP64 for MRTLB_FP64, FP32 otherwise):
+/* Population storage in HBM (compute is FP64 for MRTLB_FP64 and
+ * MRTLB_FP32_DEV_F64, FP32 otherwise):
  *   FP64      f_bar, double
  *   FP32      f_bar, float
  *   FP32_DEV  f_bar - w_j rho_ref, float
+ *   FP32_DEV_F64  f_bar - w_j rho_ref, float (RNE from the FP64 result),
+ *             with FP64 arithmetic: the bytes of FP32_DEV without the FP32
+ *             rounding of every intermediate (the force field and the NCDE
+ *             history are FP64)
  *   FP16_DEV  (f_bar - w_j rho_ref) * 128 / w_j, IEEE half (RNE)
  *   BF16_DEV  same, bfloat16 (RNE)
  *   I16_DEV   (f_bar - w_j rho_ref) * 32767 / (A_j w_j), int16 fixed point
@@ -281,7 +286,7 @@ typedef struct {
  * rho_ref = rho0 (NSE) or 0 (NCDE).  Each FP32 value is rounded once to
  * the 16-bit format. */
 typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DEV = 3, MRTLB_BF16_DEV = 4,
-               MRTLB_I16_DEV = 5 } mrtlb_storage;
+               MRTLB_I16_DEV = 5, MRTLB_FP32_DEV_F64 = 6 } mrtlb_storage;
 
 /* Create a solve on a periodic grid n[0] x n[1] (x n[2] in 3D; n[2] = 1 in
  * 2D).  Allocates two population buffers (pull streaming, double-buffered),

@@ -27,6 +27,7 @@ MRTLB_D2Q9, MRTLB_D3Q27 = 12, 13                     # standard lattices, k = 1 
 MRTLB_CUSTOM = 14                                    # user-supplied velocity set
 MRTLB_NSE_INC, MRTLB_NSE_COMP, MRTLB_NCDE, MRTLB_CDE = 0, 1, 2, 3
 MRTLB_FP64, MRTLB_FP32, MRTLB_FP32_DEV, MRTLB_FP16_DEV, MRTLB_BF16_DEV, MRTLB_I16_DEV = 0, 1, 2, 3, 4, 5
+MRTLB_FP32_DEV_F64 = 6
 TRANSFORMS = {"valu": 0, "mfma": 1}
 
 KINDS = {"rD2Q25": MRTLB_RD2Q25, "rD2Q13": MRTLB_RD2Q13, "rD3Q53": MRTLB_RD3Q53, "rD3Q33": MRTLB_RD3Q33,
@@ -34,7 +35,7 @@ KINDS = {"rD2Q25": MRTLB_RD2Q25, "rD2Q13": MRTLB_RD2Q13, "rD3Q53": MRTLB_RD3Q53,
          "D2Q9": MRTLB_D2Q9, "D3Q27": MRTLB_D3Q27, "custom": MRTLB_CUSTOM, **{"rD2Q17-%d" % k: v for k, v in MRTLB_RD2Q17.items()}}
 MODELS = {"NSE_INC": MRTLB_NSE_INC, "NSE_COMP": MRTLB_NSE_COMP, "NCDE": MRTLB_NCDE, "CDE": MRTLB_CDE}
 STORAGES = {"fp64": MRTLB_FP64, "fp32": MRTLB_FP32, "fp32_dev": MRTLB_FP32_DEV, "fp16_dev": MRTLB_FP16_DEV,
-            "bf16_dev": MRTLB_BF16_DEV, "i16_dev": MRTLB_I16_DEV}
+            "bf16_dev": MRTLB_BF16_DEV, "i16_dev": MRTLB_I16_DEV, "fp32_dev_f64": MRTLB_FP32_DEV_F64}
 
 
 class MrtlbError(RuntimeError):

@@ -109,14 +109,15 @@ struct mrtlb_solve {
 
 namespace mrtlb {
 
-static bool is_double(int storage) { return storage == kFP64; }
+// FP64 arithmetic (KParams<double>, Job<double>, FP64 node fields).
+static bool is_double(int storage) { return storage == kFP64 || storage == kFP32DevF64; }
 // The job slots of a solve and, after them, its saturation flag.
 constexpr size_t kFlagOffset = 3 * (sizeof(Job<double>) > sizeof(Job<float>) ? sizeof(Job<double>) : sizeof(Job<float>));
 constexpr size_t kJobsBytes = kFlagOffset + 256;
 static size_t elem_bytes(int storage) {
   switch (storage) {
     case kFP64: return 8;
-    case kFP32: case kFP32Dev: return 4;
+    case kFP32: case kFP32Dev: case kFP32DevF64: return 4;
     default: return 2;
   }
 }
@@ -150,7 +151,7 @@ static int pick_vec(int storage, int kind, int model, int nx) {
   // Measured on MI355X: one node per lane on the 3D lattices (register
   // pressure), for rows under 512 nodes and for the NCDE; otherwise 2 nodes
   // (FP32/FP64) or 4 nodes (16-bit storage, 8-byte accesses per lane).
-  const bool small = storage != kFP64 && storage != kFP32 && storage != kFP32Dev;
+  const bool small = storage == kFP16Dev || storage == kBF16Dev || storage == kI16Dev;
   int v = (kind == kRD3Q53 || kind == kRD3Q45 || kind == kRD3Q33 || kind == kD3Q27 || nx < 512 || model == MRTLB_NCDE ||
            model == MRTLB_CDE) ? 1
                                                                                             : (small ? 4 : 2);
@@ -615,7 +616,7 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
 mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3], int storage, int model,
                                    int has_force, size_t* bytes) {
   if (!lat || !n || !bytes) return fail(MRTLB_EINVAL, "NULL argument");
-  if (storage < kFP64 || storage > kI16Dev) return fail(MRTLB_EINVAL, "unknown storage");
+  if (storage < kFP64 || storage > kFP32DevF64) return fail(MRTLB_EINVAL, "unknown storage");
   const int D = lat->L.D;
   const int64_t nz = D == 3 ? n[2] : 1;
   if (n[0] < 1 || n[1] < 1 || nz < 1) return fail(MRTLB_EINVAL, "grid sizes must be >= 1");
@@ -743,7 +744,7 @@ mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const 
 
 mrtlb_status mrtlb_population_bytes(const mrtlb_lattice* lat, const int64_t n[3], int storage, size_t* bytes) {
   if (!lat || !n || !bytes) return fail(MRTLB_EINVAL, "NULL argument");
-  if (storage < kFP64 || storage > kI16Dev) return fail(MRTLB_EINVAL, "unknown storage");
+  if (storage < kFP64 || storage > kFP32DevF64) return fail(MRTLB_EINVAL, "unknown storage");
   const int64_t nz = lat->L.D == 3 ? n[2] : 1;
   if (n[0] < 1 || n[1] < 1 || nz < 1) return fail(MRTLB_EINVAL, "grid sizes must be >= 1");
   *bytes = (size_t)lat->L.B * (size_t)(n[1] * nz * row_pitch(n[0], storage)) * elem_bytes(storage);

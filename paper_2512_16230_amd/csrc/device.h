@@ -81,6 +81,8 @@ struct StoreT<kFP32> { using T = float; using Real = float; };
 template <>
 struct StoreT<kFP32Dev> { using T = float; using Real = float; };
 template <>
+struct StoreT<kFP32DevF64> { using T = float; using Real = double; };
+template <>
 struct StoreT<kFP16Dev> { using T = _Float16; using Real = float; };
 template <>
 struct StoreT<kBF16Dev> { using T = uint16_t; using Real = float; };
@@ -1277,6 +1279,7 @@ inline bool with_storage(int st, F&& f) {
     case kFP16Dev: f(std::integral_constant<int, kFP16Dev>{}); return true;
     case kBF16Dev: f(std::integral_constant<int, kBF16Dev>{}); return true;
     case kI16Dev: f(std::integral_constant<int, kI16Dev>{}); return true;
+    case kFP32DevF64: f(std::integral_constant<int, kFP32DevF64>{}); return true;
   }
   return false;
 }

@@ -17,7 +17,8 @@ constexpr double kI16Range = 2.0;    // default int16 range: |f - w rho_ref| <= 
 // Index of the off-diagonal pair (a, b), a < b: xy -> 0, xz -> 1, yz -> 2.
 constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
 
-enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4, kI16Dev = 5 };
+// kFP32DevF64: FP32 deviations in HBM, FP64 arithmetic in the kernels.
+enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4, kI16Dev = 5, kFP32DevF64 = 6 };
 enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2, kCde = 3 };
 
 // Per-solve constants of the collision, in the compute precision.  Row

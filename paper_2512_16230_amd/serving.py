@@ -31,7 +31,7 @@ import numpy as np
 
 from . import workloads as W
 
-STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2, "i16_dev": 2}
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp32_dev": 4, "fp16_dev": 2, "bf16_dev": 2, "i16_dev": 2, "fp32_dev_f64": 4}
 B_OF = {"rD2Q25": 25, "rD2Q13": 13, "rD3Q53": 53, "rD3Q33": 33}
 
 

@@ -128,7 +128,8 @@ def test_rd2q25_ragged(ctx, shape, eq):
     rho, u = _random_fields(card, shape, 3)
     steps = 12
     r_o, u_o, _ = _oracle_run(card, eq, rates, rho, u, steps)
-    for storage, tr, tu in (("fp64", 3e-14, 5e-13), ("fp32", 4.9e-7, 3.5e-5), ("fp32_dev", 6.7e-9, 8.5e-7)):
+    for storage, tr, tu in (("fp64", 3e-14, 5e-13), ("fp32", 4.9e-7, 3.5e-5), ("fp32_dev", 6.7e-9, 8.5e-7),
+                            ("fp32_dev_f64", 1.4e-9, 1.5e-7)):
         print("case: rD2Q25 %s %s %s" % (eq, shape, storage), flush=True)
         r, v, _ = _gpu_run(ctx, card, eq, rates, shape, storage, rho, u, steps)
         check_errs(storage, r, r_o, v, u_o, tr, tu)
@@ -320,7 +321,7 @@ def test_mass_source(ctx, card, shape, forced):
     steps, S = 12, 2e-4
     kw = dict(m30=card.kind not in ("D2Q9", "D3Q27"), mass_src=S)
     r_o, u_o, _ = _oracle_run(card, "NSE_COMP", rates, rho, u, steps, force=F, **kw)
-    for storage, tr, tu in (("fp64", 3e-14, 5e-13), ("fp32", 1.4e-6, 4.5e-5)):
+    for storage, tr, tu in (("fp64", 3e-14, 5e-13), ("fp32", 1.4e-6, 4.5e-5), ("fp32_dev_f64", 5.3e-9, 1.9e-7)):
         print("case: mass source %s %s force=%s %s" % (card.kind, shape, forced, storage), flush=True)
         r, v, s = _gpu_run(ctx, card, "NSE_COMP", rates, shape, storage, rho, u, steps, force=F, **kw)
         check_errs(storage, r, r_o, v, u_o, tr, tu)
@@ -346,7 +347,8 @@ def test_3d_comp(ctx, card, shape):
     rho, u = _random_fields(card, shape, 5)
     steps = 6
     r_o, u_o, _ = _oracle_run(card, "NSE_COMP", rates, rho, u, steps)
-    for storage, tr, tu in (("fp64", 3e-14, 5e-13), ("fp32", 5e-7, 2.5e-5), ("fp32_dev", 7.5e-9, 7e-7)):
+    for storage, tr, tu in (("fp64", 3e-14, 5e-13), ("fp32", 5e-7, 2.5e-5), ("fp32_dev", 7.5e-9, 7e-7),
+                            ("fp32_dev_f64", 1.5e-9, 1e-7)):
         print("case: %s NSE_COMP %s %s" % (card.kind, shape, storage), flush=True)
         r, v, _ = _gpu_run(ctx, card, "NSE_COMP", rates, shape, storage, rho, u, steps)
         check_errs(storage, r, r_o, v, u_o, tr, tu)
@@ -360,7 +362,8 @@ def test_body_force(ctx, card, shape, eq):
     F = W.sinusoidal_force(card, shape, 1e-4, seed=3)
     steps = 8
     r_o, u_o, _ = _oracle_run(card, eq, rates, rho, u, steps, force=F)
-    for storage, tr, tu in (("fp64", 3e-14, 4.5e-13), ("fp32", 4.8e-7, 1.25e-4), ("fp32_dev", 2e-9, 1.05e-6)):
+    for storage, tr, tu in (("fp64", 3e-14, 4.5e-13), ("fp32", 4.8e-7, 1.25e-4), ("fp32_dev", 2e-9, 1.05e-6),
+                            ("fp32_dev_f64", 2.4e-10, 1.35e-7)):
         print("case: force %s %s %s" % (card.kind, eq, storage), flush=True)
         r, v, s = _gpu_run(ctx, card, eq, rates, shape, storage, rho, u, steps, force=F)
         check_errs(storage, r, r_o, v, u_o, tr, tu)
@@ -812,6 +815,19 @@ def test_tgv_fp32_velocity_meets_the_bar(ctx, tgv_oracle):
         assert max_rel(u, u_o) < 1e-6, storage
 
 
+def test_tgv_fp32_storage_with_fp64_arithmetic_meets_the_bar(ctx, tgv_oracle):
+    """FP32 deviations in HBM with FP64 arithmetic meet 1e-6 on rho and u
+    after the 500 steps: the FP32 errors above come from the FP32
+    arithmetic, not from the stored FP32 values (an FP64 emulation that
+    rounds only the stored deviations to FP32 gives u 2.3e-8)."""
+    wl, r_o, u_o, _ = tgv_oracle
+    r, u, _ = _gpu_run(ctx, wl.card, wl.eq, wl.rates, wl.shape, "fp32_dev_f64", wl.rho_or_phi, wl.u, wl.steps)
+    er, eu = max_rel(r, r_o), max_rel(u, u_o)
+    print("fp32_dev_f64 after 500 steps: rho %.3e u %.3e" % (er, eu), flush=True)
+    assert er < 1e-6 and eu < 1e-6
+    assert er < 2e-10 and eu < 8.5e-8           # 3x the measured 6.8e-11 and 2.8e-8
+
+
 def _ncde_500(ctx, storage):
     card = W.Q13_SQUARE
     wl = W.ncde_hill((64, 64), steps=500, adv_u=(0.03, -0.02), D0=0.1, D2=1.0)
@@ -838,9 +854,16 @@ def test_ncde_phi_after_500_steps(ctx):
 
 
 @pytest.mark.skip(reason="below FP32 resolution: measured 6.7e-6 after 500 steps (the hill has spread to 0.14 "
-                         "of its peak, relative rounding 2^-24 per step and population); FP64 meets it")
+                         "of its peak, relative rounding 2^-24 per step and population); FP64 and FP32 storage "
+                         "with FP64 arithmetic meet it")
 def test_ncde_fp32_phi_meets_the_bar_after_500_steps(ctx):
     assert _ncde_500(ctx, "fp32") < 1e-6
+
+
+def test_ncde_fp32_storage_with_fp64_arithmetic_meets_the_bar(ctx):
+    """FP32 populations with FP64 arithmetic: an FP64 emulation that rounds
+    only the stored populations gives 5.3e-8 after 500 steps."""
+    assert _ncde_500(ctx, "fp32_dev_f64") < 1.6e-7      # 3x the measured 5.2e-8, under the 1e-6 bar
 
 
 # --------------------------------------------------------------------------
