@@ -92,7 +92,7 @@ class Model:
     src_q: float = 0.0
     src_k: float = 0.0
     three_level: bool = False
-    # NSE_COMP uniform mass source S
+    # NSE_COMP mass source S: a number, or a field of the grid's shape
     mass_src: float = 0.0
     # NSE: the share of the body force and of the mass source that the
     # auxiliary distribution G carries, F_G = g_share F and S_G = g_share S
@@ -103,6 +103,12 @@ class Model:
     g_share: float = 0.0
     lambda1: float = 1.0
     lambda2: float = 1.0
+    # NSE: the form of M2G_bar.  0: the local closed form with S_bar = S and
+    # d_t p + div(p u) = cs^2 S (eqs. M2Ga-1, M2G-1); 1: the gradient form,
+    # eq. M2G-1 with d_t p I + div(p u I) (NSE_COMP) or eq. M2G with
+    # F_bar = F - cs^2 grad(rho_bar) and S_bar = S - d_t rho_bar (NSE_INC,
+    # rho = rho0), from lagged differences of the previous step's fields.
+    m2g_form: int = 0
 
     def rate(self, group: str) -> float:
         return {"rho": self.s0, "j": self.s1, "bulk": self.s_bulk, "shear": self.s_shear,
@@ -200,12 +206,21 @@ def cde_source(lat: Lattice, model: Model, f: np.ndarray, vel: np.ndarray):
     return -(vel * grad).sum(axis=0)
 
 
-def nse_split(model: Model, force, n: int):
+def mass_field(model: Model, n: int, mass=None) -> np.ndarray:
+    """The mass source S per node (n,): ``mass`` if given, else the model's
+    number or field."""
+    v = model.mass_src if mass is None else mass
+    if np.ndim(v) == 0:
+        return np.full(n, float(v))
+    return np.asarray(v, dtype=np.float64).reshape(-1)
+
+
+def nse_split(model: Model, force, n: int, mass=None):
     """(F_G, F_F, S_G, S_F): the body force F (d, n) or None and the mass
     source S divided between the auxiliary distribution G and the source
     distribution F, F = F_G + F_F and S = S_G + S_F (eq. M-NSEs-2)."""
     a = float(model.g_share)
-    S = np.full(n, float(model.mass_src))
+    S = mass_field(model, n, mass)
     if force is None:
         return None, None, a * S, (1 - a) * S
     return a * force, (1 - a) * force, a * S, (1 - a) * S
@@ -333,11 +348,41 @@ def g_route_hermite(lat: Lattice, model: Model, force, n: int):
     return hermite_from_raw(lat, [M0, M1, M2, None], max_order=2)
 
 
-def aux_hermite(lat, model, S, u, force, extra=None, cross=None):
+def m2g_gradients(lat: Lattice, model: Model, R0, j, prev):
+    """The lagged differences of the gradient form of M2G_bar on the grid:
+    R0 (grid) and j (d, grid) are this step's rho (rho_bar) and rho_m u,
+    ``prev`` the previous step's pair (the first step uses this step's).
+    NSE_COMP, isothermal p = cs^2 rho: {"div": d_t p + div(p u)} with the
+    backward difference cs^2 (rho^n - rho^{n-1}) and the central difference
+    of cs^2 j^{n-1}; NSE_INC: {"gr": grad(rho_bar^{n-1}) (d, n),
+    "dt": rho_bar^n - rho_bar^{n-1}} (n,).  Central differences along axis a
+    divide by 2 c_a (the spacing is c_a dt)."""
+    d = lat.d
+    r_prev, j_prev = prev
+    if model.eq == NSE_COMP:
+        div = (R0 - r_prev) + sum(_central(lat, j_prev[a], a) for a in range(d))
+        return {"div": lat.cs2 * div.reshape(-1)}
+    gr = np.stack([_central(lat, r_prev, a).reshape(-1) for a in range(d)])
+    return {"gr": gr, "dt": (R0 - r_prev).reshape(-1)}
+
+
+def _central(lat: Lattice, X, a: int):
+    """Central difference of the grid field X along physical axis a (the
+    array axis from the end; spacing c_a dt)."""
+    ax = np.ndim(X) - 1 - a
+    return (np.roll(X, -1, axis=ax) - np.roll(X, 1, axis=ax)) / (2 * lat.c[a])
+
+
+def aux_hermite(lat, model, S, u, force, extra=None, cross=None, grad=None, mass=None):
     """Hermite moments of the auxiliary distribution G; S is the relaxation
     matrix on the rows of order <= 3.
 
-    NSE: M2G = (I - S2/2)(uF + Fu) (eqs. M2G-1, M2Ga-1), zero otherwise.
+    NSE: M2G = (I - S2/2) T with, for the local closed form,
+    T = uF + Fu + (cs^2 I - uu) S_m (eqs. M2Ga-1, M2G-1), S_m the mass source
+    (``mass`` per node, else the model's); for the gradient form (``grad``
+    from m2g_gradients): NSE_COMP T = uF + Fu - uu S_m + (d_t p + div(p u)) I
+    (eq. M2G-1, k = 0, M30 = rho uuu), NSE_INC T = u F_bar + F_bar u
+    + cs^2 S_m I - uu S_bar (eq. M2G, p = cs^2 rho_bar, k = 0).
     NCDE (eq. M-NCDE-6): M1G = (I - S1/2) B - S1 X with
     B = d_t(phi u) + div(phi uu) supplied in ``extra`` and
     X = A1 d_t(B_bar) + A2 div(D_bar) in ``cross`` (general NCDE; None = 0).
@@ -352,15 +397,22 @@ def aux_hermite(lat, model, S, u, force, extra=None, cross=None):
         if cross is not None:
             out -= S @ hermite_from_raw(lat, [np.zeros(n), cross, None, None], max_order=1)
         return out
-    if force is None and not model.mass_src:
+    Sm = mass_field(model, n, mass)
+    if force is None and not Sm.any() and grad is None:
         return np.zeros((len(lat.rows), n))
-    T = np.zeros((d, d, n))
-    if force is not None:
-        T = np.einsum("an,bn->abn", u, force) + np.einsum("an,bn->abn", force, u)
-    if model.mass_src:
+    F = np.zeros((d, n)) if force is None else force
+    I = np.eye(d)[:, :, None]
+    uu = np.einsum("an,bn->abn", u, u)
+    if grad is None:
         # (cs^2 I - uu) S: eq. M2G-1 with S_bar = S, where the isothermal
         # d_t p I + div(p u I) = cs^2 (d_t rho + div(rho u)) I = cs^2 S I
-        T = T + model.mass_src * (lat.cs2 * np.eye(d)[:, :, None] - np.einsum("an,bn->abn", u, u))
+        T = np.einsum("an,bn->abn", u, F) + np.einsum("an,bn->abn", F, u) + Sm * (lat.cs2 * I - uu)
+    elif model.eq == NSE_COMP:
+        T = np.einsum("an,bn->abn", u, F) + np.einsum("an,bn->abn", F, u) - Sm * uu + grad["div"] * I
+    else:
+        Fb = F - lat.cs2 * grad["gr"]
+        Sb = Sm - grad["dt"]
+        T = np.einsum("an,bn->abn", u, Fb) + np.einsum("an,bn->abn", Fb, u) + lat.cs2 * Sm * I - Sb * uu
     M = [np.zeros(n), np.zeros((d, n)), T, None]
     mg = hermite_from_raw(lat, M, max_order=2)
     mg[[r.order != 2 for r in lat.rows]] = 0.0
@@ -420,6 +472,8 @@ class State:
     f: np.ndarray                 # (b, *grid) pre-collision f_bar
     phi_prev: np.ndarray = None   # NCDE only: phi of the previous step
     force_prev: np.ndarray = None  # NSE three-level: the previous step's force (None: the current one)
+    mass_prev: np.ndarray = None   # NSE three-level: the previous step's mass source per node
+    hist: tuple = None             # NSE gradient form of M2G_bar: the previous step's (rho, rho_m u)
 
 
 def ncde_source_hermite(lat: Lattice, model: Model, phi):
@@ -431,14 +485,16 @@ def ncde_source_hermite(lat: Lattice, model: Model, phi):
 
 
 def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, ncde_x=None, phi_prev=None,
-            force_prev=None):
+            force_prev=None, mass_prev=None, grad=None):
     """Post-collision populations f* (b, n) from pre-collision f_bar (b, n).
 
     ``ncde_b`` and ``ncde_x`` are the NCDE fields B^n and X^n (d, n) of the
     auxiliary first moment and ``phi_prev`` the previous step's phi (the
     three-level scheme's F(t - dt)); ``force_prev`` is the NSE three-level
     scheme's force at t - dt (None: the current force); for the CDE
-    ``force`` is the velocity field (d, n)."""
+    ``force`` is the velocity field (d, n); ``mass_prev`` is the mass source
+    at t - dt (three-level scheme) and ``grad`` the lagged differences of
+    the gradient form of M2G_bar (m2g_gradients)."""
     n = f.shape[1]
     S = relaxation_matrix(lat, model)
     R0, u, rho_m = macroscopic(lat, model, f, force)
@@ -451,7 +507,7 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, 
         mG[[r.order == 0 for r in lat.rows]] = (1 - 0.5 * model.s0) * cde_source(lat, model, f, force)
         mstar = m - S @ (m - meq) + mG
         return (1 - model.s_h) * f + populations_from_hermite(lat, mstar - (1 - model.s_h) * m)
-    mG = aux_hermite(lat, model, S, u, force, extra=ncde_b, cross=ncde_x)
+    mG = aux_hermite(lat, model, S, u, force, extra=ncde_b, cross=ncde_x, grad=grad)
     if model.eq == NCDE:
         mF = ncde_source_hermite(lat, model, R0)
     else:
@@ -464,7 +520,7 @@ def collide(lat: Lattice, model: Model, f: np.ndarray, force=None, ncde_b=None, 
         if model.eq == NCDE:
             mFp = ncde_source_hermite(lat, model, R0 if phi_prev is None else phi_prev)
         else:
-            _, FFp, _, SFp = nse_split(model, force if force_prev is None else force_prev, n)
+            _, FFp, _, SFp = nse_split(model, force if force_prev is None else force_prev, n, mass_prev)
             mFp = force_hermite(lat, n, FFp, SFp)
         mstar = m - S @ (m - meq) + mG + mF + 0.5 * (mF - mFp)
     else:
@@ -494,9 +550,17 @@ def step(lat: Lattice, model: Model, st: State, force=None) -> State:
         prev = st.phi_prev.reshape(-1)
     F = None if force is None else force.reshape(lat.d, -1)
     Fp = None if st.force_prev is None else st.force_prev.reshape(lat.d, -1)
-    fstar = collide(lat, model, f, F, extra, cross, prev, force_prev=Fp)
-    keep = None if force is None or not model.three_level or model.eq == NCDE else np.array(force, dtype=np.float64)
-    return State(stream(lat, fstar.reshape(st.f.shape)), phi, keep)
+    nse = model.eq in (NSE_INC, NSE_COMP)
+    grad = hist = None
+    if nse and model.m2g_form:
+        R0, u, rho_m = macroscopic(lat, model, f, F)
+        hist = (R0.reshape(grid), (rho_m * u).reshape((lat.d,) + grid))
+        grad = m2g_gradients(lat, model, hist[0], hist[1], hist if st.hist is None else st.hist)
+    fstar = collide(lat, model, f, F, extra, cross, prev, force_prev=Fp, mass_prev=st.mass_prev, grad=grad)
+    three = nse and model.three_level
+    keep = None if force is None or not three else np.array(force, dtype=np.float64)
+    mkeep = mass_field(model, f.shape[1]).copy() if three else None
+    return State(stream(lat, fstar.reshape(st.f.shape)), phi, keep, mkeep, hist)
 
 
 def run(lat, model, st: State, steps: int, force=None) -> State:
@@ -540,7 +604,16 @@ def init_state(lat: Lattice, model: Model, rho_or_phi: np.ndarray, u=None, force
     if jc is not None or r.any():
         jc = np.zeros((lat.d, n)) if jc is None else jc
         f = f - populations_from_hermite(lat, hermite_from_raw(lat, [r, jc, np.zeros((lat.d, lat.d, n)), None], 2))
-    return State(f.reshape((lat.b,) + grid), None)
+    hist = None
+    if model.m2g_form:
+        # the history before t = 0 from the continuity equation:
+        # rho^{-1} = rho^0 - dt (S - div j^0), j^{-1} = j^0, so that the first
+        # step's lagged d_t rho + div j equals S
+        j0 = (rho_m * uv).reshape((lat.d,) + grid)
+        div = sum(_central(lat, j0[a], a) for a in range(lat.d))
+        r_prev = R0.reshape(grid) - mass_field(model, n).reshape(grid) + div
+        hist = (r_prev, j0)
+    return State(f.reshape((lat.b,) + grid), None, hist=hist)
 
 
 def moments(lat: Lattice, model: Model, st: State, force=None):

@@ -99,6 +99,22 @@ class NaiveStepper:
             Xfield = M.ncde_cross(lat, mdl, phi_grid, st.phi_prev)
             if Xfield is not None:
                 Xfield = Xfield.reshape((d,) + grid)
+        nse = mdl.eq in (M.NSE_INC, M.NSE_COMP)
+        Sgrid = None
+        if nse:
+            ms = mdl.mass_src
+            Sgrid = np.full(grid, float(ms)) if np.ndim(ms) == 0 else np.asarray(ms, dtype=np.float64).reshape(grid)
+        Rg = Jg = prev = None
+        if nse and mdl.m2g_form:
+            # the gradient form of M2G_bar: every node's rho and rho_m u first
+            Rg, Jg = np.zeros(grid), np.zeros((d,) + grid)
+            for x in itertools.product(*[range(n) for n in grid]):
+                F = None if force is None else np.array([force[(a,) + x] for a in range(d)])
+                rho, u, rho_m = self._nse_macro(st.f, x, F, Sgrid[x])
+                Rg[x] = rho
+                for a in range(d):
+                    Jg[(a,) + x] = rho_m * u[a]
+            prev = (Rg, Jg) if st.hist is None else st.hist
         for x in itertools.product(*[range(n) for n in grid]):
             f = np.array([st.f[(j,) + x] for j in range(b)])
             F = None if force is None else np.array([force[(a,) + x] for a in range(d)])
@@ -112,16 +128,12 @@ class NaiveStepper:
                 rho_m = None
                 rho = phi_grid[x]
             else:
-                # F = F_G + F_F, S = S_G + S_F; rho and rho u by eq. 2-4-2
-                # (eq. 2-4-0 for the three-level scheme: no F_F, S_F terms)
-                share, h = mdl.g_share, (0.0 if mdl.three_level else 1.0)
+                share = mdl.g_share
                 Ftot = np.zeros(d) if F is None else F
+                Sx = Sgrid[x]
                 FG, FF = share * Ftot, (1 - share) * Ftot
-                SG, SF = share * mdl.mass_src, (1 - share) * mdl.mass_src
-                mom = mom + 0.5 * (mdl.lambda2 * FG + h * FF)
-                rho = rho + 0.5 * (mdl.lambda1 * SG + h * SF)
-                rho_m = mdl.rho0 if mdl.eq == M.NSE_INC else rho
-                u = mom / rho_m
+                SG, SF = share * Sx, (1 - share) * Sx
+                rho, u, rho_m = self._nse_macro(st.f, x, F, Sx)
             R0 = np.array([rho])
             uv = u[:, None]
             rm = None if rho_m is None else np.array([rho_m])
@@ -140,7 +152,10 @@ class NaiveStepper:
                     continue
             else:
                 Fa = None if F is None else F[:, None]
-                G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, Fa)[:, 0])
+                if mdl.m2g_form:
+                    G = self._m2g_gradient_form(st.f.shape[1:], x, u, Ftot, Sx, Rg, prev)
+                else:
+                    G = self._velocity_space(M.aux_hermite(lat, mdl, self.S_low, uv, Fa, mass=np.array([Sx]))[:, 0])
                 if share:
                     # the S_G, F_G part of G: M0G, M1G (eq. M-NSEs-2) and the
                     # share of M2G beside M2G_bar (eq. M-NSEs-4-0)
@@ -152,7 +167,8 @@ class NaiveStepper:
                 Fv = self._raw_to_velocity(SF, FF, np.zeros((d, d)))
                 if mdl.three_level:
                     Fp = Ftot if st.force_prev is None else np.array([st.force_prev[(a,) + x] for a in range(d)])
-                    Fvp = self._raw_to_velocity(SF, (1 - share) * Fp, np.zeros((d, d)))
+                    SFp = SF if st.mass_prev is None else (1 - share) * np.asarray(st.mass_prev).reshape(grid)[x]
+                    Fvp = self._raw_to_velocity(SFp, (1 - share) * Fp, np.zeros((d, d)))
                     # eq. 2-1, theta = 1, gamma = 0
                     out = f - self.Lam @ (f - feq) + G + Fv + 0.5 * (Fv - Fvp)
                     for j in range(b):
@@ -172,7 +188,63 @@ class NaiveStepper:
                     ax = len(grid) - 1 - a
                     tgt[ax] = (x[ax] + int(lat.e[j, a])) % grid[ax]
                 new[(j,) + tuple(tgt)] = fstar[(j,) + x]
-        keep = None
-        if mdl.eq != M.NCDE and mdl.three_level and force is not None:
-            keep = np.array(force, dtype=np.float64)
-        return M.State(new, phi_grid, keep)
+        keep = mkeep = None
+        if nse and mdl.three_level:
+            keep = None if force is None else np.array(force, dtype=np.float64)
+            mkeep = Sgrid.reshape(-1).copy()
+        return M.State(new, phi_grid, keep, mkeep, None if Rg is None else (Rg, Jg))
+
+    def _nse_macro(self, fgrid, x, F, Sx):
+        """(rho, u, rho_m) of one node: F = F_G + F_F, S = S_G + S_F, rho and
+        rho u by eq. 2-4-2 (eq. 2-4-0 for the three-level scheme's unshifted
+        f: no F_F, S_F terms)."""
+        lat, mdl = self.lat, self.mdl
+        d = lat.d
+        rho = 0.0
+        mom = np.zeros(d)
+        for j in range(lat.b):
+            rho += fgrid[(j,) + x]
+            mom += lat.E[j] * fgrid[(j,) + x]
+        share, h = mdl.g_share, (0.0 if mdl.three_level else 1.0)
+        Ftot = np.zeros(d) if F is None else F
+        mom = mom + 0.5 * (mdl.lambda2 * share * Ftot + h * (1 - share) * Ftot)
+        rho = rho + 0.5 * (mdl.lambda1 * share * Sx + h * (1 - share) * Sx)
+        rho_m = mdl.rho0 if mdl.eq == M.NSE_INC else rho
+        return rho, mom / rho_m, rho_m
+
+    def _m2g_gradient_form(self, grid, x, u, F, Sx, Rg, prev):
+        """G of the gradient form of M2G_bar at node x, T built one component
+        at a time: NSE_COMP T_ab = u_a F_b + F_a u_b - S u_a u_b
+        + delta_ab (d_t p + div(p u)) with p = cs^2 rho, the backward time
+        difference and the central space difference of the previous step's
+        rho u; NSE_INC T_ab = u_a Fb_b + Fb_a u_b + cs^2 S delta_ab - Sb u_a u_b
+        with Fb = F - cs^2 grad(rho_bar^{n-1}) and Sb = S - (rho_bar^n -
+        rho_bar^{n-1}).  M2G_bar = (I - S2/2) T on the second-order rows."""
+        lat, mdl = self.lat, self.mdl
+        d, cs2 = lat.d, lat.cs2
+        rp, jp = prev
+
+        def nb(a, step):
+            t = list(x)
+            ax = len(grid) - 1 - a
+            t[ax] = (x[ax] + step) % grid[ax]
+            return tuple(t)
+
+        T = np.zeros((d, d))
+        if mdl.eq == M.NSE_COMP:
+            div = Rg[x] - rp[x]
+            for a in range(d):
+                div += (jp[(a,) + nb(a, 1)] - jp[(a,) + nb(a, -1)]) / (2 * lat.c[a])
+            div *= cs2
+            for a in range(d):
+                for b in range(d):
+                    T[a, b] = u[a] * F[b] + F[a] * u[b] - Sx * u[a] * u[b] + (div if a == b else 0.0)
+        else:
+            Fb = np.array([F[a] - cs2 * (rp[nb(a, 1)] - rp[nb(a, -1)]) / (2 * lat.c[a]) for a in range(d)])
+            Sb = Sx - (Rg[x] - rp[x])
+            for a in range(d):
+                for b in range(d):
+                    T[a, b] = u[a] * Fb[b] + Fb[a] * u[b] + (cs2 * Sx if a == b else 0.0) - Sb * u[a] * u[b]
+        mg = M.hermite_from_raw(lat, [np.zeros(1), np.zeros((d, 1)), T[:, :, None], None], max_order=2)[:, 0]
+        mg[[r.order != 2 for r in lat.rows]] = 0.0
+        return self._velocity_space((np.eye(self.nlow) - 0.5 * self.S_low) @ mg)

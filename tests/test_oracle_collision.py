@@ -390,9 +390,9 @@ def test_mass_source_planted_m2g_mistake_leaves_a_stress(monkeypatch):
     S, n = 2e-4, 60
     orig = M.aux_hermite
 
-    def no_mass_term(lat, model, Sm, u, force, extra=None, cross=None):
+    def no_mass_term(lat, model, Sm, u, force, extra=None, cross=None, grad=None, mass=None):
         plain = M.Model(**{**model.__dict__, "mass_src": 0.0})
-        return orig(lat, plain, Sm, u, force, extra, cross)
+        return orig(lat, plain, Sm, u, force, extra, cross, grad)
 
     monkeypatch.setattr(M, "aux_hermite", no_mass_term)
     lat, mdl, st, rho0, u0, rho, u = _uniform_mass_source(W.Q25_RECT, S, n)

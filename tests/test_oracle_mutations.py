@@ -163,11 +163,11 @@ def test_first_order_source_scheme_is_caught(monkeypatch):
     leaves a first-order (explicit Euler) source."""
     orig_collide = M.collide
 
-    def euler(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None, force_prev=None):
+    def euler(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None, **kw):
         if model.eq == M.NCDE and model.three_level:
             R0 = M.macroscopic(lat, model, f)[0]
             phi_prev = R0              # F(t - dt) = F(t): the correction term vanishes
-        return orig_collide(lat, model, f, force, ncde_b, ncde_x, phi_prev, force_prev)
+        return orig_collide(lat, model, f, force, ncde_b, ncde_x, phi_prev, **kw)
     monkeypatch.setattr(M, "collide", euler)
     _pin_fails(TD.test_source_three_level_scheme_is_second_order)
 
@@ -236,7 +236,76 @@ def test_three_level_force_difference_dropped_is_caught(monkeypatch):
     """The NSE three-level scheme without (F(t) - F(t - dt)) / 2."""
     orig = M.collide
 
-    def no_history(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None, force_prev=None):
-        return orig(lat, model, f, force, ncde_b, ncde_x, phi_prev, None)
+    def no_history(lat, model, f, force=None, ncde_b=None, ncde_x=None, phi_prev=None, force_prev=None, **kw):
+        return orig(lat, model, f, force, ncde_b, ncde_x, phi_prev, None, **kw)
     monkeypatch.setattr(M, "collide", no_history)
     _pin_fails(TP.test_uniform_force_closed_form, 0.4, 1.0, True)
+
+
+# --------------------------------------------------------------------------
+# the gradient form of M2G_bar
+# --------------------------------------------------------------------------
+
+import test_oracle_m2g_gradient as TG  # noqa: E402
+
+
+def _mutate_gradients(monkeypatch, edit):
+    orig = M.m2g_gradients
+
+    def mutated(lat, model, R0, j, prev):
+        return edit(orig(lat, model, R0, j, prev), lat, model, R0, j, prev)
+    monkeypatch.setattr(M, "m2g_gradients", mutated)
+
+
+def test_wrong_sign_of_div_pu_is_caught(monkeypatch):
+    """d_t p - div(p u) instead of d_t p + div(p u)."""
+    def edit(g, lat, model, R0, j, prev):
+        if "div" in g:
+            r_prev, j_prev = prev
+            g = {"div": lat.cs2 * ((R0 - r_prev) - sum(M._central(lat, j_prev[a], a) for a in range(lat.d))).reshape(-1)}
+        return g
+    _mutate_gradients(monkeypatch, edit)
+    _pin_fails(TG.test_lagged_continuity_residual_is_first_order, W.Q25_RECT)
+
+
+def test_dropped_dt_p_is_caught(monkeypatch):
+    def edit(g, lat, model, R0, j, prev):
+        if "div" in g:
+            g = {"div": lat.cs2 * sum(M._central(lat, prev[1][a], a) for a in range(lat.d)).reshape(-1)}
+        return g
+    _mutate_gradients(monkeypatch, edit)
+    _pin_fails(TG.test_lagged_continuity_residual_is_first_order, W.Q53_RECT)
+
+
+def test_dropped_pressure_gradient_of_f_bar_is_caught(monkeypatch):
+    """F_bar = F instead of F - cs^2 grad(rho_bar) (NSE_INC)."""
+    def edit(g, lat, model, R0, j, prev):
+        if "gr" in g:
+            g = {"gr": 0.0 * g["gr"], "dt": g["dt"]}
+        return g
+    _mutate_gradients(monkeypatch, edit)
+    _pin_fails(TG.test_hydrostatic_stream_keeps_its_speed_with_the_gradient_form, W.Q25_RECT, 1.2e-3, 2.5e-5)
+
+
+def test_dropped_dt_rho_of_s_bar_is_caught(monkeypatch):
+    """S_bar = S instead of S - d_t rho_bar (NSE_INC)."""
+    def edit(g, lat, model, R0, j, prev):
+        if "gr" in g:
+            g = {"gr": g["gr"], "dt": 0.0 * g["dt"]}
+        return g
+    _mutate_gradients(monkeypatch, edit)
+    _pin_fails(TG.test_uniform_incompressible_source_leaves_no_shear_stress, W.Q25_RECT)
+
+
+def test_history_without_the_continuity_start_is_caught(monkeypatch):
+    """rho^{-1} = rho^0 (no continuity step back): the first step's lagged
+    d_t p misses cs^2 S."""
+    orig = M.init_state
+
+    def plain_start(lat, model, rho_or_phi, u=None, force=None):
+        st = orig(lat, model, rho_or_phi, u, force)
+        if st.hist is not None:
+            st.hist = (np.asarray(rho_or_phi, dtype=np.float64), st.hist[1])
+        return st
+    monkeypatch.setattr(M, "init_state", plain_start)
+    _pin_fails(TG.test_uniform_state_gradient_form_is_the_closed_form, W.Q25_RECT, 1)
