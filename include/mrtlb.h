@@ -231,13 +231,14 @@ typedef struct {
    * zero for every model but the NCDE. */
   double src_q, src_k;
   int three_level;
-  /* MRTLB_NSE_COMP uniform mass source S (with g_share = 0: M0F = S,
-   * M1F = F, M2F = 0, eq. M-NSEs-5 with S_G = 0): rho = sum f_bar + S/2
-   * (eq. 2-4-2) and M2G = (I - S2/2)[uF + Fu + (cs^2 I - uu) S] (eq. M2G-1
-   * with S_bar = S; for isothermal p, d_t p I + div(p u I) = cs^2 S I).
-   * The initial state is f_eq - F/2.  Runs in the forced kernel: the solve
-   * needs has_force (a zero force field is fine); EINVAL otherwise and for
-   * other models. */
+  /* NSE uniform mass source S (with g_share = 0: M0F = S, M1F = F,
+   * M2F = 0, eq. M-NSEs-5 with S_G = 0): rho = sum f_bar + S/2 (eq. 2-4-2)
+   * and M2G = (I - S2/2)[uF + Fu + (cs^2 I - uu) S] (eq. M2G-1 with
+   * S_bar = S; for isothermal p, d_t p I + div(p u I) = cs^2 S I; eq.
+   * M2Ga-1 for NSE_INC).  The initial state is f_eq - F/2.  A field S(x)
+   * replaces it with mrtlb_set_mass_source_field.  Runs in the forced
+   * kernel: the solve needs has_force (a zero force field is fine); EINVAL
+   * otherwise and for the NCDE and CDE. */
   double mass_src;
   /* NSE partial correction (eqs. 2-4-0, 2-4-2, M-NSEs-2, M-NSEs-4-0): the
    * share g_share in [0, 1] of the body force and of the mass source that
@@ -262,6 +263,21 @@ typedef struct {
    * g_share = 0 (a zero-initialized descriptor) lambda1 and lambda2 act on
    * nothing.  Other models: g_share = 0 (EINVAL otherwise), lambdas ignored. */
   double g_share, lambda1, lambda2;
+  /* NSE: the form of M2G_bar.  0: the local closed form above.  1: the
+   * gradient form (eqs. M2G-1, M2G): NSE_COMP takes (d_t p + div(p u)) I,
+   * p = cs^2 rho, in place of cs^2 S I; NSE_INC (rho = rho0, p = cs^2 rho_bar)
+   * takes F_bar = F - cs^2 grad(rho_bar) and S_bar = S - d_t rho_bar in place
+   * of F and S.  d_t is the backward difference of this step's value and the
+   * previous step's, grad and div central differences (spacing c_a dt) of
+   * the previous step's rho and rho u, which the solve keeps per node (two
+   * slots of d + 1 values for NSE_COMP, 1 for NSE_INC, FP64 or FP32 as the
+   * arithmetic).  The history before t = 0 follows the continuity equation:
+   * rho^{-1} = rho^0 - dt (S - div(rho u)^0), (rho u)^{-1} = (rho u)^0.
+   * One node per lane; storages FP64, FP32, FP32_DEV and FP32_DEV_F64;
+   * compiled lattices; NSE_COMP on the multispeed lattices only (k = 0,
+   * M30 = rho uuu).  EINVAL otherwise.  mrtlb_write_populations does not
+   * set the history. */
+  int m2g_form;
 } mrtlb_model_desc;
 
 /* Population storage in HBM (compute is FP64 for MRTLB_FP64 and
@@ -290,7 +306,9 @@ typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DE
 
 /* Create a solve on a periodic grid n[0] x n[1] (x n[2] in 3D; n[2] = 1 in
  * 2D).  Allocates two population buffers (pull streaming, double-buffered),
- * the force field if has_force, and for the NCDE two phi history fields.
+ * the force field and a mass-source field (d + 1 node fields) if has_force,
+ * for the NCDE two phi history fields, and for the NSE gradient form of
+ * M2G_bar (m2g_form = 1) two slots of its history.
  * The lattice is copied; it may be destroyed afterwards.
  * Errors: EINVAL (sizes < 1, a size below the largest lattice offset, a
  * population buffer of 4 GiB or more, rates outside (0, 2), negative or
@@ -299,7 +317,9 @@ typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DE
  * the remaining budget; nothing allocated), EDEVICE. */
 mrtlb_status mrtlb_solve_create(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const mrtlb_model_desc* model,
                                 const int64_t n[3], int storage, int has_force, mrtlb_solve** out);
-/* Device bytes mrtlb_solve_create would allocate. */
+/* Device bytes mrtlb_solve_create would allocate.  model is the
+ * mrtlb_model kind, plus MRTLB_FOOTPRINT_M2G_GRADIENT for m2g_form = 1. */
+#define MRTLB_FOOTPRINT_M2G_GRADIENT 0x100
 mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3], int storage, int model,
                                    int has_force, size_t* bytes);
 /* Bytes of one population buffer of a solve on this grid and storage.  The
@@ -374,6 +394,17 @@ mrtlb_status mrtlb_set_velocity_field(mrtlb_solve* s, const double* u);
  * Waits for the work enqueued before it.  Errors: EINVAL (NULL, not an NSE
  * solve with a force field), ENUMERIC (non-finite value), ENOMEM, EDEVICE. */
 mrtlb_status mrtlb_set_force_field(mrtlb_solve* s, const double* force);
+
+/* NSE solves created with has_force: the mass source as a field S(x) (N
+ * values, node order as rho in mrtlb_init_fields), in place of the uniform
+ * mass_src, from the next step on (and for mrtlb_init_fields if set before
+ * it); each step adds S(x) to the zeroth moment and rho = sum f + cS S(x)
+ * as for the uniform source (eqs. M-NSEs-2, 2-4-2).  The three-level scheme
+ * keeps the previous source as it keeps the previous force.  The field is
+ * stored beside the force (the forced solve reserves d + 1 node fields).
+ * Waits for the work enqueued before it.  Errors: EINVAL (NULL, not an NSE
+ * solve with a force field), ENUMERIC (non-finite value), ENOMEM, EDEVICE. */
+mrtlb_status mrtlb_set_mass_source_field(mrtlb_solve* s, const double* S);
 
 /* Enqueue nsteps >= 0 collide-and-stream steps (asynchronous). */
 mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);

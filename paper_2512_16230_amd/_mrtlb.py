@@ -55,7 +55,7 @@ class mrtlb_model_desc(ctypes.Structure):
                 ("D2", c_double), ("adv_u", c_double * 3), ("u_bound", c_double), ("dev_bound", c_double),
                 ("gn_bt", c_double * 3), ("gn_dd", c_double * 3), ("src_q", c_double), ("src_k", c_double),
                 ("three_level", c_int), ("mass_src", c_double), ("g_share", c_double), ("lambda1", c_double),
-                ("lambda2", c_double)]
+                ("lambda2", c_double), ("m2g_form", c_int)]
 
 
 _lib = None
@@ -98,6 +98,7 @@ def lib():
         "mrtlb_solve_set_transform": (c_int, [c_void_p, c_int]),
         "mrtlb_set_velocity_field": (c_int, [c_void_p, _DP]),
         "mrtlb_set_force_field": (c_int, [c_void_p, _DP]),
+        "mrtlb_set_mass_source_field": (c_int, [c_void_p, _DP]),
         "mrtlb_set_drift_correction": (c_int, [c_void_p, c_int64]),
         "mrtlb_host_alloc": (c_int, [c_size_t, POINTER(c_void_p)]),
         "mrtlb_host_free": (None, [c_void_p]),
@@ -120,7 +121,7 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
             "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external",
             "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform", "mrtlb_set_velocity_field",
-            "mrtlb_set_force_field"]
+            "mrtlb_set_force_field", "mrtlb_set_mass_source_field"]
 
 
 def _check(status):
@@ -237,7 +238,7 @@ class Lattice:
 def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s_high=1.2, m30=True, D0=0.0,
                D2=0.0, adv_u=(0.0, 0.0, 0.0), u_bound=0.0, dev_bound=0.0, gn_bt=(0.0, 0.0, 0.0),
                gn_dd=(0.0, 0.0, 0.0), src_q=0.0, src_k=0.0, three_level=False, mass_src=0.0, g_share=0.0,
-               lambda1=1.0, lambda2=1.0):
+               lambda1=1.0, lambda2=1.0, m2g_form=0):
     """Model parameters; u_bound / dev_bound size the int16 storage's ranges
     (max |u| and max |rho - rho0| / rho0, or max |phi| for the NCDE);
     gn_bt / gn_dd are the general-NCDE coefficients A1 b_bar and diag(A2);
@@ -245,7 +246,8 @@ def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s
     three-level scheme instead of full correction (NCDE and NSE); mass_src is
     the compressible NSE's uniform mass source (the solve needs has_force);
     g_share is the share of the NSE force and mass source carried by G,
-    corrected with lambda2 and lambda1."""
+    corrected with lambda2 and lambda1; m2g_form 1 selects the gradient form
+    of the NSE's auxiliary second moment."""
     m = mrtlb_model_desc()
     m.model = MODELS[eq] if isinstance(eq, str) else int(eq)
     m.rho0, m.s0, m.s1, m.s_shear, m.s_bulk, m.s3, m.s_high = rho0, s0, s1, s_shear, s_bulk, s3, s_high
@@ -261,6 +263,7 @@ def model_desc(eq, rho0=1.0, s0=1.2, s1=1.2, s_shear=1.25, s_bulk=1.2, s3=1.2, s
     m.three_level = 1 if three_level else 0
     m.mass_src = float(mass_src)
     m.g_share, m.lambda1, m.lambda2 = float(g_share), float(lambda1), float(lambda2)
+    m.m2g_form = int(m2g_form)
     return m
 
 
@@ -288,11 +291,16 @@ class HostBuffer:
             pass
 
 
-def footprint(lattice, shape, storage, eq, has_force=False):
+MRTLB_FOOTPRINT_M2G_GRADIENT = 0x100
+
+
+def footprint(lattice, shape, storage, eq, has_force=False, m2g_form=0):
     n = (c_int64 * 3)(*_nxyz(shape))
     out = c_size_t()
     st = STORAGES[storage] if isinstance(storage, str) else int(storage)
     md = MODELS[eq] if isinstance(eq, str) else int(eq)
+    if m2g_form == 1:
+        md |= MRTLB_FOOTPRINT_M2G_GRADIENT
     _check(lib().mrtlb_solve_footprint(lattice.h, n, st, md, 1 if has_force else 0, byref(out)))
     return out.value
 
@@ -354,6 +362,11 @@ class Solve:
         step on (the three-level scheme's difference term uses the previous
         step's force)."""
         _check(lib().mrtlb_set_force_field(self.h, _ptr(_f64(force))))
+
+    def set_mass_source_field(self, S):
+        """NSE with a force field: the mass source S(x) (shape of the grid) used
+        from the next step on (and by init_fields if set before it)."""
+        _check(lib().mrtlb_set_mass_source_field(self.h, _ptr(_f64(S))))
 
     def step(self, n=1):
         _check(lib().mrtlb_step(self.h, int(n)))

@@ -76,10 +76,11 @@ struct mrtlb_solve {
   uint32_t N = 0;
   size_t bytes = 0;
   void* f[2] = {nullptr, nullptr};
-  void* force = nullptr;        // Real, d x N
+  void* force = nullptr;        // Real, (d + 1) x N: the NSE force, then the mass-source field (CDE: d x N velocity)
   void* fprev = nullptr;        // Real, d x N: the NSE three-level scheme's F(t - dt) (allocated on the
                                 // first force change)
   bool hist_pending = false;    // the next step adds the three-level difference term (fprev valid)
+  int sfield = 0;               // NSE: the mass source is the field in plane d of the force buffer
   void* phi[2] = {nullptr, nullptr};
   void* jobs = nullptr;         // three Job<Real> slots (parity 0, 1, drift-corrected step), then the
                                 // int16 saturation flag (an int) at jobs + kFlagOffset
@@ -339,19 +340,19 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   // NSE: force and mass source divided between G (share g) and F (eq.
   // M-NSEs-2); h = 1 for the shifted f_bar, 0 for the three-level scheme
   const bool nse = m.model == MRTLB_NSE_INC || m.model == MRTLB_NSE_COMP;
-  const double S = m.model == MRTLB_NSE_COMP ? m.mass_src : 0.0;
   const double gsh = nse ? m.g_share : 0.0, h = nse && m.three_level ? 0.0 : 1.0;
-  const double msh = 0.5 * S * (gsh * m.lambda1 + (1 - gsh) * h);
+  const double cS = 0.5 * (gsh * m.lambda1 + (1 - gsh) * h);
   const double fh = nse ? 0.5 * (gsh * m.lambda2 + (1 - gsh) * h) : 0.5;
-  P.msrc = (Real)S;
-  P.msh = (Real)msh;
+  P.msrc = (Real)(nse ? m.mass_src : 0.0);
+  P.sfield = s.sfield;
+  P.cS = (Real)cS;
   P.fh = (Real)fh;
   P.g1 = (Real)(1.0 - m.s1 * fh);
   P.hf = (Real)(nse && m.three_level ? 0.5 * (1 - gsh) : 0.0);
   for (int a = 0; a < 3; ++a) {
     double s2i = 0;                   // (S2 I)_a: row sum of the normal block
     for (int b = 0; b < D; ++b) s2i += S2[a][b];
-    P.x2n[a] = (Real)(a < D ? L.cs2 * s2i * (msh - 0.5 * S) : 0.0);
+    P.kx2[a] = (Real)(a < D ? L.cs2 * s2i * (cS - 0.5) : 0.0);
   }
   for (int a = 0; a < 3; ++a) {
     P.adv[a] = (Real)(a < D ? m.adv_u[a] : 0.0);
@@ -411,6 +412,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.force = s.has_force != 0;
   r.vec = s.vec;
   r.transform = s.transform;
+  r.m2g = s.model.m2g_form == 1;
   r.dim = s.L.D;
   r.jobs = jobs;
   r.njobs = 1;
@@ -436,6 +438,8 @@ static const void* job_ptr(const mrtlb_solve& s, int parity) {
 // GPU (two threads, or contexts with different streams) race.
 // ---------------------------------------------------------------------------
 constexpr size_t kScratchBytes = (size_t)4 << 20;
+// planes of the state sums: b populations, d force components, the mass-source field
+constexpr int kMaxPlanes = kMaxB + 4;
 constexpr size_t kScratchDoubles = kScratchBytes / sizeof(double);
 constexpr int kMaxDevices = 64;
 static __device__ __align__(256) double scratch[kScratchDoubles];
@@ -602,8 +606,13 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
     return fail(MRTLB_EINVAL, "g_share must lie in [0, 1] and lambda1, lambda2 must be finite");
   if (!nse && m.g_share != 0) return fail(MRTLB_EINVAL, "g_share belongs to the NSE models (0 otherwise)");
   if (!std::isfinite(m.mass_src)) return fail(MRTLB_EINVAL, "mass_src must be finite");
-  if (m.mass_src != 0 && m.model != MRTLB_NSE_COMP)
-    return fail(MRTLB_EINVAL, "the mass source belongs to the compressible NSE model");
+  if (m.mass_src != 0 && !nse) return fail(MRTLB_EINVAL, "the mass source belongs to the NSE models");
+  if (m.m2g_form != 0 && m.m2g_form != 1) return fail(MRTLB_EINVAL, "m2g_form must be 0 or 1");
+  if (m.m2g_form == 1 && !nse) return fail(MRTLB_EINVAL, "the gradient form of M2G belongs to the NSE models");
+  if (m.m2g_form == 1 && L.kind == kCustom)
+    return fail(MRTLB_EINVAL, "the gradient form of M2G runs on the compiled lattices");
+  if (m.m2g_form == 1 && m.model == MRTLB_NSE_COMP && L.standard)
+    return fail(MRTLB_EINVAL, "the compressible gradient form of M2G is built for the multispeed lattices (k = 0)");
   if (L.kind == kCustom && m.model != MRTLB_NSE_INC && m.model != MRTLB_NSE_COMP)
     return fail(MRTLB_EINVAL, "custom lattices carry the NSE models only");
   if (L.standard) {
@@ -624,9 +633,12 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
   const size_t real = is_double(storage) ? 8 : 4;
   const int64_t rows = N / n[0];
   size_t b = 2 * (size_t)lat->L.B * (size_t)(rows * row_pitch(n[0], storage)) * elem_bytes(storage);
-  if (has_force) b += (size_t)D * (size_t)N * real;
-  if (model == MRTLB_NCDE) b += 2 * (size_t)N * real;
-  if (model == MRTLB_CDE) b += (size_t)D * (size_t)N * real;   // velocity field
+  const int kind = model & 0xff;
+  if (has_force) b += (size_t)(D + 1) * (size_t)N * real;      // force, mass-source field
+  if (kind == MRTLB_NCDE) b += 2 * (size_t)N * real;
+  if (kind == MRTLB_CDE) b += (size_t)D * (size_t)N * real;    // velocity field
+  if (model & MRTLB_FOOTPRINT_M2G_GRADIENT)                     // history of rho (and rho u), two slots
+    b += 2 * (size_t)(kind == MRTLB_NSE_COMP ? D + 1 : 1) * (size_t)N * real;
   b += kJobsBytes + sizeof(KParams<double>);
   *bytes = b;
   return MRTLB_OK;
@@ -669,8 +681,11 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   if (model->mass_src != 0 && !has_force)
     return fail(MRTLB_EINVAL, "a mass source runs in the forced kernel: create the solve with has_force "
                               "(a zero force field is fine)");
+  if (model->m2g_form == 1 && (storage == kFP16Dev || storage == kBF16Dev || storage == kI16Dev))
+    return fail(MRTLB_EINVAL, "the gradient form of M2G runs with the FP32 and FP64 storages");
   size_t bytes = 0;
-  st = mrtlb_solve_footprint(lat, n, storage, model->model, has_force, &bytes);
+  st = mrtlb_solve_footprint(lat, n, storage, model->model | (model->m2g_form == 1 ? MRTLB_FOOTPRINT_M2G_GRADIENT : 0),
+                             has_force, &bytes);
   if (st != MRTLB_OK) return st;
   const int64_t nz = D == 3 ? n[2] : 1;
   if (external)   // the population buffers are the caller's
@@ -700,6 +715,7 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   // step kernel: each thread owns vec consecutive x-slots of the padded rows,
   // a workgroup kBlock * vec consecutive slots
   s->vec = pick_vec(storage, s->L.kind, s->model.model, s->nx);
+  if (s->model.m2g_form == 1) s->vec = 1;     // the gradient-form kernels run one node per lane
   const uint32_t slots = (uint32_t)s->ny * (uint32_t)s->nz * (uint32_t)s->nxp;
   s->nblocks = (slots + (uint32_t)(kBlock * s->vec) - 1) / (uint32_t)(kBlock * s->vec);
   s->nblocks_node = (s->N + kBlock - 1) / kBlock;
@@ -715,8 +731,15 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   bool ok = (external || (alloc(&s->f[0], pop) && alloc(&s->f[1], pop))) &&
             alloc(&s->jobs, kJobsBytes) &&
             alloc(&s->pd, sizeof(KParams<double>));
-  if (ok && has_force) ok = alloc(&s->force, (size_t)D * s->N * real);
+  if (ok && has_force) {
+    ok = alloc(&s->force, (size_t)(D + 1) * s->N * real);
+    if (ok) ok = hipMemset(s->force, 0, (size_t)(D + 1) * s->N * real) == hipSuccess;
+  }
   if (ok && model->model == MRTLB_NCDE) ok = alloc(&s->phi[0], s->N * real) && alloc(&s->phi[1], s->N * real);
+  if (ok && model->m2g_form == 1) {
+    const size_t hb = (size_t)(model->model == MRTLB_NSE_COMP ? D + 1 : 1) * s->N * real;
+    ok = alloc(&s->phi[0], hb) && alloc(&s->phi[1], hb);
+  }
   // the CDE's velocity field lives where the NSE force field would
   if (ok && model->model == MRTLB_CDE) ok = alloc(&s->force, (size_t)D * s->N * real);
   if (!ok) {
@@ -823,7 +846,7 @@ static mrtlb_status check_saturation(mrtlb_solve* s) {
 // Planes of the FP64 sums of a solve's state (populations, then the force
 // components) and the chunks each is summed in.
 static void sum_layout(const mrtlb_solve* s, int* planes, uint32_t* nchunks) {
-  const int nf = s->force && s->model.model != MRTLB_CDE ? s->L.D : 0;
+  const int nf = s->force && s->model.model != MRTLB_CDE ? s->L.D + s->sfield : 0;
   const uint32_t chunk = kBlock * kChunkIters;
   *planes = s->L.B + nf;
   *nchunks = (s->N + chunk - 1) / chunk;
@@ -837,7 +860,7 @@ static size_t sum_work_doubles(const mrtlb_solve* s) {
   return (size_t)planes * nchunks + (size_t)planes;
 }
 
-// FP64 total of every plane into plane[] (host, kMaxB + 3 entries): partial
+// FP64 total of every plane into plane[] (host, kMaxPlanes entries): partial
 // sums per chunk, then per plane in chunk order, both on the device, in
 // `work` (sum_work_doubles entries of device memory); synchronizes.
 static mrtlb_status plane_totals(mrtlb_solve* s, double* work, double* plane) {
@@ -874,8 +897,10 @@ static mrtlb_status totals_from_planes(mrtlb_solve* s, const double* plane, doub
   m += ref * (double)s->N;
   if (s->model.model == MRTLB_NCDE && s->model.three_level == 0 && (s->model.src_q != 0 || s->model.src_k != 0))
     m = (m + 0.5 * s->model.src_q * (double)s->N) / (1.0 - 0.5 * s->model.src_k);   // phi = sum f_bar + S/2
-  if (s->model.model == MRTLB_NSE_COMP) m += s->Pd.msh * (double)s->N;  // rho = sum f + msh
-  for (int a = 0; a < nf; ++a) mom[a] += s->Pd.fh * plane[B + a];        // rho u = sum c f + fh F
+  // rho = sum f + cS S, rho u = sum c f + fh F
+  if (s->model.model == MRTLB_NSE_INC || s->model.model == MRTLB_NSE_COMP)
+    m += s->Pd.cS * (s->sfield ? plane[B + D] : s->Pd.msrc * (double)s->N);
+  for (int a = 0; a < std::min(nf, D); ++a) mom[a] += s->Pd.fh * plane[B + a];
   bool finite = std::isfinite(m);
   for (int a = 0; a < D; ++a) finite = finite && std::isfinite(mom[a]);
   *mass = m;
@@ -896,7 +921,7 @@ static mrtlb_status state_sums(mrtlb_solve* s, double* mass, double* momentum) {
     HIP_TRY(hipMalloc(&s->part, need));
     s->part_bytes = need;
   }
-  double plane[kMaxB + 3];
+  double plane[kMaxPlanes];
   mrtlb_status st = plane_totals(s, static_cast<double*>(s->part), plane);
   if (st != MRTLB_OK) return st;
   return totals_from_planes(s, plane, mass, momentum);
@@ -922,7 +947,7 @@ mrtlb_status mrtlb_conserved_noalloc(mrtlb_solve* s, double* mass, double* momen
                                   " B of the allocation-free path; use mrtlb_conserved");
   HIP_TRY(hipSetDevice(s->ctx->device));
   if (!s->ctx->scratch) return fail(MRTLB_EDEVICE, "no scratch address for this device");
-  double plane[kMaxB + 3];
+  double plane[kMaxPlanes];
   mrtlb_status st = plane_totals(s, static_cast<double*>(s->ctx->scratch), plane);
   if (st != MRTLB_OK) return st;
   double m = 0, mom[3] = {0, 0, 0};
@@ -1071,8 +1096,9 @@ mrtlb_status mrtlb_solve_set_transform(mrtlb_solve* s, int transform) {
     if (s->L.D != 3 || s->L.kind == kCustom || maxe > 2 || s->L.B > 64)
       return fail(MRTLB_EINVAL, "the MFMA transform is built for the 3D lattices (rD3Q53, rD3Q45, rD3Q33, D3Q27)");
     if (s->storage != kI16Dev) return fail(MRTLB_EINVAL, "the MFMA transform runs with the int16 deviation storage");
-    if ((s->model.model != MRTLB_NSE_INC && s->model.model != MRTLB_NSE_COMP) || s->has_force)
-      return fail(MRTLB_EINVAL, "the MFMA transform runs the NSE models without a force field");
+    if ((s->model.model != MRTLB_NSE_INC && s->model.model != MRTLB_NSE_COMP) || s->has_force ||
+        s->model.m2g_form != 0)
+      return fail(MRTLB_EINVAL, "the MFMA transform runs the NSE models without a force field (closed-form M2G)");
     if (s->nxp % 64 != 0)
       return fail(MRTLB_EINVAL, "the MFMA transform needs a row pitch (nx rounded up to 32) that is a multiple of 64");
     if (!s->mtab) {
@@ -1120,24 +1146,63 @@ static mrtlb_status upload_velocity(mrtlb_solve* s, const double* u) {
   return upload_node_field(s, u, "velocity field");
 }
 
+// The three-level scheme's F(t - dt) and S(t - dt): the force and mass
+// source of the last step, kept until the next step has used them.
+static mrtlb_status keep_source_history(mrtlb_solve* s, bool* history) {
+  *history = s->model.three_level != 0 && s->model.g_share < 1.0 && s->steps > 0;
+  if (!*history || s->hist_pending) return MRTLB_OK;
+  const size_t bytes = (size_t)(s->L.D + 1) * s->N * (is_double(s->storage) ? 8 : 4);
+  if (!s->fprev && hipMalloc(&s->fprev, bytes) != hipSuccess) {
+    s->fprev = nullptr;
+    return fail(MRTLB_ENOMEM, "out of device memory for the previous force field");
+  }
+  HIP_TRY(hipMemcpyAsync(s->fprev, s->force, bytes, hipMemcpyDeviceToDevice, s->ctx->stream));
+  return MRTLB_OK;
+}
+
+static bool nse_with_force(const mrtlb_solve* s) {
+  return (s->model.model == MRTLB_NSE_INC || s->model.model == MRTLB_NSE_COMP) && s->has_force;
+}
+
 mrtlb_status mrtlb_set_force_field(mrtlb_solve* s, const double* force) {
   if (!s || !force) return fail(MRTLB_EINVAL, "NULL argument");
-  if ((s->model.model != MRTLB_NSE_INC && s->model.model != MRTLB_NSE_COMP) || !s->has_force)
-    return fail(MRTLB_EINVAL, "the force field belongs to an NSE solve created with has_force");
+  if (!nse_with_force(s)) return fail(MRTLB_EINVAL, "the force field belongs to an NSE solve created with has_force");
   HIP_TRY(hipSetDevice(s->ctx->device));
-  // the three-level scheme's F(t - dt): the force of the last step, kept
-  // until the next step has used it
-  const bool history = s->model.three_level != 0 && s->model.g_share < 1.0 && s->steps > 0;
-  if (history && !s->hist_pending) {
-    const size_t bytes = (size_t)s->L.D * s->N * (is_double(s->storage) ? 8 : 4);
-    if (!s->fprev && hipMalloc(&s->fprev, bytes) != hipSuccess) {
-      s->fprev = nullptr;
-      return fail(MRTLB_ENOMEM, "out of device memory for the previous force field");
-    }
-    HIP_TRY(hipMemcpyAsync(s->fprev, s->force, bytes, hipMemcpyDeviceToDevice, s->ctx->stream));
-  }
-  const mrtlb_status st = upload_node_field(s, force, "force field");
+  bool history = false;
+  mrtlb_status st = keep_source_history(s, &history);
   if (st != MRTLB_OK) return st;
+  st = upload_node_field(s, force, "force field");
+  if (st != MRTLB_OK) return st;
+  if (history) s->hist_pending = true;
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_set_mass_source_field(mrtlb_solve* s, const double* S) {
+  if (!s || !S) return fail(MRTLB_EINVAL, "NULL argument");
+  if (!nse_with_force(s)) return fail(MRTLB_EINVAL, "the mass source belongs to an NSE solve created with has_force");
+  for (uint32_t i = 0; i < s->N; ++i)
+    if (!std::isfinite(S[i])) return fail(MRTLB_ENUMERIC, "non-finite mass source");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  bool history = false;
+  mrtlb_status st = keep_source_history(s, &history);
+  if (st != MRTLB_OK) return st;
+  hipStream_t stream = s->ctx->stream;
+  char* plane = static_cast<char*>(s->force) + (size_t)s->L.D * s->N * (is_double(s->storage) ? 8 : 4);
+  if (is_double(s->storage)) {
+    HIP_TRY(hipMemcpyAsync(plane, S, (size_t)s->N * 8, hipMemcpyHostToDevice, stream));
+  } else {
+    std::vector<float> tmp(s->N);
+    for (uint32_t i = 0; i < s->N; ++i) tmp[i] = (float)S[i];
+    HIP_TRY(hipMemcpyAsync(plane, tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice, stream));
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (!s->sfield) {
+    s->sfield = 1;
+    s->Pd.sfield = s->Pf.sfield = 1;
+    HIP_TRY(hipMemcpy(s->pd, &s->Pd, sizeof s->Pd, hipMemcpyHostToDevice));
+    st = upload_jobs(s);
+    if (st != MRTLB_OK) return st;
+  }
   if (history) s->hist_pending = true;
   return MRTLB_OK;
 }
@@ -1358,7 +1423,7 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
       // supplied lattices share a kind), storage, model, force and VEC
       if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->L.D == a->L.D && b->storage == a->storage &&
           b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec &&
-          b->transform == a->transform) {
+          b->transform == a->transform && b->model.m2g_form == a->model.m2g_form) {
         grp.emplace_back(solves[k], nsteps[k]);
         done[k] = 1;
       }

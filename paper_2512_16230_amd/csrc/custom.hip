@@ -142,20 +142,23 @@ __global__ __launch_bounds__(kBlock) void k_init_custom(const Job<typename Store
     jm[a] = rho_m * u[a];
     if (fin) F[a] = fin[(size_t)a * N + self];
   }
+  // mass source at this node (field or uniform) and its correction cS S
+  const double msh = J.force ? P.cS * (P.sfield ? (double)J.force[(size_t)DIM * N + self] : P.msrc) : 0.0;
   Equilibrium<L, double, kNseComp> E;
   E.build(P, R, jm, u);
   double d1[3] = {0, 0, 0}, d2n[3] = {0, 0, 0}, d2o[3] = {0, 0, 0}, d3m[3][3] = {}, d3p[3] = {0, 0, 0}, dxyz = 0;
   for (int a = 0; a < DIM; ++a) {
     d1[a] = (E.e1[a] - P.fh * F[a]) * P.in1[a];
-    // mass source: -F/2 has the Hermite second-order part +cs^2 S / 2
-    d2n[a] = (E.e2n[a] + P.msh * P.cs2) * P.in2n[a];
+    // mass source: subtracting raw moments (cS S, ...) adds cs^2 cS S to the
+    // Hermite second order
+    d2n[a] = (E.e2n[a] + msh * P.cs2) * P.in2n[a];
     d3p[a] = E.e3p[a] * P.in3p[a];
     for (int c = 0; c < DIM; ++c)
       if (c != a) d3m[a][c] = E.e3m[a][c] * P.in3m[a][c];
     for (int c = a + 1; c < DIM; ++c) d2o[off_index(a, c)] = E.e2o[off_index(a, c)] * P.in2o[off_index(a, c)];
   }
   if constexpr (DIM == 3) dxyz = E.exyz * P.inxyz;
-  const double d0 = (R - P.msh) * P.in0 - P.rho_ref;
+  const double d0 = (R - msh) * P.in0 - P.rho_ref;
   BackCoeffs<double> C;
   back_coeffs<DIM, false>(P, d0, d1, d2n, d2o, d3m, d3p, dxyz, C);
   const KParams<Real>& PR = J.P;
@@ -195,7 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_custom(const Job<typename Sto
     }
   }
   if constexpr (WHAT == 0) {
-    R += P.rho_ref + P.msh;
+    R += P.rho_ref;
+    if (J.force) R += P.cS * (P.sfield ? (double)J.force[(size_t)DIM * N + self] : P.msrc);
     out0[self] = R;
     if (out1) {
       const double rho_m = P.inc ? P.rho0 : R;

@@ -759,8 +759,17 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
   Real F[3] = {0, 0, 0}, src1[3] = {0, 0, 0}, x1[3] = {0, 0, 0}, T2n[3] = {0, 0, 0}, T2o[3] = {0, 0, 0};
   Real h1[3] = {0, 0, 0};   // NSE three-level: hf (F(t) - F(t - dt)) after a force change
   Real u[3] = {0, 0, 0}, jm[3] = {0, 0, 0};
-  // NCDE: phi from the sum and the source correction (eq. 2-4-1)
-  const Real R = MODEL == kNcde ? (M.R0 + P.sqh) * P.sci : (FORCE ? M.R0 + P.rho_ref + P.msh : M.R0 + P.rho_ref);
+  const char* fbase = static_cast<const char*>(static_cast<const void*>(J.force));
+  // NSE mass source at this node (forced kernels): the field or the uniform value
+  Real Sm = 0;
+  Real dS = 0;   // three-level scheme after a source change: hf (S(t) - S(t - dt))
+  if constexpr (FORCE && MODEL != kNcde && MODEL != kCde) {
+    Sm = P.msrc;
+    if (P.sfield) Sm = gload<Real>(fbase + (size_t)D * N * sizeof(Real), self * (uint32_t)sizeof(Real));
+  }
+  // NCDE: phi from the sum and the source correction (eq. 2-4-1); NSE: rho
+  // with the mass-source correction (eqs. 2-4-0, 2-4-2)
+  const Real R = MODEL == kNcde ? (M.R0 + P.sqh) * P.sci : (FORCE ? M.R0 + P.rho_ref + P.cS * Sm : M.R0 + P.rho_ref);
   Real src0 = 0;   // source increment of the zeroth moment (NCDE source, NSE mass source)
   Real sg = 0;   // CDE: S_G = -u . grad(phi), grad(phi) = -s1 sum_j c_j f_j / cs^2
   if constexpr (MODEL == kCde) {
@@ -796,8 +805,7 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
     if constexpr (FORCE) {
 #pragma unroll
       for (int a = 0; a < D; ++a)
-        F[a] = gload<Real>(static_cast<const char*>(static_cast<const void*>(J.force)) + (size_t)a * N * sizeof(Real),
-                           self * (uint32_t)sizeof(Real));
+        F[a] = gload<Real>(fbase + (size_t)a * N * sizeof(Real), self * (uint32_t)sizeof(Real));
     }
     const Real rho_m = P.inc ? P.rho0 : R;
     const Real inv = Real(1) / rho_m;
@@ -808,24 +816,68 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
       src1[a] = F[a];
     }
     if constexpr (FORCE) {
-      if (J.fprev) {
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-          h1[a] = P.hf * (F[a] - gload<Real>(static_cast<const char*>(static_cast<const void*>(J.fprev)) +
-                                                 (size_t)a * N * sizeof(Real),
-                                             self * (uint32_t)sizeof(Real)));
-      }
-    }
-    if constexpr (FORCE) {
       // uF + Fu, and for a mass source (cs^2 I - uu) S of M2G together with
       // the -cs^2 S I Hermite part of the source distribution (M0F = S): -uu S
 #pragma unroll
-      for (int a = 0; a < D; ++a) T2n[a] = 2 * u[a] * F[a] - P.msrc * u[a] * u[a];
+      for (int a = 0; a < D; ++a) T2n[a] = 2 * u[a] * F[a] - Sm * u[a] * u[a];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = a + 1; b < D; ++b) T2o[off_index(a, b)] = u[a] * F[b] + u[b] * F[a] - P.msrc * u[a] * u[b];
-      src0 = P.msrc;
+        for (int b = a + 1; b < D; ++b) T2o[off_index(a, b)] = u[a] * F[b] + u[b] * F[a] - Sm * u[a] * u[b];
+      src0 = Sm;
+      if (J.fprev) {
+        // three-level scheme, the step after a change: hf (F(t) - F(t - dt))
+        const char* pbase = static_cast<const char*>(static_cast<const void*>(J.fprev));
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          h1[a] = P.hf * (F[a] - gload<Real>(pbase + (size_t)a * N * sizeof(Real), self * (uint32_t)sizeof(Real)));
+        // the source's difference term: raw M0 only, so Hermite rows 0 and
+        // (with -cs^2) the normal second-order ones
+        if (P.sfield) {
+          dS = P.hf * (Sm - gload<Real>(pbase + (size_t)D * N * sizeof(Real), self * (uint32_t)sizeof(Real)));
+          src0 += dS;
+        }
+      }
+    }
+    if constexpr (MODEL == kNseGrad) {
+      // gradient form of M2G_bar from the previous step's fields: the
+      // backward difference in time and central differences in space
+      const Real rp = gload<Real>(J.phi_prev, self * (uint32_t)sizeof(Real));
+      if (P.inc) {
+        // eq. M2G with p = cs^2 rho_bar, rho = rho0: T gains
+        // u F_bar + F_bar u - uu S_bar minus its closed form,
+        // F_bar - F = -cs^2 grad(rho_bar), S_bar - S = -d_t rho_bar
+        const Real dtr = R - rp;
+        Real gr[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          gr[a] = (gload<Real>(J.phi_prev, g.shifted(ix, a, 1) * (uint32_t)sizeof(Real)) -
+                   gload<Real>(J.phi_prev, g.shifted(ix, a, -1) * (uint32_t)sizeof(Real))) /
+                  (2 * P.c1[a]);
+#pragma unroll
+        for (int a = 0; a < D; ++a) T2n[a] += u[a] * (u[a] * dtr - 2 * P.cs2 * gr[a]);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = a + 1; b < D; ++b)
+            T2o[off_index(a, b)] += u[a] * u[b] * dtr - P.cs2 * (u[a] * gr[b] + u[b] * gr[a]);
+      } else {
+        // eq. M2G-1: (d_t p + div(p u)) I in place of cs^2 S I, p = cs^2 rho
+        const char* jp = static_cast<const char*>(static_cast<const void*>(J.phi_prev));
+        Real div = R - rp;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          div += (gload<Real>(jp + (size_t)(1 + a) * N * sizeof(Real), g.shifted(ix, a, 1) * (uint32_t)sizeof(Real)) -
+                  gload<Real>(jp + (size_t)(1 + a) * N * sizeof(Real), g.shifted(ix, a, -1) * (uint32_t)sizeof(Real))) /
+                 (2 * P.c1[a]);
+        const Real extra = P.cs2 * (div - Sm);
+#pragma unroll
+        for (int a = 0; a < D; ++a) T2n[a] += extra;
+        char* jo = static_cast<char*>(static_cast<void*>(J.phi_out));
+#pragma unroll
+        for (int a = 0; a < D; ++a) gstore<Real>(jo + (size_t)(1 + a) * N * sizeof(Real), self * (uint32_t)sizeof(Real), jm[a]);
+      }
+      gstore<Real>(J.phi_out, self * (uint32_t)sizeof(Real), R);
     }
   }
 
@@ -863,16 +915,16 @@ __device__ __forceinline__ void relax_node(Moments<typename StoreT<ST>::Real>& M
 #pragma unroll
         for (int b = 0; b < D; ++b) {
           ms += P.k2[a][b] * neq[b];
-          if constexpr (FORCE) ms += P.g2[a][b] * T2n[b];
+          if constexpr (FORCE || MODEL == kNseGrad) ms += P.g2[a][b] * T2n[b];
         }
-        if constexpr (FORCE) ms += P.x2n[a];
+        if constexpr (FORCE) ms += P.kx2[a] * Sm - P.cs2 * dS;
         d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
       }
     } else {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         Real ms = E.e2n[a] + kb * tn + ks * (neq[a] - tn) + gb * tT + gs * (T2n[a] - tT);
-        if constexpr (FORCE) ms += P.x2n[a];
+        if constexpr (FORCE) ms += P.kx2[a] * Sm - P.cs2 * dS;
         d2n[a] = (ms - kx * M.m2n[a]) * P.in2n[a];
       }
     }
@@ -1094,6 +1146,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   const uint32_t N = P.N;
   const double R = rho[self];
   double u[3] = {0, 0, 0}, jm[3] = {0, 0, 0}, F[3] = {0, 0, 0};
+  double Sm = 0;    // NSE mass source at this node
   if constexpr (MODEL == kCde) {
     // equilibrium w_j phi; the velocity field is stored by the host
   } else if constexpr (MODEL == kNcde) {
@@ -1106,6 +1159,23 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
       u[a] = uin[(size_t)a * N + self];
       jm[a] = rho_m * u[a];
       if (fin) F[a] = fin[(size_t)a * N + self];
+    }
+    if (J.force) Sm = P.sfield ? (double)J.force[(size_t)D * N + self] : P.msrc;
+    if constexpr (MODEL == kNseGrad) {
+      // the history before t = 0 from the continuity equation:
+      // rho^{-1} = rho^0 - S + div(rho_m u)^0 (central), (rho u)^{-1} = (rho u)^0,
+      // in both slots
+      double div = 0;
+      for (int a = 0; a < D; ++a) {
+        const uint32_t xp = g.shifted(ix, a, 1), xm = g.shifted(ix, a, -1);
+        const double rp = P.inc ? P.rho0 : rho[xp], rm = P.inc ? P.rho0 : rho[xm];
+        div += (rp * uin[(size_t)a * N + xp] - rm * uin[(size_t)a * N + xm]) / (2 * P.c1[a]);
+      }
+      Real* h0 = static_cast<Real*>(J.phi_out);
+      Real* h1 = const_cast<Real*>(J.phi_prev);
+      h0[self] = h1[self] = (Real)(R - Sm + div);
+      if (!P.inc)
+        for (int a = 0; a < D; ++a) h0[(size_t)(1 + a) * N + self] = h1[(size_t)(1 + a) * N + self] = (Real)jm[a];
     }
   }
   Equilibrium<L, double, MODEL> E;
@@ -1123,11 +1193,12 @@ __global__ __launch_bounds__(kBlock) void k_init(const Job<typename StoreT<ST>::
   double x[B];
   for (int j = 0; j < B; ++j) x[j] = 0;
   // NCDE, full correction: f_bar = f_eq - w S(phi0) / 2
-  // NSE: f_bar = f_eq minus the distribution of raw moments (msh, fh F, 0)
-  // (Hermite second order -cs^2 msh); the F route: F/2 with M0F = S
-  const double r0 = MODEL == kNcde ? R - P.sinit * (P.sq + P.sk * R) : R - P.msh;
+  // NSE: f_bar = f_eq minus the distribution of raw moments (cS S, fh F, 0)
+  // (Hermite second order -cs^2 cS S); the F route: F/2 with M0F = S
+  const double msh = P.cS * Sm;
+  const double r0 = MODEL == kNcde ? R - P.sinit * (P.sq + P.sk * R) : R - msh;
   if constexpr (MODEL != kNcde && MODEL != kCde)
-    for (int a = 0; a < D; ++a) d2n[a] += P.msh * P.cs2 * P.in2n[a];
+    for (int a = 0; a < D; ++a) d2n[a] += msh * P.cs2 * P.in2n[a];
   const double d0 = r0 * P.in0 - P.rho_ref;
   backward<L>(x, P, 0.0, P.w, d0, d1, d2n, d2o, d3m, d3p, dxyz);
   const KParams<Real>& PR = J.P;
@@ -1183,7 +1254,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(const Job<typename StoreT<ST>
         for (int a = 0; a < D; ++a) out1[(size_t)a * N + self] = (double)J.force[(size_t)a * N + self];
       return;
     }
-    if constexpr (MODEL != kNcde) R += P.msh;
+    if constexpr (MODEL != kNcde)
+      if (J.force) R += P.cS * (P.sfield ? (double)J.force[(size_t)D * N + self] : P.msrc);
     out0[self] = MODEL == kNcde ? (R + P.sqh) * P.sci : R;
     if (out1) {
       if constexpr (MODEL == kNcde) {

@@ -19,7 +19,9 @@ constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
 
 // kFP32DevF64: FP32 deviations in HBM, FP64 arithmetic in the kernels.
 enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4, kI16Dev = 5, kFP32DevF64 = 6 };
-enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2, kCde = 3 };
+// kNseGrad: the NSE kernels with the gradient form of M2G_bar (lagged
+// differences of the previous step's rho and rho u, stored per node).
+enum ModelKind { kNseInc = 0, kNseComp = 1, kNcde = 2, kCde = 3, kNseGrad = 4 };
 
 // Per-solve constants of the collision, in the compute precision.  Row
 // constants refer to the component-form Hermite rows of order <= 3.
@@ -68,20 +70,24 @@ struct KParams {
   // (sa, sp) = (1, 0), sinit = 1/2; three-level: sqh = 0, sci = 1,
   // (sa, sp) = (3/2, -1/2), sinit = 0.  No source: all terms vanish.
   Real sq, sk, sqh, sci, sa, sp, sinit;
-  // NSE_COMP mass source S (forced kernel only): the zeroth moment gains S,
-  // the second-order source gains -uu S.  NSE body force F and mass source
-  // divided between G (share g, corrected with lambda2 and lambda1) and F
-  // (eq. M-NSEs-2), h = 1 for the shifted f_bar and 0 for the three-level
-  // scheme's unshifted f: rho = sum f + msh, msh = S (g lambda1 + (1-g) h)/2,
-  // and rho u = sum c f + fh F, fh = (g lambda2 + (1-g) h)/2 (eqs. 2-4-0,
-  // 2-4-2); the first moment gains g1 F with g1 = 1 - s1 fh (NCDE: the
-  // factor 1 - s1/2 of M1G), plus hf (F - F_prev) on the step after a force
-  // change (three-level scheme, hf = (1-g)/2); the normal second-order rows
-  // gain x2n = cs^2 (S2 I)_a (msh - S/2), the S20 share of M2G (eq.
-  // M-NSEs-4-0) and of the source distribution's -cs^2 S_F I.
-  Real msrc, msh;
-  Real fh, g1, hf;
-  Real x2n[3];
+  // NSE mass source S (forced kernel only): the uniform msrc, or per node
+  // the plane d of the force buffer when sfield is set.  The zeroth moment
+  // gains S, the second-order source gains -uu S.  NSE body force F and mass
+  // source divided between G (share g, corrected with lambda2 and lambda1)
+  // and F (eq. M-NSEs-2), h = 1 for the shifted f_bar and 0 for the
+  // three-level scheme's unshifted f: rho = sum f + cS S with
+  // cS = (g lambda1 + (1-g) h)/2, and rho u = sum c f + fh F with
+  // fh = (g lambda2 + (1-g) h)/2 (eqs. 2-4-0, 2-4-2); the first moment gains
+  // g1 F with g1 = 1 - s1 fh (NCDE: the factor 1 - s1/2 of M1G), plus
+  // hf (F - F_prev) on the step after a force change (three-level scheme,
+  // hf = (1-g)/2; the zeroth moment likewise hf (S - S_prev)); the normal
+  // second-order rows gain kx2_a S with kx2_a = cs^2 (S2 I)_a (cS - 1/2),
+  // the S20 share of M2G (eq. M-NSEs-4-0) and of the source distribution's
+  // -cs^2 S_F I.
+  Real msrc;
+  int sfield;
+  Real cS, fh, g1, hf;
+  Real kx2[3];
   // velocity set at run time (read by the user-supplied-lattice kernels)
   int cb;                    // b
   int8_t ce[kMaxB][3];       // integer velocity multiples e_j
@@ -103,8 +109,8 @@ struct Job {
   void* fout;               // populations at t + 1
   const Real* force;        // d x N, or nullptr (CDE: the velocity field)
   const Real* fprev;        // NSE three-level: the force before the last change, else nullptr
-  const Real* phi_prev;     // NCDE: phi^{n-1}
-  Real* phi_out;            // NCDE: phi^n
+  const Real* phi_prev;     // NCDE: phi^{n-1}; NSE gradient form: rho^{n-1} (rho_bar), then rho u^{n-1} (compressible)
+  Real* phi_out;            // NCDE: phi^n; NSE gradient form: the same fields at step n
   int* sat;                 // int16 storage: set to 1 when a value saturates
   const void* mtab;         // MFMA transform: operand tables (16 KB), or nullptr
   uint32_t block_begin;     // first linear workgroup of this job

@@ -18,6 +18,8 @@ hipError_t launch_lattice(const LaunchReq& r) {
     const auto* PD = static_cast<const KParams<double>*>(r.pd);
     const bool ncde = r.model == kNcde;
     const bool cde = r.model == kCde;
+    // the gradient form of M2G_bar is built for the FP32 and FP64 storages
+    constexpr bool kGradBuilt = ST == kFP64 || ST == kFP32 || ST == kFP32Dev || ST == kFP32DevF64;
     switch (r.op) {
       case kOpStep: {
         // Several nodes per thread are built only where the host picks them:
@@ -43,7 +45,17 @@ hipError_t launch_lattice(const LaunchReq& r) {
             launched = true;
           }
         };
-        if (r.transform == 1) {
+        if (r.m2g) {
+          if constexpr (kGradBuilt) {
+            if (!ncde && !cde && r.vec == 1) {
+              if (r.force)
+                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, true, 1>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              else
+                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, false, 1>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              launched = true;
+            }
+          }
+        } else if (r.transform == 1) {
           // MFMA transforms: 3D lattices, int16 storage, the NSE models without a force field
           if constexpr (L::D == 3 && ST == kI16Dev) {
             if (!ncde && !cde && !r.force) {
@@ -62,7 +74,13 @@ hipError_t launch_lattice(const LaunchReq& r) {
         break;
       }
       case kOpInit:
-        if (ncde) {
+        if (r.m2g) {
+          if constexpr (kGradBuilt) {
+            hipLaunchKernelGGL((k_init<L, ST, kNseGrad>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
+          } else {
+            return;
+          }
+        } else if (ncde) {
           hipLaunchKernelGGL((k_init<L, ST, kNcde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);
         } else if (cde) {
           hipLaunchKernelGGL((k_init<L, ST, kCde>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2, r.blocks);

@@ -99,6 +99,15 @@ def test_footprint():
     b16 = H.footprint(lat, (4096, 4096), "fp16_dev", "NSE_INC")
     assert b32 >= 2 * 25 * 4 * 4096 * 4096
     assert b16 < 0.51 * b32
+    # the gradient form of M2G keeps two slots of rho, rho u (compressible)
+    # or rho_bar (incompressible) per node
+    n = 64 * 64
+    bf = H.footprint(lat, (64, 64), "fp32", "NSE_COMP", has_force=True)
+    assert H.footprint(lat, (64, 64), "fp32", "NSE_COMP", has_force=True, m2g_form=1) - bf == 2 * 3 * n * 4
+    assert H.footprint(lat, (64, 64), "fp64", "NSE_INC", m2g_form=1) - H.footprint(lat, (64, 64), "fp64", "NSE_INC") \
+        == 2 * n * 8
+    # a forced solve reserves d + 1 node fields: the force and a mass-source field
+    assert bf - H.footprint(lat, (64, 64), "fp32", "NSE_COMP") == 3 * n * 4
 
 
 def _header_struct_fields(name):
