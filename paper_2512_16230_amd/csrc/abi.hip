@@ -46,6 +46,10 @@ static mrtlb_status fail(mrtlb_status st, const std::string& msg) {
 
 using namespace mrtlb;
 
+// side streams of one context for overlapping lattice groups (the box runs
+// 4 hardware queues per process: the context stream and 3 side streams)
+constexpr int kSideStreams = 3;
+
 struct mrtlb_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -59,6 +63,11 @@ struct mrtlb_ctx {
   size_t job_cap = 0;
   // device address of this GPU's scratch array (mrtlb_conserved_noalloc)
   void* scratch = nullptr;
+  // side streams of mrtlb_batch_step (created on first use, default
+  // priority): each runs one lattice group; events join them to `stream`
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t side_done[kSideStreams] = {};
+  hipEvent_t staged = nullptr;
 };
 
 struct mrtlb_lattice {
@@ -535,6 +544,12 @@ void mrtlb_ctx_destroy(mrtlb_ctx* c) {
   if (c->job_host) (void)hipHostFree(c->job_host);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (int i = 0; i < kSideStreams; ++i) {
+    if (c->side[i]) (void)hipStreamSynchronize(c->side[i]);
+    if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
+    if (c->side_done[i]) (void)hipEventDestroy(c->side_done[i]);
+  }
+  if (c->staged) (void)hipEventDestroy(c->staged);
   delete c;
 }
 
@@ -1328,73 +1343,174 @@ static mrtlb_status reserve_jobs(mrtlb_ctx* c, size_t bytes) {
 
 // One group (same lattice, storage, model, force, nodes per thread).  Members
 // are ordered by decreasing step count, so the solves still running at step
-// k form a prefix of the job table: launch k covers jobs [0, m_k).  The call
-// runs in segments that end where a member with drift correction is due for
-// its FP64 check (one segment without drift correction).  Per segment three
-// tables are uploaded: the first launch (pending corrections applied) and
-// one per parity of the ping-pong buffers for the later launches.
+// k form a prefix of the job table: launch k covers jobs [0, m_k).  A
+// segment of launches uses three job tables: the first launch (pending
+// corrections and force history applied) and one per parity of the
+// ping-pong buffers for the later launches.
+using Group = std::vector<std::pair<mrtlb_solve*, int64_t>>;
+
+static std::vector<uint32_t> group_prefix(const Group& g) {
+  std::vector<uint32_t> prefix(g.size() + 1, 0);
+  for (size_t i = 0; i < g.size(); ++i) prefix[i + 1] = prefix[i] + g[i].first->nblocks;
+  return prefix;
+}
+
+// Steps of the group's next segment: up to the first member due for its FP64
+// drift check.
+static int64_t group_segment(const Group& g, int64_t done) {
+  int64_t seg = g[0].second - done;
+  for (const auto& m : g) {
+    const mrtlb_solve& s = *m.first;
+    if (s.drift_every > 0 && m.second > done) seg = std::min(seg, s.drift_every - s.since_check);
+  }
+  return seg;
+}
+
 template <class Real>
-static mrtlb_status batch_group(std::vector<std::pair<mrtlb_solve*, int64_t>>& g) {
+static void stage_group(const Group& g, const std::vector<uint32_t>& prefix, Job<Real>* jobs) {
+  const size_t n = g.size();
+  for (size_t i = 0; i < n; ++i) {
+    const mrtlb_solve& s = *g[i].first;
+    const KParams<Real>& P = *reinterpret_cast<const KParams<Real>*>(is_double(s.storage) ? (const void*)&s.Pd
+                                                                                          : (const void*)&s.Pf);
+    Job<Real> J0 = make_job(s, s.cur, with_drift(s, P));
+    if (s.hist_pending) J0.fprev = static_cast<const Real*>(s.fprev);
+    J0.block_begin = prefix[i];
+    jobs[i] = J0;
+    for (int par = 0; par < 2; ++par) {
+      Job<Real> J = make_job(s, s.cur ^ par, P);
+      J.block_begin = prefix[i];
+      jobs[(size_t)(1 + par) * n + i] = J;
+    }
+  }
+}
+
+// Launches of steps [done, done + seg) of the group on `stream`, job tables at `table_dev`.
+template <class Real>
+static mrtlb_status launch_group(const Group& g, const std::vector<uint32_t>& prefix, const void* table_dev,
+                                 int64_t done, int64_t seg, hipStream_t stream) {
+  const size_t n = g.size();
+  int m = (int)n;
+  for (int64_t k = 0; k < seg; ++k) {
+    while (m > 0 && g[m - 1].second <= done + k) --m;
+    const size_t table = k == 0 ? 0 : 1 + (size_t)(k & 1);
+    const void* jp = static_cast<const char*>(table_dev) + table * n * sizeof(Job<Real>);
+    LaunchReq r = base_req(*g[0].first, kOpStep, jp);
+    r.njobs = m;
+    r.blocks = prefix[m];
+    r.stream = stream;
+    hipError_t e = dispatch(g[0].first->L.kind, r);
+    if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+  }
+  return MRTLB_OK;
+}
+
+// Host state after a segment has run (the stream synchronized): parities,
+// step counts, and the FP64 drift checks that fall due.
+static mrtlb_status finish_segment(const Group& g, int64_t done, int64_t seg) {
+  for (const auto& m : g) {
+    mrtlb_solve* s = m.first;
+    const int64_t adv = std::max<int64_t>(0, std::min(m.second, done + seg) - done);
+    if (adv == 0) continue;
+    s->pending = false;
+    s->hist_pending = false;
+    s->cur ^= (int)(adv & 1);
+    s->steps += adv;
+    if (s->drift_every > 0 && (s->since_check += adv) >= s->drift_every) {
+      mrtlb_status r2 = drift_check(s);
+      if (r2 != MRTLB_OK) return r2;
+    }
+  }
+  return MRTLB_OK;
+}
+
+// A group on the context stream, segment by segment.
+template <class Real>
+static mrtlb_status batch_group(Group& g) {
   std::stable_sort(g.begin(), g.end(), [](const auto& a, const auto& b) { return a.second > b.second; });
-  const int n = (int)g.size();
   mrtlb_ctx* c = g[0].first->ctx;
-  mrtlb_status rs = reserve_jobs(c, 3 * (size_t)n * sizeof(Job<Real>));
+  const size_t n = g.size();
+  mrtlb_status rs = reserve_jobs(c, 3 * n * sizeof(Job<Real>));
   if (rs != MRTLB_OK) return rs;
   hipStream_t st = c->stream;
-  std::vector<uint32_t> prefix(n + 1, 0);
-  for (int i = 0; i < n; ++i) prefix[i + 1] = prefix[i] + g[i].first->nblocks;
+  const std::vector<uint32_t> prefix = group_prefix(g);
   const int64_t total = g[0].second;
   int64_t done = 0;
   while (done < total) {
-    int64_t seg = total - done;
-    for (int i = 0; i < n; ++i) {
-      const mrtlb_solve& s = *g[i].first;
-      if (s.drift_every > 0 && g[i].second > done) seg = std::min(seg, s.drift_every - s.since_check);
-    }
+    const int64_t seg = group_segment(g, done);
     // the previous segment's copy out of the staging buffer has completed:
     // every segment ends with a stream synchronization
-    Job<Real>* jobs = static_cast<Job<Real>*>(c->job_host);
-    for (int i = 0; i < n; ++i) {
-      const mrtlb_solve& s = *g[i].first;
-      const KParams<Real>& P = *reinterpret_cast<const KParams<Real>*>(is_double(s.storage) ? (const void*)&s.Pd
-                                                                                            : (const void*)&s.Pf);
-      Job<Real> J0 = make_job(s, s.cur, with_drift(s, P));
-      if (s.hist_pending) J0.fprev = static_cast<const Real*>(s.fprev);
-      J0.block_begin = prefix[i];
-      jobs[i] = J0;
-      for (int par = 0; par < 2; ++par) {
-        Job<Real> J = make_job(s, s.cur ^ par, P);
-        J.block_begin = prefix[i];
-        jobs[(size_t)(1 + par) * n + i] = J;
-      }
-    }
-    HIP_TRY(hipMemcpyAsync(c->job_dev, jobs, 3 * (size_t)n * sizeof(Job<Real>), hipMemcpyHostToDevice, st));
-    int m = n;
-    for (int64_t k = 0; k < seg; ++k) {
-      while (m > 0 && g[m - 1].second <= done + k) --m;
-      const size_t table = k == 0 ? 0 : 1 + (size_t)(k & 1);
-      const void* jp = static_cast<const char*>(c->job_dev) + table * n * sizeof(Job<Real>);
-      LaunchReq r = base_req(*g[0].first, kOpStep, jp);
-      r.njobs = m;
-      r.blocks = prefix[m];
-      hipError_t e = dispatch(g[0].first->L.kind, r);
-      if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
-    }
+    stage_group<Real>(g, prefix, static_cast<Job<Real>*>(c->job_host));
+    HIP_TRY(hipMemcpyAsync(c->job_dev, c->job_host, 3 * n * sizeof(Job<Real>), hipMemcpyHostToDevice, st));
+    rs = launch_group<Real>(g, prefix, c->job_dev, done, seg, st);
+    if (rs != MRTLB_OK) return rs;
     HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < n; ++i) {
-      mrtlb_solve* s = g[i].first;
-      const int64_t adv = std::max<int64_t>(0, std::min(g[i].second, done + seg) - done);
-      if (adv == 0) continue;
-      s->pending = false;
-      s->hist_pending = false;
-      s->cur ^= (int)(adv & 1);
-      s->steps += adv;
-      if (s->drift_every > 0 && (s->since_check += adv) >= s->drift_every) {
-        mrtlb_status r2 = drift_check(s);
-        if (r2 != MRTLB_OK) return r2;
-      }
-    }
+    rs = finish_segment(g, done, seg);
+    if (rs != MRTLB_OK) return rs;
     done += seg;
+  }
+  return MRTLB_OK;
+}
+
+static size_t table_bytes(const Group& g) {
+  const size_t job = is_double(g[0].first->storage) ? sizeof(Job<double>) : sizeof(Job<float>);
+  return (3 * g.size() * job + 255) / 256 * 256;
+}
+
+// Groups that run in one segment (no drift check due inside the call), each
+// on a side stream of the context so that their launches overlap on the
+// device: one copy stages every group's job tables, an event releases the
+// side streams after it, and the context stream waits for every group's
+// last launch.
+static mrtlb_status batch_concurrent(mrtlb_ctx* c, std::vector<Group>& groups) {
+  size_t bytes = 0;
+  std::vector<size_t> off;
+  for (auto& g : groups) {
+    std::stable_sort(g.begin(), g.end(), [](const auto& a, const auto& b) { return a.second > b.second; });
+    off.push_back(bytes);
+    bytes += table_bytes(g);
+  }
+  mrtlb_status rs = reserve_jobs(c, bytes);
+  if (rs != MRTLB_OK) return rs;
+  if (!c->side[0]) {
+    for (int i = 0; i < kSideStreams; ++i) {
+      HIP_TRY(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&c->side_done[i], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
+  }
+  std::vector<std::vector<uint32_t>> prefix;
+  for (size_t k = 0; k < groups.size(); ++k) {
+    prefix.push_back(group_prefix(groups[k]));
+    char* host = static_cast<char*>(c->job_host) + off[k];
+    if (is_double(groups[k][0].first->storage))
+      stage_group<double>(groups[k], prefix.back(), reinterpret_cast<Job<double>*>(host));
+    else
+      stage_group<float>(groups[k], prefix.back(), reinterpret_cast<Job<float>*>(host));
+  }
+  HIP_TRY(hipMemcpyAsync(c->job_dev, c->job_host, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->staged, c->stream));
+  bool used[kSideStreams] = {};
+  for (size_t k = 0; k < groups.size(); ++k) {
+    const int si = (int)(k % kSideStreams);
+    hipStream_t st = c->side[si];
+    if (!used[si]) HIP_TRY(hipStreamWaitEvent(st, c->staged, 0));
+    used[si] = true;
+    const void* dev = static_cast<const char*>(c->job_dev) + off[k];
+    const int64_t total = groups[k][0].second;
+    rs = is_double(groups[k][0].first->storage) ? launch_group<double>(groups[k], prefix[k], dev, 0, total, st)
+                                                 : launch_group<float>(groups[k], prefix[k], dev, 0, total, st);
+    if (rs != MRTLB_OK) return rs;
+  }
+  for (int si = 0; si < kSideStreams; ++si) {
+    if (!used[si]) continue;
+    HIP_TRY(hipEventRecord(c->side_done[si], c->side[si]));
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->side_done[si], 0));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& g : groups) {
+    rs = finish_segment(g, 0, g[0].second);
+    if (rs != MRTLB_OK) return rs;
   }
   return MRTLB_OK;
 }
@@ -1413,9 +1529,10 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
   // group by (lattice kind, storage, model, force, nodes per thread) in order
   // of first appearance; solves with nsteps == 0 are left alone
   std::vector<int> done(n, 0);
+  std::vector<Group> groups;
   for (int i = 0; i < n; ++i) {
     if (done[i] || nsteps[i] == 0) continue;
-    std::vector<std::pair<mrtlb_solve*, int64_t>> grp;
+    Group grp;
     const mrtlb_solve* a = solves[i];
     for (int k = i; k < n; ++k) {
       const mrtlb_solve* b = solves[k];
@@ -1428,7 +1545,29 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
         done[k] = 1;
       }
     }
-    mrtlb_status st = is_double(a->storage) ? batch_group<double>(grp) : batch_group<float>(grp);
+    groups.push_back(std::move(grp));
+  }
+  // Several groups whose launches run in one segment overlap on side
+  // streams; the rest (and a single group) run on the context stream.
+  // MRTLB_BATCH_OVERLAP=0 runs every group on the context stream (A/B runs).
+  const char* ov = std::getenv("MRTLB_BATCH_OVERLAP");
+  const bool overlap = !(ov && ov[0] == '0');
+  std::vector<Group> together, alone;
+  for (auto& g : groups) {
+    int64_t total = 0;
+    for (const auto& m : g) total = std::max(total, m.second);
+    int64_t seg = total;
+    for (const auto& m : g)
+      if (m.first->drift_every > 0) seg = std::min(seg, m.first->drift_every - m.first->since_check);
+    (overlap && seg >= total ? together : alone).push_back(std::move(g));
+  }
+  if (together.size() == 1) alone.insert(alone.begin(), std::move(together[0]));
+  if (together.size() > 1) {
+    mrtlb_status st = batch_concurrent(solves[0]->ctx, together);
+    if (st != MRTLB_OK) return st;
+  }
+  for (auto& g : alone) {
+    mrtlb_status st = is_double(g[0].first->storage) ? batch_group<double>(g) : batch_group<float>(g);
     if (st != MRTLB_OK) return st;
   }
   return MRTLB_OK;

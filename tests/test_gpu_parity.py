@@ -514,6 +514,45 @@ def test_batch_equals_single_new_models(ctx):
                 assert np.array_equal(a.read_populations(), b.read_populations())
 
 
+@pytest.mark.parametrize("overlap", ["1", "0"], ids=["side-streams", "one-stream"])
+def test_mixed_batch_groups_equal_solo(ctx, overlap, monkeypatch):
+    """A batch that mixes lattices, models and storages runs as several
+    groups: on side streams that overlap on the device (the default), or one
+    after another on the context stream.  Either way each solve ends bit for
+    bit where it ends stepped alone, with drift correction on one member
+    (its group then runs on the context stream, in segments)."""
+    monkeypatch.setenv("MRTLB_BATCH_OVERLAP", overlap)
+    members = []
+    for i, (card, shape, eq, storage) in enumerate([(W.Q25_RECT, (40, 96), "NSE_INC", "fp32"),
+                                                    (W.Q13_SQUARE, (64, 48), "NCDE", "fp32"),
+                                                    (W.Q33_CUBIC, (12, 10, 40), "NSE_COMP", "fp32"),
+                                                    (W.Q25_RECT, (24, 70), "NSE_COMP", "fp64"),
+                                                    (W.Q9_RECT, (30, 64), "NSE_INC", "fp32_dev")]):
+        if eq == "NCDE":
+            wl = W.ncde_hill(shape, adv_u=(0.02, -0.01), D0=0.1, D2=1.0)
+            kw, r, u = dict(D0=wl.D0, D2=wl.D2, adv=wl.adv_u), wl.rho_or_phi, None
+        else:
+            kw = dict(m30=card.kind not in ("D2Q9", "D3Q27"))
+            r, u = _random_fields(card, shape, 50 + i)
+        members.append((card, shape, eq, storage, kw, r, u))
+    counts = [7, 11, 5, 9, 3]
+    solo, batch = [], []
+    for card, shape, eq, storage, kw, r, u in members:
+        for lst in (solo, batch):
+            s = H.Solve(ctx, hip_lattice(card), hip_model(eq, W.rates_tau(0.8), **kw), shape, storage)
+            s.init_fields(r, u)
+            lst.append(s)
+    for s in (solo[3], batch[3]):
+        s.set_drift_correction(4)
+    for s, k in zip(solo, counts):
+        s.step(k)
+    H.batch_step(batch, counts)
+    for a, b in zip(solo, batch):
+        assert np.array_equal(a.read_populations(), b.read_populations())
+    for s in solo + batch:
+        s.close()
+
+
 def _shuffled_set(card, seed):
     from oracle import lattice as OL
     lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
