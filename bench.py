@@ -43,10 +43,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage, launch_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_step_rD2Q25_%s_4096x4096_traffic.json" % storage)
+def measured_traffic(kind, storage, shape, launch_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this lattice, storage and grid, if it was taken on the current kernel
+    source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_step_%s_%s_%s_traffic.json" % (kind, storage, shape))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -138,7 +139,8 @@ def bench_tgv3d(torch, H, W, stream, args):
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
     md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                      m30=card.kind not in STANDARD, mass_src=args.mass_src, **_bounds(W, args.storage, wl))
+                      m30=card.kind not in STANDARD, mass_src=args.mass_src, m2g_form=1 if args.m2g else 0,
+                      **_bounds(W, args.storage, wl))
     forced = args.mass_src != 0          # the mass source runs in the forced kernel (zero force field)
     s = H.Solve(ctx, lat, md, shape, args.storage, has_force=forced)
     if args.transform != "valu":
@@ -153,15 +155,23 @@ def bench_tgv3d(torch, H, W, stream, args):
     wall = time.perf_counter() - t0
     nodes = n ** 3
     bq = {"rD3Q53": 53, "rD3Q45": 45, "rD3Q33": 33, "D3Q27": 27}[card.kind]
-    launch_bytes = (2 * bq * STORE_BYTES[args.storage] + (3 * 4 if forced else 0)) * nodes
-    out = _line("%s MRT-LB MLUPS (fused collide-and-stream%s%s), %% of HBM roofline"
+    real = 8 if args.storage in ("fp64", "fp32_dev_f64") else 4
+    # per node: b populations read and written, the force field read when
+    # forced, and with the gradient form of M2G the history read and written
+    # (rho and rho u of the compressible model)
+    launch_bytes = (2 * bq * STORE_BYTES[args.storage] + (3 * real if forced else 0)
+                    + (2 * 4 * real if args.m2g else 0)) * nodes
+    out = _line("%s MRT-LB MLUPS (fused collide-and-stream%s%s%s), %% of HBM roofline"
                 % (card.kind, ", mass source" if forced else "",
-                   ", Hermite transforms on MFMA" if args.transform == "mfma" else ""),
+                   ", Hermite transforms on MFMA" if args.transform == "mfma" else "",
+                   ", gradient form of M2G" if args.m2g else ""),
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
                 {"workload": "tgv3d-%s-%dx%dx%d" % (card.kind, n, n, n), "lattice": card.kind,
                  "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes,
-                 "transform": args.transform},
+                 "transform": args.transform, "m2g_form": 1 if args.m2g else 0},
                 args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
+    if not forced and not args.m2g and args.transform == "valu":
+        out["roofline"]["traffic"] = measured_traffic(card.kind, args.storage, "%dx%dx%d" % (n, n, n), launch_bytes)
     s.close()
     ctx.close()
     return out
@@ -296,6 +306,8 @@ def main():
                     help="ncde-batch: general NCDE terms (gn_bt, gn_dd), a source and the three-level scheme")
     ap.add_argument("--mass-src", type=float, default=0.0,
                     help="tgv3d: compressible NSE with this uniform mass source (forced kernel)")
+    ap.add_argument("--m2g", action="store_true",
+                    help="tgv2d / tgv3d: the gradient form of the auxiliary second moment M2G (m2g_form = 1)")
     ap.add_argument("--custom", action="store_true",
                     help="tgv2d: run the lattice's velocity set as a user-supplied (run-time) lattice")
     ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33", "D3Q27"],
@@ -407,7 +419,7 @@ def bench_tgv2d(torch, H, W, stream, args):
         q = lat.query()
         lat = H.Lattice("custom", card.c, card.cs2, e=q["e"], w=q["w"])
     md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
-                      m30=card.kind not in STANDARD, **_bounds(W, args.storage, wl))
+                      m30=card.kind not in STANDARD, m2g_form=1 if args.m2g else 0, **_bounds(W, args.storage, wl))
     s = H.Solve(ctx, lat, md, shape, args.storage)
     s.init_fields(wl.rho_or_phi, wl.u)
     del wl
@@ -420,13 +432,16 @@ def bench_tgv2d(torch, H, W, stream, args):
     mass, _ = s.conserved()
     nodes = shape[0] * shape[1]
     b = {"rD2Q25": 25, "rD2Q21": 21, "D2Q21K": 21, "D2Q9": 9}[card.kind]
-    launch_bytes = 2 * b * STORE_BYTES[args.storage] * nodes
+    real = 8 if args.storage in ("fp64", "fp32_dev_f64") else 4
+    # the gradient form of M2G (incompressible) reads and writes rho_bar per node
+    launch_bytes = (2 * b * STORE_BYTES[args.storage] + (2 * real if args.m2g else 0)) * nodes
     per_launch_s = kernel_ms / 1e3 / args.steps
     achieved = launch_bytes / per_launch_s / 1e9
     value = nodes * args.steps / wall / 1e6
     out = {
-        "metric": "%s%s MRT-LB MLUPS (fused collide-and-stream), %% of HBM roofline"
-                  % (card.kind, " as a user-supplied lattice" if args.custom else ""),
+        "metric": "%s%s MRT-LB MLUPS (fused collide-and-stream%s), %% of HBM roofline"
+                  % (card.kind, " as a user-supplied lattice" if args.custom else "",
+                     ", gradient form of M2G" if args.m2g else ""),
         "value": round(value, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -441,11 +456,12 @@ def bench_tgv2d(torch, H, W, stream, args):
         "config": {"workload": "tgv-%s-%dx%d" % (card.kind, shape[1], shape[0]),
                    "lattice": card.kind + (" (user-supplied)" if args.custom else ""),
                    "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes,
-                   "tau_shear": 0.6, "mass_check": mass},
+                   "tau_shear": 0.6, "m2g_form": 1 if args.m2g else 0, "mass_check": mass},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (measured_traffic(args.storage, launch_bytes)
-                                 if card.kind == "rD2Q25" and not args.custom else None),
+                     "traffic": (measured_traffic(card.kind, args.storage, "%dx%d" % (shape[1], shape[0]),
+                                                  launch_bytes)
+                                 if not args.custom and not args.m2g else None),
                      "kernel_ms_per_launch": round(per_launch_s * 1e3, 5),
                      "algorithmic_bytes_per_launch": launch_bytes},
     }
