@@ -57,7 +57,7 @@ def measured_traffic(kind, storage, shape, launch_bytes):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(sample_shape=(512, 512), steps=100):
+def cpu_baseline(sample_shape=(512, 512), steps=300):
     """The FP64 oracle on a bounded sample of the same workload, timed with
     the host's BLAS threads and again with one thread."""
     from oracle import lattice as OL
@@ -400,7 +400,10 @@ def other_legs(torch, H, W, stream, args):
     print("leg: served stream %.1f requests/s (capacity %.1f), %d requests" % (low, cap or 0, a.requests),
           file=sys.stderr, flush=True)
     line = keep(bench_serve(stream, a))
+    # this window's own MLUPS include idle time, so its load is stated
+    # against the capacity the saturated window measured
     line["measured_capacity_per_s"] = round(cap, 1) if cap else None
+    line["load_vs_capacity"] = round(low / cap, 3) if cap else None
     legs["serve-0.8-capacity"] = line
     return legs
 
