@@ -253,9 +253,9 @@ static hipError_t launch_custom_dim(const LaunchReq& r) {
       case kOpStep:
         if (r.vec != 1) return;
         if (r.force)
-          hipLaunchKernelGGL((k_step_custom<DIM, ST, true>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+          hipLaunchKernelGGL((k_step_custom<DIM, ST, true>), grid, block, 0, r.stream, J, r.njobs, r.xcd_order ? r.blocks : 0u);
         else
-          hipLaunchKernelGGL((k_step_custom<DIM, ST, false>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+          hipLaunchKernelGGL((k_step_custom<DIM, ST, false>), grid, block, 0, r.stream, J, r.njobs, r.xcd_order ? r.blocks : 0u);
         break;
       case kOpInit:
         hipLaunchKernelGGL((k_init_custom<DIM, ST>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2);

@@ -990,7 +990,7 @@ __device__ __forceinline__ void collide_node(typename StoreT<ST>::Real (&x)[L::B
 // j >= 1 at a wave-uniform base (soffset) plus a lane offset that depends on
 // the source row only (RowGeom); at the periodic x-edges the wrapped
 // elements are loaded one by one with one lane offset per distinct e_x.
-template <class L, int ST, int VEC>
+template <class L, int ST, int VEC, bool UNIROW>
 __device__ __forceinline__ void gather(const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix0,
                                        typename StoreT<ST>::T (&raw)[L::B][VEC]) {
   using T = typename StoreT<ST>::T;
@@ -1002,13 +1002,29 @@ __device__ __forceinline__ void gather(const Job<typename StoreT<ST>::Real>& J, 
   // one node per lane: a wave-uniform choice, so no wave runs both paths
   const bool inside = ix0 >= M && ix0 + VEC - 1 + M < P.nx;
   const bool interior = VEC == 1 ? __all(inside) != 0 : inside;
+  // With UNIROW the wave lies in one grid row (g built from wave-uniform
+  // y, z): every source row offset is wave-uniform and rides in soffset
+  // with the population's own uniform part, and the lane part is x alone.
+  auto split = [&](uint32_t uni, uint32_t row, uint32_t x, uint32_t& u, uint32_t& l) {
+    if constexpr (UNIROW) {
+      u = uni + row;
+      l = x;
+    } else {
+      u = uni;
+      l = row + x;
+    }
+  };
   if (interior) {
     // whole VEC-runs inside the row: the lane part depends on the row only
     const uint32_t lx = (uint32_t)(ix0 + M);
-    load_vec<ST, VEC>(rin, 0u, g.lown() + (uint32_t)ix0, raw[0]);
+    uint32_t u, l;
+    split(0u, g.lown(), (uint32_t)ix0, u, l);
+    load_vec<ST, VEC>(rin, u, l, raw[0]);
     static_for<1, B>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
-      load_vec<ST, VEC>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx, raw[j]);
+      uint32_t uj, lj;
+      split(g.template uni_src<j>(), g.template lrow<j>(), lx, uj, lj);
+      load_vec<ST, VEC>(rin, uj, lj, raw[j]);
     });
   } else {
 #pragma unroll
@@ -1017,11 +1033,15 @@ __device__ __forceinline__ void gather(const Job<typename StoreT<ST>::Real>& J, 
 #pragma unroll
       for (int e = -M; e <= M; ++e) lx[e + M] = (uint32_t)(wrap(ix0 + k - e, P.nx) + e + M);
       T one[1];
-      load_vec<ST, 1>(rin, 0u, g.lown() + (uint32_t)(ix0 + k), one);
+      uint32_t u, l;
+      split(0u, g.lown(), (uint32_t)(ix0 + k), u, l);
+      load_vec<ST, 1>(rin, u, l, one);
       raw[0][k] = one[0];
       static_for<1, B>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
-        load_vec<ST, 1>(rin, g.template uni_src<j>(), g.template lrow<j>() + lx[L::EX[j] + M], one);
+        uint32_t uj, lj;
+        split(g.template uni_src<j>(), g.template lrow<j>(), lx[L::EX[j] + M], uj, lj);
+        load_vec<ST, 1>(rin, uj, lj, one);
         raw[j][k] = one[0];
       });
     }
@@ -1053,9 +1073,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const uint32_t N = P.N;
 
-  // a1: gather along -e_j
+  // a1: gather along -e_j.  When the row pitch is a multiple of the slots
+  // of a wave, no wave crosses a grid row: the source rows are wave-uniform
+  // and their offsets are computed once per wave on the scalar unit.
   T raw[B][VEC];
-  gather<L, ST, VEC>(J, g, ix0, raw);
+  if (P.nxp % (64 * VEC) == 0) {
+    RowGeom<L> gw;
+    gw.init(__builtin_amdgcn_readfirstlane(iy), __builtin_amdgcn_readfirstlane(iz), P.nx, P.nxp, P.ny, P.nz);
+    gather<L, ST, VEC, true>(J, gw, ix0, raw);
+  } else {
+    gather<L, ST, VEC, false>(J, g, ix0, raw);
+  }
 
   // a2-a7 in registers: x holds the numbers the storage reads as, the
   // back-transform leaves the numbers it writes (equal for FP32/FP64).  The

@@ -18,6 +18,7 @@ struct LaunchReq {
   int vec = 1;               // step kernel: nodes per thread along x (1, 2, 4)
   int transform = 0;         // step kernel: Hermite transforms on VALU (0) or MFMA (1)
   bool m2g = false;          // NSE: the gradient form of M2G_bar (history fields, one node per lane)
+  bool xcd_order = true;     // step kernel: tiles in contiguous ranges per XCD (else the dispatch order)
   int dim = 2;               // lattice dimension (user-supplied lattices)
   const void* jobs = nullptr;
   int njobs = 1;

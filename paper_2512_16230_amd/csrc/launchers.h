@@ -11,6 +11,8 @@ template <class L>
 hipError_t launch_lattice(const LaunchReq& r) {
   hipError_t err = hipErrorInvalidValue;
   const dim3 grid(r.blocks), block(kBlock);
+  // a tile total of 0 leaves the dispatch order (xcd_remap is the identity)
+  const uint32_t tb = r.xcd_order ? r.blocks : 0u;
   with_storage(r.storage, [&](auto stc) {
     constexpr int ST = decltype(stc)::value;
     using Real = typename StoreT<ST>::Real;
@@ -29,19 +31,19 @@ hipError_t launch_lattice(const LaunchReq& r) {
           constexpr int V = decltype(vc)::value;
           if (ncde) {
             if constexpr (V == 1) {
-              hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, tb);
               launched = true;
             }
           } else if (cde) {
             if constexpr (V == 1) {
-              hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, tb);
               launched = true;
             }
           } else if constexpr (L::D == 2 || V == 1) {
             if (r.force)
-              hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, tb);
             else
-              hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, tb);
             launched = true;
           }
         };
@@ -49,9 +51,9 @@ hipError_t launch_lattice(const LaunchReq& r) {
           if constexpr (kGradBuilt) {
             if (!ncde && !cde && r.vec == 1) {
               if (r.force)
-                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, true, 1>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, true, 1>), grid, block, 0, r.stream, J, r.njobs, tb);
               else
-                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, false, 1>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, false, 1>), grid, block, 0, r.stream, J, r.njobs, tb);
               launched = true;
             }
           }
@@ -59,7 +61,7 @@ hipError_t launch_lattice(const LaunchReq& r) {
           // MFMA transforms: 3D lattices, int16 storage, the NSE models without a force field
           if constexpr (L::D == 3 && ST == kI16Dev) {
             if (!ncde && !cde && !r.force) {
-              hipLaunchKernelGGL((k_step_mfma<L, kNseComp>), grid, block, 0, r.stream, J, r.njobs, r.blocks);
+              hipLaunchKernelGGL((k_step_mfma<L, kNseComp>), grid, block, 0, r.stream, J, r.njobs, tb);
               launched = true;
             }
           }

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_step_mfma(const Job<float>* __restri
   {
     T raw[B][1];
     if (valid) {
-      gather<L, ST, 1>(J, g, ix, raw);
+      gather<L, ST, 1, false>(J, g, ix, raw);
     } else {
       static_for<0, B>([&](auto jj) { raw[decltype(jj)::value][0] = 0; });
     }
