@@ -108,6 +108,18 @@ def copy_probe(torch, dev, steps, warmup):
                       "GB_per_s": round(2 * 4 * n / ms / 1e6, 1)}), flush=True)
 
 
+def stream_ceiling(s, passes, pop_bytes, step_s):
+    """The solve's streaming alone (no collision: mrtlb_stream_only), timed
+    like the step on the same grid, tiles and buffers: the rate of the step
+    kernel's memory access pattern.  ``pattern_frac`` = stream time / step
+    time per launch, i.e. the step's rate as a fraction of that ceiling."""
+    s.stream_only(1)
+    ms = s.stream_only(passes, timed=True) / passes
+    gbs = pop_bytes / (ms / 1e3) / 1e9
+    return {"ms_per_pass": round(ms, 5), "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "pattern_frac": round(ms / 1e3 / step_s, 4)}
+
+
 def _bounds(W, storage, wl):
     """Flow bounds that size the int16 storage's ranges (only that storage uses them)."""
     if storage != "i16_dev":
@@ -172,6 +184,7 @@ def bench_tgv3d(torch, H, W, stream, args):
                 args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
     if not forced and not args.m2g and args.transform == "valu":
         out["roofline"]["traffic"] = measured_traffic(card.kind, args.storage, "%dx%dx%d" % (n, n, n), launch_bytes)
+        out["roofline"]["stream_only"] = stream_ceiling(s, args.steps, launch_bytes, kernel_ms / 1e3 / args.steps)
     s.close()
     ctx.close()
     return out
@@ -468,6 +481,8 @@ def bench_tgv2d(torch, H, W, stream, args):
                      "kernel_ms_per_launch": round(per_launch_s * 1e3, 5),
                      "algorithmic_bytes_per_launch": launch_bytes},
     }
+    if not args.custom and not args.m2g:
+        out["roofline"]["stream_only"] = stream_ceiling(s, args.steps, launch_bytes, per_launch_s)
     s.close()
     ctx.close()
     return out

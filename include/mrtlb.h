@@ -413,6 +413,19 @@ mrtlb_status mrtlb_step(mrtlb_solve* s, int64_t nsteps);
  * events recorded on the context stream around the launches (synchronous). */
 mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms);
 
+/* Streaming alone, a measurement aid: npasses >= 0 passes of the pull
+ * streaming of eq. (2-2), f_j(x) <- f_j(x - e_j) on the periodic grid, with
+ * no collision; every stored number moves unchanged.  Each pass runs the
+ * step kernel's tiles, gather, tile order and store policy with nothing
+ * between load and store, so its rate bounds the step kernel's on the same
+ * solve.  The step counter, drift reference, force and M2G history are left
+ * as they were: the populations afterwards are not a state of the method's
+ * time stepping.  If ms is not NULL the call returns the device time of the
+ * passes in *ms (HIP events on the context stream, synchronous); otherwise
+ * it is asynchronous.  Errors: EINVAL (NULL solve, npasses < 0, a
+ * user-supplied lattice), EDEVICE. */
+mrtlb_status mrtlb_stream_only(mrtlb_solve* s, int64_t npasses, double* ms);
+
 /* Drift correction of the conserved totals.  The collision conserves mass,
  * and momentum without a force, exactly (Sec. II, eq. M-NSEs-1); the
  * rounding of the stored populations does not.  With every > 0, after each

@@ -91,6 +91,7 @@ def lib():
         "mrtlb_init_fields": (c_int, [c_void_p, _DP, _DP, _DP]),
         "mrtlb_step": (c_int, [c_void_p, c_int64]),
         "mrtlb_step_timed": (c_int, [c_void_p, c_int64, _DP]),
+        "mrtlb_stream_only": (c_int, [c_void_p, c_int64, _DP]),
         "mrtlb_batch_step": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int64)]),
         "mrtlb_read_moments": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
@@ -117,7 +118,8 @@ def lib():
 EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_destroy", "mrtlb_ctx_memory",
             "mrtlb_ctx_synchronize", "mrtlb_lattice_create", "mrtlb_lattice_destroy", "mrtlb_lattice_query",
             "mrtlb_solve_create", "mrtlb_solve_footprint", "mrtlb_solve_destroy", "mrtlb_init_fields",
-            "mrtlb_step", "mrtlb_step_timed", "mrtlb_batch_step", "mrtlb_read_moments", "mrtlb_conserved",
+            "mrtlb_step", "mrtlb_step_timed", "mrtlb_stream_only", "mrtlb_batch_step", "mrtlb_read_moments",
+            "mrtlb_conserved",
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
             "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external",
             "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform", "mrtlb_set_velocity_field",
@@ -374,6 +376,16 @@ class Solve:
     def step_timed(self, n):
         ms = c_double()
         _check(lib().mrtlb_step_timed(self.h, int(n), byref(ms)))
+        return ms.value
+
+    def stream_only(self, n=1, timed=False):
+        """n passes of streaming alone (no collision), a measurement aid;
+        with ``timed`` returns their device time in ms."""
+        if not timed:
+            _check(lib().mrtlb_stream_only(self.h, int(n), None))
+            return None
+        ms = c_double()
+        _check(lib().mrtlb_stream_only(self.h, int(n), byref(ms)))
         return ms.value
 
     def read_moments(self, with_u=True, out=None):

@@ -445,7 +445,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.dim = s.L.D;
   r.jobs = jobs;
   r.njobs = 1;
-  r.blocks = op == kOpStep ? s.nblocks : s.nblocks_node;
+  r.blocks = (op == kOpStep || op == kOpStream) ? s.nblocks : s.nblocks_node;
   r.stream = s.ctx->stream;
   r.pd = s.pd;
   return r;
@@ -1345,6 +1345,27 @@ mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms) {
   float t = 0;
   HIP_TRY(hipEventElapsedTime(&t, s->ctx->ev0, s->ctx->ev1));
   *ms = t;
+  return MRTLB_OK;
+}
+
+mrtlb_status mrtlb_stream_only(mrtlb_solve* s, int64_t npasses, double* ms) {
+  if (!s) return fail(MRTLB_EINVAL, "solve is NULL");
+  if (npasses < 0) return fail(MRTLB_EINVAL, "npasses must be >= 0");
+  if (s->L.kind == kCustom) return fail(MRTLB_EINVAL, "streaming alone is built for the compiled lattices only");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  if (ms) HIP_TRY(hipEventRecord(s->ctx->ev0, s->ctx->stream));
+  for (int64_t k = 0; k < npasses; ++k) {
+    hipError_t e = dispatch(s->L.kind, base_req(*s, kOpStream, job_ptr(*s, s->cur)));
+    if (e != hipSuccess) return fail(MRTLB_EDEVICE, std::string("stream launch: ") + hipGetErrorString(e));
+    s->cur ^= 1;
+  }
+  if (ms) {
+    HIP_TRY(hipEventRecord(s->ctx->ev1, s->ctx->stream));
+    HIP_TRY(hipEventSynchronize(s->ctx->ev1));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, s->ctx->ev0, s->ctx->ev1));
+    *ms = t;
+  }
   return MRTLB_OK;
 }
 

@@ -1048,6 +1048,35 @@ __device__ __forceinline__ void gather(const Job<typename StoreT<ST>::Real>& J, 
   }
 }
 
+// a1 for the node run (ix0 .. ix0 + VEC - 1) of row (iy, iz).  When the row
+// pitch is a multiple of the slots of a wave, no wave crosses a grid row:
+// the source rows are wave-uniform and their offsets are computed once per
+// wave on the scalar unit.
+template <class L, int ST, int VEC>
+__device__ __forceinline__ void gather_run(const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix0,
+                                           int iy, int iz, typename StoreT<ST>::T (&raw)[L::B][VEC]) {
+  const auto& P = J.P;
+  if (P.nxp % (64 * VEC) == 0) {
+    RowGeom<L> gw;
+    gw.init(__builtin_amdgcn_readfirstlane(iy), __builtin_amdgcn_readfirstlane(iz), P.nx, P.nxp, P.ny, P.nz);
+    gather<L, ST, VEC, true>(J, gw, ix0, raw);
+  } else {
+    gather<L, ST, VEC, false>(J, g, ix0, raw);
+  }
+}
+
+// a8: VEC-wide aligned stores of the run at the own nodes
+template <class L, int ST, int VEC>
+__device__ __forceinline__ void store_run(const Job<typename StoreT<ST>::Real>& J, const RowGeom<L>& g, int ix0,
+                                          const typename StoreT<ST>::T (&raw)[L::B][VEC]) {
+  const auto rout = make_rsrc(J.fout, J.P.pop_bytes);
+  const uint32_t lo = g.lown() + (uint32_t)ix0;
+  static_for<0, L::B>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    store_vec<ST, VEC>(rout, (uint32_t)j * (uint32_t)J.P.nxp, lo, raw[j]);
+  });
+}
+
 // ---------------------------------------------------------------------------
 // the fused collide-and-stream step: every thread owns VEC consecutive nodes
 // along x.  a1: each population is gathered with one VEC-wide load from the
@@ -1062,7 +1091,6 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   using Real = typename StoreT<ST>::Real;
   using T = typename StoreT<ST>::T;
   constexpr int B = L::B;
-  constexpr int M = L::MAXE;
   const uint32_t lin = xcd_remap(blockIdx.x, total_blocks);
   const int jb = njobs > 1 ? find_job(jobs, njobs, lin) : 0;
   const Job<Real>& J = jobs[jb];
@@ -1071,19 +1099,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   if (!tile_node<VEC>(J, lin - J.block_begin, ix0, iy, iz)) return;
   RowGeom<L> g;
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
-  const uint32_t N = P.N;
 
-  // a1: gather along -e_j.  When the row pitch is a multiple of the slots
-  // of a wave, no wave crosses a grid row: the source rows are wave-uniform
-  // and their offsets are computed once per wave on the scalar unit.
+  // a1: gather along -e_j
   T raw[B][VEC];
-  if (P.nxp % (64 * VEC) == 0) {
-    RowGeom<L> gw;
-    gw.init(__builtin_amdgcn_readfirstlane(iy), __builtin_amdgcn_readfirstlane(iz), P.nx, P.nxp, P.ny, P.nz);
-    gather<L, ST, VEC, true>(J, gw, ix0, raw);
-  } else {
-    gather<L, ST, VEC, false>(J, g, ix0, raw);
-  }
+  gather_run<L, ST, VEC>(J, g, ix0, iy, iz, raw);
 
   // a2-a7 in registers: x holds the numbers the storage reads as, the
   // back-transform leaves the numbers it writes (equal for FP32/FP64).  The
@@ -1132,12 +1151,26 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job<typename StoreT<ST>::
   }
 
   // a8: store at the own nodes
-  const auto rout = make_rsrc(J.fout, P.pop_bytes);
-  const uint32_t lo = g.lown() + (uint32_t)ix0;
-  static_for<0, B>([&](auto jj) {
-    constexpr int j = decltype(jj)::value;
-    store_vec<ST, VEC>(rout, (uint32_t)j * (uint32_t)P.nxp, lo, raw[j]);
-  });
+  store_run<L, ST, VEC>(J, g, ix0, raw);
+}
+
+// Streaming alone (eq. 2-2 with no collision): every stored number moves from
+// x - e_j to x unchanged.  The step kernel's tiles, gather, tile order and
+// store policy with nothing between them, so its rate is the ceiling of the
+// step kernel's memory access pattern on the same grid.  One job.
+template <class L, int ST, int VEC>
+__global__ __launch_bounds__(kBlock) void k_stream(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
+                                                  uint32_t total_blocks) {
+  const uint32_t lin = xcd_remap(blockIdx.x, total_blocks);
+  const auto& J = jobs[0];
+  const auto& P = J.P;
+  int ix0, iy, iz;
+  if (!tile_node<VEC>(J, lin, ix0, iy, iz)) return;
+  RowGeom<L> g;
+  g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
+  typename StoreT<ST>::T raw[L::B][VEC];
+  gather_run<L, ST, VEC>(J, g, ix0, iy, iz, raw);
+  store_run<L, ST, VEC>(J, g, ix0, raw);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,7 +8,7 @@
 
 namespace mrtlb {
 
-enum LaunchOp { kOpStep = 0, kOpInit = 1, kOpMoments = 2, kOpPopulations = 3, kOpScatter = 4 };
+enum LaunchOp { kOpStep = 0, kOpInit = 1, kOpMoments = 2, kOpPopulations = 3, kOpScatter = 4, kOpStream = 5 };
 
 struct LaunchReq {
   int op = kOpStep;

@@ -105,6 +105,20 @@ hipError_t launch_lattice(const LaunchReq& r) {
       case kOpScatter:
         hipLaunchKernelGGL((k_scatter<L, ST>), grid, block, 0, r.stream, J, PD, r.in0);
         break;
+      case kOpStream:
+        // the step kernel's launch shape: VEC 2 and 4 on the 2D lattices only
+        if constexpr (L::D == 2) {
+          if (r.vec == 4)
+            hipLaunchKernelGGL((k_stream<L, ST, 4>), grid, block, 0, r.stream, J, tb);
+          else if (r.vec == 2)
+            hipLaunchKernelGGL((k_stream<L, ST, 2>), grid, block, 0, r.stream, J, tb);
+          else
+            hipLaunchKernelGGL((k_stream<L, ST, 1>), grid, block, 0, r.stream, J, tb);
+        } else {
+          if (r.vec != 1) return;
+          hipLaunchKernelGGL((k_stream<L, ST, 1>), grid, block, 0, r.stream, J, tb);
+        }
+        break;
       default:
         return;
     }
