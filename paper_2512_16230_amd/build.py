@@ -15,10 +15,11 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrtlb.so")
-# the 3D lattices compile longest and start first
-SOURCES = ["inst_rd3q53.hip", "inst_rd3q45.hip", "inst_rd3q33.hip", "inst_d3q27.hip", "abi.hip",
-           "host_lattice.cpp", "inst_common.hip", "inst_rd2q25.hip", "inst_rd2q13.hip", "inst_rd2q21.hip",
-           "inst_d2q21k.hip", "inst_d2q9.hip", "custom.hip"] + ["inst_rd2q17_%d.hip" % k for k in range(1, 6)]
+# the user-supplied-lattice kernels and the 3D lattices compile longest and
+# start first
+SOURCES = ["custom_3d.hip", "custom_2d.hip", "inst_rd3q53.hip", "inst_rd3q45.hip", "inst_rd3q33.hip",
+           "inst_d3q27.hip", "abi.hip", "host_lattice.cpp", "inst_common.hip", "inst_rd2q25.hip", "inst_rd2q13.hip",
+           "inst_rd2q21.hip", "inst_d2q21k.hip", "inst_d2q9.hip"] + ["inst_rd2q17_%d.hip" % k for k in range(1, 6)]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -363,8 +363,13 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
     P.sci = (Real)1;
   }
   P.cb = L.B;
-  for (int j = 0; j < L.B; ++j)
+  P.cmx = P.cmy = P.cmz = 0;
+  for (int j = 0; j < L.B; ++j) {
     for (int a = 0; a < 3; ++a) P.ce[j][a] = (int8_t)(a < D ? L.e[j * D + a] : 0);
+    P.cmx = std::max(P.cmx, std::abs((int)P.ce[j][0]));
+    P.cmy = std::max(P.cmy, std::abs((int)P.ce[j][1]));
+    P.cmz = std::max(P.cmz, std::abs((int)P.ce[j][2]));
+  }
   // NSE: force and mass source divided between G (share g) and F (eq.
   // M-NSEs-2); h = 1 for the shifted f_bar, 0 for the three-level scheme
   const bool nse = m.model == MRTLB_NSE_INC || m.model == MRTLB_NSE_COMP;
@@ -443,6 +448,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.m2g = s.model.m2g_form == 1;
   r.xcd_order = s.xcd_order;
   r.dim = s.L.D;
+  r.custom_b = s.L.kind == kCustom ? s.L.B : 0;
   r.jobs = jobs;
   r.njobs = 1;
   r.blocks = (op == kOpStep || op == kOpStream) ? s.nblocks : s.nblocks_node;
@@ -657,6 +663,47 @@ static mrtlb_status check_model(const mrtlb_model_desc& m, const HostLattice& L)
   return MRTLB_OK;
 }
 
+// User-supplied lattices: register class of the step kernel (b rounded up to
+// 16, 32 or 64) and the per-velocity table (weight and monomials of each
+// e_j, kCMono<D> reals per population, in the compute precision).
+static int custom_class(const HostLattice& L) {
+  return L.kind != kCustom ? 0 : L.B <= 16 ? 16 : L.B <= 32 ? 32 : 64;
+}
+static size_t custom_table_bytes(const HostLattice& L, int storage) {
+  if (L.kind != kCustom) return 0;
+  return (size_t)L.B * ((size_t)(L.D == 3 ? kCMono<3> : kCMono<2>) * (is_double(storage) ? 8 : 4) + 16);
+}
+template <class Real>
+static std::vector<char> custom_table(const HostLattice& L, int64_t ny, int64_t nxp) {
+  const int D = L.D, K = D == 3 ? kCMono<3> : kCMono<2>;
+  std::vector<Real> t((size_t)L.B * K, Real(0));
+  std::vector<uint32_t> ie((size_t)L.B * 4, 0);
+  for (int j = 0; j < L.B; ++j) {
+    for (int a = 0; a < D; ++a) ie[(size_t)j * 4 + a] = (uint32_t)L.e[j * D + a];
+    const int64_t ey = L.e[j * D + 1], ez = D == 3 ? L.e[j * D + 2] : 0;
+    ie[(size_t)j * 4 + 3] = (uint32_t)(((-ez * ny - ey) * L.B + j) * nxp);   // modulo 2^32
+    double e[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) e[a] = L.e[j * D + a];
+    Real* m = t.data() + (size_t)j * K;
+    m[0] = (Real)L.w[j];
+    for (int a = 0; a < D; ++a) {
+      m[cm_1(D, a)] = (Real)e[a];
+      m[cm_2n(D, a)] = (Real)(e[a] * e[a]);
+      m[cm_3p(D, a)] = (Real)(e[a] * e[a] * e[a]);
+      for (int c = 0; c < D; ++c) {
+        if (c == a) continue;
+        m[cm_3m(D, a, c)] = (Real)(e[a] * e[c] * e[c]);
+        if (c > a) m[cm_2o(D, a, c)] = (Real)(e[a] * e[c]);
+      }
+    }
+    if (D == 3) m[cm_xyz()] = (Real)(e[0] * e[1] * e[2]);
+  }
+  std::vector<char> out(t.size() * sizeof(Real) + ie.size() * sizeof(uint32_t));
+  std::memcpy(out.data(), t.data(), t.size() * sizeof(Real));
+  std::memcpy(out.data() + t.size() * sizeof(Real), ie.data(), ie.size() * sizeof(uint32_t));
+  return out;
+}
+
 mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3], int storage, int model,
                                    int has_force, size_t* bytes) {
   if (!lat || !n || !bytes) return fail(MRTLB_EINVAL, "NULL argument");
@@ -675,6 +722,7 @@ mrtlb_status mrtlb_solve_footprint(const mrtlb_lattice* lat, const int64_t n[3],
   if (model & MRTLB_FOOTPRINT_M2G_GRADIENT)                     // history of rho (and rho u), two slots
     b += 2 * (size_t)(kind == MRTLB_NSE_COMP ? D + 1 : 1) * (size_t)N * real;
   b += kJobsBytes + sizeof(KParams<double>);
+  b += custom_table_bytes(lat->L, storage);
   *bytes = b;
   return MRTLB_OK;
 }
@@ -778,6 +826,19 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   }
   // the CDE's velocity field lives where the NSE force field would
   if (ok && model->model == MRTLB_CDE) ok = alloc(&s->force, (size_t)D * s->N * real);
+  // a user-supplied lattice's per-velocity table rides in the jobs' table slot
+  if (ok && s->L.kind == kCustom) {
+    const size_t tb = custom_table_bytes(s->L, storage);
+    ok = alloc(&s->mtab, tb);
+    if (ok) {
+      hipError_t e = is_double(storage)
+                         ? hipMemcpy(s->mtab, custom_table<double>(s->L, s->ny, s->nxp).data(), tb,
+                                     hipMemcpyHostToDevice)
+                         : hipMemcpy(s->mtab, custom_table<float>(s->L, s->ny, s->nxp).data(), tb,
+                                     hipMemcpyHostToDevice);
+      ok = e == hipSuccess;
+    }
+  }
   if (!ok) {
     release(s);
     delete s;
@@ -1579,8 +1640,10 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
     for (int k = i; k < n; ++k) {
       const mrtlb_solve* b = solves[k];
       // one launch serves one kernel: same lattice kind and dimension (user-
-      // supplied lattices share a kind), storage, model, force and VEC
-      if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->L.D == a->L.D && b->storage == a->storage &&
+      // supplied lattices share a kind; their register class too), storage,
+      // model, force and VEC
+      if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->L.D == a->L.D &&
+          custom_class(b->L) == custom_class(a->L) && b->storage == a->storage &&
           b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec &&
           b->transform == a->transform && b->model.m2g_form == a->model.m2g_form) {
         grp.emplace_back(solves[k], nsteps[k]);

@@ -1,17 +1,19 @@
-// Kernels for a user-supplied velocity set (kind MRTLB_CUSTOM).  The
-// structured kernels are compiled per velocity set; here the set is read at
-// run time from KParams (b velocities, integer multiples e_j), so every
-// population is addressed and summed in a run-time loop.  The moment-space
-// part of the step (conserved variables, sources, equilibrium, relaxation)
-// is the same code as for the compiled lattices; the NSE models only.
-//
-// Each population is read twice per step (once for the monomial sums, once
-// for the update, the second read mostly from L2), so this path trades
-// speed for generality.  Keeping the gathered values in LDS instead
-// ([b][thread], 54 KB per workgroup for 4-byte storage) measured slower on
-// MI355X (rD2Q25 4096^2: 7.7k against 10.2k MLUPS FP32 deviations, 9.3k
-// against 10.1k int16): the LDS caps the CU at two workgroups, where the
-// kernel's 31-63 VGPRs otherwise allow eight waves per SIMD.
+// Kernels for a user-supplied velocity set (kind MRTLB_CUSTOM), included by
+// custom_2d.hip and custom_3d.hip.  The structured kernels are compiled per
+// velocity set; here the set is read at run time: the integer multiples e_j
+// from KParams, and a per-velocity table of weights and monomials
+// (kCMono<D> reals per population, built by the ABI layer) through the
+// constant address space.  The step holds the b gathered populations in
+// registers (loops unrolled to a class of 16, 32 or 64 slots and guarded by
+// the run-time b), so every population is read once and written once.  The
+// moment-space part of the step (conserved variables, sources, equilibrium,
+// relaxation) is the same code as for the compiled lattices; the NSE models
+// only.  Measured alternatives on MI355X (rD2Q25's set, 4096^2, FP32
+// deviations): a two-pass step that read every population again for the
+// update, 10.2k MLUPS; the gathered values kept in LDS ([b][thread], 54 KB
+// per workgroup, two workgroups per CU), 7.7k.
+#pragma once
+
 #include "device.h"
 
 namespace mrtlb {
@@ -58,12 +60,27 @@ __device__ __forceinline__ void velocity(const KParams<Real>& P, int j, int (&e)
 
 }  // namespace
 
-// One fused step, one node per thread over the padded rows.
-template <int DIM, int ST, bool FORCE>
+// One fused step, one node per thread over the padded rows, the b gathered
+// populations held in registers (BC >= b slots, loops unrolled to BC and
+// guarded by the run-time b).  The per-velocity table (weights and
+// monomials, kCMono<DIM> reals per population) is read through the
+// constant address space: uniform scalar loads whose values enter the
+// FMAs as scalar operands.  When the row pitch is a multiple of 64 no
+// wavefront crosses a grid row, so the source rows are computed once per
+// wavefront on the scalar unit and the lane offset is x - e_x (wrapped per
+// lane only in wavefronts that hold a periodic x-edge).
+template <class Real>
+using ConstReal = __attribute__((address_space(4))) const Real;
+using ConstU32 = __attribute__((address_space(4))) const uint32_t;
+
+template <int DIM, int ST, bool FORCE, int BC>
 __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
                                                        int njobs, uint32_t total_blocks) {
   using Real = typename StoreT<ST>::Real;
+  using T = typename StoreT<ST>::T;
   using L = LatCustom<DIM>;
+  constexpr int K = kCMono<DIM>;
+  constexpr int TB = (int)sizeof(T);
   const uint32_t lin = xcd_remap(blockIdx.x, total_blocks);
   const int jb = njobs > 1 ? find_job(jobs, njobs, lin) : 0;
   const Job<Real>& J = jobs[jb];
@@ -73,51 +90,127 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
   RowGeom<L> g;
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
   const int b = P.cb;
+  const auto* tab = (const ConstReal<Real>*)J.mtab;
+  const auto* tie = (const ConstU32*)((const char*)J.mtab + (size_t)b * K * sizeof(Real));
+  const uint32_t ny = (uint32_t)P.ny, nxp = (uint32_t)P.nxp, ub = (uint32_t)b;
+  const bool interior = __all(ix >= P.cmx && ix + P.cmx < P.nx) != 0;
 
-  // a1 + a3: monomial sums of the gathered populations (physical deviations)
+  // a1: gather (u: wave-uniform element offset in soffset, l: per lane).
+  // MODE 0: rows vary within the wavefront, all per lane; 1: one row per
+  // wavefront, y and z wrapped on the scalar unit; 2: one row per wavefront
+  // and no y or z wrap needed, the source row at a fixed offset from the own
+  // row (the table's fourth word).
+  T raw[BC];
+  const uint32_t own = ((uint32_t)iz * ny + (uint32_t)iy) * ub * nxp;
+  auto gather = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
+    const auto rin = make_rsrc(J.fin, P.pop_bytes);
+    const int wy = MODE > 0 ? __builtin_amdgcn_readfirstlane(iy) : iy;
+    const int wz = MODE > 0 ? __builtin_amdgcn_readfirstlane(iz) : iz;
+    const uint32_t wown = MODE > 0 ? (uint32_t)__builtin_amdgcn_readfirstlane(own) : own;
+#pragma unroll
+    for (int j = 0; j < BC; ++j) {
+      if (j < b) {
+        const int ex = (int)tie[4 * j];
+        uint32_t xs = (uint32_t)(ix - ex);
+        if (!interior) xs = (uint32_t)wrap(ix - ex, P.nx);
+        uint32_t u, l;
+        if constexpr (MODE == 2) {
+          u = wown + tie[4 * j + 3];
+          l = xs;
+        } else {
+          const int ey = (int)tie[4 * j + 1], ez = DIM == 3 ? (int)tie[4 * j + 2] : 0;
+          const uint32_t ys = (uint32_t)wrap(wy - ey, P.ny);
+          const uint32_t zs = DIM == 3 ? (uint32_t)wrap(wz - ez, P.nz) : 0u;
+          const uint32_t row = ((zs * ny + ys) * ub + (uint32_t)j) * nxp;
+          u = MODE == 1 ? row : 0u;
+          l = MODE == 1 ? xs : row + xs;
+        }
+        raw[j] = __builtin_bit_cast(T, buf_load<TB>(rin, l * (uint32_t)TB, u * (uint32_t)TB));
+      } else {
+        raw[j] = T(0);
+      }
+    }
+  };
+  const bool unirow = P.nxp % 64 == 0;
+  if (unirow) {
+    const int wy = __builtin_amdgcn_readfirstlane(iy), wz = __builtin_amdgcn_readfirstlane(iz);
+    const bool yz_inside = wy >= P.cmy && wy + P.cmy < P.ny && (DIM == 2 || (wz >= P.cmz && wz + P.cmz < P.nz));
+    if (yz_inside) gather(std::integral_constant<int, 2>{});
+    else gather(std::integral_constant<int, 1>{});
+  } else {
+    gather(std::integral_constant<int, 0>{});
+  }
+
+  // a3: raw moment sums of the populations (physical deviations)
   const Real z = Real(-0.0);
   Real R0 = z, R1[3] = {z, z, z}, R2n[3] = {z, z, z}, R2o[3] = {z, z, z}, R3p[3] = {z, z, z};
   Real R3m[3][3] = {{z, z, z}, {z, z, z}, {z, z, z}};
   Real Rxyz = z;
-  for (int j = 0; j < b; ++j) {
-    const Real v = load_pop<ST>(J.fin, csrc(P, j, ix, iy, iz), P, j);
-    int e[3];
-    velocity(P, j, e);
-    R0 += v;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const Real ea = (Real)e[a];
-      R1[a] += ea * v;
-      R2n[a] += ea * ea * v;
-      R3p[a] += ea * ea * ea * v;
+  for (int j = 0; j < BC; ++j) {
+    if (j < b) {
+      const Real v = decode<ST>(raw[j], P, j);
+      const auto* m = tab + j * K;
+      R0 += v;
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        if (c == a) continue;
-        R3m[a][c] += ea * (Real)(e[c] * e[c]) * v;
-        if (c > a) R2o[off_index(a, c)] += ea * (Real)e[c] * v;
+      for (int a = 0; a < DIM; ++a) {
+        R1[a] += m[cm_1(DIM, a)] * v;
+        R2n[a] += m[cm_2n(DIM, a)] * v;
+        R3p[a] += m[cm_3p(DIM, a)] * v;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          if (c == a) continue;
+          R3m[a][c] += m[cm_3m(DIM, a, c)] * v;
+          if (c > a) R2o[off_index(a, c)] += m[cm_2o(DIM, a, c)] * v;
+        }
       }
+      if constexpr (DIM == 3) Rxyz += m[cm_xyz()] * v;
     }
-    if constexpr (DIM == 3) Rxyz += (Real)(e[0] * e[1] * e[2]) * v;
   }
   Moments<Real> M;
   finish_moments<DIM, false>(P, R0, R1, R2n, R2o, R3p, R3m, Rxyz, M);
 
   // a2, a4-a6
-  Targets<Real> T;
-  relax_node<L, ST, kNseComp, FORCE>(M, J, g, ix, T);
+  Targets<Real> tg;
+  relax_node<L, ST, kNseComp, FORCE>(M, J, g, ix, tg);
 
   // a7 + a8: f* = kx f + w (sum_r H_r delta_r / n_r), stored at the own node
   BackCoeffs<Real> C;
-  back_coeffs<DIM, false>(P, T.d0, T.d1, T.d2n, T.d2o, T.d3m, T.d3p, T.dxyz, C);
-  const uint32_t own = ((uint32_t)iz * (uint32_t)P.ny + (uint32_t)iy) * (uint32_t)b * (uint32_t)P.nxp + (uint32_t)ix;
+  back_coeffs<DIM, false>(P, tg.d0, tg.d1, tg.d2n, tg.d2o, tg.d3m, tg.d3p, tg.dxyz, C);
+  Real cf[K];
+  cf[0] = C.b0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    cf[cm_1(DIM, a)] = C.b1[a];
+    cf[cm_2n(DIM, a)] = C.b2n[a];
+    cf[cm_3p(DIM, a)] = C.b3p[a];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      if (c == a) continue;
+      cf[cm_3m(DIM, a, c)] = C.b3m[a][c];
+      if (c > a) cf[cm_2o(DIM, a, c)] = C.b2o[off_index(a, c)];
+    }
+  }
+  if constexpr (DIM == 3) cf[cm_xyz()] = C.bxyz;
+  const auto rout = make_rsrc(J.fout, P.pop_bytes);
+  const uint32_t own_u = unirow ? (uint32_t)__builtin_amdgcn_readfirstlane(own) : 0u;
+  const uint32_t own_l = unirow ? (uint32_t)ix : own + (uint32_t)ix;
   float smax = 0.0f;
-  for (int j = 0; j < b; ++j) {
-    const Real v = load_pop<ST>(J.fin, csrc(P, j, ix, iy, iz), P, j);
-    int e[3];
-    velocity(P, j, e);
-    const Real out = T.kx * v + P.w[j] * poly_at<DIM>(C, e);
-    smax = fmaxf(smax, sat_of<ST>(out, P, j));
-    store_pop<ST>(J.fout, own + (uint32_t)j * (uint32_t)P.nxp, out, P, j);
+#pragma unroll
+  for (int j = 0; j < BC; ++j) {
+    if (j < b) {
+      const Real v = decode<ST>(raw[j], P, j);
+      const auto* m = tab + j * K;
+      Real poly = cf[0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) poly += m[k] * cf[k];
+      const Real out = tg.kx * v + m[0] * poly;
+      smax = fmaxf(smax, sat_of<ST>(out, P, j));
+      const T q = encode<ST>(out, P, j);
+      buf_store<TB>(rout, __builtin_bit_cast(typename RawChunk<TB>::T, q), own_l * (uint32_t)TB,
+                    (own_u + (uint32_t)j * nxp) * (uint32_t)TB);
+    }
   }
   raise_saturation<ST>(J, smax);
 }
@@ -240,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_custom(const Job<typename St
 }
 
 template <int DIM>
-static hipError_t launch_custom_dim(const LaunchReq& r) {
+hipError_t launch_custom_dim(const LaunchReq& r) {
   hipError_t err = hipErrorInvalidValue;
   const dim3 grid(r.blocks), block(kBlock);
   if (r.model == kNcde || r.model == kCde) return err;   // the NSE models only
@@ -250,13 +343,22 @@ static hipError_t launch_custom_dim(const LaunchReq& r) {
     const auto* J = static_cast<const Job<Real>*>(r.jobs);
     const auto* PD = static_cast<const KParams<double>*>(r.pd);
     switch (r.op) {
-      case kOpStep:
+      case kOpStep: {
         if (r.vec != 1) return;
-        if (r.force)
-          hipLaunchKernelGGL((k_step_custom<DIM, ST, true>), grid, block, 0, r.stream, J, r.njobs, r.xcd_order ? r.blocks : 0u);
-        else
-          hipLaunchKernelGGL((k_step_custom<DIM, ST, false>), grid, block, 0, r.stream, J, r.njobs, r.xcd_order ? r.blocks : 0u);
+        // register slots for the populations: the smallest class that holds b
+        const uint32_t tb = r.xcd_order ? r.blocks : 0u;
+        auto step = [&](auto bc) {
+          constexpr int BC = decltype(bc)::value;
+          if (r.force)
+            hipLaunchKernelGGL((k_step_custom<DIM, ST, true, BC>), grid, block, 0, r.stream, J, r.njobs, tb);
+          else
+            hipLaunchKernelGGL((k_step_custom<DIM, ST, false, BC>), grid, block, 0, r.stream, J, r.njobs, tb);
+        };
+        if (r.custom_b <= 16) step(std::integral_constant<int, 16>{});
+        else if (r.custom_b <= 32) step(std::integral_constant<int, 32>{});
+        else step(std::integral_constant<int, 64>{});
         break;
+      }
       case kOpInit:
         hipLaunchKernelGGL((k_init_custom<DIM, ST>), grid, block, 0, r.stream, J, PD, r.in0, r.in1, r.in2);
         break;
@@ -277,8 +379,7 @@ static hipError_t launch_custom_dim(const LaunchReq& r) {
   return err;
 }
 
-hipError_t launch_custom(const LaunchReq& r) {
-  return r.dim == 3 ? launch_custom_dim<3>(r) : launch_custom_dim<2>(r);
-}
+hipError_t launch_custom_2d(const LaunchReq& r);
+hipError_t launch_custom_3d(const LaunchReq& r);
 
 }  // namespace mrtlb

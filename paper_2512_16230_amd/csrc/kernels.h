@@ -17,6 +17,24 @@ constexpr double kI16Range = 2.0;    // default int16 range: |f - w rho_ref| <= 
 // Index of the off-diagonal pair (a, b), a < b: xy -> 0, xz -> 1, yz -> 2.
 constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
 
+// Per-velocity table of a user-supplied lattice: b rows of kCMono<D> reals
+// (the weight w_j, then the monomials of e_j that the moments of order <= 3
+// sum, in the order e_a, e_a^2, e_a e_b (a < b), e_a^3, e_a e_b^2 (a != b),
+// e_x e_y e_z), then b rows of four 32-bit words: e_x, e_y, e_z and the
+// element offset of population j's source row from the own row's first
+// element, ((-e_z ny - e_y) b + j) nxp modulo 2^32 (for rows whose y and z
+// neighbours need no wrap).  The forward
+// transform adds monomial k times f_j to raw moment k; the back-transform
+// evaluates sum_k monomial k times its coefficient.
+template <int D>
+constexpr int kCMono = D == 2 ? 10 : 20;
+constexpr int cm_1(int D, int a) { return 1 + a; }
+constexpr int cm_2n(int D, int a) { return 1 + D + a; }
+constexpr int cm_2o(int D, int a, int b) { return 1 + 2 * D + off_index(a, b); }
+constexpr int cm_3p(int D, int a) { return 1 + 2 * D + D * (D - 1) / 2 + a; }
+constexpr int cm_3m(int D, int a, int b) { return 1 + 3 * D + D * (D - 1) / 2 + a * (D - 1) + (b < a ? b : b - 1); }
+constexpr int cm_xyz() { return 19; }
+
 // kFP32DevF64: FP32 deviations in HBM, FP64 arithmetic in the kernels.
 enum Storage { kFP64 = 0, kFP32 = 1, kFP32Dev = 2, kFP16Dev = 3, kBF16Dev = 4, kI16Dev = 5, kFP32DevF64 = 6 };
 // kNseGrad: the NSE kernels with the gradient form of M2G_bar (lagged
@@ -90,6 +108,7 @@ struct KParams {
   Real kx2[3];
   // velocity set at run time (read by the user-supplied-lattice kernels)
   int cb;                    // b
+  int cmx, cmy, cmz;         // largest |e_x|, |e_y|, |e_z| over the set
   int8_t ce[kMaxB][3];       // integer velocity multiples e_j
   // MFMA transform (3D lattices, int16 storage): the forward product gives
   // the raw monomial sums as msig * (acc - mbias[P]) (see mfma.h)
@@ -112,7 +131,8 @@ struct Job {
   const Real* phi_prev;     // NCDE: phi^{n-1}; NSE gradient form: rho^{n-1} (rho_bar), then rho u^{n-1} (compressible)
   Real* phi_out;            // NCDE: phi^n; NSE gradient form: the same fields at step n
   int* sat;                 // int16 storage: set to 1 when a value saturates
-  const void* mtab;         // MFMA transform: operand tables (16 KB), or nullptr
+  const void* mtab;         // MFMA transform: operand tables (16 KB); user-supplied lattice: the
+                            // per-velocity table (b x kCMono<D> reals); or nullptr
   uint32_t block_begin;     // first linear workgroup of this job
   uint32_t nblocks;
   int vec;                  // nodes per thread along x

@@ -20,6 +20,7 @@ struct LaunchReq {
   bool m2g = false;          // NSE: the gradient form of M2G_bar (history fields, one node per lane)
   bool xcd_order = true;     // step kernel: tiles in contiguous ranges per XCD (else the dispatch order)
   int dim = 2;               // lattice dimension (user-supplied lattices)
+  int custom_b = 0;          // user-supplied lattices: b (sizes the step kernel's register slots)
   const void* jobs = nullptr;
   int njobs = 1;
   uint32_t blocks = 0;

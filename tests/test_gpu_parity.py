@@ -560,9 +560,13 @@ def _shuffled_set(card, seed):
     return OL.custom_lattice("custom", card.c, card.cs2, lat.e[perm], lat.w[perm])
 
 
+# row pitches that are (320, 64, 128) and are not (96) multiples of a
+# wavefront, and grids with rows far enough from the y and z edges that the
+# source rows need no wrap (the user-supplied kernel's three gather paths)
 @pytest.mark.parametrize("card,shape", [(W.Q25_RECT, (7, 300)), (W.Q25_RECT, (37, 66)), (W.Q21K_RECT, (20, 40)),
-                                        (W.Q33_CUBIC, (5, 9, 66))],
-                         ids=["rD2Q25-7x300", "rD2Q25-37x66", "D2Q21K", "rD3Q33"])
+                                        (W.Q25_RECT, (20, 128)), (W.Q33_CUBIC, (5, 9, 66)),
+                                        (W.Q33_CUBIC, (9, 10, 64))],
+                         ids=["rD2Q25-7x300", "rD2Q25-37x66", "D2Q21K", "rD2Q25-20x128", "rD3Q33", "rD3Q33-64"])
 @pytest.mark.parametrize("eq", ["NSE_INC", "NSE_COMP"])
 @pytest.mark.parametrize("forced", [False, True], ids=["free", "force"])
 def test_custom_lattice(ctx, card, shape, eq, forced):
