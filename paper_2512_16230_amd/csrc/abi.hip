@@ -115,8 +115,11 @@ struct mrtlb_solve {
   size_t part_bytes = 0;
   bool external = false;        // f[0], f[1] belong to the caller
   int transform = 0;            // Hermite transforms of the step: 0 VALU, 1 MFMA
-  void* mtab = nullptr;         // MFMA operand tables (kMfmaTabBytes)
+  void* mtab = nullptr;         // MFMA operand tables (kMfmaTabBytes), or a user-supplied set's slot table
 };
+
+// Slot order of a user-supplied set (defined with the slot table below).
+static std::vector<int> custom_slots(const HostLattice& L, int* npairs);
 
 namespace mrtlb {
 
@@ -364,6 +367,8 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   }
   P.cb = L.B;
   P.cmx = P.cmy = P.cmz = 0;
+  P.cnp = 0;
+  if (L.kind == kCustom) (void)custom_slots(L, &P.cnp);
   for (int j = 0; j < L.B; ++j) {
     for (int a = 0; a < 3; ++a) P.ce[j][a] = (int8_t)(a < D ? L.e[j * D + a] : 0);
     P.cmx = std::max(P.cmx, std::abs((int)P.ce[j][0]));
@@ -671,21 +676,66 @@ static int custom_class(const HostLattice& L) {
 }
 static size_t custom_table_bytes(const HostLattice& L, int storage) {
   if (L.kind != kCustom) return 0;
-  return (size_t)L.B * ((size_t)(L.D == 3 ? kCMono<3> : kCMono<2>) * (is_double(storage) ? 8 : 4) + 16);
+  const size_t K = L.D == 3 ? kCSlot<3> : kCSlot<2>;
+  return (size_t)L.B * (K * (is_double(storage) ? 8 : 4) + kCInts * 4);
 }
+
+// Slot order of a user-supplied set: pairs of opposite velocities first
+// (each velocity with its first unused opposite, in index order), then the
+// velocities without one.  Returns the slots' population indices and sets
+// *npairs.
+static std::vector<int> custom_slots(const HostLattice& L, int* npairs) {
+  const int D = L.D;
+  std::vector<int> pairs, singles;
+  std::vector<char> used(L.B, 0);
+  auto opposite = [&](int i, int j) {
+    bool any = false;
+    for (int a = 0; a < D; ++a) {
+      if (L.e[i * D + a] != -L.e[j * D + a]) return false;
+      any |= L.e[i * D + a] != 0;
+    }
+    return any;
+  };
+  for (int i = 0; i < L.B; ++i) {
+    if (used[i]) continue;
+    used[i] = 1;
+    int partner = -1;
+    for (int j = i + 1; j < L.B && partner < 0; ++j)
+      if (!used[j] && opposite(i, j)) partner = j;
+    if (partner >= 0) {
+      used[partner] = 1;
+      pairs.push_back(i);
+      pairs.push_back(partner);
+    } else {
+      singles.push_back(i);
+    }
+  }
+  *npairs = (int)pairs.size() / 2;
+  pairs.insert(pairs.end(), singles.begin(), singles.end());
+  return pairs;
+}
+
 template <class Real>
-static std::vector<char> custom_table(const HostLattice& L, int64_t ny, int64_t nxp) {
-  const int D = L.D, K = D == 3 ? kCMono<3> : kCMono<2>;
+static std::vector<char> custom_table(const HostLattice& L, const KParams<Real>& P, int64_t ny, int64_t nxp) {
+  const int D = L.D, K = D == 3 ? kCSlot<3> : kCSlot<2>;
+  int np = 0;
+  const std::vector<int> slot = custom_slots(L, &np);
   std::vector<Real> t((size_t)L.B * K, Real(0));
-  std::vector<uint32_t> ie((size_t)L.B * 4, 0);
-  for (int j = 0; j < L.B; ++j) {
-    for (int a = 0; a < D; ++a) ie[(size_t)j * 4 + a] = (uint32_t)L.e[j * D + a];
+  std::vector<uint32_t> ie((size_t)L.B * kCInts, 0);
+  for (int s = 0; s < L.B; ++s) {
+    const int j = slot[s];
+    uint32_t* w = ie.data() + (size_t)s * kCInts;
+    w[0] = (uint32_t)j;
+    for (int a = 0; a < D; ++a) w[1 + a] = (uint32_t)L.e[j * D + a];
     const int64_t ey = L.e[j * D + 1], ez = D == 3 ? L.e[j * D + 2] : 0;
-    ie[(size_t)j * 4 + 3] = (uint32_t)(((-ez * ny - ey) * L.B + j) * nxp);   // modulo 2^32
+    w[4] = (uint32_t)(((-ez * ny - ey) * L.B + j) * nxp);   // modulo 2^32
     double e[3] = {0, 0, 0};
     for (int a = 0; a < D; ++a) e[a] = L.e[j * D + a];
-    Real* m = t.data() + (size_t)j * K;
-    m[0] = (Real)L.w[j];
+    Real* r = t.data() + (size_t)s * K;
+    r[0] = (Real)L.w[j];
+    r[1] = P.wsc[j];
+    r[2] = P.iwsc[j];
+    Real* m = r + 2;     // monomial k at m[k], k >= 1
     for (int a = 0; a < D; ++a) {
       m[cm_1(D, a)] = (Real)e[a];
       m[cm_2n(D, a)] = (Real)(e[a] * e[a]);
@@ -826,19 +876,8 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   }
   // the CDE's velocity field lives where the NSE force field would
   if (ok && model->model == MRTLB_CDE) ok = alloc(&s->force, (size_t)D * s->N * real);
-  // a user-supplied lattice's per-velocity table rides in the jobs' table slot
-  if (ok && s->L.kind == kCustom) {
-    const size_t tb = custom_table_bytes(s->L, storage);
-    ok = alloc(&s->mtab, tb);
-    if (ok) {
-      hipError_t e = is_double(storage)
-                         ? hipMemcpy(s->mtab, custom_table<double>(s->L, s->ny, s->nxp).data(), tb,
-                                     hipMemcpyHostToDevice)
-                         : hipMemcpy(s->mtab, custom_table<float>(s->L, s->ny, s->nxp).data(), tb,
-                                     hipMemcpyHostToDevice);
-      ok = e == hipSuccess;
-    }
-  }
+  // a user-supplied lattice's slot table rides in the jobs' table slot
+  if (ok && s->L.kind == kCustom) ok = alloc(&s->mtab, custom_table_bytes(s->L, storage));
   if (!ok) {
     release(s);
     delete s;
@@ -847,7 +886,15 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   }
   fill_params(*s, s->Pd);
   fill_params(*s, s->Pf);
-  if (hipMemcpy(s->pd, &s->Pd, sizeof s->Pd, hipMemcpyHostToDevice) != hipSuccess || upload_jobs(s) != MRTLB_OK) {
+  if (s->L.kind == kCustom) {
+    const size_t tb = custom_table_bytes(s->L, storage);
+    ok = (is_double(storage) ? hipMemcpy(s->mtab, custom_table(s->L, s->Pd, s->ny, s->nxp).data(), tb,
+                                         hipMemcpyHostToDevice)
+                             : hipMemcpy(s->mtab, custom_table(s->L, s->Pf, s->ny, s->nxp).data(), tb,
+                                         hipMemcpyHostToDevice)) == hipSuccess;
+  }
+  if (!ok || hipMemcpy(s->pd, &s->Pd, sizeof s->Pd, hipMemcpyHostToDevice) != hipSuccess ||
+      upload_jobs(s) != MRTLB_OK) {
     release(s);
     delete s;
     return fail(MRTLB_EDEVICE, "parameter upload failed");

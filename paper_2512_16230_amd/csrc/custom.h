@@ -1,9 +1,9 @@
 // Kernels for a user-supplied velocity set (kind MRTLB_CUSTOM), included by
 // custom_2d.hip and custom_3d.hip.  The structured kernels are compiled per
 // velocity set; here the set is read at run time: the integer multiples e_j
-// from KParams, and a per-velocity table of weights and monomials
-// (kCMono<D> reals per population, built by the ABI layer) through the
-// constant address space.  The step holds the b gathered populations in
+// from KParams, and for the step a slot table of weights, scales,
+// monomials and offsets (built by the ABI layer) through the constant
+// address space.  The step holds the b gathered populations in
 // registers (loops unrolled to a class of 16, 32 or 64 slots and guarded by
 // the run-time b), so every population is read once and written once.  The
 // moment-space part of the step (conserved variables, sources, equilibrium,
@@ -61,14 +61,18 @@ __device__ __forceinline__ void velocity(const KParams<Real>& P, int j, int (&e)
 }  // namespace
 
 // One fused step, one node per thread over the padded rows, the b gathered
-// populations held in registers (BC >= b slots, loops unrolled to BC and
-// guarded by the run-time b).  The per-velocity table (weights and
-// monomials, kCMono<DIM> reals per population) is read through the
-// constant address space: uniform scalar loads whose values enter the
-// FMAs as scalar operands.  When the row pitch is a multiple of 64 no
-// wavefront crosses a grid row, so the source rows are computed once per
-// wavefront on the scalar unit and the lane offset is x - e_x (wrapped per
-// lane only in wavefronts that hold a periodic x-edge).
+// populations held in register slots (BC >= b slots, loops unrolled to BC
+// and guarded by the run-time counts).  The slot table (kernels.h: pairs
+// of opposite velocities first, then the velocities without one; weights,
+// scales, monomials, population indices and source-row offsets) is read
+// through the constant address space: uniform scalar loads whose values
+// enter the FMAs as scalar operands.  A pair sums its even monomials over
+// f_a + f_b and its odd ones over f_a - f_b, and the back-transform
+// evaluates the even and odd parts E, O once for both (E + O at e_a, E - O
+// at e_b = -e_a).  When the row pitch is a multiple of 64 no wavefront
+// crosses a grid row, so the source rows are computed once per wavefront
+// on the scalar unit and the lane offset is x - e_x (wrapped per lane only
+// in wavefronts that hold a periodic x-edge).
 template <class Real>
 using ConstReal = __attribute__((address_space(4))) const Real;
 using ConstU32 = __attribute__((address_space(4))) const uint32_t;
@@ -79,7 +83,8 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
   using Real = typename StoreT<ST>::Real;
   using T = typename StoreT<ST>::T;
   using L = LatCustom<DIM>;
-  constexpr int K = kCMono<DIM>;
+  constexpr int K = kCMono<DIM>;     // monomials k = 1 .. K - 1
+  constexpr int KS = kCSlot<DIM>;
   constexpr int TB = (int)sizeof(T);
   const uint32_t lin = xcd_remap(blockIdx.x, total_blocks);
   const int jb = njobs > 1 ? find_job(jobs, njobs, lin) : 0;
@@ -89,17 +94,17 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
   if (!tile_node<1>(J, lin - J.block_begin, ix, iy, iz)) return;
   RowGeom<L> g;
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
-  const int b = P.cb;
+  const int b = P.cb, np = P.cnp;
   const auto* tab = (const ConstReal<Real>*)J.mtab;
-  const auto* tie = (const ConstU32*)((const char*)J.mtab + (size_t)b * K * sizeof(Real));
+  const auto* tie = (const ConstU32*)((const char*)J.mtab + (size_t)b * KS * sizeof(Real));
   const uint32_t ny = (uint32_t)P.ny, nxp = (uint32_t)P.nxp, ub = (uint32_t)b;
   const bool interior = __all(ix >= P.cmx && ix + P.cmx < P.nx) != 0;
 
   // a1: gather (u: wave-uniform element offset in soffset, l: per lane).
   // MODE 0: rows vary within the wavefront, all per lane; 1: one row per
   // wavefront, y and z wrapped on the scalar unit; 2: one row per wavefront
-  // and no y or z wrap needed, the source row at a fixed offset from the own
-  // row (the table's fourth word).
+  // and no y or z wrap needed, the source row at the table's offset from
+  // the own row.
   T raw[BC];
   const uint32_t own = ((uint32_t)iz * ny + (uint32_t)iy) * ub * nxp;
   auto gather = [&](auto mode) {
@@ -109,26 +114,27 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
     const int wz = MODE > 0 ? __builtin_amdgcn_readfirstlane(iz) : iz;
     const uint32_t wown = MODE > 0 ? (uint32_t)__builtin_amdgcn_readfirstlane(own) : own;
 #pragma unroll
-    for (int j = 0; j < BC; ++j) {
-      if (j < b) {
-        const int ex = (int)tie[4 * j];
+    for (int s = 0; s < BC; ++s) {
+      if (s < b) {
+        const auto* w = tie + s * kCInts;
+        const int ex = (int)w[1];
         uint32_t xs = (uint32_t)(ix - ex);
         if (!interior) xs = (uint32_t)wrap(ix - ex, P.nx);
         uint32_t u, l;
         if constexpr (MODE == 2) {
-          u = wown + tie[4 * j + 3];
+          u = wown + w[4];
           l = xs;
         } else {
-          const int ey = (int)tie[4 * j + 1], ez = DIM == 3 ? (int)tie[4 * j + 2] : 0;
+          const int ey = (int)w[2], ez = DIM == 3 ? (int)w[3] : 0;
           const uint32_t ys = (uint32_t)wrap(wy - ey, P.ny);
           const uint32_t zs = DIM == 3 ? (uint32_t)wrap(wz - ez, P.nz) : 0u;
-          const uint32_t row = ((zs * ny + ys) * ub + (uint32_t)j) * nxp;
+          const uint32_t row = ((zs * ny + ys) * ub + w[0]) * nxp;
           u = MODE == 1 ? row : 0u;
           l = MODE == 1 ? xs : row + xs;
         }
-        raw[j] = __builtin_bit_cast(T, buf_load<TB>(rin, l * (uint32_t)TB, u * (uint32_t)TB));
+        raw[s] = __builtin_bit_cast(T, buf_load<TB>(rin, l * (uint32_t)TB, u * (uint32_t)TB));
       } else {
-        raw[j] = T(0);
+        raw[s] = T(0);
       }
     }
   };
@@ -142,32 +148,54 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
     gather(std::integral_constant<int, 0>{});
   }
 
-  // a3: raw moment sums of the populations (physical deviations)
+  // the physical deviation held by slot s
+  auto val = [&](int s) -> Real {
+    if constexpr (scaled_storage<ST>()) return (Real)pin(units<ST>(raw[s]) * (float)tab[s * KS + 1]);
+    else return (Real)raw[s];
+  };
+
+  // a3: raw moment sums, Rk[k] = sum_j monomial_k(e_j) f_j
   const Real z = Real(-0.0);
-  Real R0 = z, R1[3] = {z, z, z}, R2n[3] = {z, z, z}, R2o[3] = {z, z, z}, R3p[3] = {z, z, z};
+  Real R0 = z, Rk[K];
+#pragma unroll
+  for (int k = 1; k < K; ++k) Rk[k] = z;
+#pragma unroll
+  for (int p = 0; p < BC / 2; ++p) {
+    if (p < np) {
+      const Real fa = val(2 * p), fb = val(2 * p + 1);
+      const Real sm = fa + fb, df = fa - fb;
+      const auto* m = tab + 2 * p * KS + 2;
+      R0 += sm;
+#pragma unroll
+      for (int k = 1; k < K; ++k) Rk[k] += m[k] * (cm_even(DIM, k) ? sm : df);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < BC; ++s) {
+    if (s >= 2 * np && s < b) {
+      const Real f = val(s);
+      const auto* m = tab + s * KS + 2;
+      R0 += f;
+#pragma unroll
+      for (int k = 1; k < K; ++k) Rk[k] += m[k] * f;
+    }
+  }
+  Real R1[3] = {z, z, z}, R2n[3] = {z, z, z}, R2o[3] = {z, z, z}, R3p[3] = {z, z, z};
   Real R3m[3][3] = {{z, z, z}, {z, z, z}, {z, z, z}};
   Real Rxyz = z;
 #pragma unroll
-  for (int j = 0; j < BC; ++j) {
-    if (j < b) {
-      const Real v = decode<ST>(raw[j], P, j);
-      const auto* m = tab + j * K;
-      R0 += v;
+  for (int a = 0; a < DIM; ++a) {
+    R1[a] = Rk[cm_1(DIM, a)];
+    R2n[a] = Rk[cm_2n(DIM, a)];
+    R3p[a] = Rk[cm_3p(DIM, a)];
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        R1[a] += m[cm_1(DIM, a)] * v;
-        R2n[a] += m[cm_2n(DIM, a)] * v;
-        R3p[a] += m[cm_3p(DIM, a)] * v;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-          if (c == a) continue;
-          R3m[a][c] += m[cm_3m(DIM, a, c)] * v;
-          if (c > a) R2o[off_index(a, c)] += m[cm_2o(DIM, a, c)] * v;
-        }
-      }
-      if constexpr (DIM == 3) Rxyz += m[cm_xyz()] * v;
+    for (int c = 0; c < DIM; ++c) {
+      if (c == a) continue;
+      R3m[a][c] = Rk[cm_3m(DIM, a, c)];
+      if (c > a) R2o[off_index(a, c)] = Rk[cm_2o(DIM, a, c)];
     }
   }
+  if constexpr (DIM == 3) Rxyz = Rk[cm_xyz()];
   Moments<Real> M;
   finish_moments<DIM, false>(P, R0, R1, R2n, R2o, R3p, R3m, Rxyz, M);
 
@@ -197,19 +225,40 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
   const uint32_t own_u = unirow ? (uint32_t)__builtin_amdgcn_readfirstlane(own) : 0u;
   const uint32_t own_l = unirow ? (uint32_t)ix : own + (uint32_t)ix;
   float smax = 0.0f;
+  auto put = [&](int s, Real out) {
+    T q;
+    if constexpr (scaled_storage<ST>()) {
+      const float o = pin((float)out * (float)tab[s * KS + 2]);
+      if constexpr (ST == kI16Dev) smax = fmaxf(smax, fabsf(o));
+      q = to_stored<ST>(o);
+    } else {
+      q = (T)out;
+    }
+    buf_store<TB>(rout, __builtin_bit_cast(typename RawChunk<TB>::T, q), own_l * (uint32_t)TB,
+                  (own_u + tie[s * kCInts] * nxp) * (uint32_t)TB);
+  };
 #pragma unroll
-  for (int j = 0; j < BC; ++j) {
-    if (j < b) {
-      const Real v = decode<ST>(raw[j], P, j);
-      const auto* m = tab + j * K;
+  for (int p = 0; p < BC / 2; ++p) {
+    if (p < np) {
+      const auto* m = tab + 2 * p * KS + 2;
+      Real E = cf[0], O = z;
+#pragma unroll
+      for (int k = 1; k < K; ++k) {
+        if (cm_even(DIM, k)) E += m[k] * cf[k];
+        else O += m[k] * cf[k];
+      }
+      put(2 * p, tg.kx * val(2 * p) + tab[2 * p * KS] * (E + O));
+      put(2 * p + 1, tg.kx * val(2 * p + 1) + tab[(2 * p + 1) * KS] * (E - O));
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < BC; ++s) {
+    if (s >= 2 * np && s < b) {
+      const auto* m = tab + s * KS + 2;
       Real poly = cf[0];
 #pragma unroll
       for (int k = 1; k < K; ++k) poly += m[k] * cf[k];
-      const Real out = tg.kx * v + m[0] * poly;
-      smax = fmaxf(smax, sat_of<ST>(out, P, j));
-      const T q = encode<ST>(out, P, j);
-      buf_store<TB>(rout, __builtin_bit_cast(typename RawChunk<TB>::T, q), own_l * (uint32_t)TB,
-                    (own_u + (uint32_t)j * nxp) * (uint32_t)TB);
+      put(s, tg.kx * val(s) + tab[s * KS] * poly);
     }
   }
   raise_saturation<ST>(J, smax);

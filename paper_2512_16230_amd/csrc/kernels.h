@@ -17,17 +17,26 @@ constexpr double kI16Range = 2.0;    // default int16 range: |f - w rho_ref| <= 
 // Index of the off-diagonal pair (a, b), a < b: xy -> 0, xz -> 1, yz -> 2.
 constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
 
-// Per-velocity table of a user-supplied lattice: b rows of kCMono<D> reals
-// (the weight w_j, then the monomials of e_j that the moments of order <= 3
-// sum, in the order e_a, e_a^2, e_a e_b (a < b), e_a^3, e_a e_b^2 (a != b),
-// e_x e_y e_z), then b rows of four 32-bit words: e_x, e_y, e_z and the
-// element offset of population j's source row from the own row's first
-// element, ((-e_z ny - e_y) b + j) nxp modulo 2^32 (for rows whose y and z
-// neighbours need no wrap).  The forward
-// transform adds monomial k times f_j to raw moment k; the back-transform
-// evaluates sum_k monomial k times its coefficient.
+// Slot table of a user-supplied lattice.  The step kernel holds the b
+// populations in slots: first the pairs of opposite velocities (slots 2p,
+// 2p + 1, P.cnp pairs), then the velocities without an opposite (the rest
+// velocity among them).  Per slot, kCSlot<D> reals: the weight w_j, the
+// storage scales wsc_j and iwsc_j, then the monomials of e_j that the
+// moments of order <= 3 sum, numbered k = 1 .. kCMono<D> - 1 in the order
+// e_a, e_a^2, e_a e_b (a < b), e_a^3, e_a e_b^2 (a != b), e_x e_y e_z (at
+// index 2 + k); after the b rows of reals, b rows of kCInts 32-bit words:
+// j, e_x, e_y, e_z, and the element offset of population j's source row
+// from the own row's first element, ((-e_z ny - e_y) b + j) nxp modulo 2^32
+// (rows whose y and z neighbours need no wrap).  The forward transform adds
+// monomial k times f_j to raw moment k; the back-transform evaluates sum_k
+// monomial k times its coefficient.  For a pair, the even monomials (order
+// 2) multiply f_a + f_b and the odd ones f_a - f_b.
 template <int D>
 constexpr int kCMono = D == 2 ? 10 : 20;
+template <int D>
+constexpr int kCSlot = kCMono<D> + 2;
+constexpr int kCInts = 8;
+constexpr bool cm_even(int D, int k) { return k >= 1 + D && k < 1 + 2 * D + D * (D - 1) / 2; }
 constexpr int cm_1(int D, int a) { return 1 + a; }
 constexpr int cm_2n(int D, int a) { return 1 + D + a; }
 constexpr int cm_2o(int D, int a, int b) { return 1 + 2 * D + off_index(a, b); }
@@ -109,6 +118,7 @@ struct KParams {
   // velocity set at run time (read by the user-supplied-lattice kernels)
   int cb;                    // b
   int cmx, cmy, cmz;         // largest |e_x|, |e_y|, |e_z| over the set
+  int cnp;                   // pairs of opposite velocities (slot table of the step kernel)
   int8_t ce[kMaxB][3];       // integer velocity multiples e_j
   // MFMA transform (3D lattices, int16 storage): the forward product gives
   // the raw monomial sums as msig * (acc - mbias[P]) (see mfma.h)
