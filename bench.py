@@ -150,6 +150,10 @@ def bench_tgv3d(torch, H, W, stream, args):
     card, r = wl.card, wl.rates
     ctx = H.Context(0, stream=stream.cuda_stream)
     lat = H.Lattice(card.kind, card.c, card.cs2, card.free)
+    if args.custom:
+        # the same velocity set and weights as a user-supplied (run-time) lattice
+        q = lat.query()
+        lat = H.Lattice("custom", card.c, card.cs2, e=q["e"], w=q["w"])
     md = H.model_desc(wl.eq, s0=r.s0, s1=r.s1, s_shear=r.s_shear, s_bulk=r.s_bulk, s3=r.s3, s_high=r.s_h,
                       m30=card.kind not in STANDARD, mass_src=args.mass_src, m2g_form=1 if args.m2g else 0,
                       **_bounds(W, args.storage, wl))
@@ -173,16 +177,17 @@ def bench_tgv3d(torch, H, W, stream, args):
     # (rho and rho u of the compressible model)
     launch_bytes = (2 * bq * STORE_BYTES[args.storage] + (3 * real if forced else 0)
                     + (2 * 4 * real if args.m2g else 0)) * nodes
-    out = _line("%s MRT-LB MLUPS (fused collide-and-stream%s%s%s), %% of HBM roofline"
-                % (card.kind, ", mass source" if forced else "",
+    out = _line("%s%s MRT-LB MLUPS (fused collide-and-stream%s%s%s), %% of HBM roofline"
+                % (card.kind, " as a user-supplied lattice" if args.custom else "", ", mass source" if forced else "",
                    ", Hermite transforms on MFMA" if args.transform == "mfma" else "",
                    ", gradient form of M2G" if args.m2g else ""),
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
-                {"workload": "tgv3d-%s-%dx%dx%d" % (card.kind, n, n, n), "lattice": card.kind,
+                {"workload": "tgv3d-%s-%dx%dx%d" % (card.kind, n, n, n),
+                 "lattice": card.kind + (" (user-supplied)" if args.custom else ""),
                  "c": list(card.c), "cs2": card.cs2, "storage": args.storage, "nodes": nodes,
                  "transform": args.transform, "m2g_form": 1 if args.m2g else 0},
                 args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
-    if not forced and not args.m2g and args.transform == "valu":
+    if not forced and not args.m2g and args.transform == "valu" and not args.custom:
         out["roofline"]["traffic"] = measured_traffic(card.kind, args.storage, "%dx%dx%d" % (n, n, n), launch_bytes)
         out["roofline"]["stream_only"] = stream_ceiling(s, args.steps, launch_bytes, kernel_ms / 1e3 / args.steps)
     s.close()
@@ -322,7 +327,7 @@ def main():
     ap.add_argument("--m2g", action="store_true",
                     help="tgv2d / tgv3d: the gradient form of the auxiliary second moment M2G (m2g_form = 1)")
     ap.add_argument("--custom", action="store_true",
-                    help="tgv2d: run the lattice's velocity set as a user-supplied (run-time) lattice")
+                    help="tgv2d, tgv3d: run the lattice's velocity set as a user-supplied (run-time) lattice")
     ap.add_argument("--lattice3d", default="rD3Q53", choices=["rD3Q53", "rD3Q45", "rD3Q33", "D3Q27"],
                     help="lattice of the tgv3d workload (rD3Q33 runs on a cube)")
     ap.add_argument("--transform", default="valu", choices=["valu", "mfma"],
