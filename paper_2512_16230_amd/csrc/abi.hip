@@ -118,8 +118,10 @@ struct mrtlb_solve {
   void* mtab = nullptr;         // MFMA operand tables (kMfmaTabBytes), or a user-supplied set's slot table
 };
 
-// Slot order of a user-supplied set (defined with the slot table below).
-static std::vector<int> custom_slots(const HostLattice& L, int* npairs);
+// Slot order of a user-supplied set and whether its step uses rays
+// (defined with the slot table below).
+static std::vector<int> custom_slots(const HostLattice& L, bool rays, int* nrays, int* npairs, std::vector<int>* mult);
+static bool custom_rays(const HostLattice& L, int storage);
 
 namespace mrtlb {
 
@@ -367,8 +369,11 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   }
   P.cb = L.B;
   P.cmx = P.cmy = P.cmz = 0;
-  P.cnp = 0;
-  if (L.kind == kCustom) (void)custom_slots(L, &P.cnp);
+  P.cnr = P.cnp = 0;
+  if (L.kind == kCustom) {
+    std::vector<int> mult;
+    (void)custom_slots(L, custom_rays(L, s.storage), &P.cnr, &P.cnp, &mult);
+  }
   for (int j = 0; j < L.B; ++j) {
     for (int a = 0; a < 3; ++a) P.ce[j][a] = (int8_t)(a < D ? L.e[j * D + a] : 0);
     P.cmx = std::max(P.cmx, std::abs((int)P.ce[j][0]));
@@ -454,6 +459,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.xcd_order = s.xcd_order;
   r.dim = s.L.D;
   r.custom_b = s.L.kind == kCustom ? s.L.B : 0;
+  r.custom_rays = s.L.kind == kCustom && custom_rays(s.L, s.storage);
   r.jobs = jobs;
   r.njobs = 1;
   r.blocks = (op == kOpStep || op == kOpStream) ? s.nblocks : s.nblocks_node;
@@ -680,19 +686,23 @@ static size_t custom_table_bytes(const HostLattice& L, int storage) {
   return (size_t)L.B * (K * (is_double(storage) ? 8 : 4) + kCInts * 4);
 }
 
-// Slot order of a user-supplied set: pairs of opposite velocities first
-// (each velocity with its first unused opposite, in index order), then the
-// velocities without one.  Returns the slots' population indices and sets
-// *npairs.
-static std::vector<int> custom_slots(const HostLattice& L, int* npairs) {
+// Slot order of a user-supplied set: rays first (a pair of opposite
+// velocities +-e with a second pair +-c e, c >= 2 an integer, the smallest
+// such c; bases taken shortest first), then the remaining pairs of opposite
+// velocities (each velocity with its first unused opposite, in index
+// order), then the velocities without one.  Returns the slots' population
+// indices and sets *nrays, *npairs; *mult receives c per ray.
+static std::vector<int> custom_slots(const HostLattice& L, bool rays, int* nrays, int* npairs, std::vector<int>* mult) {
   const int D = L.D;
-  std::vector<int> pairs, singles;
+  auto comp = [&](int j, int a) { return L.e[j * D + a]; };
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<int> singles;
   std::vector<char> used(L.B, 0);
   auto opposite = [&](int i, int j) {
     bool any = false;
     for (int a = 0; a < D; ++a) {
-      if (L.e[i * D + a] != -L.e[j * D + a]) return false;
-      any |= L.e[i * D + a] != 0;
+      if (comp(i, a) != -comp(j, a)) return false;
+      any |= comp(i, a) != 0;
     }
     return any;
   };
@@ -704,22 +714,95 @@ static std::vector<int> custom_slots(const HostLattice& L, int* npairs) {
       if (!used[j] && opposite(i, j)) partner = j;
     if (partner >= 0) {
       used[partner] = 1;
-      pairs.push_back(i);
-      pairs.push_back(partner);
+      pairs.emplace_back(i, partner);
     } else {
       singles.push_back(i);
     }
   }
-  *npairs = (int)pairs.size() / 2;
-  pairs.insert(pairs.end(), singles.begin(), singles.end());
-  return pairs;
+  // c such that e_j = c e_i (0 if none)
+  auto multiple = [&](int i, int j) {
+    int c = 0;
+    for (int a = 0; a < D; ++a) {
+      if (comp(i, a) == 0) {
+        if (comp(j, a) != 0) return 0;
+        continue;
+      }
+      if (comp(j, a) % comp(i, a) != 0) return 0;
+      const int q = comp(j, a) / comp(i, a);
+      if (q < 2 || (c != 0 && q != c)) return 0;
+      c = q;
+    }
+    return c;
+  };
+  auto norm1 = [&](int j) {
+    int n = 0;
+    for (int a = 0; a < D; ++a) n += std::abs(comp(j, a));
+    return n;
+  };
+  std::vector<size_t> order(pairs.size());
+  for (size_t p = 0; p < pairs.size(); ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return norm1(pairs[x].first) < norm1(pairs[y].first); });
+  std::vector<char> taken(pairs.size(), 0);
+  std::vector<int> slots, rest;
+  mult->clear();
+  for (size_t oi = 0; oi < (rays ? order.size() : 0); ++oi) {
+    const size_t p = order[oi];
+    if (taken[p]) continue;
+    const int base = pairs[p].first;
+    int best = -1, bestc = 0;
+    bool flip = false;
+    for (size_t q = 0; q < pairs.size(); ++q) {
+      if (q == p || taken[q]) continue;
+      for (int side = 0; side < 2; ++side) {
+        const int c = multiple(base, side ? pairs[q].second : pairs[q].first);
+        if (c >= 2 && (best < 0 || c < bestc)) {
+          best = (int)q;
+          bestc = c;
+          flip = side == 1;
+        }
+      }
+    }
+    if (best < 0) continue;
+    taken[p] = taken[best] = 1;
+    const auto& qp = pairs[best];
+    slots.insert(slots.end(), {base, pairs[p].second, flip ? qp.second : qp.first, flip ? qp.first : qp.second});
+    mult->push_back(bestc);
+  }
+  *nrays = (int)mult->size();
+  int np = 0;
+  for (size_t p = 0; p < pairs.size(); ++p)
+    if (!taken[p]) {
+      slots.push_back(pairs[p].first);
+      slots.push_back(pairs[p].second);
+      ++np;
+    }
+  *npairs = np;
+  slots.insert(slots.end(), singles.begin(), singles.end());
+  return slots;
+}
+
+// The step uses rays (measured on MI355X): for the unscaled storages, when
+// the register class is at most 32 slots or rays hold at least half of the
+// populations; in the 64-slot class a few rays do not pay for the registers
+// the ray form takes (rD3Q33's set: 3 rays, 7% slower; rD3Q53's: 13 rays,
+// 8% faster; rD2Q25's set +9%, the knight D2Q21's +12%), and the 16-bit
+// storages are slower with them (int16: 11% on rD2Q25's set).
+static bool custom_rays(const HostLattice& L, int storage) {
+  if (L.kind != kCustom || storage == kFP16Dev || storage == kBF16Dev || storage == kI16Dev) return false;
+  int nr = 0, np = 0;
+  std::vector<int> mult;
+  (void)custom_slots(L, true, &nr, &np, &mult);
+  return nr > 0 && (custom_class(L) <= 32 || 8 * nr >= L.B);
 }
 
 template <class Real>
-static std::vector<char> custom_table(const HostLattice& L, const KParams<Real>& P, int64_t ny, int64_t nxp) {
+static std::vector<char> custom_table(const HostLattice& L, int storage, const KParams<Real>& P, int64_t ny,
+                                      int64_t nxp) {
   const int D = L.D, K = D == 3 ? kCSlot<3> : kCSlot<2>;
-  int np = 0;
-  const std::vector<int> slot = custom_slots(L, &np);
+  int nr = 0, np = 0;
+  std::vector<int> mult;
+  const std::vector<int> slot = custom_slots(L, custom_rays(L, storage), &nr, &np, &mult);
   std::vector<Real> t((size_t)L.B * K, Real(0));
   std::vector<uint32_t> ie((size_t)L.B * kCInts, 0);
   for (int s = 0; s < L.B; ++s) {
@@ -747,6 +830,13 @@ static std::vector<char> custom_table(const HostLattice& L, const KParams<Real>&
       }
     }
     if (D == 3) m[cm_xyz()] = (Real)(e[0] * e[1] * e[2]);
+    if (s < 4 * nr && s % 4 == 2) {      // the ray's multiplier c, c^2, c^3 after the monomials
+      const double c = mult[s / 4];
+      const int km = D == 3 ? kCMono<3> : kCMono<2>;
+      m[km] = (Real)c;
+      m[km + 1] = (Real)(c * c);
+      m[km + 2] = (Real)(c * c * c);
+    }
   }
   std::vector<char> out(t.size() * sizeof(Real) + ie.size() * sizeof(uint32_t));
   std::memcpy(out.data(), t.data(), t.size() * sizeof(Real));
@@ -888,9 +978,9 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   fill_params(*s, s->Pf);
   if (s->L.kind == kCustom) {
     const size_t tb = custom_table_bytes(s->L, storage);
-    ok = (is_double(storage) ? hipMemcpy(s->mtab, custom_table(s->L, s->Pd, s->ny, s->nxp).data(), tb,
+    ok = (is_double(storage) ? hipMemcpy(s->mtab, custom_table(s->L, storage, s->Pd, s->ny, s->nxp).data(), tb,
                                          hipMemcpyHostToDevice)
-                             : hipMemcpy(s->mtab, custom_table(s->L, s->Pf, s->ny, s->nxp).data(), tb,
+                             : hipMemcpy(s->mtab, custom_table(s->L, storage, s->Pf, s->ny, s->nxp).data(), tb,
                                          hipMemcpyHostToDevice)) == hipSuccess;
   }
   if (!ok || hipMemcpy(s->pd, &s->Pd, sizeof s->Pd, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1691,6 +1781,7 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
       // model, force and VEC
       if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->L.D == a->L.D &&
           custom_class(b->L) == custom_class(a->L) && b->storage == a->storage &&
+          custom_rays(b->L, b->storage) == custom_rays(a->L, a->storage) &&
           b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec &&
           b->transform == a->transform && b->model.m2g_form == a->model.m2g_form) {
         grp.emplace_back(solves[k], nsteps[k]);

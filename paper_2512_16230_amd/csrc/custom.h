@@ -69,7 +69,8 @@ __device__ __forceinline__ void velocity(const KParams<Real>& P, int j, int (&e)
 // enter the FMAs as scalar operands.  A pair sums its even monomials over
 // f_a + f_b and its odd ones over f_a - f_b, and the back-transform
 // evaluates the even and odd parts E, O once for both (E + O at e_a, E - O
-// at e_b = -e_a).  When the row pitch is a multiple of 64 no wavefront
+// at e_b = -e_a); a ray of two pairs (+-e, +-c e) shares e's monomials,
+// scaled by c, c^2, c^3 for orders 1, 2, 3.  When the row pitch is a multiple of 64 no wavefront
 // crosses a grid row, so the source rows are computed once per wavefront
 // on the scalar unit and the lane offset is x - e_x (wrapped per lane only
 // in wavefronts that hold a periodic x-edge).
@@ -77,7 +78,7 @@ template <class Real>
 using ConstReal = __attribute__((address_space(4))) const Real;
 using ConstU32 = __attribute__((address_space(4))) const uint32_t;
 
-template <int DIM, int ST, bool FORCE, int BC>
+template <int DIM, int ST, bool FORCE, int BC, bool RAYS>
 __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename StoreT<ST>::Real>* __restrict__ jobs,
                                                        int njobs, uint32_t total_blocks) {
   using Real = typename StoreT<ST>::Real;
@@ -94,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
   if (!tile_node<1>(J, lin - J.block_begin, ix, iy, iz)) return;
   RowGeom<L> g;
   g.init(iy, iz, P.nx, P.nxp, P.ny, P.nz);
-  const int b = P.cb, np = P.cnp;
+  const int b = P.cb, nr = RAYS ? P.cnr : 0, np = P.cnp;
+  const int pe = 4 * nr + 2 * np;    // first slot without an opposite
   const auto* tab = (const ConstReal<Real>*)J.mtab;
   const auto* tie = (const ConstU32*)((const char*)J.mtab + (size_t)b * KS * sizeof(Real));
   const uint32_t ny = (uint32_t)P.ny, nxp = (uint32_t)P.nxp, ub = (uint32_t)b;
@@ -154,17 +156,35 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
     else return (Real)raw[s];
   };
 
-  // a3: raw moment sums, Rk[k] = sum_j monomial_k(e_j) f_j
+  // a3: raw moment sums, Rk[k] = sum_j monomial_k(e_j) f_j.  A ray
+  // (slots 4r .. 4r + 3: +-e, then +-c e) adds to monomial k of e the sum
+  // (f_a + f_b) of the first pair plus c^order times that of the second
+  // (order 2), or the difference (f_a - f_b) likewise (orders 1 and 3).
   const Real z = Real(-0.0);
   Real R0 = z, Rk[K];
 #pragma unroll
   for (int k = 1; k < K; ++k) Rk[k] = z;
 #pragma unroll
-  for (int p = 0; p < BC / 2; ++p) {
-    if (p < np) {
-      const Real fa = val(2 * p), fb = val(2 * p + 1);
+  for (int r = 0; r < (RAYS ? BC / 4 : 0); ++r) {
+    if (r < nr) {
+      const int s0 = 4 * r;
+      const Real fa = val(s0), fb = val(s0 + 1), ga = val(s0 + 2), gb = val(s0 + 3);
+      const auto* c = tab + (s0 + 2) * KS + 2 + K;   // c, c^2, c^3
+      const Real s1 = fa + fb, d1 = fa - fb, s2 = ga + gb, d2 = ga - gb;
+      const Real S = s1 + c[1] * s2, D1 = d1 + c[0] * d2, D3 = d1 + c[2] * d2;
+      const auto* m = tab + s0 * KS + 2;
+      R0 += s1;
+      R0 += s2;
+#pragma unroll
+      for (int k = 1; k < K; ++k) Rk[k] += m[k] * (cm_order(DIM, k) == 2 ? S : cm_order(DIM, k) == 1 ? D1 : D3);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < BC; s += 2) {
+    if (s >= 4 * nr && s < pe) {
+      const Real fa = val(s), fb = val(s + 1);
       const Real sm = fa + fb, df = fa - fb;
-      const auto* m = tab + 2 * p * KS + 2;
+      const auto* m = tab + s * KS + 2;
       R0 += sm;
 #pragma unroll
       for (int k = 1; k < K; ++k) Rk[k] += m[k] * (cm_even(DIM, k) ? sm : df);
@@ -172,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
   }
 #pragma unroll
   for (int s = 0; s < BC; ++s) {
-    if (s >= 2 * np && s < b) {
+    if (s >= pe && s < b) {
       const Real f = val(s);
       const auto* m = tab + s * KS + 2;
       R0 += f;
@@ -238,22 +258,45 @@ __global__ __launch_bounds__(kBlock) void k_step_custom(const Job<typename Store
                   (own_u + tie[s * kCInts] * nxp) * (uint32_t)TB);
   };
 #pragma unroll
-  for (int p = 0; p < BC / 2; ++p) {
-    if (p < np) {
-      const auto* m = tab + 2 * p * KS + 2;
+  for (int r = 0; r < (RAYS ? BC / 4 : 0); ++r) {
+    if (r < nr) {
+      // the polynomial's order-2, order-1 and order-3 parts at e; at c e
+      // they scale by c^2, c, c^3
+      const int s0 = 4 * r;
+      const auto* m = tab + s0 * KS + 2;
+      const auto* c = tab + (s0 + 2) * KS + 2 + K;
+      Real E2 = z, O1 = z, O3 = z;
+#pragma unroll
+      for (int k = 1; k < K; ++k) {
+        if (cm_order(DIM, k) == 2) E2 += m[k] * cf[k];
+        else if (cm_order(DIM, k) == 1) O1 += m[k] * cf[k];
+        else O3 += m[k] * cf[k];
+      }
+      const Real E = cf[0] + E2, O = O1 + O3;
+      put(s0, tg.kx * val(s0) + tab[s0 * KS] * (E + O));
+      put(s0 + 1, tg.kx * val(s0 + 1) + tab[(s0 + 1) * KS] * (E - O));
+      const Real Ec = cf[0] + c[1] * E2, Oc = c[0] * O1 + c[2] * O3;
+      put(s0 + 2, tg.kx * val(s0 + 2) + tab[(s0 + 2) * KS] * (Ec + Oc));
+      put(s0 + 3, tg.kx * val(s0 + 3) + tab[(s0 + 3) * KS] * (Ec - Oc));
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < BC; s += 2) {
+    if (s >= 4 * nr && s < pe) {
+      const auto* m = tab + s * KS + 2;
       Real E = cf[0], O = z;
 #pragma unroll
       for (int k = 1; k < K; ++k) {
         if (cm_even(DIM, k)) E += m[k] * cf[k];
         else O += m[k] * cf[k];
       }
-      put(2 * p, tg.kx * val(2 * p) + tab[2 * p * KS] * (E + O));
-      put(2 * p + 1, tg.kx * val(2 * p + 1) + tab[(2 * p + 1) * KS] * (E - O));
+      put(s, tg.kx * val(s) + tab[s * KS] * (E + O));
+      put(s + 1, tg.kx * val(s + 1) + tab[(s + 1) * KS] * (E - O));
     }
   }
 #pragma unroll
   for (int s = 0; s < BC; ++s) {
-    if (s >= 2 * np && s < b) {
+    if (s >= pe && s < b) {
       const auto* m = tab + s * KS + 2;
       Real poly = cf[0];
 #pragma unroll
@@ -396,12 +439,19 @@ hipError_t launch_custom_dim(const LaunchReq& r) {
         if (r.vec != 1) return;
         // register slots for the populations: the smallest class that holds b
         const uint32_t tb = r.xcd_order ? r.blocks : 0u;
+        // the ray form is built for the unscaled storages (measured slower
+        // for the 16-bit ones, whose conversions raise its register count)
         auto step = [&](auto bc) {
           constexpr int BC = decltype(bc)::value;
-          if (r.force)
-            hipLaunchKernelGGL((k_step_custom<DIM, ST, true, BC>), grid, block, 0, r.stream, J, r.njobs, tb);
-          else
-            hipLaunchKernelGGL((k_step_custom<DIM, ST, false, BC>), grid, block, 0, r.stream, J, r.njobs, tb);
+          auto go = [&](auto rays) {
+            constexpr bool RAYS = decltype(rays)::value;
+            if (r.force)
+              hipLaunchKernelGGL((k_step_custom<DIM, ST, true, BC, RAYS>), grid, block, 0, r.stream, J, r.njobs, tb);
+            else
+              hipLaunchKernelGGL((k_step_custom<DIM, ST, false, BC, RAYS>), grid, block, 0, r.stream, J, r.njobs, tb);
+          };
+          if (!r.custom_rays) go(std::false_type{});
+          else if constexpr (!scaled_storage<ST>()) go(std::true_type{});
         };
         if (r.custom_b <= 16) step(std::integral_constant<int, 16>{});
         else if (r.custom_b <= 32) step(std::integral_constant<int, 32>{});

@@ -18,25 +18,31 @@ constexpr double kI16Range = 2.0;    // default int16 range: |f - w rho_ref| <= 
 constexpr int off_index(int a, int b) { return a == 0 ? (b == 1 ? 0 : 1) : 2; }
 
 // Slot table of a user-supplied lattice.  The step kernel holds the b
-// populations in slots: first the pairs of opposite velocities (slots 2p,
-// 2p + 1, P.cnp pairs), then the velocities without an opposite (the rest
-// velocity among them).  Per slot, kCSlot<D> reals: the weight w_j, the
-// storage scales wsc_j and iwsc_j, then the monomials of e_j that the
-// moments of order <= 3 sum, numbered k = 1 .. kCMono<D> - 1 in the order
-// e_a, e_a^2, e_a e_b (a < b), e_a^3, e_a e_b^2 (a != b), e_x e_y e_z (at
-// index 2 + k); after the b rows of reals, b rows of kCInts 32-bit words:
-// j, e_x, e_y, e_z, and the element offset of population j's source row
-// from the own row's first element, ((-e_z ny - e_y) b + j) nxp modulo 2^32
-// (rows whose y and z neighbours need no wrap).  The forward transform adds
-// monomial k times f_j to raw moment k; the back-transform evaluates sum_k
-// monomial k times its coefficient.  For a pair, the even monomials (order
-// 2) multiply f_a + f_b and the odd ones f_a - f_b.
+// populations in slots: first P.cnr rays (slots 4r .. 4r + 3: the pair of
+// opposite velocities +-e, then the pair +-c e for an integer c >= 2), then
+// P.cnp further pairs of opposite velocities (two slots each), then the
+// velocities without an opposite (the rest velocity among them).  Per
+// slot, kCSlot<D> reals: the weight w_j, the storage scales wsc_j and
+// iwsc_j, the monomials of e_j that the moments of order <= 3 sum,
+// numbered k = 1 .. kCMono<D> - 1 in the order e_a, e_a^2, e_a e_b (a < b),
+// e_a^3, e_a e_b^2 (a != b), e_x e_y e_z (at index 2 + k), and c, c^2, c^3
+// (the ray multiplier, set in the third slot of a ray); after the b rows of
+// reals, b rows of kCInts 32-bit words: j, e_x, e_y, e_z, and the element
+// offset of population j's source row from the own row's first element,
+// ((-e_z ny - e_y) b + j) nxp modulo 2^32 (rows whose y and z neighbours
+// need no wrap).  The forward transform adds monomial k times f_j to raw
+// moment k; the back-transform evaluates sum_k monomial k times its
+// coefficient.  A pair sums its even monomials (order 2) over f_a + f_b and
+// its odd ones over f_a - f_b; a ray also folds its second pair into the
+// first pair's monomials with the factors c, c^2, c^3 of orders 1, 2, 3.
 template <int D>
 constexpr int kCMono = D == 2 ? 10 : 20;
 template <int D>
-constexpr int kCSlot = kCMono<D> + 2;
+constexpr int kCSlot = kCMono<D> + 5;
 constexpr int kCInts = 8;
 constexpr bool cm_even(int D, int k) { return k >= 1 + D && k < 1 + 2 * D + D * (D - 1) / 2; }
+// order of monomial k (1, 2 or 3)
+constexpr int cm_order(int D, int k) { return k < 1 + D ? 1 : (cm_even(D, k) ? 2 : 3); }
 constexpr int cm_1(int D, int a) { return 1 + a; }
 constexpr int cm_2n(int D, int a) { return 1 + D + a; }
 constexpr int cm_2o(int D, int a, int b) { return 1 + 2 * D + off_index(a, b); }
@@ -118,7 +124,7 @@ struct KParams {
   // velocity set at run time (read by the user-supplied-lattice kernels)
   int cb;                    // b
   int cmx, cmy, cmz;         // largest |e_x|, |e_y|, |e_z| over the set
-  int cnp;                   // pairs of opposite velocities (slot table of the step kernel)
+  int cnr, cnp;              // rays and further pairs of opposite velocities (slot table)
   int8_t ce[kMaxB][3];       // integer velocity multiples e_j
   // MFMA transform (3D lattices, int16 storage): the forward product gives
   // the raw monomial sums as msig * (acc - mbias[P]) (see mfma.h)

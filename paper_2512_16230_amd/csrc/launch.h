@@ -21,6 +21,7 @@ struct LaunchReq {
   bool xcd_order = true;     // step kernel: tiles in contiguous ranges per XCD (else the dispatch order)
   int dim = 2;               // lattice dimension (user-supplied lattices)
   int custom_b = 0;          // user-supplied lattices: b (sizes the step kernel's register slots)
+  bool custom_rays = false;  // user-supplied lattices: the step's slot table holds rays
   const void* jobs = nullptr;
   int njobs = 1;
   uint32_t blocks = 0;
