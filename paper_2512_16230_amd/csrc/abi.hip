@@ -118,9 +118,8 @@ struct mrtlb_solve {
   void* mtab = nullptr;         // MFMA operand tables (kMfmaTabBytes), or a user-supplied set's slot table
 };
 
-// Slot order of a user-supplied set and whether its step uses rays
-// (defined with the slot table below).
-static std::vector<int> custom_slots(const HostLattice& L, bool rays, int* nrays, int* npairs, std::vector<int>* mult);
+// Whether a user-supplied set's step uses rays (defined with the slot
+// table below).
 static bool custom_rays(const HostLattice& L, int storage);
 
 namespace mrtlb {
@@ -372,7 +371,7 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   P.cnr = P.cnp = 0;
   if (L.kind == kCustom) {
     std::vector<int> mult;
-    (void)custom_slots(L, custom_rays(L, s.storage), &P.cnr, &P.cnp, &mult);
+    (void)velocity_slots(L, custom_rays(L, s.storage), &P.cnr, &P.cnp, &mult);
   }
   for (int j = 0; j < L.B; ++j) {
     for (int a = 0; a < 3; ++a) P.ce[j][a] = (int8_t)(a < D ? L.e[j * D + a] : 0);
@@ -686,102 +685,6 @@ static size_t custom_table_bytes(const HostLattice& L, int storage) {
   return (size_t)L.B * (K * (is_double(storage) ? 8 : 4) + kCInts * 4);
 }
 
-// Slot order of a user-supplied set: rays first (a pair of opposite
-// velocities +-e with a second pair +-c e, c >= 2 an integer, the smallest
-// such c; bases taken shortest first), then the remaining pairs of opposite
-// velocities (each velocity with its first unused opposite, in index
-// order), then the velocities without one.  Returns the slots' population
-// indices and sets *nrays, *npairs; *mult receives c per ray.
-static std::vector<int> custom_slots(const HostLattice& L, bool rays, int* nrays, int* npairs, std::vector<int>* mult) {
-  const int D = L.D;
-  auto comp = [&](int j, int a) { return L.e[j * D + a]; };
-  std::vector<std::pair<int, int>> pairs;
-  std::vector<int> singles;
-  std::vector<char> used(L.B, 0);
-  auto opposite = [&](int i, int j) {
-    bool any = false;
-    for (int a = 0; a < D; ++a) {
-      if (comp(i, a) != -comp(j, a)) return false;
-      any |= comp(i, a) != 0;
-    }
-    return any;
-  };
-  for (int i = 0; i < L.B; ++i) {
-    if (used[i]) continue;
-    used[i] = 1;
-    int partner = -1;
-    for (int j = i + 1; j < L.B && partner < 0; ++j)
-      if (!used[j] && opposite(i, j)) partner = j;
-    if (partner >= 0) {
-      used[partner] = 1;
-      pairs.emplace_back(i, partner);
-    } else {
-      singles.push_back(i);
-    }
-  }
-  // c such that e_j = c e_i (0 if none)
-  auto multiple = [&](int i, int j) {
-    int c = 0;
-    for (int a = 0; a < D; ++a) {
-      if (comp(i, a) == 0) {
-        if (comp(j, a) != 0) return 0;
-        continue;
-      }
-      if (comp(j, a) % comp(i, a) != 0) return 0;
-      const int q = comp(j, a) / comp(i, a);
-      if (q < 2 || (c != 0 && q != c)) return 0;
-      c = q;
-    }
-    return c;
-  };
-  auto norm1 = [&](int j) {
-    int n = 0;
-    for (int a = 0; a < D; ++a) n += std::abs(comp(j, a));
-    return n;
-  };
-  std::vector<size_t> order(pairs.size());
-  for (size_t p = 0; p < pairs.size(); ++p) order[p] = p;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](size_t x, size_t y) { return norm1(pairs[x].first) < norm1(pairs[y].first); });
-  std::vector<char> taken(pairs.size(), 0);
-  std::vector<int> slots, rest;
-  mult->clear();
-  for (size_t oi = 0; oi < (rays ? order.size() : 0); ++oi) {
-    const size_t p = order[oi];
-    if (taken[p]) continue;
-    const int base = pairs[p].first;
-    int best = -1, bestc = 0;
-    bool flip = false;
-    for (size_t q = 0; q < pairs.size(); ++q) {
-      if (q == p || taken[q]) continue;
-      for (int side = 0; side < 2; ++side) {
-        const int c = multiple(base, side ? pairs[q].second : pairs[q].first);
-        if (c >= 2 && (best < 0 || c < bestc)) {
-          best = (int)q;
-          bestc = c;
-          flip = side == 1;
-        }
-      }
-    }
-    if (best < 0) continue;
-    taken[p] = taken[best] = 1;
-    const auto& qp = pairs[best];
-    slots.insert(slots.end(), {base, pairs[p].second, flip ? qp.second : qp.first, flip ? qp.first : qp.second});
-    mult->push_back(bestc);
-  }
-  *nrays = (int)mult->size();
-  int np = 0;
-  for (size_t p = 0; p < pairs.size(); ++p)
-    if (!taken[p]) {
-      slots.push_back(pairs[p].first);
-      slots.push_back(pairs[p].second);
-      ++np;
-    }
-  *npairs = np;
-  slots.insert(slots.end(), singles.begin(), singles.end());
-  return slots;
-}
-
 // The step uses rays (measured on MI355X): for the unscaled storages, when
 // the register class is at most 32 slots or rays hold at least half of the
 // populations; in the 64-slot class a few rays do not pay for the registers
@@ -792,7 +695,7 @@ static bool custom_rays(const HostLattice& L, int storage) {
   if (L.kind != kCustom || storage == kFP16Dev || storage == kBF16Dev || storage == kI16Dev) return false;
   int nr = 0, np = 0;
   std::vector<int> mult;
-  (void)custom_slots(L, true, &nr, &np, &mult);
+  (void)velocity_slots(L, true, &nr, &np, &mult);
   return nr > 0 && (custom_class(L) <= 32 || 8 * nr >= L.B);
 }
 
@@ -802,7 +705,7 @@ static std::vector<char> custom_table(const HostLattice& L, int storage, const K
   const int D = L.D, K = D == 3 ? kCSlot<3> : kCSlot<2>;
   int nr = 0, np = 0;
   std::vector<int> mult;
-  const std::vector<int> slot = custom_slots(L, custom_rays(L, storage), &nr, &np, &mult);
+  const std::vector<int> slot = velocity_slots(L, custom_rays(L, storage), &nr, &np, &mult);
   std::vector<Real> t((size_t)L.B * K, Real(0));
   std::vector<uint32_t> ie((size_t)L.B * kCInts, 0);
   for (int s = 0; s < L.B; ++s) {

@@ -3,9 +3,11 @@
 // pure third-order rows, and their W-norms.  All FP64.
 #include "host_lattice.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <utility>
 
 #include "kernels.h"
 #include "lattices.h"
@@ -364,6 +366,97 @@ mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std
     }
   *out = std::move(L);
   return MRTLB_OK;
+}
+
+// Slot order for the user-supplied lattices' step kernel (host_lattice.h).
+std::vector<int> velocity_slots(const HostLattice& L, bool rays, int* nrays, int* npairs, std::vector<int>* mult) {
+  const int D = L.D;
+  auto comp = [&](int j, int a) { return L.e[j * D + a]; };
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<int> singles;
+  std::vector<char> used(L.B, 0);
+  auto opposite = [&](int i, int j) {
+    bool any = false;
+    for (int a = 0; a < D; ++a) {
+      if (comp(i, a) != -comp(j, a)) return false;
+      any |= comp(i, a) != 0;
+    }
+    return any;
+  };
+  for (int i = 0; i < L.B; ++i) {
+    if (used[i]) continue;
+    used[i] = 1;
+    int partner = -1;
+    for (int j = i + 1; j < L.B && partner < 0; ++j)
+      if (!used[j] && opposite(i, j)) partner = j;
+    if (partner >= 0) {
+      used[partner] = 1;
+      pairs.emplace_back(i, partner);
+    } else {
+      singles.push_back(i);
+    }
+  }
+  // c such that e_j = c e_i (0 if none)
+  auto multiple = [&](int i, int j) {
+    int c = 0;
+    for (int a = 0; a < D; ++a) {
+      if (comp(i, a) == 0) {
+        if (comp(j, a) != 0) return 0;
+        continue;
+      }
+      if (comp(j, a) % comp(i, a) != 0) return 0;
+      const int q = comp(j, a) / comp(i, a);
+      if (q < 2 || (c != 0 && q != c)) return 0;
+      c = q;
+    }
+    return c;
+  };
+  auto norm1 = [&](int j) {
+    int n = 0;
+    for (int a = 0; a < D; ++a) n += std::abs(comp(j, a));
+    return n;
+  };
+  std::vector<size_t> order(pairs.size());
+  for (size_t p = 0; p < pairs.size(); ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return norm1(pairs[x].first) < norm1(pairs[y].first); });
+  std::vector<char> taken(pairs.size(), 0);
+  std::vector<int> slots, rest;
+  mult->clear();
+  for (size_t oi = 0; oi < (rays ? order.size() : 0); ++oi) {
+    const size_t p = order[oi];
+    if (taken[p]) continue;
+    const int base = pairs[p].first;
+    int best = -1, bestc = 0;
+    bool flip = false;
+    for (size_t q = 0; q < pairs.size(); ++q) {
+      if (q == p || taken[q]) continue;
+      for (int side = 0; side < 2; ++side) {
+        const int c = multiple(base, side ? pairs[q].second : pairs[q].first);
+        if (c >= 2 && (best < 0 || c < bestc)) {
+          best = (int)q;
+          bestc = c;
+          flip = side == 1;
+        }
+      }
+    }
+    if (best < 0) continue;
+    taken[p] = taken[best] = 1;
+    const auto& qp = pairs[best];
+    slots.insert(slots.end(), {base, pairs[p].second, flip ? qp.second : qp.first, flip ? qp.first : qp.second});
+    mult->push_back(bestc);
+  }
+  *nrays = (int)mult->size();
+  int np = 0;
+  for (size_t p = 0; p < pairs.size(); ++p)
+    if (!taken[p]) {
+      slots.push_back(pairs[p].first);
+      slots.push_back(pairs[p].second);
+      ++np;
+    }
+  *npairs = np;
+  slots.insert(slots.end(), singles.begin(), singles.end());
+  return slots;
 }
 
 }  // namespace mrtlb

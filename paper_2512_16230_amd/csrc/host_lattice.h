@@ -28,6 +28,15 @@ struct HostLattice {
 // Fills *out from the descriptor; returns MRTLB_OK or an error with *err set.
 mrtlb_status build_lattice(const mrtlb_lattice_desc& desc, HostLattice* out, std::string* err);
 
+// Slot order of the populations for the user-supplied lattices' step
+// kernel: with rays, first rays (slots 4r .. 4r + 3: +-e, then +-c e for an
+// integer c >= 2, the smallest such c; bases taken shortest first), then
+// the remaining pairs of opposite velocities (each velocity with its first
+// unused opposite, in index order), then the velocities without one.
+// Returns the population index of each slot; sets *nrays, *npairs and the
+// multiplier c of each ray in *mult.
+std::vector<int> velocity_slots(const HostLattice& L, bool rays, int* nrays, int* npairs, std::vector<int>* mult);
+
 // Index helpers for the component row order above.
 int row_j(int D, int a);             // order 1, axis a
 int row_nn(int D, int a);            // order 2 normal (c_a^2 - cs^2)

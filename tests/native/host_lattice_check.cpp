@@ -7,8 +7,12 @@
 // where max_offdiag is the largest |sum_j w_j H_r(j) H_s(j)| / sqrt(n_r n_s)
 // over r != s (weighted orthogonality of the Hermite rows), or
 //   err <status> <message>
-// for a refused descriptor.  A last pass builds descriptors with missing
-// arrays and out-of-range sizes, which must be refused.
+// for a refused descriptor.  A line that starts with "S" instead prints,
+// for the descriptor after it, the slot order of the user-supplied step
+// kernel (mrtlb::velocity_slots) with and without rays:
+//   slots <rays> <nrays> <npairs> <c_1 .. c_nrays> : <slot population indices>
+// A last pass builds descriptors with missing arrays and out-of-range
+// sizes, which must be refused.
 #include <cmath>
 #include <cstdio>
 #include <iostream>
@@ -19,6 +23,25 @@
 #include "../../paper_2512_16230_amd/csrc/host_lattice.h"
 
 using mrtlb::HostLattice;
+
+static void report_slots(const mrtlb_lattice_desc& desc) {
+  HostLattice L;
+  std::string err;
+  if (mrtlb::build_lattice(desc, &L, &err) != MRTLB_OK) {
+    std::printf("err %s\n", err.c_str());
+    return;
+  }
+  for (int rays = 1; rays >= 0; --rays) {
+    int nr = -1, np = -1;
+    std::vector<int> mult;
+    const std::vector<int> slot = mrtlb::velocity_slots(L, rays == 1, &nr, &np, &mult);
+    std::printf("slots %d %d %d", rays, nr, np);
+    for (int c : mult) std::printf(" %d", c);
+    std::printf(" :");
+    for (int j : slot) std::printf(" %d", j);
+    std::printf("\n");
+  }
+}
 
 static void report(const mrtlb_lattice_desc& desc) {
   HostLattice L;
@@ -45,7 +68,8 @@ int main() {
   std::string line;
   while (std::getline(std::cin, line)) {
     if (line.empty()) continue;
-    std::istringstream in(line);
+    const bool slots = line[0] == 'S';
+    std::istringstream in(slots ? line.substr(1) : line);
     mrtlb_lattice_desc desc{};
     in >> desc.kind >> desc.d >> desc.b >> desc.c[0] >> desc.c[1] >> desc.c[2] >> desc.cs2 >> desc.n_free;
     for (int k = 0; k < 4; ++k) in >> desc.free_w[k];
@@ -59,7 +83,8 @@ int main() {
       desc.e = e.data();
       desc.w = w.data();
     }
-    report(desc);
+    if (slots) report_slots(desc);
+    else report(desc);
   }
   // refused descriptors: no arrays, sizes out of range, a bad kind
   mrtlb_lattice_desc bad{};

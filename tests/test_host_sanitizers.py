@@ -74,3 +74,63 @@ def test_builder_runs_clean_under_sanitizers(driver):
         assert len(tok) == 4 + B + nlow
     for row in out[len(lines):]:
         assert row.startswith("err %d " % H.MRTLB_EINVAL), row
+
+
+def _slot_rows(driver, cards, seed):
+    lines, sets = [], []
+    for card in cards:
+        lat = OL.make_lattice(card.kind, card.c, card.cs2, card.free)
+        perm = np.random.default_rng(seed).permutation(lat.b)
+        c = list(card.c) + [1.0] * (3 - len(card.c))
+        head = "S %d %d %d %r %r %r %r 0 0 0 0 0" % ((H.KINDS["custom"], lat.d, lat.b) + tuple(c) + (card.cs2,))
+        lines.append(head + " " + " ".join(str(int(v)) for v in lat.e[perm].ravel()) + " " +
+                     " ".join(repr(float(v)) for v in lat.w[perm]))
+        sets.append(lat.e[perm].astype(int))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    res = subprocess.run([driver], input="\n".join(lines) + "\n", capture_output=True, text=True, timeout=300,
+                         env=env)
+    assert res.returncode == 0, res.stderr[-3000:]
+    assert "ERROR: AddressSanitizer" not in res.stderr and "runtime error" not in res.stderr, res.stderr[-3000:]
+    rows = [r for r in res.stdout.splitlines() if r.startswith("slots")]
+    assert len(rows) == 2 * len(cards)
+    out = []
+    for k, e in enumerate(sets):
+        for row in rows[2 * k:2 * k + 2]:
+            head, slots = row.split(":")
+            tok = [int(v) for v in head.split()[1:]]
+            rays, nr, np_ = tok[0], tok[1], tok[2]
+            out.append((e, rays, nr, np_, tok[3:3 + nr], [int(v) for v in slots.split()]))
+    return out
+
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_velocity_slots(driver, seed):
+    """The slot order of the user-supplied step kernel on shuffled velocity
+    sets: a permutation; rays are +-e followed by +-c e (integer c >= 2);
+    pairs are opposite velocities; no two velocities left over are
+    opposites; without rays there are no rays; the counts of the two sets
+    whose structure is known (rD2Q25: 4 rays with c = 2, the (+-3) pairs
+    and the rest velocity; rD3Q53: 13 rays, the rest velocity)."""
+    cards = [W.Q25_RECT, W.Q53_RECT, W.Q13_SQUARE, W.Q21K_RECT, W.Q33_CUBIC, W.Q45_RECT]
+    known = {0: (4, 4), 1: (13, 0)}
+    for k, (e, rays, nr, np_, mult, slot) in enumerate(_slot_rows(driver, cards, seed)):
+        b = len(e)
+        assert sorted(slot) == list(range(b))
+        if not rays:
+            assert nr == 0 and mult == []
+        for r in range(nr):
+            s0 = 4 * r
+            a, a2, c2, c3 = (e[slot[s0 + i]] for i in range(4))
+            assert np.array_equal(a2, -a) and a.any()
+            assert mult[r] >= 2 and np.array_equal(c2, mult[r] * a) and np.array_equal(c3, -c2)
+        for p in range(np_):
+            s = 4 * nr + 2 * p
+            assert np.array_equal(e[slot[s + 1]], -e[slot[s]]) and e[slot[s]].any()
+        left = [e[j] for j in slot[4 * nr + 2 * np_:]]
+        for i in range(len(left)):
+            for j in range(i + 1, len(left)):
+                assert not (np.array_equal(left[i], -left[j]) and left[i].any())
+        if k // 2 in known and rays:
+            assert (nr, np_) == known[k // 2]
+            assert all(c == 2 for c in mult)
+
