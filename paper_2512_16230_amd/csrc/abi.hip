@@ -116,6 +116,7 @@ struct mrtlb_solve {
   bool external = false;        // f[0], f[1] belong to the caller
   int transform = 0;            // Hermite transforms of the step: 0 VALU, 1 MFMA
   void* mtab = nullptr;         // MFMA operand tables (kMfmaTabBytes), or a user-supplied set's slot table
+  bool crays = false;           // user-supplied set: the step's slot table holds rays (custom_rays)
 };
 
 // Whether a user-supplied set's step uses rays (defined with the slot
@@ -371,7 +372,7 @@ static void fill_params(const mrtlb_solve& s, KParams<Real>& P) {
   P.cnr = P.cnp = 0;
   if (L.kind == kCustom) {
     std::vector<int> mult;
-    (void)velocity_slots(L, custom_rays(L, s.storage), &P.cnr, &P.cnp, &mult);
+    (void)velocity_slots(L, s.crays, &P.cnr, &P.cnp, &mult);
   }
   for (int j = 0; j < L.B; ++j) {
     for (int a = 0; a < 3; ++a) P.ce[j][a] = (int8_t)(a < D ? L.e[j * D + a] : 0);
@@ -458,7 +459,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.xcd_order = s.xcd_order;
   r.dim = s.L.D;
   r.custom_b = s.L.kind == kCustom ? s.L.B : 0;
-  r.custom_rays = s.L.kind == kCustom && custom_rays(s.L, s.storage);
+  r.custom_rays = s.crays;
   r.jobs = jobs;
   r.njobs = 1;
   r.blocks = (op == kOpStep || op == kOpStream) ? s.nblocks : s.nblocks_node;
@@ -700,12 +701,12 @@ static bool custom_rays(const HostLattice& L, int storage) {
 }
 
 template <class Real>
-static std::vector<char> custom_table(const HostLattice& L, int storage, const KParams<Real>& P, int64_t ny,
+static std::vector<char> custom_table(const HostLattice& L, bool rays, const KParams<Real>& P, int64_t ny,
                                       int64_t nxp) {
   const int D = L.D, K = D == 3 ? kCSlot<3> : kCSlot<2>;
   int nr = 0, np = 0;
   std::vector<int> mult;
-  const std::vector<int> slot = velocity_slots(L, custom_rays(L, storage), &nr, &np, &mult);
+  const std::vector<int> slot = velocity_slots(L, rays, &nr, &np, &mult);
   std::vector<Real> t((size_t)L.B * K, Real(0));
   std::vector<uint32_t> ie((size_t)L.B * kCInts, 0);
   for (int s = 0; s < L.B; ++s) {
@@ -843,6 +844,7 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   s->vec = pick_vec(storage, s->L.kind, s->model.model, s->nx);
   if (s->model.m2g_form == 1) s->vec = 1;     // the gradient-form kernels run one node per lane
   s->xcd_order = pick_xcd_order(s->nxp, s->vec);
+  s->crays = custom_rays(s->L, storage);
   const uint32_t slots = (uint32_t)s->ny * (uint32_t)s->nz * (uint32_t)s->nxp;
   s->nblocks = (slots + (uint32_t)(kBlock * s->vec) - 1) / (uint32_t)(kBlock * s->vec);
   s->nblocks_node = (s->N + kBlock - 1) / kBlock;
@@ -881,9 +883,9 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   fill_params(*s, s->Pf);
   if (s->L.kind == kCustom) {
     const size_t tb = custom_table_bytes(s->L, storage);
-    ok = (is_double(storage) ? hipMemcpy(s->mtab, custom_table(s->L, storage, s->Pd, s->ny, s->nxp).data(), tb,
+    ok = (is_double(storage) ? hipMemcpy(s->mtab, custom_table(s->L, s->crays, s->Pd, s->ny, s->nxp).data(), tb,
                                          hipMemcpyHostToDevice)
-                             : hipMemcpy(s->mtab, custom_table(s->L, storage, s->Pf, s->ny, s->nxp).data(), tb,
+                             : hipMemcpy(s->mtab, custom_table(s->L, s->crays, s->Pf, s->ny, s->nxp).data(), tb,
                                          hipMemcpyHostToDevice)) == hipSuccess;
   }
   if (!ok || hipMemcpy(s->pd, &s->Pd, sizeof s->Pd, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1684,7 +1686,7 @@ mrtlb_status mrtlb_batch_step(mrtlb_solve* const* solves, int n, const int64_t* 
       // model, force and VEC
       if (!done[k] && nsteps[k] > 0 && b->L.kind == a->L.kind && b->L.D == a->L.D &&
           custom_class(b->L) == custom_class(a->L) && b->storage == a->storage &&
-          custom_rays(b->L, b->storage) == custom_rays(a->L, a->storage) &&
+          b->crays == a->crays &&
           b->model.model == a->model.model && b->has_force == a->has_force && b->vec == a->vec &&
           b->transform == a->transform && b->model.m2g_form == a->model.m2g_form) {
         grp.emplace_back(solves[k], nsteps[k]);
