@@ -563,13 +563,14 @@ def _shuffled_set(card, seed):
 # row pitches that are (320, 64, 128) and are not (96) multiples of a
 # wavefront, and grids with rows far enough from the y and z edges that the
 # source rows need no wrap (the user-supplied kernel's three gather paths);
-# sets whose step runs with rays (rD2Q25, the knight D2Q21 and rD3Q53 in the
-# unscaled storages) and without (rD3Q33, int16)
+# sets whose step runs with rays (rD2Q25, the knight D2Q21, rD2Q13 and
+# rD3Q53 in the unscaled storages) and without (rD3Q33, int16); register
+# classes of 16 (rD2Q13), 32 and 64 slots
 @pytest.mark.parametrize("card,shape", [(W.Q25_RECT, (7, 300)), (W.Q25_RECT, (37, 66)), (W.Q21K_RECT, (20, 40)),
                                         (W.Q25_RECT, (20, 128)), (W.Q33_CUBIC, (5, 9, 66)),
-                                        (W.Q33_CUBIC, (9, 10, 64)), (W.Q53_RECT, (6, 10, 64))],
+                                        (W.Q33_CUBIC, (9, 10, 64)), (W.Q53_RECT, (6, 10, 64)), (W.Q13_SQUARE, (11, 64))],
                          ids=["rD2Q25-7x300", "rD2Q25-37x66", "D2Q21K", "rD2Q25-20x128", "rD3Q33", "rD3Q33-64",
-                              "rD3Q53-64"])
+                              "rD3Q53-64", "rD2Q13-64"])
 @pytest.mark.parametrize("eq", ["NSE_INC", "NSE_COMP"])
 @pytest.mark.parametrize("forced", [False, True], ids=["free", "force"])
 def test_custom_lattice(ctx, card, shape, eq, forced):
