@@ -307,8 +307,11 @@ typedef enum { MRTLB_FP64 = 0, MRTLB_FP32 = 1, MRTLB_FP32_DEV = 2, MRTLB_FP16_DE
 /* Create a solve on a periodic grid n[0] x n[1] (x n[2] in 3D; n[2] = 1 in
  * 2D).  Allocates two population buffers (pull streaming, double-buffered),
  * the force field and a mass-source field (d + 1 node fields) if has_force,
- * for the NCDE two phi history fields, and for the NSE gradient form of
- * M2G_bar (m2g_form = 1) two slots of its history.
+ * for the NCDE two phi history fields, for the NSE gradient form of
+ * M2G_bar (m2g_form = 1) two slots of its history, and for a user-supplied
+ * lattice (MRTLB_CUSTOM) the step kernel's table of its velocities (per
+ * population: weight, storage scales, the monomials of e_j up to third
+ * order, index and source-row offset; a few KB).
  * The lattice is copied; it may be destroyed afterwards.
  * Errors: EINVAL (sizes < 1, a size below the largest lattice offset, a
  * population buffer of 4 GiB or more, rates outside (0, 2), negative or
