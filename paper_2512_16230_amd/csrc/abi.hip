@@ -68,6 +68,7 @@ struct mrtlb_ctx {
   hipStream_t side[kSideStreams] = {};
   hipEvent_t side_done[kSideStreams] = {};
   hipEvent_t staged = nullptr;
+  int lds_per_cu = 0;           // LDS bytes of one compute unit (occupancy cap of the 2D steps)
 };
 
 struct mrtlb_lattice {
@@ -117,6 +118,7 @@ struct mrtlb_solve {
   int transform = 0;            // Hermite transforms of the step: 0 VALU, 1 MFMA
   void* mtab = nullptr;         // MFMA operand tables (kMfmaTabBytes), or a user-supplied set's slot table
   bool crays = false;           // user-supplied set: the step's slot table holds rays (custom_rays)
+  uint32_t step_lds = 0;        // LDS each step workgroup reserves (pick_step_lds)
 };
 
 // Whether a user-supplied set's step uses rays (defined with the slot
@@ -198,6 +200,34 @@ static bool pick_xcd_order(int64_t nxp, int vec) {
     if (o == 0 || o == 1) v = o == 1;
   }
   return v;
+}
+
+// Occupancy cap of the step kernel.  The 2D NSE steps with 32- and 64-bit
+// storage run at the rate of their access pattern, b short streams per
+// lane; with fewer workgroups resident per compute unit fewer streams
+// compete for the DRAM banks and the pattern runs faster.  Measured on
+// MI355X, 4096^2, three workgroups per CU against the eight the registers
+// allow: streaming alone +4%, the rD2Q25 FP32 step +1.2%, rD2Q21 +1.9%,
+// D2Q9 +3%, the gradient form of M2G +1.1%.  The cap is left off where the
+// collision's share of the time needs the occupancy: the 16-bit storages
+// (rD2Q25 int16 +0.6%, D2Q21K int16 -1.4%), the NCDE and CDE (one node
+// per lane: the 256-solve NCDE batch -7% FP32 and -44% int16, the CDE
+// int16 -37%), the 3D lattices (rD3Q53 int16 -3%) and the user-supplied
+// lattices.  A capped step workgroup reserves a third of the CU's LDS,
+// which it does not use.  MRTLB_STEP_WG_PER_CU (0: no cap, 1-8) overrides
+// it for tuning runs.
+static uint32_t pick_step_lds(int lds_per_cu, int dim, int kind, int model, int storage) {
+  const bool nse = model == MRTLB_NSE_INC || model == MRTLB_NSE_COMP;
+  const bool wide = storage == kFP32 || storage == kFP32Dev || storage == kFP64 || storage == kFP32DevF64;
+  int wg = (dim == 2 && kind != kCustom && nse && wide) ? 3 : 0;
+  if (const char* e = std::getenv("MRTLB_STEP_WG_PER_CU")) {
+    const int o = std::atoi(e);
+    if (o >= 0 && o <= 8) wg = o;
+  }
+  if (wg <= 0 || lds_per_cu <= 0) return 0;
+  // the largest multiple of 4 KiB that lets wg workgroups, not wg + 1, share the CU
+  const uint32_t lds = (uint32_t)(lds_per_cu / wg) / 4096u * 4096u;
+  return lds * (uint32_t)(wg + 1) > (uint32_t)lds_per_cu ? lds : 0;
 }
 
 // S2 on the normal second-order component rows (FP64).  Standard lattices
@@ -460,6 +490,7 @@ static LaunchReq base_req(const mrtlb_solve& s, int op, const void* jobs) {
   r.dim = s.L.D;
   r.custom_b = s.L.kind == kCustom ? s.L.B : 0;
   r.custom_rays = s.crays;
+  r.lds = (op == kOpStep || op == kOpStream) ? s.step_lds : 0u;
   r.jobs = jobs;
   r.njobs = 1;
   r.blocks = (op == kOpStep || op == kOpStream) ? s.nblocks : s.nblocks_node;
@@ -550,6 +581,11 @@ mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx
   if (!c) return fail(MRTLB_ENOMEM, "host allocation failed");
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  if (hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    c->lds_per_cu = 0;
+  }
   {
     const mrtlb_status sst = scratch_setup(device, &c->scratch);
     if (sst != MRTLB_OK) {
@@ -845,6 +881,7 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   if (s->model.m2g_form == 1) s->vec = 1;     // the gradient-form kernels run one node per lane
   s->xcd_order = pick_xcd_order(s->nxp, s->vec);
   s->crays = custom_rays(s->L, storage);
+  s->step_lds = pick_step_lds(ctx->lds_per_cu, s->L.D, s->L.kind, s->model.model, storage);
   const uint32_t slots = (uint32_t)s->ny * (uint32_t)s->nz * (uint32_t)s->nxp;
   s->nblocks = (slots + (uint32_t)(kBlock * s->vec) - 1) / (uint32_t)(kBlock * s->vec);
   s->nblocks_node = (s->N + kBlock - 1) / kBlock;

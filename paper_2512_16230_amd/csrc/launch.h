@@ -19,6 +19,7 @@ struct LaunchReq {
   int transform = 0;         // step kernel: Hermite transforms on VALU (0) or MFMA (1)
   bool m2g = false;          // NSE: the gradient form of M2G_bar (history fields, one node per lane)
   bool xcd_order = true;     // step kernel: tiles in contiguous ranges per XCD (else the dispatch order)
+  uint32_t lds = 0;          // step and streaming kernels: LDS bytes each workgroup reserves (occupancy cap)
   int dim = 2;               // lattice dimension (user-supplied lattices)
   int custom_b = 0;          // user-supplied lattices: b (sizes the step kernel's register slots)
   bool custom_rays = false;  // user-supplied lattices: the step's slot table holds rays

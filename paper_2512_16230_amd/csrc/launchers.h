@@ -31,19 +31,19 @@ hipError_t launch_lattice(const LaunchReq& r) {
           constexpr int V = decltype(vc)::value;
           if (ncde) {
             if constexpr (V == 1) {
-              hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, 0, r.stream, J, r.njobs, tb);
+              hipLaunchKernelGGL((k_step<L, ST, kNcde, false, V>), grid, block, r.lds, r.stream, J, r.njobs, tb);
               launched = true;
             }
           } else if (cde) {
             if constexpr (V == 1) {
-              hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, 0, r.stream, J, r.njobs, tb);
+              hipLaunchKernelGGL((k_step<L, ST, kCde, false, V>), grid, block, r.lds, r.stream, J, r.njobs, tb);
               launched = true;
             }
           } else if constexpr (L::D == 2 || V == 1) {
             if (r.force)
-              hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, 0, r.stream, J, r.njobs, tb);
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, true, V>), grid, block, r.lds, r.stream, J, r.njobs, tb);
             else
-              hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, 0, r.stream, J, r.njobs, tb);
+              hipLaunchKernelGGL((k_step<L, ST, kNseComp, false, V>), grid, block, r.lds, r.stream, J, r.njobs, tb);
             launched = true;
           }
         };
@@ -51,9 +51,9 @@ hipError_t launch_lattice(const LaunchReq& r) {
           if constexpr (kGradBuilt) {
             if (!ncde && !cde && r.vec == 1) {
               if (r.force)
-                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, true, 1>), grid, block, 0, r.stream, J, r.njobs, tb);
+                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, true, 1>), grid, block, r.lds, r.stream, J, r.njobs, tb);
               else
-                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, false, 1>), grid, block, 0, r.stream, J, r.njobs, tb);
+                hipLaunchKernelGGL((k_step<L, ST, kNseGrad, false, 1>), grid, block, r.lds, r.stream, J, r.njobs, tb);
               launched = true;
             }
           }
@@ -109,14 +109,14 @@ hipError_t launch_lattice(const LaunchReq& r) {
         // the step kernel's launch shape: VEC 2 and 4 on the 2D lattices only
         if constexpr (L::D == 2) {
           if (r.vec == 4)
-            hipLaunchKernelGGL((k_stream<L, ST, 4>), grid, block, 0, r.stream, J, tb);
+            hipLaunchKernelGGL((k_stream<L, ST, 4>), grid, block, r.lds, r.stream, J, tb);
           else if (r.vec == 2)
-            hipLaunchKernelGGL((k_stream<L, ST, 2>), grid, block, 0, r.stream, J, tb);
+            hipLaunchKernelGGL((k_stream<L, ST, 2>), grid, block, r.lds, r.stream, J, tb);
           else
-            hipLaunchKernelGGL((k_stream<L, ST, 1>), grid, block, 0, r.stream, J, tb);
+            hipLaunchKernelGGL((k_stream<L, ST, 1>), grid, block, r.lds, r.stream, J, tb);
         } else {
           if (r.vec != 1) return;
-          hipLaunchKernelGGL((k_stream<L, ST, 1>), grid, block, 0, r.stream, J, tb);
+          hipLaunchKernelGGL((k_stream<L, ST, 1>), grid, block, r.lds, r.stream, J, tb);
         }
         break;
       default:
