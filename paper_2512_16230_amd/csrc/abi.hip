@@ -69,6 +69,7 @@ struct mrtlb_ctx {
   hipEvent_t side_done[kSideStreams] = {};
   hipEvent_t staged = nullptr;
   int lds_per_cu = 0;           // LDS bytes of one compute unit (occupancy cap of the 2D steps)
+  int lds_per_block = 0;        // largest LDS allocation of one workgroup
 };
 
 struct mrtlb_lattice {
@@ -208,7 +209,10 @@ static bool pick_xcd_order(int64_t nxp, int vec) {
 // compete for the DRAM banks and the pattern runs faster.  Measured on
 // MI355X, 4096^2, three workgroups per CU against the eight the registers
 // allow: streaming alone +4%, the rD2Q25 FP32 step +1.2%, rD2Q21 +1.9%,
-// D2Q9 +3%, the gradient form of M2G +1.1%.  The cap is left off where the
+// D2Q9 +3%, the gradient form of M2G +1.1%; two per CU pay further where a
+// workgroup streams b >= 25 populations at two nodes per lane (rD2Q25 FP32
+// +0.8%, FP64 +1.4% over three) and cost elsewhere (D2Q9 -4%, the
+// one-node-per-lane gradient form -10%).  The cap is left off where the
 // collision's share of the time needs the occupancy: the 16-bit storages
 // (rD2Q25 int16 +0.6%, D2Q21K int16 -1.4%), the NCDE and CDE (one node
 // per lane: the 256-solve NCDE batch -7% FP32 and -44% int16, the CDE
@@ -216,18 +220,20 @@ static bool pick_xcd_order(int64_t nxp, int vec) {
 // lattices.  A capped step workgroup reserves a third of the CU's LDS,
 // which it does not use.  MRTLB_STEP_WG_PER_CU (0: no cap, 1-8) overrides
 // it for tuning runs.
-static uint32_t pick_step_lds(int lds_per_cu, int dim, int kind, int model, int storage) {
+static uint32_t pick_step_lds(int lds_per_cu, int lds_per_block, int dim, int kind, int model, int storage, int b,
+                              int vec) {
   const bool nse = model == MRTLB_NSE_INC || model == MRTLB_NSE_COMP;
   const bool wide = storage == kFP32 || storage == kFP32Dev || storage == kFP64 || storage == kFP32DevF64;
-  int wg = (dim == 2 && kind != kCustom && nse && wide) ? 3 : 0;
+  int wg = (dim == 2 && kind != kCustom && nse && wide) ? (b >= 25 && vec >= 2 ? 2 : 3) : 0;
   if (const char* e = std::getenv("MRTLB_STEP_WG_PER_CU")) {
     const int o = std::atoi(e);
     if (o >= 0 && o <= 8) wg = o;
   }
-  if (wg <= 0 || lds_per_cu <= 0) return 0;
-  // the largest multiple of 4 KiB that lets wg workgroups, not wg + 1, share the CU
-  const uint32_t lds = (uint32_t)(lds_per_cu / wg) / 4096u * 4096u;
-  return lds * (uint32_t)(wg + 1) > (uint32_t)lds_per_cu ? lds : 0;
+  if (wg <= 0 || lds_per_cu <= 0 || lds_per_block <= 0) return 0;
+  // a multiple of 4 KiB, within one workgroup's limit, that lets wg
+  // workgroups, not wg + 1, share the CU (else no cap)
+  const uint32_t lds = (uint32_t)std::min(lds_per_cu / wg, lds_per_block) / 4096u * 4096u;
+  return lds * (uint32_t)wg <= (uint32_t)lds_per_cu && lds * (uint32_t)(wg + 1) > (uint32_t)lds_per_cu ? lds : 0;
 }
 
 // S2 on the normal second-order component rows (FP64).  Standard lattices
@@ -582,9 +588,10 @@ mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
   if (hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
-      hipSuccess) {
+          hipSuccess ||
+      hipDeviceGetAttribute(&c->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
     (void)hipGetLastError();
-    c->lds_per_cu = 0;
+    c->lds_per_cu = c->lds_per_block = 0;
   }
   {
     const mrtlb_status sst = scratch_setup(device, &c->scratch);
@@ -881,7 +888,8 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   if (s->model.m2g_form == 1) s->vec = 1;     // the gradient-form kernels run one node per lane
   s->xcd_order = pick_xcd_order(s->nxp, s->vec);
   s->crays = custom_rays(s->L, storage);
-  s->step_lds = pick_step_lds(ctx->lds_per_cu, s->L.D, s->L.kind, s->model.model, storage);
+  s->step_lds = pick_step_lds(ctx->lds_per_cu, ctx->lds_per_block, s->L.D, s->L.kind, s->model.model, storage,
+                              s->L.B, s->vec);
   const uint32_t slots = (uint32_t)s->ny * (uint32_t)s->nz * (uint32_t)s->nxp;
   s->nblocks = (slots + (uint32_t)(kBlock * s->vec) - 1) / (uint32_t)(kBlock * s->vec);
   s->nblocks_node = (s->N + kBlock - 1) / kBlock;
