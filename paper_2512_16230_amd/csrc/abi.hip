@@ -192,10 +192,16 @@ static int pick_vec(int storage, int kind, int model, int nx) {
 // dispatch order, which deals consecutive tiles to the XCDs in turn, keeps
 // the rows in flight in a narrow band.  Measured on MI355X: rD3Q53 256^3
 // int16 +4% and D3Q27 +4% in dispatch order; rD2Q25 4096^2 FP32 +3% and the
-// rD2Q13 NCDE batch +9% in XCD ranges.  MRTLB_XCD_ORDER (0 or 1) overrides
-// it for tuning runs.
-static bool pick_xcd_order(int64_t nxp, int vec) {
+// rD2Q13 NCDE batch +9% (FP32) in XCD ranges.  One 2D solve with 16-bit
+// storage runs 1-3% faster in dispatch order (rD2Q25, rD2Q21, D2Q21K, D2Q9
+// and the rD2Q13 CDE at 4096^2), while a batch of many solves with 16-bit
+// storage keeps XCD ranges (the NCDE batch: +8% in int16), so `batched`
+// selects the rule for a launch over several solves' job tables.
+// MRTLB_XCD_ORDER (0 or 1) overrides it for tuning runs.
+static bool pick_xcd_order(int64_t nxp, int vec, int dim, int storage, bool batched) {
   bool v = nxp > (int64_t)kBlock * vec;
+  const bool narrow = storage == kFP16Dev || storage == kBF16Dev || storage == kI16Dev;
+  if (dim == 2 && narrow && !batched) v = false;
   if (const char* e = std::getenv("MRTLB_XCD_ORDER")) {
     const int o = std::atoi(e);
     if (o == 0 || o == 1) v = o == 1;
@@ -886,7 +892,7 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   // a workgroup kBlock * vec consecutive slots
   s->vec = pick_vec(storage, s->L.kind, s->model.model, s->nx);
   if (s->model.m2g_form == 1) s->vec = 1;     // the gradient-form kernels run one node per lane
-  s->xcd_order = pick_xcd_order(s->nxp, s->vec);
+  s->xcd_order = pick_xcd_order(s->nxp, s->vec, s->L.D, storage, false);
   s->crays = custom_rays(s->L, storage);
   s->step_lds = pick_step_lds(ctx->lds_per_cu, ctx->lds_per_block, s->L.D, s->L.kind, s->model.model, storage,
                               s->L.B, s->vec);
@@ -1586,6 +1592,7 @@ static mrtlb_status launch_group(const Group& g, const std::vector<uint32_t>& pr
     const size_t table = k == 0 ? 0 : 1 + (size_t)(k & 1);
     const void* jp = static_cast<const char*>(table_dev) + table * n * sizeof(Job<Real>);
     LaunchReq r = base_req(*g[0].first, kOpStep, jp);
+    if (n > 1) r.xcd_order = pick_xcd_order(g[0].first->nxp, g[0].first->vec, g[0].first->L.D, g[0].first->storage, true);
     r.njobs = m;
     r.blocks = prefix[m];
     r.stream = stream;
