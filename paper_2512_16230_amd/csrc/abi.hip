@@ -70,6 +70,7 @@ struct mrtlb_ctx {
   hipEvent_t staged = nullptr;
   int lds_per_cu = 0;           // LDS bytes of one compute unit (occupancy cap of the 2D steps)
   int lds_per_block = 0;        // largest LDS allocation of one workgroup
+  int cus = 0;                  // compute units (occupancy cap: workgroups per resident round)
 };
 
 struct mrtlb_lattice {
@@ -209,7 +210,7 @@ static bool pick_xcd_order(int64_t nxp, int vec, int dim, int storage, bool batc
   return v;
 }
 
-// Occupancy cap of the step kernel.  The 2D NSE steps with 32- and 64-bit
+// Occupancy cap of the step kernel.  The NSE steps with 32- and 64-bit
 // storage run at the rate of their access pattern, b short streams per
 // lane; with fewer workgroups resident per compute unit fewer streams
 // compete for the DRAM banks and the pattern runs faster.  Measured on
@@ -218,19 +219,36 @@ static bool pick_xcd_order(int64_t nxp, int vec, int dim, int storage, bool batc
 // D2Q9 +3%, the gradient form of M2G +1.1%; two per CU pay further where a
 // workgroup streams b >= 25 populations at two nodes per lane (rD2Q25 FP32
 // +0.8%, FP64 +1.4% over three) and cost elsewhere (D2Q9 -4%, the
-// one-node-per-lane gradient form -10%).  The cap is left off where the
+// one-node-per-lane gradient form -10%).  In 3D (256^3, against no cap)
+// two per CU pay where a node stores at least 180 bytes (rD3Q53 FP32
+// +2.3%, with a mass source +2.4%, rD3Q45 FP32 +1.9%, D3Q27 FP64 +5.1%) and
+// three elsewhere (D3Q27 FP32 +1.8%; rD3Q33 FP32 level at 256^3 and +2.0%
+// at 128^3, where two cost 5%); the gradient form takes three (two cost it
+// 1.7%).  The cap is left off where the
 // collision's share of the time needs the occupancy: the 16-bit storages
-// (rD2Q25 int16 +0.6%, D2Q21K int16 -1.4%), the NCDE and CDE (one node
-// per lane: the 256-solve NCDE batch -7% FP32 and -44% int16, the CDE
-// int16 -37%), the 3D lattices (rD3Q53 int16 -3%) and the user-supplied
-// lattices.  A capped step workgroup reserves a third of the CU's LDS,
-// which it does not use.  MRTLB_STEP_WG_PER_CU (0: no cap, 1-8) overrides
-// it for tuning runs.
-static uint32_t pick_step_lds(int lds_per_cu, int lds_per_block, int dim, int kind, int model, int storage, int b,
-                              int vec) {
+// (rD2Q25 int16 +0.6%, D2Q21K int16 -1.4%, rD3Q53 int16 -3%), the NCDE and
+// CDE (one node per lane: the 256-solve NCDE batch -7% FP32 and -44% int16,
+// the CDE int16 -37%) and the user-supplied lattices.  A capped step
+// workgroup reserves a third or a half of the CU's LDS, which it does not
+// use.  On smaller grids the cap leaves the chip part-empty in the last
+// rounds of workgroups, so it applies only where the launch fills at least
+// eight rounds of the capped residency (measured, cap against none: rD2Q25
+// FP32 2048^2 +3.6% and 1024^2 +0.3%; D2Q9 FP32 1024^2, 2.7 rounds, -2%;
+// rD3Q53 FP32 128^3 +1.0%, 96^3 -3%, 64^3 -5%; D3Q27 FP32 128^3 +2.6%, 96^3
+// -1.6%, 64^3 -14%).  MRTLB_STEP_WG_PER_CU (0: no cap, 1-8) overrides it,
+// at any size, for tuning runs.
+static uint32_t pick_step_lds(int lds_per_cu, int lds_per_block, int cus, uint32_t nblocks, int dim, int kind,
+                              int model, int storage, int b, int vec, bool m2g) {
   const bool nse = model == MRTLB_NSE_INC || model == MRTLB_NSE_COMP;
   const bool wide = storage == kFP32 || storage == kFP32Dev || storage == kFP64 || storage == kFP32DevF64;
-  int wg = (dim == 2 && kind != kCustom && nse && wide) ? (b >= 25 && vec >= 2 ? 2 : 3) : 0;
+  int wg = 0;
+  if (kind != kCustom && nse && wide) {
+    if (dim == 2)
+      wg = b >= 25 && vec >= 2 ? 2 : 3;
+    else
+      wg = (size_t)b * elem_bytes(storage) >= 180 && !m2g ? 2 : 3;
+  }
+  if (wg > 0 && (uint64_t)nblocks < 8ull * (uint64_t)wg * (uint64_t)(cus > 0 ? cus : 0)) wg = 0;
   if (const char* e = std::getenv("MRTLB_STEP_WG_PER_CU")) {
     const int o = std::atoi(e);
     if (o >= 0 && o <= 8) wg = o;
@@ -595,9 +613,10 @@ mrtlb_status mrtlb_ctx_create(int device, void* stream, size_t budget, mrtlb_ctx
   c->stream = static_cast<hipStream_t>(stream);
   if (hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
           hipSuccess ||
-      hipDeviceGetAttribute(&c->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+      hipDeviceGetAttribute(&c->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
     (void)hipGetLastError();
-    c->lds_per_cu = c->lds_per_block = 0;
+    c->lds_per_cu = c->lds_per_block = c->cus = 0;
   }
   {
     const mrtlb_status sst = scratch_setup(device, &c->scratch);
@@ -894,10 +913,10 @@ static mrtlb_status create_solve(mrtlb_ctx* ctx, const mrtlb_lattice* lat, const
   if (s->model.m2g_form == 1) s->vec = 1;     // the gradient-form kernels run one node per lane
   s->xcd_order = pick_xcd_order(s->nxp, s->vec, s->L.D, storage, false);
   s->crays = custom_rays(s->L, storage);
-  s->step_lds = pick_step_lds(ctx->lds_per_cu, ctx->lds_per_block, s->L.D, s->L.kind, s->model.model, storage,
-                              s->L.B, s->vec);
   const uint32_t slots = (uint32_t)s->ny * (uint32_t)s->nz * (uint32_t)s->nxp;
   s->nblocks = (slots + (uint32_t)(kBlock * s->vec) - 1) / (uint32_t)(kBlock * s->vec);
+  s->step_lds = pick_step_lds(ctx->lds_per_cu, ctx->lds_per_block, ctx->cus, s->nblocks, s->L.D, s->L.kind,
+                              s->model.model, storage, s->L.B, s->vec, s->model.m2g_form == 1);
   s->nblocks_node = (s->N + kBlock - 1) / kBlock;
   (void)hipSetDevice(ctx->device);
   const size_t pop = (size_t)s->L.B * (size_t)s->ny * s->nz * s->nxp * elem_bytes(storage);
