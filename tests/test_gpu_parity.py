@@ -837,6 +837,34 @@ def test_launch_shape_invariance(ctx, storage, monkeypatch):
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("card,shape", [(W.Q25_RECT, (6, 1024)), (W.Q53_RECT, (6, 10, 40)), (W.Q27_RECT, (5, 6, 64))],
+                         ids=["rD2Q25", "rD3Q53", "D3Q27"])
+@pytest.mark.parametrize("storage", ["fp32", "i16_dev"])
+def test_tile_order_and_occupancy_cap_invariance(ctx, card, shape, storage, monkeypatch):
+    """The order of the step's tiles over the XCDs and the occupancy cap
+    (LDS reserved so that fewer workgroups share a compute unit) are launch
+    choices only: every combination gives bit-identical populations.  The
+    environment forces both at any grid size; 1024-node rows hold two or four
+    tiles, so the two orders differ."""
+    rates = W.rates_tau(0.7)
+    rho, u = _random_fields(card, shape, 23)
+    m30 = card.kind not in ("D2Q9", "D3Q27")
+    outs = []
+    for order in ("0", "1"):
+        for wg in ("0", "2", "3"):
+            monkeypatch.setenv("MRTLB_XCD_ORDER", order)
+            monkeypatch.setenv("MRTLB_STEP_WG_PER_CU", wg)
+            print("case: tile order %s, %s workgroups per CU, %s %s %s" % (order, wg, card.kind, shape, storage),
+                  flush=True)
+            s = H.Solve(ctx, hip_lattice(card), hip_model("NSE_COMP", rates, m30=m30), shape, storage)
+            s.init_fields(rho, u)
+            s.step(7)
+            outs.append(s.read_populations())
+            s.close()
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
 # --------------------------------------------------------------------------
 # the FP32 bar of 1e-6 after 500 steps
 # --------------------------------------------------------------------------
