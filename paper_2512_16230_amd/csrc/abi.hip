@@ -224,29 +224,34 @@ static bool pick_xcd_order(int64_t nxp, int vec, int dim, int storage, bool batc
 // +2.3%, with a mass source +2.4%, rD3Q45 FP32 +1.9%, D3Q27 FP64 +5.1%) and
 // three elsewhere (D3Q27 FP32 +1.8%; rD3Q33 FP32 level at 256^3 and +2.0%
 // at 128^3, where two cost 5%); the gradient form takes three (two cost it
-// 1.7%).  The cap is left off where the
-// collision's share of the time needs the occupancy: the 16-bit storages
-// (rD2Q25 int16 +0.6%, D2Q21K int16 -1.4%, rD3Q53 int16 -3%), the NCDE and
-// CDE (one node per lane: the 256-solve NCDE batch -7% FP32 and -44% int16,
-// the CDE int16 -37%) and the user-supplied lattices.  A capped step
+// 1.7%).  The 2D NCDE and CDE steps (one node per lane) with 32- and 64-bit
+// storage take four (the 256-solve NCDE batch +3.7%, the CDE at 4096^2
+// +1.5%; three cost the batch 7%, two cost the CDE 7%).  The cap is left off
+// where the collision's share of the time needs the occupancy: the 16-bit
+// storages (rD2Q25 int16 +0.6%, D2Q21K int16 -1.4%, rD3Q53 int16 -3%, the
+// NCDE batch int16 -44% and the CDE int16 -37% at three) and the
+// user-supplied lattices.  A capped step
 // workgroup reserves a third or a half of the CU's LDS, which it does not
 // use.  On smaller grids the cap leaves the chip part-empty in the last
 // rounds of workgroups, so it applies only where the launch fills at least
 // eight rounds of the capped residency (measured, cap against none: rD2Q25
 // FP32 2048^2 +3.6% and 1024^2 +0.3%; D2Q9 FP32 1024^2, 2.7 rounds, -2%;
 // rD3Q53 FP32 128^3 +1.0%, 96^3 -3%, 64^3 -5%; D3Q27 FP32 128^3 +2.6%, 96^3
-// -1.6%, 64^3 -14%).  MRTLB_STEP_WG_PER_CU (0: no cap, 1-8) overrides it,
-// at any size, for tuning runs.
+// -1.6%, 64^3 -14%).  A batched launch decides on the workgroups of all its
+// solves.  MRTLB_STEP_WG_PER_CU (0: no cap, 1-8) overrides it, at any size,
+// for tuning runs.
 static uint32_t pick_step_lds(int lds_per_cu, int lds_per_block, int cus, uint32_t nblocks, int dim, int kind,
                               int model, int storage, int b, int vec, bool m2g) {
   const bool nse = model == MRTLB_NSE_INC || model == MRTLB_NSE_COMP;
   const bool wide = storage == kFP32 || storage == kFP32Dev || storage == kFP64 || storage == kFP32DevF64;
   int wg = 0;
-  if (kind != kCustom && nse && wide) {
-    if (dim == 2)
+  if (kind != kCustom && wide) {
+    if (nse && dim == 2)
       wg = b >= 25 && vec >= 2 ? 2 : 3;
-    else
+    else if (nse)
       wg = (size_t)b * elem_bytes(storage) >= 180 && !m2g ? 2 : 3;
+    else if (dim == 2)
+      wg = 4;
   }
   if (wg > 0 && (uint64_t)nblocks < 8ull * (uint64_t)wg * (uint64_t)(cus > 0 ? cus : 0)) wg = 0;
   if (const char* e = std::getenv("MRTLB_STEP_WG_PER_CU")) {
@@ -1606,12 +1611,20 @@ static mrtlb_status launch_group(const Group& g, const std::vector<uint32_t>& pr
                                  int64_t done, int64_t seg, hipStream_t stream) {
   const size_t n = g.size();
   int m = (int)n;
+  // several solves in one launch: tile order and occupancy cap for the batch
+  const mrtlb_solve& a = *g[0].first;
+  const bool xcd = pick_xcd_order(a.nxp, a.vec, a.L.D, a.storage, true);
+  const uint32_t lds = pick_step_lds(a.ctx->lds_per_cu, a.ctx->lds_per_block, a.ctx->cus, prefix[n], a.L.D, a.L.kind,
+                                     a.model.model, a.storage, a.L.B, a.vec, a.model.m2g_form == 1);
   for (int64_t k = 0; k < seg; ++k) {
     while (m > 0 && g[m - 1].second <= done + k) --m;
     const size_t table = k == 0 ? 0 : 1 + (size_t)(k & 1);
     const void* jp = static_cast<const char*>(table_dev) + table * n * sizeof(Job<Real>);
     LaunchReq r = base_req(*g[0].first, kOpStep, jp);
-    if (n > 1) r.xcd_order = pick_xcd_order(g[0].first->nxp, g[0].first->vec, g[0].first->L.D, g[0].first->storage, true);
+    if (n > 1) {
+      r.xcd_order = xcd;
+      r.lds = lds;
+    }
     r.njobs = m;
     r.blocks = prefix[m];
     r.stream = stream;
