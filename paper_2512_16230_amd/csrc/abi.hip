@@ -224,9 +224,11 @@ static bool pick_xcd_order(int64_t nxp, int vec, int dim, int storage, bool batc
 // +2.3%, with a mass source +2.4%, rD3Q45 FP32 +1.9%, D3Q27 FP64 +5.1%) and
 // three elsewhere (D3Q27 FP32 +1.8%; rD3Q33 FP32 level at 256^3 and +2.0%
 // at 128^3, where two cost 5%); the gradient form takes three (two cost it
-// 1.7%).  The 2D NCDE and CDE steps (one node per lane) with 32- and 64-bit
-// storage take four (the 256-solve NCDE batch +3.7%, the CDE at 4096^2
-// +1.5%; three cost the batch 7%, two cost the CDE 7%).  The cap is left off
+// 1.7%).  The 3D CDE steps follow the same rule (FP32 at 256^3: rD3Q53 +5%
+// at two, rD3Q33 +3% and D3Q27 +2% at three).  The 2D NCDE and CDE steps
+// (one node per lane) with 32- and 64-bit storage take four (the 256-solve
+// NCDE batch +3.7%, the CDE at 4096^2 +1.5%; three cost the batch 7%, two
+// cost the CDE 7%).  The cap is left off
 // where the collision's share of the time needs the occupancy: the 16-bit
 // storages (rD2Q25 int16 +0.6%, D2Q21K int16 -1.4%, rD3Q53 int16 -3%, the
 // NCDE batch int16 -44% and the CDE int16 -37% at three) and the
@@ -246,12 +248,10 @@ static uint32_t pick_step_lds(int lds_per_cu, int lds_per_block, int cus, uint32
   const bool wide = storage == kFP32 || storage == kFP32Dev || storage == kFP64 || storage == kFP32DevF64;
   int wg = 0;
   if (kind != kCustom && wide) {
-    if (nse && dim == 2)
-      wg = b >= 25 && vec >= 2 ? 2 : 3;
-    else if (nse)
+    if (dim == 3)
       wg = (size_t)b * elem_bytes(storage) >= 180 && !m2g ? 2 : 3;
-    else if (dim == 2)
-      wg = 4;
+    else
+      wg = !nse ? 4 : b >= 25 && vec >= 2 ? 2 : 3;
   }
   if (wg > 0 && (uint64_t)nblocks < 8ull * (uint64_t)wg * (uint64_t)(cus > 0 ? cus : 0)) wg = 0;
   if (const char* e = std::getenv("MRTLB_STEP_WG_PER_CU")) {
