@@ -190,6 +190,7 @@ def bench_tgv3d(torch, H, W, stream, args):
     if not forced and not args.m2g and args.transform == "valu" and not args.custom:
         out["roofline"]["traffic"] = measured_traffic(card.kind, args.storage, "%dx%dx%d" % (n, n, n), launch_bytes)
         out["roofline"]["stream_only"] = stream_ceiling(s, args.steps, launch_bytes, kernel_ms / 1e3 / args.steps)
+    out["roofline"]["launch"] = s.launch_shape()
     s.close()
     ctx.close()
     return out
@@ -223,6 +224,7 @@ def bench_cde(torch, H, W, stream, args):
                 nodes * args.steps / wall / 1e6, "MLUPS", args, wall,
                 {"workload": "cde-shear-rD2Q13-%dx%d" % (n, n), "lattice": "rD2Q13", "storage": args.storage,
                  "nodes": nodes}, args.storage, launch_bytes, kernel_ms / 1e3 / args.steps)
+    out["roofline"]["launch"] = s.launch_shape()
     s.close()
     ctx.close()
     return out
@@ -488,6 +490,7 @@ def bench_tgv2d(torch, H, W, stream, args):
     }
     if not args.custom and not args.m2g:
         out["roofline"]["stream_only"] = stream_ceiling(s, args.steps, launch_bytes, per_launch_s)
+    out["roofline"]["launch"] = s.launch_shape()
     s.close()
     ctx.close()
     return out

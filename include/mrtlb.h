@@ -429,6 +429,20 @@ mrtlb_status mrtlb_step_timed(mrtlb_solve* s, int64_t nsteps, double* ms);
  * user-supplied lattice), EDEVICE. */
 mrtlb_status mrtlb_stream_only(mrtlb_solve* s, int64_t npasses, double* ms);
 
+/* The launch shape chosen for a solve's step kernel, a measurement aid (the
+ * choices are measured heuristics of the library; the environment variables
+ * MRTLB_STEP_VEC, MRTLB_XCD_ORDER and MRTLB_STEP_WG_PER_CU, read when the
+ * solve is created, override them for tuning runs).  *nodes_per_lane:
+ * consecutive x-nodes per thread (1, 2 or 4); *xcd_ranges: 1 if the tiles
+ * run in contiguous ranges per XCD, 0 if in dispatch order; *wg_per_cu: the
+ * workgroups per compute unit that the occupancy cap allows (LDS reserved
+ * and not used), 0 if uncapped; *workgroups: workgroups of one step launch.
+ * Any output pointer may be NULL.  A batched launch over several solves
+ * takes its own tile order and cap from the whole batch.  Errors: EINVAL
+ * (NULL solve).  No device work. */
+mrtlb_status mrtlb_solve_launch_shape(const mrtlb_solve* s, int* nodes_per_lane, int* xcd_ranges, int* wg_per_cu,
+                                      int64_t* workgroups);
+
 /* Drift correction of the conserved totals.  The collision conserves mass,
  * and momentum without a force, exactly (Sec. II, eq. M-NSEs-1); the
  * rounding of the stored populations does not.  With every > 0, after each

@@ -92,6 +92,8 @@ def lib():
         "mrtlb_step": (c_int, [c_void_p, c_int64]),
         "mrtlb_step_timed": (c_int, [c_void_p, c_int64, _DP]),
         "mrtlb_stream_only": (c_int, [c_void_p, c_int64, _DP]),
+        "mrtlb_solve_launch_shape": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                             POINTER(c_int64)]),
         "mrtlb_batch_step": (c_int, [POINTER(c_void_p), c_int, POINTER(c_int64)]),
         "mrtlb_read_moments": (c_int, [c_void_p, _DP, _DP]),
         "mrtlb_conserved": (c_int, [c_void_p, _DP, _DP]),
@@ -123,7 +125,7 @@ EXPORTED = ["mrtlb_last_error", "mrtlb_version", "mrtlb_ctx_create", "mrtlb_ctx_
             "mrtlb_read_populations", "mrtlb_write_populations", "mrtlb_solve_steps", "mrtlb_set_drift_correction",
             "mrtlb_host_alloc", "mrtlb_host_free", "mrtlb_population_bytes", "mrtlb_solve_create_external",
             "mrtlb_conserved_noalloc", "mrtlb_solve_set_transform", "mrtlb_set_velocity_field",
-            "mrtlb_set_force_field", "mrtlb_set_mass_source_field"]
+            "mrtlb_set_force_field", "mrtlb_set_mass_source_field", "mrtlb_solve_launch_shape"]
 
 
 def _check(status):
@@ -387,6 +389,15 @@ class Solve:
         ms = c_double()
         _check(lib().mrtlb_stream_only(self.h, int(n), byref(ms)))
         return ms.value
+
+    def launch_shape(self):
+        """The step kernel's launch shape: nodes per lane, tile order
+        ("xcd" ranges or "dispatch"), workgroups per CU under the occupancy
+        cap (0: uncapped) and workgroups per launch."""
+        v, x, w, g = c_int(), c_int(), c_int(), c_int64()
+        _check(lib().mrtlb_solve_launch_shape(self.h, byref(v), byref(x), byref(w), byref(g)))
+        return {"nodes_per_lane": v.value, "tile_order": "xcd" if x.value else "dispatch",
+                "wg_per_cu": w.value, "workgroups": g.value}
 
     def read_moments(self, with_u=True, out=None):
         """(rho_or_phi, u) as arrays of the grid shape; ``out`` = (r, u) lets

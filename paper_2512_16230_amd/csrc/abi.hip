@@ -1547,6 +1547,16 @@ mrtlb_status mrtlb_stream_only(mrtlb_solve* s, int64_t npasses, double* ms) {
   return MRTLB_OK;
 }
 
+mrtlb_status mrtlb_solve_launch_shape(const mrtlb_solve* s, int* nodes_per_lane, int* xcd_ranges, int* wg_per_cu,
+                                      int64_t* workgroups) {
+  if (!s) return fail(MRTLB_EINVAL, "solve is NULL");
+  if (nodes_per_lane) *nodes_per_lane = s->vec;
+  if (xcd_ranges) *xcd_ranges = s->xcd_order ? 1 : 0;
+  if (wg_per_cu) *wg_per_cu = s->step_lds > 0 ? (int)((uint32_t)s->ctx->lds_per_cu / s->step_lds) : 0;
+  if (workgroups) *workgroups = (int64_t)s->nblocks;
+  return MRTLB_OK;
+}
+
 static mrtlb_status reserve_jobs(mrtlb_ctx* c, size_t bytes) {
   if (bytes <= c->job_cap) return MRTLB_OK;
   size_t cap = std::max<size_t>(bytes, 2 * c->job_cap);
